@@ -1,0 +1,422 @@
+/*
+ * fkmc.c -- FP64 CPU oracle for the Monte Carlo Feynman-Kac estimator of the
+ * fixed-point Helmholtz iteration.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is the slow, plainly written reference the
+ * HIP library is checked against.  Only the test suite, the smoke entry point
+ * and the benchmark's CPU-baseline leg may load it; the product path never
+ * does.  It shares no source, header, table or helper with the HIP library.
+ *
+ * Method (Bernal, Chen, dos Reis, "An iterative method for Helmholtz boundary
+ * value problems arising in wave propagation"):
+ *   - Problem: Delta u + k^2 u = f in Omega, u = g on dOmega, k real, f and g
+ *     complex (Sec. 1, eq. (1.1); Sec. 2.2, eq. (2.4) with damping p = 0 and
+ *     no reflecting boundary part).
+ *   - With the shift alpha = k^2 (Sec. 1, eq. (1.4)) the problem becomes the
+ *     fixed-point sequence  Delta u_{n+1} = f - k^2 u_n,  u_{n+1} = g on the
+ *     boundary, u_0 = 0.  These are the partial sums sum_{j<=n} (v_j + i w_j)
+ *     of the iteration (2.6)-(2.8), as written out in the proof of Theorem 2.2.
+ *   - Each Poisson step is solved pointwise with the Feynman-Kac formula of
+ *     Sec. 2.1, eq. (2.3), specialised to c = 0 and a purely absorbing
+ *     boundary:  u_{n+1}(y) = E[g(Y_tau)] - E[int_0^tau (f - k^2 u_n)(Y_t) dt],
+ *     with Y_t = y + sqrt(2) W_t (eq. (2.2)).
+ *   - Every iterate n uses a new, independent Brownian motion (Remark 2.1);
+ *     the counter of the random-number generator therefore contains n.
+ *
+ * Discretisation (the readings where the paper is silent):
+ *   - Euler-Maruyama: X_0 = y, X_{t+1} = X_t + sqrt(2h) (z_x, z_y).
+ *   - Normals from Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) with
+ *     key = (seed mod 2^32, seed div 2^32) and counter
+ *     (floor(t/2), m, node_id, n)  (n replaced by 0 in common-random-number
+ *     mode).  Increment t uses words (r0, r1) when t is even, (r2, r3) when
+ *     odd.  Uniform U(r) = (2 (r >> 9) + 1) 2^-24, exactly representable in
+ *     binary32 and binary64.  Box-Muller: rho = sqrt(-2 ln U(ra)),
+ *     phi = 2 pi U(rb), z = rho (cos phi, sin phi).
+ *   - Exit: J = first t >= 1 with X_t outside the open domain (a point on the
+ *     boundary counts as outside), capped at jmax.  The boundary datum is taken
+ *     at the nearest boundary point of X_J.
+ *   - Integral: left-point rule over the J increments,
+ *     s = g(Pi X_J) - h sum_{t<J} (f - k^2 I_h[u_n])(X_t),
+ *     where I_h is bilinear interpolation of the grid of u_n.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ---------------------------------------------------------------- types -- */
+
+enum { ORC_RECT = 0, ORC_RECT_MINUS_DISC = 1 };
+enum { ORC_SRC_ZERO = 0, ORC_SRC_CONST = 1, ORC_SRC_GAUSSIAN = 2 };
+enum { ORC_BC_ZERO = 0, ORC_BC_PLANE_WAVE = 1, ORC_BC_BILINEAR = 2, ORC_BC_TABLE = 3 };
+
+/* Boundary datum.  PLANE_WAVE: c = (amp_re, amp_im, theta) and
+ * g = amp exp(i k (x cos theta + y sin theta)).  BILINEAR: c holds the complex
+ * coefficients (c0, c1, c2, c3), g = c0 + c1 x + c2 y + c3 x y.  TABLE: samples
+ * (re, im interleaved) at equal arclength steps round the rectangle,
+ * counter-clockwise from (x0, y0), linearly interpolated and periodic. */
+typedef struct {
+    int32_t kind;
+    int32_t pad;
+    double c[8];
+    const double *table;
+    int64_t table_len;
+} orc_bc;
+
+typedef struct {
+    int32_t domain_kind;
+    int32_t nx, ny;
+    int32_t src_kind;
+    double x0, x1, y0, y1;
+    double cx, cy, r;
+    double src_re, src_im, src_cx, src_cy, src_sigma;
+    orc_bc outer, inner;
+    double k, h;
+    int64_t M;
+    uint64_t seed;
+    int64_t jmax;
+    int32_t crn;
+    int32_t g_unprojected; /* test variant: g taken at X_J itself */
+} orc_problem;
+
+/* --------------------------------------------------------------- Philox -- */
+
+/* One Philox4x32 round and the key schedule as defined by Salmon et al.,
+ * SC'11, Sec. on the Philox family: two 32x32->64 products, the high halves
+ * xor-ed with the other counter words and the key. */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+void orc_philox_batch(const uint32_t *ctrs, const uint32_t key[2], int64_t n, uint32_t *out)
+{
+    for (int64_t i = 0; i < n; ++i) orc_philox4x32_10(ctrs + 4 * i, key, out + 4 * i);
+}
+
+double orc_uniform(uint32_t r)
+{
+    return (2.0 * (double)(r >> 9) + 1.0) * ldexp(1.0, -24);
+}
+
+void orc_box_muller(uint32_t ra, uint32_t rb, double z[2])
+{
+    const double two_pi = 6.283185307179586476925286766559;
+    double rho = sqrt(-2.0 * log(orc_uniform(ra)));
+    double phi = two_pi * orc_uniform(rb);
+    z[0] = rho * cos(phi);
+    z[1] = rho * sin(phi);
+}
+
+/* ------------------------------------------------------ grid and domain -- */
+
+static double grid_dx(const orc_problem *P) { return (P->x1 - P->x0) / (double)(P->nx - 1); }
+static double grid_dy(const orc_problem *P) { return (P->y1 - P->y0) / (double)(P->ny - 1); }
+
+void orc_node_xy(const orc_problem *P, int32_t node_id, double xy[2])
+{
+    int32_t i = node_id % P->nx, j = node_id / P->nx;
+    xy[0] = P->x0 + (double)i * grid_dx(P);
+    xy[1] = P->y0 + (double)j * grid_dy(P);
+}
+
+static int in_hole(const orc_problem *P, double x, double y)
+{
+    if (P->domain_kind != ORC_RECT_MINUS_DISC) return 0;
+    double ex = x - P->cx, ey = y - P->cy;
+    return ex * ex + ey * ey <= P->r * P->r;
+}
+
+/* The open domain: strictly inside the rectangle and strictly outside the disc. */
+int orc_outside(const orc_problem *P, double x, double y)
+{
+    if (x <= P->x0 || x >= P->x1 || y <= P->y0 || y >= P->y1) return 1;
+    return in_hole(P, x, y);
+}
+
+/* 0 interior, 1 on the rectangle edge, 2 in the closed disc. */
+int orc_node_class(const orc_problem *P, int32_t node_id)
+{
+    int32_t i = node_id % P->nx, j = node_id / P->nx;
+    if (i == 0 || j == 0 || i == P->nx - 1 || j == P->ny - 1) return 1;
+    double xy[2];
+    orc_node_xy(P, node_id, xy);
+    return in_hole(P, xy[0], xy[1]) ? 2 : 0;
+}
+
+/* Nearest boundary point of X.  Outside the rectangle: clamp into it (outer
+ * boundary).  In the closed disc: radial projection onto the circle.  Inside
+ * the domain (only for a path stopped by the step cap): the nearest of the four
+ * edges and the circle.  Returns 1 for the outer boundary, 2 for the circle. */
+int orc_project(const orc_problem *P, double x, double y, double p[2])
+{
+    if (x <= P->x0 || x >= P->x1 || y <= P->y0 || y >= P->y1) {
+        p[0] = x < P->x0 ? P->x0 : (x > P->x1 ? P->x1 : x);
+        p[1] = y < P->y0 ? P->y0 : (y > P->y1 ? P->y1 : y);
+        return 1;
+    }
+    double ex = x - P->cx, ey = y - P->cy;
+    double d = sqrt(ex * ex + ey * ey);
+    int disc = P->domain_kind == ORC_RECT_MINUS_DISC;
+    if (!(disc && d <= P->r)) {
+        double dd[4] = {x - P->x0, P->x1 - x, y - P->y0, P->y1 - y};
+        int e = 0;
+        for (int c = 1; c < 4; ++c)
+            if (dd[c] < dd[e]) e = c;
+        if (!disc || dd[e] <= d - P->r) {
+            p[0] = e == 0 ? P->x0 : (e == 1 ? P->x1 : x);
+            p[1] = e == 2 ? P->y0 : (e == 3 ? P->y1 : y);
+            return 1;
+        }
+    }
+    if (d > 0.0) {
+        p[0] = P->cx + P->r * ex / d;
+        p[1] = P->cy + P->r * ey / d;
+    } else {
+        p[0] = P->cx + P->r;
+        p[1] = P->cy;
+    }
+    return 2;
+}
+
+/* Arclength of a point on the rectangle edge, counter-clockwise from (x0,y0). */
+static double perimeter_s(const orc_problem *P, double x, double y)
+{
+    double a = P->x1 - P->x0, b = P->y1 - P->y0;
+    if (y == P->y0) return x - P->x0;
+    if (x == P->x1) return a + (y - P->y0);
+    if (y == P->y1) return a + b + (P->x1 - x);
+    return 2.0 * a + b + (P->y1 - y);
+}
+
+static void bc_eval(const orc_problem *P, const orc_bc *B, double x, double y, double g[2])
+{
+    switch (B->kind) {
+    case ORC_BC_PLANE_WAVE: {
+        double ph = P->k * (x * cos(B->c[2]) + y * sin(B->c[2]));
+        double cr = cos(ph), si = sin(ph);
+        g[0] = B->c[0] * cr - B->c[1] * si;
+        g[1] = B->c[0] * si + B->c[1] * cr;
+        return;
+    }
+    case ORC_BC_BILINEAR:
+        g[0] = B->c[0] + B->c[2] * x + B->c[4] * y + B->c[6] * x * y;
+        g[1] = B->c[1] + B->c[3] * x + B->c[5] * y + B->c[7] * x * y;
+        return;
+    case ORC_BC_TABLE: {
+        double a = P->x1 - P->x0, b = P->y1 - P->y0;
+        double per = 2.0 * (a + b);
+        int64_t L = B->table_len;
+        double u = perimeter_s(P, x, y) / per * (double)L;
+        double fl = floor(u);
+        double w = u - fl;
+        int64_t i0 = ((int64_t)fl % L + L) % L;
+        int64_t i1 = (i0 + 1) % L;
+        g[0] = (1.0 - w) * B->table[2 * i0] + w * B->table[2 * i1];
+        g[1] = (1.0 - w) * B->table[2 * i0 + 1] + w * B->table[2 * i1 + 1];
+        return;
+    }
+    default:
+        g[0] = 0.0;
+        g[1] = 0.0;
+    }
+}
+
+/* g at a boundary point; which = 1 outer rectangle, 2 circle. */
+void orc_g(const orc_problem *P, int which, double x, double y, double g[2])
+{
+    bc_eval(P, which == 2 ? &P->inner : &P->outer, x, y, g);
+}
+
+/* Grid values that the iterate carries on non-interior nodes for n >= 1:
+ * g on the rectangle edge, the inner datum's own formula on hole nodes. */
+void orc_fill_boundary(const orc_problem *P, double *u)
+{
+    int64_t nn = (int64_t)P->nx * P->ny;
+    for (int64_t id = 0; id < nn; ++id) {
+        int cls = orc_node_class(P, (int32_t)id);
+        if (cls == 0) continue;
+        double xy[2], g[2];
+        orc_node_xy(P, (int32_t)id, xy);
+        orc_g(P, cls, xy[0], xy[1], g);
+        u[2 * id] = g[0];
+        u[2 * id + 1] = g[1];
+    }
+}
+
+/* Bilinear interpolation I_h of a complex grid (re, im interleaved, node
+ * (i, j) at index i + nx j) on the cell that contains (x, y). */
+void orc_interp(const orc_problem *P, const double *u, double x, double y, double out[2])
+{
+    double fx = (x - P->x0) / grid_dx(P);
+    double fy = (y - P->y0) / grid_dy(P);
+    int64_t p = (int64_t)floor(fx), q = (int64_t)floor(fy);
+    if (p < 0) p = 0;
+    if (p > P->nx - 2) p = P->nx - 2;
+    if (q < 0) q = 0;
+    if (q > P->ny - 2) q = P->ny - 2;
+    double a = fx - (double)p, b = fy - (double)q;
+    int64_t i00 = p + (int64_t)P->nx * q, i10 = i00 + 1, i01 = i00 + P->nx, i11 = i01 + 1;
+    for (int c = 0; c < 2; ++c)
+        out[c] = (1.0 - a) * (1.0 - b) * u[2 * i00 + c] + a * (1.0 - b) * u[2 * i10 + c]
+               + (1.0 - a) * b * u[2 * i01 + c] + a * b * u[2 * i11 + c];
+}
+
+static void source_eval(const orc_problem *P, double x, double y, double f[2])
+{
+    switch (P->src_kind) {
+    case ORC_SRC_CONST:
+        f[0] = P->src_re;
+        f[1] = P->src_im;
+        return;
+    case ORC_SRC_GAUSSIAN: {
+        double ex = x - P->src_cx, ey = y - P->src_cy;
+        double e = exp(-(ex * ex + ey * ey) / (2.0 * P->src_sigma * P->src_sigma));
+        f[0] = P->src_re * e;
+        f[1] = P->src_im * e;
+        return;
+    }
+    default:
+        f[0] = 0.0;
+        f[1] = 0.0;
+    }
+}
+
+/* ----------------------------------------------------------- one path -- */
+
+/* Simulates path m from node node_id for the Poisson step that produces
+ * u_{n+1} from u_n (u == NULL means u_n = 0 everywhere, the start u_0).
+ * Writes the score s (re, im), the exit-step index J, whether the cap was
+ * hit, and the exit point X_J. */
+void orc_path(const orc_problem *P, const double *u, int32_t n, int32_t node_id, int64_t m,
+              double s[2], int64_t *J_out, int32_t *capped, double xJ[2])
+{
+    const double sigma = sqrt(2.0 * P->h);
+    const double k2 = P->k * P->k;
+    uint32_t key[2] = {(uint32_t)(P->seed & 0xFFFFFFFFu), (uint32_t)(P->seed >> 32)};
+    uint32_t ctr[4], r[4];
+    double X[2];
+    orc_node_xy(P, node_id, X);
+    double acc[2] = {0.0, 0.0};
+    int64_t t = 0;
+    int exited = 0;
+    for (;;) {
+        if (t % 2 == 0) {
+            ctr[0] = (uint32_t)(t / 2);
+            ctr[1] = (uint32_t)m;
+            ctr[2] = (uint32_t)node_id;
+            ctr[3] = P->crn ? 0u : (uint32_t)n;
+            orc_philox4x32_10(ctr, key, r);
+        }
+        double z[2];
+        if (t % 2 == 0)
+            orc_box_muller(r[0], r[1], z);
+        else
+            orc_box_muller(r[2], r[3], z);
+        /* left-point value of the right-hand side f - k^2 u_n at X_t */
+        double f[2], un[2] = {0.0, 0.0};
+        source_eval(P, X[0], X[1], f);
+        if (u) orc_interp(P, u, X[0], X[1], un);
+        acc[0] += f[0] - k2 * un[0];
+        acc[1] += f[1] - k2 * un[1];
+        X[0] = X[0] + sigma * z[0];
+        X[1] = X[1] + sigma * z[1];
+        t += 1;
+        if (orc_outside(P, X[0], X[1])) { exited = 1; break; }
+        if (t >= P->jmax) break;
+    }
+    double g[2];
+    if (P->g_unprojected) {
+        /* test variant: the datum's own formula at X_J (needs a global g) */
+        int outer = X[0] <= P->x0 || X[0] >= P->x1 || X[1] <= P->y0 || X[1] >= P->y1;
+        orc_g(P, (outer || !exited) ? 1 : 2, X[0], X[1], g);
+    } else {
+        double pr[2];
+        int which = orc_project(P, X[0], X[1], pr);
+        orc_g(P, which, pr[0], pr[1], g);
+    }
+    s[0] = g[0] - P->h * acc[0];
+    s[1] = g[1] - P->h * acc[1];
+    *J_out = t;
+    *capped = exited ? 0 : 1;
+    xJ[0] = X[0];
+    xJ[1] = X[1];
+}
+
+/* ------------------------------------------------- node estimates -- */
+
+/* Node statistics of one Poisson step at the listed nodes: mean score
+ * (re, im), unbiased sample variance (re, im; denominator M - 1), the sum of
+ * exit-step indices and the number of capped paths.  Scores are kept and
+ * reduced in path order m = 0 .. M-1 (two-pass variance). */
+int orc_fk_nodes(const orc_problem *P, const double *u, int32_t n, const int32_t *node_ids,
+                 int64_t count, double *mean, double *var, int64_t *sumJ, int64_t *capped,
+                 int32_t nthreads)
+{
+    const int64_t M = P->M;
+    int bad = 0;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : bad)
+    for (int64_t c = 0; c < count; ++c) {
+        double *sc = (double *)malloc((size_t)M * 2 * sizeof(double));
+        if (!sc) { bad = 1; continue; }
+        int64_t sj = 0, nc = 0;
+        for (int64_t m = 0; m < M; ++m) {
+            double s[2], xj[2];
+            int64_t J;
+            int32_t cap;
+            orc_path(P, u, n, node_ids[c], m, s, &J, &cap, xj);
+            sc[2 * m] = s[0];
+            sc[2 * m + 1] = s[1];
+            sj += J;
+            nc += cap;
+        }
+        for (int comp = 0; comp < 2; ++comp) {
+            double sum = 0.0;
+            for (int64_t m = 0; m < M; ++m) sum += sc[2 * m + comp];
+            double mu = sum / (double)M;
+            double ss = 0.0;
+            for (int64_t m = 0; m < M; ++m) {
+                double d = sc[2 * m + comp] - mu;
+                ss += d * d;
+            }
+            mean[2 * c + comp] = mu;
+            var[2 * c + comp] = M > 1 ? ss / (double)(M - 1) : 0.0;
+        }
+        sumJ[c] = sj;
+        capped[c] = nc;
+        free(sc);
+    }
+    return bad;
+}
+
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

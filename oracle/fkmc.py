@@ -1,0 +1,297 @@
+"""Python face of the C oracle (``fkmc.c``) and the fixed-point loop.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
+
+Problem descriptions are duck-typed: any object with the attributes of
+``paper_2308_11469_amd.workloads.Problem`` works; this module imports nothing
+from the product package.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_KIND_DOMAIN = {"rect": 0, "rect_minus_disc": 1}
+_KIND_SRC = {"zero": 0, "const": 1, "gaussian": 2}
+_KIND_BC = {"zero": 0, "plane_wave": 1, "bilinear": 2, "table": 3}
+
+
+class _BC(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("pad", C.c_int32), ("c", C.c_double * 8),
+                ("table", C.POINTER(C.c_double)), ("table_len", C.c_int64)]
+
+
+class _Problem(C.Structure):
+    _fields_ = [("domain_kind", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32),
+                ("src_kind", C.c_int32),
+                ("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
+                ("cx", C.c_double), ("cy", C.c_double), ("r", C.c_double),
+                ("src_re", C.c_double), ("src_im", C.c_double), ("src_cx", C.c_double),
+                ("src_cy", C.c_double), ("src_sigma", C.c_double),
+                ("outer", _BC), ("inner", _BC),
+                ("k", C.c_double), ("h", C.c_double), ("M", C.c_int64), ("seed", C.c_uint64),
+                ("jmax", C.c_int64), ("crn", C.c_int32), ("g_unprojected", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.ensure_built()
+        L = C.CDLL(path)
+        dp = C.POINTER(C.c_double)
+        u32p = C.POINTER(C.c_uint32)
+        i32p = C.POINTER(C.c_int32)
+        i64p = C.POINTER(C.c_int64)
+        pp = C.POINTER(_Problem)
+        L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
+        L.orc_philox_batch.argtypes = [u32p, u32p, C.c_int64, u32p]
+        L.orc_uniform.argtypes = [C.c_uint32]
+        L.orc_uniform.restype = C.c_double
+        L.orc_box_muller.argtypes = [C.c_uint32, C.c_uint32, dp]
+        L.orc_node_xy.argtypes = [pp, C.c_int32, dp]
+        L.orc_outside.argtypes = [pp, C.c_double, C.c_double]
+        L.orc_outside.restype = C.c_int
+        L.orc_node_class.argtypes = [pp, C.c_int32]
+        L.orc_node_class.restype = C.c_int
+        L.orc_project.argtypes = [pp, C.c_double, C.c_double, dp]
+        L.orc_project.restype = C.c_int
+        L.orc_g.argtypes = [pp, C.c_int, C.c_double, C.c_double, dp]
+        L.orc_fill_boundary.argtypes = [pp, dp]
+        L.orc_interp.argtypes = [pp, dp, C.c_double, C.c_double, dp]
+        L.orc_path.argtypes = [pp, dp, C.c_int32, C.c_int32, C.c_int64, dp, i64p, i32p, dp]
+        L.orc_fk_nodes.argtypes = [pp, dp, C.c_int32, i32p, C.c_int64, dp, dp, i64p, i64p, C.c_int32]
+        L.orc_fk_nodes.restype = C.c_int
+        L.orc_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def jmax_auto(p) -> int:
+    """Step cap: ceil(40 / (lambda_1 h)) with lambda_1 = pi^2 (1/a^2 + 1/b^2) of
+    the bounding rectangle (a lower bound for lambda_1 of the holed domain), so
+    that P(tau > cap) is about e^-40."""
+    a, b = p.x1 - p.x0, p.y1 - p.y0
+    lam = math.pi ** 2 * (1.0 / a ** 2 + 1.0 / b ** 2)
+    return int(math.ceil(40.0 / (lam * p.h)))
+
+
+class Handle:
+    """ctypes view of one problem; keeps the table alive."""
+
+    def __init__(self, p):
+        self.p = p
+        s = _Problem()
+        s.domain_kind = _KIND_DOMAIN[p.domain_kind]
+        s.nx, s.ny = int(p.nx), int(p.ny)
+        s.src_kind = _KIND_SRC[p.src_kind]
+        s.x0, s.x1, s.y0, s.y1 = p.x0, p.x1, p.y0, p.y1
+        s.cx, s.cy, s.r = p.cx, p.cy, p.r
+        s.src_re, s.src_im = complex(p.src_amp).real, complex(p.src_amp).imag
+        s.src_cx, s.src_cy, s.src_sigma = p.src_cx, p.src_cy, p.src_sigma
+        self._tables = []
+        for name in ("outer", "inner"):
+            bc = getattr(p, name)
+            dst = getattr(s, name)
+            dst.kind = _KIND_BC[bc.kind]
+            if bc.kind == "plane_wave":
+                dst.c[0], dst.c[1], dst.c[2] = complex(bc.amp).real, complex(bc.amp).imag, bc.theta
+            elif bc.kind == "bilinear":
+                for i, z in enumerate(bc.coeffs):
+                    dst.c[2 * i], dst.c[2 * i + 1] = complex(z).real, complex(z).imag
+            elif bc.kind == "table":
+                t = np.ascontiguousarray(np.asarray(bc.table, dtype=np.complex128)).view(np.float64)
+                self._tables.append(t)
+                dst.table = _dptr(t)
+                dst.table_len = len(t) // 2
+        s.k, s.h, s.M, s.seed = p.k, p.h, int(p.M), int(p.seed)
+        s.jmax = int(p.jmax) if p.jmax else jmax_auto(p)
+        s.crn = 1 if p.crn else 0
+        s.g_unprojected = 1 if getattr(p, "g_unprojected", False) else 0
+        self.s = s
+        self.ref = C.byref(s)
+
+
+# ----------------------------------------------------------- RNG pieces
+
+def philox(ctrs, key):
+    """Philox4x32-10 words for an (n, 4) array of counters and a 2-word key."""
+    ctrs = np.ascontiguousarray(np.asarray(ctrs, dtype=np.uint32).reshape(-1, 4))
+    key = np.ascontiguousarray(np.asarray(key, dtype=np.uint32).reshape(2))
+    out = np.empty_like(ctrs)
+    u32p = C.POINTER(C.c_uint32)
+    lib().orc_philox_batch(ctrs.ctypes.data_as(u32p), key.ctypes.data_as(u32p),
+                           ctrs.shape[0], out.ctypes.data_as(u32p))
+    return out
+
+
+def uniform(r: int) -> float:
+    return lib().orc_uniform(int(r) & 0xFFFFFFFF)
+
+
+def box_muller(ra: int, rb: int):
+    z = (C.c_double * 2)()
+    lib().orc_box_muller(int(ra) & 0xFFFFFFFF, int(rb) & 0xFFFFFFFF, z)
+    return z[0], z[1]
+
+
+# ----------------------------------------------------------- geometry
+
+def node_classes(p) -> np.ndarray:
+    """0 interior, 1 rectangle edge, 2 hole (closed disc); shape (ny, nx)."""
+    H = Handle(p)
+    cls = np.array([lib().orc_node_class(H.ref, i) for i in range(p.nx * p.ny)], dtype=np.int32)
+    return cls.reshape(p.ny, p.nx)
+
+
+def interior_ids(p) -> np.ndarray:
+    return np.nonzero(node_classes(p).ravel() == 0)[0].astype(np.int32)
+
+
+def outside(p, x, y) -> bool:
+    return bool(lib().orc_outside(Handle(p).ref, float(x), float(y)))
+
+
+def project(p, x, y):
+    out = (C.c_double * 2)()
+    which = lib().orc_project(Handle(p).ref, float(x), float(y), out)
+    return which, (out[0], out[1])
+
+
+def g_at(p, which, x, y) -> complex:
+    out = (C.c_double * 2)()
+    lib().orc_g(Handle(p).ref, int(which), float(x), float(y), out)
+    return complex(out[0], out[1])
+
+
+def interp(p, u, x, y) -> complex:
+    """Bilinear interpolant of the complex grid u (shape (ny, nx)) at (x, y)."""
+    ub = np.ascontiguousarray(np.asarray(u, dtype=np.complex128)).view(np.float64).ravel()
+    out = (C.c_double * 2)()
+    lib().orc_interp(Handle(p).ref, _dptr(ub), float(x), float(y), out)
+    return complex(out[0], out[1])
+
+
+def boundary_grid(p) -> np.ndarray:
+    """Complex grid with g on edge nodes and the inner datum on hole nodes,
+    zero on interior nodes (the iterate's fixed part for n >= 1)."""
+    u = np.zeros((p.ny, p.nx), dtype=np.complex128)
+    ub = u.view(np.float64).ravel()
+    lib().orc_fill_boundary(Handle(p).ref, _dptr(ub))
+    return u
+
+
+# ----------------------------------------------------------- estimator
+
+def path(p, u, n, node_id, m):
+    """One path: returns (score, J, capped, X_J).  u is the complex grid of u_n
+    (None for u_0 = 0)."""
+    H = Handle(p)
+    s = (C.c_double * 2)()
+    xj = (C.c_double * 2)()
+    J = C.c_int64()
+    cap = C.c_int32()
+    if u is None:
+        up = None
+    else:
+        ub = np.ascontiguousarray(np.asarray(u, dtype=np.complex128)).view(np.float64).ravel()
+        up = _dptr(ub)
+    lib().orc_path(H.ref, up, int(n), int(node_id), int(m), s, C.byref(J), C.byref(cap), xj)
+    return complex(s[0], s[1]), int(J.value), int(cap.value), (xj[0], xj[1])
+
+
+def fk_nodes(p, u, n, node_ids=None, nthreads=0):
+    """Feynman-Kac estimates of one Poisson step (u_n -> u_{n+1}) at the given
+    nodes (all interior nodes by default).  Returns a dict with complex
+    ``mean``, ``var_re``, ``var_im`` (sample variances), ``se`` (complex:
+    sqrt(var_re/M) + i sqrt(var_im/M)), ``sumJ`` and ``capped``."""
+    H = Handle(p)
+    ids = interior_ids(p) if node_ids is None else np.ascontiguousarray(np.asarray(node_ids, dtype=np.int32))
+    cnt = len(ids)
+    mean = np.zeros(2 * cnt)
+    var = np.zeros(2 * cnt)
+    sumJ = np.zeros(cnt, dtype=np.int64)
+    capped = np.zeros(cnt, dtype=np.int64)
+    if u is None:
+        up = None
+    else:
+        ub = np.ascontiguousarray(np.asarray(u, dtype=np.complex128)).view(np.float64).ravel()
+        up = _dptr(ub)
+    rc = lib().orc_fk_nodes(H.ref, up, int(n), ids.ctypes.data_as(C.POINTER(C.c_int32)), cnt,
+                            _dptr(mean), _dptr(var), sumJ.ctypes.data_as(C.POINTER(C.c_int64)),
+                            capped.ctypes.data_as(C.POINTER(C.c_int64)), int(nthreads))
+    if rc:
+        raise MemoryError("oracle: allocation failed")
+    mean_c = mean[0::2] + 1j * mean[1::2]
+    M = float(p.M)
+    return dict(ids=ids, mean=mean_c, var_re=var[0::2], var_im=var[1::2],
+                se=np.sqrt(var[0::2] / M) + 1j * np.sqrt(var[1::2] / M),
+                sumJ=sumJ, capped=capped)
+
+
+def solve(p, max_iters=None, tol=None, nthreads=0, u0=None, n0=0, callback=None):
+    """The fixed-point loop  Delta u_{n+1} = f - k^2 u_n  (Sec. 1 eq. (1.4)
+    with alpha = k^2; the partial sums of Theorem 2.2), each step by
+    ``fk_nodes``.  u_0 = 0 everywhere; from n = 1 the grid carries g on edge
+    and hole nodes.  Stops when max_interior |u_{n+1} - u_n| < tol (the
+    sup-norm control of Sec. 3) or after max_iters steps.
+
+    Divergence rule: the change is non-finite, or, five iterations apart, both
+    the sup norm of the iterate and the change have grown by at least 25%
+    (a contraction shrinks the change; the noise floor of fresh paths keeps
+    both flat).  Also records the first iteration whose change is below the
+    noise floor 4 max SE.  Returns a dict with the final grid, per-node SE and
+    the per-iteration history."""
+    max_iters = p.max_iters if max_iters is None else max_iters
+    tol = p.tol if tol is None else tol
+    ids = interior_ids(p)
+    bgrid = boundary_grid(p)
+    u = None if u0 is None else np.array(u0, dtype=np.complex128)
+    hist = []
+    diverged = False
+    se = None
+    for it in range(n0, n0 + max_iters):
+        est = fk_nodes(p, u, it, ids, nthreads)
+        new = bgrid.copy()
+        new.ravel()[ids] = est["mean"]
+        old_int = np.zeros(len(ids), dtype=np.complex128) if u is None else u.ravel()[ids]
+        du = float(np.max(np.abs(est["mean"] - old_int))) if len(ids) else 0.0
+        sup = float(np.max(np.abs(est["mean"]))) if len(ids) else 0.0
+        se = est["se"]
+        floor = 4.0 * float(np.max(np.abs(se))) if len(ids) else 0.0
+        diverging = not (math.isfinite(du) and math.isfinite(sup))
+        if len(hist) >= 5 and not diverging:
+            back = hist[-5]
+            diverging = sup >= 1.25 * back["sup"] and du >= 1.25 * back["max_du"]
+        rec = dict(n=it, max_du=du, sup=sup, noise_floor=floor, sumJ=int(est["sumJ"].sum()),
+                   capped=int(est["capped"].sum()), diverging=bool(diverging))
+        hist.append(rec)
+        if callback:
+            callback(rec, new)
+        u = new
+        if rec["diverging"]:
+            diverged = True
+            break
+        if tol > 0 and du < tol:
+            break
+    se_grid = np.zeros((p.ny, p.nx), dtype=np.complex128)
+    if se is not None:
+        se_grid.ravel()[ids] = se
+    below = [h["n"] for h in hist if h["max_du"] < h["noise_floor"]]
+    return dict(u=u, se=se_grid, history=hist, diverged=diverged,
+                noise_floor_iter=below[0] if below else None)
+
+
+def threads() -> int:
+    return int(lib().orc_threads())

@@ -1,0 +1,201 @@
+"""Pins of the oracle's Feynman-Kac estimator and fixed-point loop (CPU only).
+
+Each test checks the oracle against something other than itself:
+
+* martingale: with k = 0, f = 0 and a harmonic quadratic g evaluated at the
+  exit point itself, g(X_t) is an exact martingale of the Gaussian walk, so the
+  estimator is unbiased for g(y) (optional stopping);
+* exit time: with k = 0, f = -1, g = 0 the score is h J, whose mean is the
+  exit time of y + sqrt(2) W (Remark 2.5), pinned by the torsion series of
+  the rectangle enlarged by the Broadie-Glasserman-Kou shift
+  beta sqrt(2h) that discrete monitoring causes;
+* scaling E_{Lambda Omega}(Lambda x) = Lambda^2 E_Omega(x) (Sec. 3), exact
+  path by path for Lambda = 2;
+* integral rule: with u_n equal to the exact plane wave on the grid and g at
+  the exit point, the discrete Dynkin formula bounds the bias by
+  E[hJ] k^4 ((dx^2 cos^2 + dy^2 sin^2)/8 + h/2);
+* the whole iteration (fresh paths per iterate, Remark 2.1) against a
+  finite-difference solve on the BGK-enlarged square, and the sqrt(h) decay
+  of the error against the exact plane wave;
+* Remark 2.1: the exit-time law does not depend on n; common random numbers
+  reproduce exit steps exactly.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import closed_forms as cf
+from oracle import fd, fkmc
+from paper_2308_11469_amd import workloads as W
+
+
+def node_id(p, i, j):
+    return i + p.nx * j
+
+
+def test_harmonic_martingale_unbiased():
+    coeffs = (0.4 - 0.2j, 1.5 + 0.3j, -0.8 + 1.1j, 2.0 - 0.7j)   # c0 + c1 x + c2 y + c3 x y
+    p = W.Problem(nx=9, ny=9, k=0.0, h=2e-3, M=6000, seed=11,
+                  outer=W.BC("bilinear", coeffs=coeffs), g_unprojected=True)
+    ids = [node_id(p, 2, 2), node_id(p, 4, 4), node_id(p, 6, 3), node_id(p, 1, 7)]
+    est = fkmc.fk_nodes(p, None, 0, ids)
+    for c, nid in enumerate(ids):
+        x, y = (nid % 9) / 8, (nid // 9) / 8
+        g = coeffs[0] + coeffs[1] * x + coeffs[2] * y + coeffs[3] * x * y
+        d = est["mean"][c] - g
+        assert abs(d.real) <= 4 * est["se"][c].real + 1e-15
+        assert abs(d.imag) <= 4 * est["se"][c].imag + 1e-15
+
+
+def test_projected_harmonic_bias_is_order_sqrt_h():
+    # with the datum at the nearest boundary point the overshoot biases the
+    # mean by O(sqrt(h)); it shrinks by about 2 when h shrinks by 4
+    coeffs = (0j, 1.0 + 0j, 0j, 0j)     # g = x
+    errs = []
+    for h in (8e-3, 5e-4):
+        p = W.Problem(nx=9, ny=9, k=0.0, h=h, M=40000, seed=12, outer=W.BC("bilinear", coeffs=coeffs))
+        est = fkmc.fk_nodes(p, None, 0, [node_id(p, 1, 4)])
+        errs.append(est["mean"][0].real - 1 / 8)
+    # near x = 0 the clamp moves exits right: the estimate is biased upwards
+    assert errs[0] > 0 and errs[1] > 0
+    assert 2.5 < errs[0] / errs[1] < 5.5
+
+
+@pytest.mark.parametrize("ij", [(4, 4), (2, 2), (2, 6)])
+def test_exit_time_matches_bgk_shifted_torsion(ij):
+    h = 1e-3
+    p = W.Problem(nx=9, ny=9, k=0.0, h=h, M=20000, seed=7, src_kind="const", src_amp=-1.0)
+    est = fkmc.fk_nodes(p, None, 0, [node_id(p, *ij)])
+    d = cf.bgk_beta() * math.sqrt(2 * h)
+    x, y = ij[0] / 8, ij[1] / 8
+    shifted = float(cf.torsion_rect(1 + 2 * d, 1 + 2 * d, x + d, y + d))
+    continuous = float(cf.torsion_rect(1, 1, x, y))
+    m = est["mean"][0].real
+    # score is h J exactly
+    assert math.isclose(m, h * est["sumJ"][0] / p.M, rel_tol=1e-12)
+    assert abs(m - shifted) <= 4 * est["se"][0].real + 0.01 * shifted
+    assert abs(m - continuous) > 4 * est["se"][0].real   # the shift is real and resolved
+
+
+def test_exit_time_scaling_exact_for_lambda_two():
+    p = W.Problem(nx=9, ny=9, k=0.0, h=1e-3, M=2000, seed=3, src_kind="const", src_amp=-1.0)
+    q = p.replace(x1=2.0, y1=2.0, h=4e-3, jmax=fkmc.jmax_auto(p))
+    ids = [node_id(p, 3, 5), node_id(p, 4, 4)]
+    a = fkmc.fk_nodes(p, None, 0, ids)
+    b = fkmc.fk_nodes(q, None, 0, ids)
+    assert np.array_equal(a["sumJ"], b["sumJ"])
+    assert np.array_equal(4.0 * a["mean"], b["mean"])
+
+
+def test_integral_rule_bias_bound_with_exact_iterate():
+    k, th, h = 3.0, math.pi / 6, 2.5e-4
+    p = W.Problem(nx=33, ny=33, k=k, h=h, M=3000, seed=21,
+                  outer=W.BC("plane_wave", 1.0 + 0j, th), g_unprojected=True)
+    xs = np.arange(33) / 32
+    X, Y = np.meshgrid(xs, xs)
+    u = W.plane_wave(k, th, X, Y)
+    ids = [node_id(p, 16, 16), node_id(p, 8, 20), node_id(p, 25, 5)]
+    est = fkmc.fk_nodes(p, u, 3, ids)
+    dx = 1 / 32
+    for c, nid in enumerate(ids):
+        ehj = h * est["sumJ"][c] / p.M
+        bound = ehj * k ** 4 * ((dx ** 2 * math.cos(th) ** 2 + dx ** 2 * math.sin(th) ** 2) / 8 + h / 2)
+        d = est["mean"][c] - u.ravel()[nid]
+        assert abs(d.real) <= 4 * est["se"][c].real + bound
+        assert abs(d.imag) <= 4 * est["se"][c].imag + bound
+    # the same run with the integral dropped is far off: the pin sees the term
+    est0 = fkmc.fk_nodes(p, None, 3, ids)
+    assert np.max(np.abs(est0["mean"] - u.ravel()[ids])) > 0.2
+
+
+def bgk_fd_prediction(p, N=257):
+    """Continuous-monitoring model of the discretely monitored estimator: the
+    direct FD solve on the rectangle enlarged by delta = beta sqrt(2h) per side,
+    with the datum g taken at the clamped point (the estimator's projection),
+    sampled at the nodes of p by spline interpolation."""
+    import scipy.interpolate as si
+    d = cf.bgk_beta() * math.sqrt(2 * p.h)
+    q = W.Problem(x0=p.x0 - d, x1=p.x1 + d, y0=p.y0 - d, y1=p.y1 + d, nx=N, ny=N, k=p.k,
+                  outer=W.BC("table"))
+    L = 4 * 8192
+    px, py = W.perimeter_points(q.x0, q.x1, q.y0, q.y1, L)
+    q.outer.table = cf.plane_wave(p.k, p.outer.theta, np.clip(px, p.x0, p.x1), np.clip(py, p.y0, p.y1))
+    u = fd.direct(q)
+    xs = np.linspace(q.x0, q.x1, N)
+    fr = si.RectBivariateSpline(xs, xs, u.real)
+    fi = si.RectBivariateSpline(xs, xs, u.imag)
+    ids = fkmc.interior_ids(p)
+    x = p.x0 + (ids % p.nx) * (p.x1 - p.x0) / (p.nx - 1)
+    y = p.y0 + (ids // p.nx) * (p.y1 - p.y0) / (p.ny - 1)
+    return fr(y, x, grid=False) + 1j * fi(y, x, grid=False)
+
+
+def test_cavity_small_workload_against_bgk_model_and_exact():
+    p = W.cavity_small()
+    res = fkmc.solve(p)
+    assert len(res["history"]) == 10 and not res["diverged"]
+    assert all(h["capped"] == 0 for h in res["history"])
+    ids = fkmc.interior_ids(p)
+    u = res["u"].ravel()[ids]
+    se = np.abs(res["se"].ravel()[ids])
+    pred = bgk_fd_prediction(p)
+    rho = p.k ** 2 / cf.lambda1h_rect(9, 9, 1, 1)
+    se_eff = se / math.sqrt(1 - rho ** 2)
+    b_x = p.k ** 4 * 0.0737 * (2 / 64) / 8 / (1 - rho)
+    assert np.all(np.abs(u - pred) <= 4.5 * se_eff + b_x)
+    ex = W.exact_solution(p).ravel()[ids]
+    # the error against the exact wave is the predicted sqrt(h) bias plus noise
+    assert np.all(np.abs(u - ex) <= np.abs(pred - ex) + 4.5 * se_eff + b_x)
+
+
+@pytest.mark.slow
+def test_error_decays_like_sqrt_h():
+    errs = []
+    for h in (8e-3, 5e-4):
+        p = W.cavity_small().replace(h=h, M=8000, max_iters=8, crn=True)
+        res = fkmc.solve(p)
+        ids = fkmc.interior_ids(p)
+        ex = W.exact_solution(p).ravel()[ids]
+        errs.append(math.sqrt(np.mean(np.abs(res["u"].ravel()[ids] - ex) ** 2)))
+    assert 3.0 < errs[0] / errs[1] < 6.0      # sqrt(16) = 4
+
+
+def test_exit_time_law_independent_of_iterate_and_crn_reuses_paths():
+    p = W.cavity_small().replace(M=4000)
+    ids = [node_id(p, 4, 4), node_id(p, 2, 3)]
+    a = fkmc.fk_nodes(p, None, 0, ids)
+    b = fkmc.fk_nodes(p, None, 7, ids)
+    assert not np.array_equal(a["sumJ"], b["sumJ"])      # fresh paths per iterate
+    # mean exit step agrees within noise (sd of J is about its mean)
+    for c in range(2):
+        mJ = a["sumJ"][c] / p.M
+        assert abs(a["sumJ"][c] - b["sumJ"][c]) / p.M < 5 * mJ * math.sqrt(2 / p.M)
+    q = p.replace(crn=True)
+    a = fkmc.fk_nodes(q, None, 0, ids)
+    b = fkmc.fk_nodes(q, None, 7, ids)
+    assert np.array_equal(a["sumJ"], b["sumJ"])
+
+
+def test_crn_iteration_contracts_at_rate_rho():
+    # with common random numbers the iteration is u -> b + K u with a fixed
+    # operator K ~ k^2 (-Delta)^{-1}: successive changes shrink by about rho
+    p = W.cavity_small().replace(M=2000, crn=True, max_iters=12, k=3.0)
+    res = fkmc.solve(p)
+    du = [h["max_du"] for h in res["history"]]
+    ratios = [du[i + 1] / du[i] for i in range(4, 10)]
+    d = cf.bgk_beta() * math.sqrt(2 * p.h)
+    rho_eff = 9.0 / cf.lambda1_rect(1 + 2 * d, 1 + 2 * d)
+    assert all(0.6 * rho_eff < r < 1.4 * rho_eff for r in ratios)
+
+
+def test_divergence_flagged_above_kmax():
+    # k = 4.6 > pi sqrt(2): k^2 > lambda_1, the iteration must diverge
+    p = W.cavity_small().replace(k=4.6, M=400, crn=True, max_iters=60)
+    res = fkmc.solve(p)
+    assert res["diverged"] and len(res["history"]) < 60
+    h = res["history"]
+    assert h[-1]["max_du"] >= 1.25 * h[-6]["max_du"] and h[-1]["sup"] >= 1.25 * h[-6]["sup"]
+    # a convergent wavenumber under the same noise is not flagged
+    ok = fkmc.solve(p.replace(k=4.0, crn=False, max_iters=40))
+    assert not ok["diverged"] and len(ok["history"]) == 40
