@@ -1,0 +1,250 @@
+/*
+ * fk_helmholtz.h -- C ABI of the MI355X (gfx950) Monte Carlo Feynman-Kac
+ * solver for the fixed-point Helmholtz iteration.
+ *
+ * The method (Bernal, Chen, dos Reis, "An iterative method for Helmholtz
+ * boundary value problems arising in wave propagation"):
+ *   Delta u + k^2 u = f in Omega, u = g on dOmega (Sec. 1 eq. (1.1); Sec. 2.2
+ *   eq. (2.4) with damping p = 0 and no reflecting boundary part) is solved as
+ *   the sequence of Poisson problems  Delta u_{n+1} = f - k^2 u_n,
+ *   u_{n+1} = g on dOmega, u_0 = 0 (the shift alpha = k^2 of eq. (1.4); the
+ *   partial sums in the proof of Theorem 2.2).  Each Poisson step is solved at
+ *   every interior grid node y by the Feynman-Kac formula of Sec. 2.1 eq. (2.3)
+ *   with c = 0:  u_{n+1}(y) = E[g(Y_tau)] - E[int_0^tau (f - k^2 u_n)(Y_t) dt],
+ *   Y = y + sqrt(2) W, averaged over M paths that are independent for every n
+ *   (Remark 2.1).  The iteration converges when k^2 is below the first
+ *   Dirichlet eigenvalue (Sec. 2.4, Remark 2.4); it is stopped by the
+ *   sup-norm change (Sec. 3).
+ *
+ * Discretisation: Euler-Maruyama with step h; normals by Box-Muller from
+ * Philox4x32-10 words, key = seed, counter = (t/2, path m, node id, n) (n
+ * replaced by 0 when crn != 0); uniform U(r) = (2 (r >> 9) + 1) 2^-24; exit at
+ * the first step outside the open domain, boundary datum at the nearest
+ * boundary point; left-point rule for the integral; u_n read by bilinear
+ * interpolation of the grid.
+ *
+ * Conventions for every entry point:
+ *   - Grids are row-major nx * ny, node (i, j) at index i + nx * j, x fastest;
+ *     complex values are interleaved (re, im) doubles.
+ *   - Host pointers unless the argument says "device".  The library copies
+ *     what it needs from host inputs before returning.
+ *   - Every call returns an fk_status; nothing is thrown across the ABI.  On
+ *     failure fk_helmholtz_last_error() returns a message (thread-local,
+ *     valid until the next call on that thread).
+ *   - A solver handle is not thread-safe; distinct handles may be used from
+ *     distinct threads on distinct streams.
+ *   - hip_stream is a hipStream_t (NULL = the null stream).  All device work
+ *     of a handle is ordered on that stream.
+ */
+#ifndef FK_HELMHOLTZ_H
+#define FK_HELMHOLTZ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FK_OK = 0,
+    FK_EINVAL = 1,         /* invalid argument: geometry, sizes, parameters   */
+    FK_ENOMEM = 2,         /* arena too small / allocation failed             */
+    FK_EDEVICE = 3,        /* a HIP runtime call failed                       */
+    FK_EDIVERGED = 4,      /* divergence rule fired (result still readable)   */
+    FK_ENOTCONVERGED = 5,  /* max_iters reached above tol (result readable)   */
+    FK_EBUSY = 6           /* engine: no free slot                            */
+} fk_status;
+
+/* Omega: the open rectangle (x0,x1) x (y0,y1); for RECT_MINUS_DISC also
+ * minus the closed disc of radius r at (cx, cy), which must lie strictly
+ * inside the rectangle.  nx, ny >= 3 nodes per side, edges included. */
+typedef enum { FK_DOMAIN_RECT = 0, FK_DOMAIN_RECT_MINUS_DISC = 1 } fk_domain_kind;
+typedef struct {
+    int32_t kind;
+    int32_t nx, ny;
+    int32_t reserved;
+    double x0, x1, y0, y1;
+    double cx, cy, r;
+} fk_domain;
+
+/* Source f: ZERO; CONST f = amp; GAUSSIAN f = amp exp(-|x-c|^2 / (2 sigma^2)). */
+typedef enum { FK_SRC_ZERO = 0, FK_SRC_CONST = 1, FK_SRC_GAUSSIAN = 2 } fk_source_kind;
+typedef struct {
+    int32_t kind;
+    int32_t reserved;
+    double amp_re, amp_im, cx, cy, sigma;
+} fk_source;
+
+/* Dirichlet datum on one boundary part.
+ *   PLANE_WAVE  c = {amp_re, amp_im, theta}: g = amp exp(i k (x cos th + y sin th))
+ *   BILINEAR    c = {c0re, c0im, c1re, c1im, c2re, c2im, c3re, c3im}:
+ *               g = c0 + c1 x + c2 y + c3 x y
+ *   TABLE       (outer boundary only) table_len complex samples (re, im
+ *               interleaved; host pointer, copied at create) at equal
+ *               arclength steps round the rectangle, counter-clockwise from
+ *               (x0, y0), linearly interpolated, periodic.
+ * On hole nodes (inside the disc) the grid carries the inner datum's own
+ * formula (a smooth extension); TABLE is not allowed there. */
+typedef enum { FK_BC_ZERO = 0, FK_BC_PLANE_WAVE = 1, FK_BC_BILINEAR = 2, FK_BC_TABLE = 3 } fk_bc_kind;
+typedef struct {
+    int32_t kind;
+    int32_t reserved;
+    double c[8];
+    const double *table;
+    int64_t table_len;
+} fk_bc;
+
+typedef struct {
+    double k;              /* wavenumber (real, >= 0)                          */
+    double h;              /* Euler-Maruyama time step (> 0)                  */
+    int64_t M;             /* paths per node per iteration (>= 2)             */
+    uint64_t seed;         /* Philox key                                       */
+    int32_t precision;     /* 64: FP64 stepping; 32: FP32 stepping with
+                              compensated sums (node sums always FP64)        */
+    int32_t max_iters;     /* for fk_helmholtz_solve                          */
+    double tol;            /* stop when max |u_{n+1} - u_n| < tol (0: never)  */
+    int64_t max_steps;     /* step cap per path; 0 = ceil(40/(lambda1 h)),
+                              lambda1 of the bounding rectangle              */
+    int32_t crn;           /* 1: same paths every iteration (counter n -> 0)  */
+    int32_t g_unprojected; /* verification variant: g at X_J itself           */
+    int32_t paths_per_item;/* paths per wavefront work item; 0 = auto         */
+    int32_t reserved;
+} fk_params;
+
+/* Per-iteration report (after the iteration that produced u_n). */
+typedef struct {
+    int32_t n;             /* iterations completed (index of the iterate)     */
+    int32_t diverging;     /* divergence rule fired at this iteration          */
+    double max_du;         /* max over interior nodes |u_n - u_{n-1}|          */
+    double sup;            /* max over interior nodes |u_n|                    */
+    double max_se;         /* max node standard error (|SE_re + i SE_im|)      */
+    double noise_floor;    /* 4 * max_se                                       */
+    int64_t path_steps;    /* sum of exit-step indices over all paths          */
+    int64_t capped;        /* paths stopped by the step cap                    */
+    int64_t nonfinite;     /* nodes whose estimate is not finite               */
+    double step_ms;        /* device time of the path kernel (HIP events)      */
+} fk_iter_report;
+
+typedef struct fk_solver fk_solver;
+
+/* Device bytes a solver needs for this problem (the arena size to pass to
+ * fk_helmholtz_create).  g_outer may be NULL unless it is a TABLE. */
+fk_status fk_helmholtz_arena_bytes(const fk_domain *domain, const fk_bc *g_outer,
+                                   const fk_params *params, size_t *bytes);
+
+/* Validates the problem, classifies the grid nodes (interior, rectangle edge,
+ * hole), uploads the boundary data and sets u_0 = 0.  device_arena: device
+ * memory of at least fk_helmholtz_arena_bytes bytes, 256-byte aligned, owned
+ * by the caller and kept alive until destroy; NULL makes the library allocate
+ * (and free) its own.  FK_EINVAL: bad geometry, nx or ny < 3, h <= 0, M < 2,
+ * precision not 32/64, disc not strictly inside, TABLE as inner datum or
+ * table_len < 2.  FK_ENOMEM: arena too small. */
+fk_status fk_helmholtz_create(const fk_domain *domain, const fk_source *f, const fk_bc *g_outer,
+                              const fk_bc *g_inner, const fk_params *params, void *device_arena,
+                              size_t arena_bytes, void *hip_stream, fk_solver **out);
+
+/* Runs n_iters fixed-point iterations on the device (u_n -> u_{n+1}: one
+ * Feynman-Kac solve at every interior node, then the update of the iterate)
+ * and fills *last (may be NULL) with the report of the last one.  Returns
+ * FK_EDIVERGED as soon as the divergence rule fires: the change is not
+ * finite, or five iterations apart both max |u| and max |du| grew by 25%. */
+fk_status fk_helmholtz_iterate(fk_solver *s, int32_t n_iters, fk_iter_report *last);
+
+/* Iterates until max |du| < tol or max_iters iterations in total (Sec. 3's
+ * sup-norm control).  FK_ENOTCONVERGED if tol > 0 was not reached. */
+fk_status fk_helmholtz_solve(fk_solver *s, fk_iter_report *final_report);
+
+/* Copies the current iterate u_n (nx*ny complex) and, if se_reim is not NULL,
+ * the per-node standard errors (SE_re, SE_im; 0 on non-interior nodes) of the
+ * last iteration.  on_device != 0: the pointers are device pointers. */
+fk_status fk_helmholtz_get(fk_solver *s, double *u_reim, double *se_reim, int32_t on_device);
+
+/* Per-node sum of exit-step indices and capped-path counts of the last
+ * iteration (nx*ny each, host pointers; 0 on non-interior nodes). */
+fk_status fk_helmholtz_node_stats(fk_solver *s, int64_t *sum_j, int64_t *capped);
+
+/* Replaces the iterate by u_reim (nx*ny complex, host or device) on interior
+ * nodes and sets the iteration index to n (the next iteration uses counter
+ * word n).  Boundary and hole nodes keep their data.  Used to resume from a
+ * checkpoint and to feed the same u_n to another implementation. */
+fk_status fk_helmholtz_set_iterate(fk_solver *s, const double *u_reim, int32_t n, int32_t on_device);
+
+/* Accumulated device time of the path kernel since creation or the last
+ * reset (HIP events recorded on the solver's stream around each launch). */
+fk_status fk_helmholtz_timing(fk_solver *s, double *step_ms_total, int64_t *launches, int32_t reset);
+
+fk_status fk_helmholtz_destroy(fk_solver *s);
+
+const char *fk_helmholtz_last_error(void);
+
+/* ---------------------------------------------------------------- debug -- */
+
+/* Philox4x32-10 words computed on the device: for each of the n counters
+ * (4 words each) with key (seed mod 2^32, seed div 2^32), 4 output words. */
+fk_status fk_debug_philox(uint64_t seed, const uint32_t *ctrs, int64_t n, uint32_t *out);
+
+/* Box-Muller normals computed on the device in the given precision (32|64)
+ * from n word pairs (ra, rb): z = sqrt(-2 ln U(ra)) (cos 2pi U(rb), sin 2pi U(rb)). */
+fk_status fk_debug_normals(int32_t precision, const uint32_t *words, int64_t n, double *z);
+
+/* Runs the listed paths (node id, path index m) of the next iteration of s
+ * with the solver's kernels and current iterate: exit-step index J, score
+ * (re, im) and exit point X_J (x, y) per path.  Host pointers, count each. */
+fk_status fk_helmholtz_debug_paths(fk_solver *s, const int32_t *node_ids, const int64_t *ms,
+                                   int64_t count, int64_t *J, double *score_reim, double *xj);
+
+/* --------------------------------------------------------------- engine -- */
+/*
+ * Batched, continuous-batching engine: many instances (each its own domain,
+ * k, M, seed, grid) advanced together, one fixed-point iteration per tick,
+ * by one persistent work-stealing kernel launch replayed from a HIP graph.
+ * Instances are admitted into free slots between ticks and retire on
+ * convergence; the result of an instance does not depend on what else is in
+ * the batch (fixed per-(node, chunk) result slots, fixed reduction order).
+ */
+typedef struct fk_engine fk_engine;
+
+typedef struct {
+    int32_t max_instances;     /* slots                                           */
+    int32_t precision;         /* 32 | 64 for every instance                      */
+    int64_t max_grid_nodes;    /* sum of nx*ny over resident instances            */
+    int64_t max_items;         /* sum of work items over resident instances       */
+    int64_t max_table;         /* sum of TABLE lengths over resident instances    */
+    int32_t waves_per_cu;      /* persistent grid = CUs * waves_per_cu; 0 = auto  */
+    int32_t max_instance_nodes;/* largest nx*ny of one instance; 0 = 257*257      */
+} fk_engine_config;
+
+/* Creates an engine with its own device memory (sized by cfg) on hip_stream. */
+fk_status fk_engine_create(const fk_engine_config *cfg, void *hip_stream, fk_engine **out);
+
+/* Admits an instance into a free slot (*slot).  FK_EBUSY: no free slot;
+ * FK_ENOMEM: the resident instances leave too little room; FK_EINVAL as in
+ * fk_helmholtz_create (precision must match the engine's). */
+fk_status fk_engine_add(fk_engine *e, const fk_domain *domain, const fk_source *f,
+                        const fk_bc *g_outer, const fk_bc *g_inner, const fk_params *params,
+                        int32_t *slot);
+
+/* One iteration of every active instance (one persistent launch).  reports:
+ * max_instances entries, filled for active slots; active_mask: max_instances
+ * bytes, 1 where the slot was active in this tick.  Instances whose report
+ * says converged (max_du < tol), diverging or max_iters stay resident until
+ * fk_engine_remove. */
+fk_status fk_engine_tick(fk_engine *e, fk_iter_report *reports, uint8_t *active_mask);
+
+/* Copies the iterate and SE of a slot (host pointers, nx*ny complex each). */
+fk_status fk_engine_get(fk_engine *e, int32_t slot, double *u_reim, double *se_reim);
+
+/* Frees a slot and its memory for new instances. */
+fk_status fk_engine_remove(fk_engine *e, int32_t slot);
+
+/* Device time of the persistent kernel (HIP events around each launch). */
+fk_status fk_engine_timing(fk_engine *e, double *kernel_ms_total, int64_t *launches, int32_t reset);
+
+fk_status fk_engine_destroy(fk_engine *e);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FK_HELMHOLTZ_H */

@@ -1,0 +1,276 @@
+// fk_device.hpp -- device-side pieces of the Feynman-Kac Helmholtz path for
+// gfx950: counter-based normals, geometry, interpolation of the iterate and
+// the per-wavefront work item (a chunk of paths from one grid node).
+//
+// Method: each Poisson step  Delta u_{n+1} = f - k^2 u_n  (Sec. 1 eq. (1.4)
+// with alpha = k^2) is solved at a node y by the Feynman-Kac formula of
+// Sec. 2.1 eq. (2.3) with c = 0 and a purely absorbing boundary:
+//   u_{n+1}(y) = E[ g(Y_tau) - int_0^tau (f - k^2 u_n)(Y_t) dt ],
+//   Y_t = y + sqrt(2) W_t,
+// with a new Brownian motion for every n (Remark 2.1).
+//
+// Execution model: one wavefront (64 lanes) owns a work item = (node, chunk
+// of consecutive path indices m).  Each lane runs one path at a time; when a
+// lane's path exits, the lane takes the next unused path index of the chunk
+// (ballot + mbcnt), so lanes never wait for the longest path of a group.
+// Every loop trip draws one Philox block (4 words) and takes two Euler steps.
+// Per-lane sums are FP64; the wave reduces them in a fixed butterfly order
+// into the item's own slot, so results do not depend on scheduling.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fkd {
+
+constexpr int kWave = 64;
+
+enum : int32_t { BC_ZERO = 0, BC_PLANE_WAVE = 1, BC_BILINEAR = 2, BC_TABLE = 3 };
+enum : int32_t { SRC_ZERO = 0, SRC_CONST = 1, SRC_GAUSSIAN = 2 };
+
+struct BCDev {
+    int32_t kind;
+    int32_t pad;
+    double c[8];            // PLANE_WAVE: amp_re, amp_im, cos th, sin th; BILINEAR: c0..c3
+    const double2 *table;   // TABLE samples (device)
+    int64_t len;
+};
+
+// Result slot of one work item: sums over the item's paths.
+struct Slot {
+    double s_re, s_im, q_re, q_im;   // sum s, sum s^2 (per component)
+    int64_t sum_j;                   // sum of exit-step indices
+    int64_t capped;                  // paths stopped by the step cap
+};
+
+// Per-instance device state written by the update kernel.
+struct DevState {
+    int32_t iter;          // index n of the iterate held in the grid
+    int32_t use_u;         // 0 while u_n == 0 everywhere (n == 0)
+    uint64_t max_du;       // bit pattern of a non-negative double (atomicMax)
+    uint64_t sup;
+    uint64_t max_se;
+    unsigned long long path_steps;
+    unsigned long long capped;
+    unsigned long long nonfinite;
+    int32_t pad[2];
+};
+
+// Everything a work item needs about its instance (device memory, read
+// through the scalar cache).
+struct Inst {
+    double x0, x1, y0, y1, dx, dy, idx, idy;
+    double cx, cy, r, r2;
+    int32_t nx, ny, disc, n_interior;
+    int32_t src_kind, g_unproj;
+    double src_re, src_im, src_cx, src_cy, src_c;   // src_c = 1 / (2 sigma^2)
+    BCDev outer, inner;
+    double k, k2, h, sigma;                          // sigma = sqrt(2 h)
+    int64_t M, jmax;
+    uint32_t key0, key1;
+    int32_t crn, ppi;                                // ppi: paths per item
+    int32_t items_per_node, pad1;
+    int64_t n_items;
+    const int32_t *nodes;                            // interior node ids
+    double2 *u64;                                    // iterate, FP64 master
+    float2 *u32;                                     // iterate, FP32 copy
+    Slot *slots;                                     // n_items
+    double2 *se;                                     // per grid node
+    int64_t *node_sum_j, *node_capped;               // per grid node
+    DevState *state;
+};
+
+// ------------------------------------------------------------ Philox4x32-10
+// Counter-based generator of Salmon, Moraes, Dror and Shaw (SC'11): ten
+// rounds of two 32x32->64 products whose high halves are xor-ed into the
+// other words with the round key; the key is bumped by two Weyl constants.
+__device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                               uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
+// -------------------------------------------------------------- normals
+// U(r) = (2 (r >> 9) + 1) 2^-24 in (0, 1), exact in binary32 and binary64.
+// Box-Muller: z = sqrt(-2 ln U(ra)) (cos 2 pi U(rb), sin 2 pi U(rb)).
+
+__device__ __forceinline__ void normals(uint32_t ra, uint32_t rb, double &zx, double &zy)
+{
+    const double ua = (double)((ra >> 8) | 1u) * 0x1p-24;
+    const double ub = (double)((rb >> 8) | 1u) * 0x1p-24;
+    const double rho = sqrt(-2.0 * log(ua));
+    double s, c;
+    sincospi(2.0 * ub, &s, &c);
+    zx = rho * c;
+    zy = rho * s;
+}
+
+// FP32: 1 + (r >> 9) 2^-23 built from the bits, minus (1 - 2^-24), is the
+// same uniform exactly.  Hardware log2, sqrt, sin and cos; the sin/cos
+// instructions take their argument in revolutions, so 2 pi U needs no multiply.
+__device__ __forceinline__ void normals(uint32_t ra, uint32_t rb, float &zx, float &zy)
+{
+    const float ua = __uint_as_float(0x3f800000u | (ra >> 9)) - 0x1.fffffep-1f;
+    const float ub = __uint_as_float(0x3f800000u | (rb >> 9)) - 0x1.fffffep-1f;
+    const float rho = __builtin_amdgcn_sqrtf(-1.38629436111989061f * __builtin_amdgcn_logf(ua));
+    zx = rho * __builtin_amdgcn_cosf(ub);
+    zy = rho * __builtin_amdgcn_sinf(ub);
+}
+
+// ------------------------------------------------------------- geometry
+
+// Exit test on an FP64 point: outside the open rectangle, or in the closed disc.
+__device__ __forceinline__ bool outside64(const Inst &D, double x, double y)
+{
+    if (x <= D.x0 || x >= D.x1 || y <= D.y0 || y >= D.y1) return true;
+    if (D.disc) {
+        const double ex = x - D.cx, ey = y - D.cy;
+        return ex * ex + ey * ey <= D.r2;
+    }
+    return false;
+}
+
+// Exit test on an FP32 point.  The rectangle test compares the point
+// (converted exactly to FP64) with the FP64 edges.  The disc test runs in FP32
+// and falls back to FP64 only within a thin band around the circle.
+__device__ __forceinline__ bool outside32(const Inst &D, float x, float y, float cxf, float cyf,
+                                          float r2f, float band)
+{
+    const double xd = (double)x, yd = (double)y;
+    if (xd <= D.x0 || xd >= D.x1 || yd <= D.y0 || yd >= D.y1) return true;
+    if (D.disc) {
+        const float ex = x - cxf, ey = y - cyf;
+        const float d = ex * ex + ey * ey - r2f;
+        if (d > band) return false;
+        if (d < -band) return true;
+        const double exd = xd - D.cx, eyd = yd - D.cy;
+        return exd * exd + eyd * eyd <= D.r2;
+    }
+    return false;
+}
+
+// Nearest boundary point of X (FP64).  Outside the rectangle: clamp (outer
+// part).  In the closed disc: radial projection onto the circle.  Inside the
+// domain (a path stopped by the cap): the nearest of the four edges and the
+// circle.  Returns 1 for the outer boundary, 2 for the circle.
+__device__ __forceinline__ int project(const Inst &D, double x, double y, double &px, double &py)
+{
+    if (x <= D.x0 || x >= D.x1 || y <= D.y0 || y >= D.y1) {
+        px = fmin(fmax(x, D.x0), D.x1);
+        py = fmin(fmax(y, D.y0), D.y1);
+        return 1;
+    }
+    const double ex = x - D.cx, ey = y - D.cy;
+    const double d = sqrt(ex * ex + ey * ey);
+    if (!(D.disc && d <= D.r)) {
+        double dd[4] = {x - D.x0, D.x1 - x, y - D.y0, D.y1 - y};
+        int e = 0;
+        for (int c = 1; c < 4; ++c)
+            if (dd[c] < dd[e]) e = c;
+        if (!D.disc || dd[e] <= d - D.r) {
+            px = e == 0 ? D.x0 : (e == 1 ? D.x1 : x);
+            py = e == 2 ? D.y0 : (e == 3 ? D.y1 : y);
+            return 1;
+        }
+    }
+    if (d > 0.0) {
+        px = D.cx + D.r * ex / d;
+        py = D.cy + D.r * ey / d;
+    } else {
+        px = D.cx + D.r;
+        py = D.cy;
+    }
+    return 2;
+}
+
+// Boundary datum at a point (FP64, once per path).
+__device__ __forceinline__ double2 bc_eval(const Inst &D, const BCDev &B, double x, double y)
+{
+    switch (B.kind) {
+    case BC_PLANE_WAVE: {
+        const double ph = D.k * (x * B.c[2] + y * B.c[3]);
+        double s, c;
+        sincos(ph, &s, &c);
+        return make_double2(B.c[0] * c - B.c[1] * s, B.c[0] * s + B.c[1] * c);
+    }
+    case BC_BILINEAR:
+        return make_double2(B.c[0] + B.c[2] * x + B.c[4] * y + B.c[6] * x * y,
+                            B.c[1] + B.c[3] * x + B.c[5] * y + B.c[7] * x * y);
+    case BC_TABLE: {
+        const double a = D.x1 - D.x0, b = D.y1 - D.y0;
+        double s;
+        if (y == D.y0) s = x - D.x0;
+        else if (x == D.x1) s = a + (y - D.y0);
+        else if (y == D.y1) s = a + b + (D.x1 - x);
+        else s = 2.0 * a + b + (D.y1 - y);
+        const double u = s / (2.0 * (a + b)) * (double)B.len;
+        const double fl = floor(u);
+        const double w = u - fl;
+        int64_t i0 = (int64_t)fl % B.len;
+        if (i0 < 0) i0 += B.len;
+        const int64_t i1 = i0 + 1 == B.len ? 0 : i0 + 1;
+        const double2 t0 = B.table[i0], t1 = B.table[i1];
+        return make_double2((1.0 - w) * t0.x + w * t1.x, (1.0 - w) * t0.y + w * t1.y);
+    }
+    default:
+        return make_double2(0.0, 0.0);
+    }
+}
+
+// Score datum g at the end of a path whose last point is (x, y).
+__device__ __forceinline__ double2 exit_datum(const Inst &D, double x, double y, bool exited)
+{
+    if (D.g_unproj) {
+        const bool outer = x <= D.x0 || x >= D.x1 || y <= D.y0 || y >= D.y1;
+        return bc_eval(D, (outer || !exited) ? D.outer : D.inner, x, y);
+    }
+    double px, py;
+    const int which = project(D, x, y, px, py);
+    return bc_eval(D, which == 2 ? D.inner : D.outer, px, py);
+}
+
+// ------------------------------------------ right-hand side f - k^2 I_h[u_n]
+
+template <class R> struct Grid;
+template <> struct Grid<double> {
+    using C2 = double2;
+    static __device__ __forceinline__ const double2 *ptr(const Inst &D) { return D.u64; }
+};
+template <> struct Grid<float> {
+    using C2 = float2;
+    static __device__ __forceinline__ const float2 *ptr(const Inst &D) { return D.u32; }
+};
+
+// Bilinear interpolation on the cell containing (x, y): p = floor((x-x0)/dx)
+// clamped to [0, nx-2], fractions a, b; lerp in x then in y.
+template <class R, class C2>
+__device__ __forceinline__ void interp(const C2 *__restrict__ u, int nx, int ny, R x0, R y0, R idx, R idy,
+                                       R x, R y, R &vr, R &vi)
+{
+    const R fx = (x - x0) * idx, fy = (y - y0) * idy;
+    int p = (int)fx, q = (int)fy;     // fx, fy >= 0 inside the domain: truncation is floor
+    p = p > nx - 2 ? nx - 2 : (p < 0 ? 0 : p);
+    q = q > ny - 2 ? ny - 2 : (q < 0 ? 0 : q);
+    const R a = fx - (R)p, b = fy - (R)q;
+    const int i00 = p + nx * q;
+    const C2 u00 = u[i00], u10 = u[i00 + 1], u01 = u[i00 + nx], u11 = u[i00 + nx + 1];
+    const R lr0 = u00.x + a * (u10.x - u00.x), li0 = u00.y + a * (u10.y - u00.y);
+    const R lr1 = u01.x + a * (u11.x - u01.x), li1 = u01.y + a * (u11.y - u01.y);
+    vr = lr0 + b * (lr1 - lr0);
+    vi = li0 + b * (li1 - li0);
+}
+
+}  // namespace fkd

@@ -1,0 +1,39 @@
+// fk_internal.hpp -- declarations shared by the kernels and the host runtime
+// of the HIP library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fkd {
+struct Inst;
+struct DevState;
+struct Slot;
+
+// Segment table of a batched launch (device): segment s covers the items of
+// instance seg_inst[s]; seg_end is the inclusive prefix sum of item counts.
+constexpr int kMaxSlots = 1024;
+struct EngineQueue {
+    int32_t n_seg;
+    int32_t pad;
+    int64_t seg_end[kMaxSlots];
+    int32_t seg_inst[kMaxSlots];
+};
+}  // namespace fkd
+
+namespace fkk {
+hipError_t launch_paths(int precision, const fkd::Inst *d_inst, int64_t item_begin, int64_t item_end,
+                        hipStream_t s);
+hipError_t launch_persistent(int precision, const fkd::Inst *d_insts, const fkd::EngineQueue *Q,
+                             unsigned long long *head, int n_blocks, hipStream_t s);
+hipError_t launch_reset(const fkd::Inst *d_insts, const int32_t *which, int32_t n, const int32_t *n_dev,
+                        unsigned long long *head, hipStream_t s);
+hipError_t launch_update(const fkd::Inst *d_insts, const int32_t *which, int32_t n_inst, const int32_t *n_dev,
+                         int32_t max_interior, hipStream_t s);
+hipError_t launch_advance(const fkd::Inst *d_insts, const int32_t *which, int32_t n, const int32_t *n_dev,
+                          hipStream_t s);
+hipError_t launch_debug_philox(uint32_t k0, uint32_t k1, const uint4 *ctr, int64_t n, uint4 *out, hipStream_t s);
+hipError_t launch_debug_normals(int precision, const uint2 *words, int64_t n, double2 *z, hipStream_t s);
+hipError_t launch_debug_paths(int precision, const fkd::Inst *d_inst, const int32_t *nodes, const int64_t *ms,
+                              int64_t n, long long *J, double2 *score, double2 *xj, hipStream_t s);
+}  // namespace fkk

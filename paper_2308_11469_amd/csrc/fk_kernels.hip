@@ -1,0 +1,515 @@
+// fk_kernels.hip -- HIP kernels of the Feynman-Kac Helmholtz path (gfx950).
+//
+//   fk_paths_kernel<R>        one wavefront per work item (node, chunk of paths)
+//   fk_persistent_kernel<R>   batched: waves pull (instance, node, chunk)
+//                             items from a device queue until it is empty
+//   fk_update_kernel          node mean / variance from the item slots, the
+//                             fixed-point update of the iterate and the
+//                             per-iteration status (max |du|, sup, max SE,
+//                             path steps, capped and non-finite counts)
+//   debug kernels             Philox words, normals, single paths
+//
+// No MFMA: nothing on this path is a dense contraction.  The stepping loop is
+// bound by VALU issue (Philox integer products, transcendentals, the bilinear
+// gather of u_n and the FP arithmetic of the step).
+#include "fk_device.hpp"
+#include "fk_internal.hpp"
+
+namespace fkd {
+
+// Per-precision constants of an instance, hoisted out of the stepping loop.
+template <class R> struct Consts {
+    R x0, y0, idx, idy, sigma, k2, h;
+    R cxf, cyf, r2f, band;
+    R src_re, src_im, src_cx, src_cy, src_c;
+    int nx, ny;
+    __device__ explicit Consts(const Inst &D)
+        : x0((R)D.x0), y0((R)D.y0), idx((R)D.idx), idy((R)D.idy), sigma((R)D.sigma), k2((R)D.k2),
+          h((R)D.h), cxf((R)D.cx), cyf((R)D.cy), r2f((R)D.r2), band((R)(1e-5 * (D.r + 1.0))),
+          src_re((R)D.src_re), src_im((R)D.src_im), src_cx((R)D.src_cx), src_cy((R)D.src_cy),
+          src_c((R)D.src_c), nx(D.nx), ny(D.ny) {}
+};
+
+template <class R> struct PathState {
+    R x, y;       // position
+    R ar, ai;     // sum of the integrand over the left points
+    R cr, ci;     // Kahan compensation of ar, ai (FP32 only)
+    int t;        // steps taken
+};
+
+__device__ __forceinline__ double exp_src(double a) { return exp(a); }
+__device__ __forceinline__ float exp_src(float a) { return __builtin_amdgcn_exp2f(a * 1.44269504088896341f); }
+
+__device__ __forceinline__ bool is_out(const Inst &D, const Consts<double> &, double x, double y)
+{
+    return outside64(D, x, y);
+}
+__device__ __forceinline__ bool is_out(const Inst &D, const Consts<float> &K, float x, float y)
+{
+    return outside32(D, x, y, K.cxf, K.cyf, K.r2f, K.band);
+}
+
+// integrand f - k^2 I_h[u_n] at the current point, added to the path sum
+template <class R>
+__device__ __forceinline__ void accumulate(const Inst &D, const Consts<R> &K, PathState<R> &P, bool use_u)
+{
+    R fr = (R)0, fi = (R)0;
+    if (D.src_kind == SRC_CONST) {
+        fr = K.src_re;
+        fi = K.src_im;
+    } else if (D.src_kind == SRC_GAUSSIAN) {
+        const R ex = P.x - K.src_cx, ey = P.y - K.src_cy;
+        const R e = exp_src(-K.src_c * (ex * ex + ey * ey));
+        fr = K.src_re * e;
+        fi = K.src_im * e;
+    }
+    if (use_u) {
+        R vr, vi;
+        interp<R>(Grid<R>::ptr(D), K.nx, K.ny, K.x0, K.y0, K.idx, K.idy, P.x, P.y, vr, vi);
+        fr -= K.k2 * vr;
+        fi -= K.k2 * vi;
+    }
+    if constexpr (sizeof(R) == 8) {
+        P.ar += fr;
+        P.ai += fi;
+    } else {
+        // Kahan summation of the FP32 path integral
+        const R yr = fr - P.cr, yi = fi - P.ci;
+        const R tr = P.ar + yr, ti = P.ai + yi;
+        P.cr = (tr - P.ar) - yr;
+        P.ci = (ti - P.ai) - yi;
+        P.ar = tr;
+        P.ai = ti;
+    }
+}
+
+// One Philox block = normals for two increments; takes up to two Euler steps.
+// Returns true when the path is finished (exited or capped).
+template <class R>
+__device__ __forceinline__ bool advance(const Inst &D, const Consts<R> &K, PathState<R> &P, uint32_t m,
+                                        uint32_t node, uint32_t ctr3, bool use_u, bool &exited)
+{
+    const uint4 w = philox4x32_10((uint32_t)(P.t >> 1), m, node, ctr3, D.key0, D.key1);
+    R z0x, z0y, z1x, z1y;
+    normals(w.x, w.y, z0x, z0y);
+    normals(w.z, w.w, z1x, z1y);
+    accumulate<R>(D, K, P, use_u);
+    P.x += K.sigma * z0x;
+    P.y += K.sigma * z0y;
+    P.t += 1;
+    exited = is_out(D, K, P.x, P.y);
+    if (!exited && P.t < D.jmax) {
+        accumulate<R>(D, K, P, use_u);
+        P.x += K.sigma * z1x;
+        P.y += K.sigma * z1y;
+        P.t += 1;
+        exited = is_out(D, K, P.x, P.y);
+    }
+    return exited || P.t >= D.jmax;
+}
+
+// Score of a finished path: g at the nearest boundary point minus h times
+// the left-point sum (Sec. 2.1 eq. (2.3) with c = 0: the f-term enters with
+// a minus sign).
+template <class R>
+__device__ __forceinline__ double2 score(const Inst &D, const PathState<R> &P, bool exited)
+{
+    const double2 g = exit_datum(D, (double)P.x, (double)P.y, exited);
+    double ar, ai;
+    if constexpr (sizeof(R) == 8) {
+        ar = P.ar;
+        ai = P.ai;
+    } else {
+        ar = (double)P.ar - (double)P.cr;
+        ai = (double)P.ai - (double)P.ci;
+    }
+    return make_double2(g.x - D.h * ar, g.y - D.h * ai);
+}
+
+template <class R>
+__device__ __forceinline__ void start(PathState<R> &P, R sx, R sy)
+{
+    P.x = sx;
+    P.y = sy;
+    P.ar = P.ai = P.cr = P.ci = (R)0;
+    P.t = 0;
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+__device__ __forceinline__ long long wave_sum(long long v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// One work item: paths [chunk*ppi, min(M, (chunk+1)*ppi)) of interior node
+// node_idx, executed by the calling wavefront; sums land in *slot.
+template <class R>
+__device__ __forceinline__ void run_item(const Inst &D, int32_t node_idx, int32_t chunk, Slot *slot)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const Consts<R> K(D);
+    const int32_t iter = D.state->iter;
+    const bool use_u = D.state->use_u != 0;
+    const uint32_t ctr3 = D.crn ? 0u : (uint32_t)iter;
+    const int32_t node = D.nodes[node_idx];
+    const int32_t gi = node % D.nx, gj = node / D.nx;
+    const R sx = (R)(D.x0 + (double)gi * D.dx);
+    const R sy = (R)(D.y0 + (double)gj * D.dy);
+    const int64_t m_begin = (int64_t)chunk * D.ppi;
+    const int64_t m_end = m_begin + D.ppi < D.M ? m_begin + D.ppi : D.M;
+    int64_t next = m_begin + kWave;
+    int64_t m = m_begin + lane;
+    bool active = m < m_end;
+
+    PathState<R> P;
+    start(P, sx, sy);
+    double s_re = 0.0, s_im = 0.0, q_re = 0.0, q_im = 0.0;
+    long long sj = 0, nc = 0;
+
+    for (;;) {
+        if (__ballot(active) == 0ull) break;
+        bool fin = false;
+        if (active) {
+            bool exited;
+            fin = advance<R>(D, K, P, (uint32_t)m, (uint32_t)node, ctr3, use_u, exited);
+            if (fin) {
+                const double2 s = score<R>(D, P, exited);
+                s_re += s.x;
+                s_im += s.y;
+                q_re += s.x * s.x;
+                q_im += s.y * s.y;
+                sj += P.t;
+                nc += exited ? 0 : 1;
+            }
+        }
+        // lanes whose path ended take the next unused path indices in lane order
+        const unsigned long long done = __ballot(fin);
+        if (done) {
+            if (fin) {
+                const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(done >> 32),
+                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)done, 0u));
+                m = next + rank;
+                if (m < m_end) start(P, sx, sy);
+                else active = false;
+            }
+            next += __popcll(done);
+        }
+    }
+    s_re = wave_sum(s_re);
+    s_im = wave_sum(s_im);
+    q_re = wave_sum(q_re);
+    q_im = wave_sum(q_im);
+    sj = wave_sum(sj);
+    nc = wave_sum(nc);
+    if (lane == 0) {
+        slot->s_re = s_re;
+        slot->s_im = s_im;
+        slot->q_re = q_re;
+        slot->q_im = q_im;
+        slot->sum_j = sj;
+        slot->capped = nc;
+    }
+}
+
+// ----------------------------------------------------------------- kernels
+
+template <class R>
+__global__ void __launch_bounds__(256) fk_paths_kernel(const Inst *__restrict__ inst, int64_t item_begin,
+                                                       int64_t item_end)
+{
+    const Inst &D = *inst;
+    const int64_t item = item_begin + (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    if (item >= item_end) return;
+    const int32_t node_idx = (int32_t)(item / D.items_per_node);
+    const int32_t chunk = (int32_t)(item % D.items_per_node);
+    run_item<R>(D, node_idx, chunk, D.slots + item);
+}
+
+// Batched work queue.  The items of the active instances are numbered
+// consecutively, instance after instance in the order of seg_inst (longest
+// expected paths first); seg_end[s] is the exclusive prefix end of segment s.
+// Each wave takes the next item number from an atomic counter until all are
+// taken, finds its segment by binary search (wave-uniform) and runs it.
+template <class R>
+__global__ void __launch_bounds__(256) fk_persistent_kernel(const Inst *__restrict__ insts,
+                                                            const EngineQueue *__restrict__ Q,
+                                                            unsigned long long *head)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int32_t nseg = Q->n_seg;
+    const int64_t total = nseg > 0 ? Q->seg_end[nseg - 1] : 0;
+    for (;;) {
+        unsigned long long g = 0;
+        if (lane == 0) g = atomicAdd(head, 1ull);
+        g = __shfl(g, 0, kWave);
+        if ((int64_t)g >= total) break;
+        int32_t lo = 0, hi = nseg - 1;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (Q->seg_end[mid] > (int64_t)g) hi = mid;
+            else lo = mid + 1;
+        }
+        const Inst &D = insts[Q->seg_inst[lo]];
+        const int64_t item = (int64_t)g - (lo > 0 ? Q->seg_end[lo - 1] : 0);
+        run_item<R>(D, (int32_t)(item / D.items_per_node), (int32_t)(item % D.items_per_node), D.slots + item);
+    }
+}
+
+// Instance lists: `which` (device, optional) names the instances by index
+// into `insts`; their count is *n_dev when given (graph replays read it from
+// the device), else n.
+__device__ __forceinline__ int32_t list_count(int32_t n, const int32_t *n_dev) { return n_dev ? *n_dev : n; }
+
+__global__ void fk_reset_kernel(const Inst *__restrict__ insts, const int32_t *__restrict__ which, int32_t n,
+                                const int32_t *__restrict__ n_dev, unsigned long long *head)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (head && i == 0) *head = 0ull;
+    if (i >= list_count(n, n_dev)) return;
+    DevState *st = insts[which ? which[i] : i].state;
+    st->max_du = 0ull;
+    st->sup = 0ull;
+    st->max_se = 0ull;
+    st->path_steps = 0ull;
+    st->capped = 0ull;
+    st->nonfinite = 0ull;
+}
+
+__device__ __forceinline__ unsigned long long bits_of(double v)
+{
+    return (unsigned long long)__double_as_longlong(v);
+}
+
+// One thread per interior node of instance which[blockIdx.y] (or instance
+// blockIdx.y when which is null): fixed-order sum over the node's item slots,
+// mean and unbiased variance, the new iterate (FP64 master and FP32 copy),
+// and the instance status by atomics that do not depend on order (max of
+// non-negative doubles via their bit patterns, integer sums).
+__global__ void __launch_bounds__(256) fk_update_kernel(const Inst *__restrict__ insts,
+                                                        const int32_t *__restrict__ which,
+                                                        const int32_t *__restrict__ n_dev)
+{
+    if (n_dev && (int32_t)blockIdx.y >= *n_dev) return;
+    const Inst &D = insts[which ? which[blockIdx.y] : blockIdx.y];
+    if ((int64_t)blockIdx.x * blockDim.x >= D.n_interior) return;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    double du = 0.0, sup = 0.0, sem = 0.0;
+    long long sj = 0, nc = 0, nf = 0;
+    const bool use_u = D.state->use_u != 0;
+    if (idx < D.n_interior) {
+        const int32_t node = D.nodes[idx];
+        const Slot *sl = D.slots + (int64_t)idx * D.items_per_node;
+        double s_re = 0.0, s_im = 0.0, q_re = 0.0, q_im = 0.0;
+        for (int c = 0; c < D.items_per_node; ++c) {
+            s_re += sl[c].s_re;
+            s_im += sl[c].s_im;
+            q_re += sl[c].q_re;
+            q_im += sl[c].q_im;
+            sj += sl[c].sum_j;
+            nc += sl[c].capped;
+        }
+        const double Mf = (double)D.M;
+        const double mr = s_re / Mf, mi = s_im / Mf;
+        const double vr = fmax((q_re - s_re * mr) / (Mf - 1.0), 0.0);
+        const double vi = fmax((q_im - s_im * mi) / (Mf - 1.0), 0.0);
+        const double ser = sqrt(vr / Mf), sei = sqrt(vi / Mf);
+        const double2 old = use_u ? D.u64[node] : make_double2(0.0, 0.0);
+        D.u64[node] = make_double2(mr, mi);
+        D.u32[node] = make_float2((float)mr, (float)mi);
+        D.se[node] = make_double2(ser, sei);
+        D.node_sum_j[node] = sj;
+        D.node_capped[node] = nc;
+        du = hypot(mr - old.x, mi - old.y);
+        sup = hypot(mr, mi);
+        sem = hypot(ser, sei);
+        if (!(isfinite(mr) && isfinite(mi))) {
+            nf = 1;
+            du = HUGE_VAL;
+            sup = HUGE_VAL;
+        }
+    }
+    // block reduction: waves by shuffles, then across the block's waves
+    __shared__ double r_du[4], r_sup[4], r_se[4];
+    __shared__ long long r_sj[4], r_nc[4], r_nf[4];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        du = fmax(du, __shfl_xor(du, o, kWave));
+        sup = fmax(sup, __shfl_xor(sup, o, kWave));
+        sem = fmax(sem, __shfl_xor(sem, o, kWave));
+        sj += __shfl_xor(sj, o, kWave);
+        nc += __shfl_xor(nc, o, kWave);
+        nf += __shfl_xor(nf, o, kWave);
+    }
+    const int w = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        r_du[w] = du; r_sup[w] = sup; r_se[w] = sem;
+        r_sj[w] = sj; r_nc[w] = nc; r_nf[w] = nf;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = blockDim.x / kWave;
+        for (int i = 1; i < nw; ++i) {
+            du = fmax(du, r_du[i]); sup = fmax(sup, r_sup[i]); sem = fmax(sem, r_se[i]);
+            sj += r_sj[i]; nc += r_nc[i]; nf += r_nf[i];
+        }
+        DevState *st = D.state;
+        atomicMax(&st->max_du, bits_of(du));
+        atomicMax(&st->sup, bits_of(sup));
+        atomicMax(&st->max_se, bits_of(sem));
+        atomicAdd(&st->path_steps, (unsigned long long)sj);
+        atomicAdd(&st->capped, (unsigned long long)nc);
+        atomicAdd(&st->nonfinite, (unsigned long long)nf);
+    }
+}
+
+// Advances the iteration index of each listed instance after its update.
+__global__ void fk_advance_kernel(const Inst *__restrict__ insts, const int32_t *__restrict__ which, int32_t n,
+                                  const int32_t *__restrict__ n_dev)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= list_count(n, n_dev)) return;
+    DevState *st = insts[which ? which[i] : i].state;
+    st->iter += 1;
+    st->use_u = 1;
+}
+
+// ------------------------------------------------------------------ debug
+
+__global__ void fk_debug_philox_kernel(uint32_t k0, uint32_t k1, const uint4 *__restrict__ ctr, int64_t n,
+                                       uint4 *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint4 c = ctr[i];
+    out[i] = philox4x32_10(c.x, c.y, c.z, c.w, k0, k1);
+}
+
+template <class R>
+__global__ void fk_debug_normals_kernel(const uint2 *__restrict__ words, int64_t n, double2 *__restrict__ z)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    R zx, zy;
+    normals(words[i].x, words[i].y, zx, zy);
+    z[i] = make_double2((double)zx, (double)zy);
+}
+
+// One lane per listed path, same step code as the item kernels.
+template <class R>
+__global__ void fk_debug_paths_kernel(const Inst *__restrict__ inst, const int32_t *__restrict__ nodes,
+                                      const int64_t *__restrict__ ms, int64_t n, long long *__restrict__ J,
+                                      double2 *__restrict__ score_out, double2 *__restrict__ xj)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const Inst &D = *inst;
+    const Consts<R> K(D);
+    const bool use_u = D.state->use_u != 0;
+    const uint32_t ctr3 = D.crn ? 0u : (uint32_t)D.state->iter;
+    if (i >= n) return;
+    const int32_t node = nodes[i];
+    const int32_t gi = node % D.nx, gj = node / D.nx;
+    PathState<R> P;
+    start(P, (R)(D.x0 + (double)gi * D.dx), (R)(D.y0 + (double)gj * D.dy));
+    bool exited = false;
+    while (!advance<R>(D, K, P, (uint32_t)ms[i], (uint32_t)node, ctr3, use_u, exited)) {
+    }
+    J[i] = P.t;
+    score_out[i] = score<R>(D, P, exited);
+    xj[i] = make_double2((double)P.x, (double)P.y);
+}
+
+}  // namespace fkd
+
+// ------------------------------------------------------------ launchers
+
+namespace fkk {
+using namespace fkd;
+
+static int blocks_for(int64_t n, int per) { return (int)((n + per - 1) / per); }
+
+hipError_t launch_paths(int precision, const Inst *d_inst, int64_t item_begin, int64_t item_end, hipStream_t s)
+{
+    const int64_t n = item_end - item_begin;
+    if (n <= 0) return hipSuccess;
+    const int waves = 4;
+    dim3 grid(blocks_for(n, waves)), block(waves * kWave);
+    if (precision == 32)
+        hipLaunchKernelGGL(fk_paths_kernel<float>, grid, block, 0, s, d_inst, item_begin, item_end);
+    else
+        hipLaunchKernelGGL(fk_paths_kernel<double>, grid, block, 0, s, d_inst, item_begin, item_end);
+    return hipGetLastError();
+}
+
+hipError_t launch_persistent(int precision, const Inst *d_insts, const EngineQueue *Q, unsigned long long *head,
+                             int n_blocks, hipStream_t s)
+{
+    dim3 grid(n_blocks), block(256);
+    if (precision == 32)
+        hipLaunchKernelGGL(fk_persistent_kernel<float>, grid, block, 0, s, d_insts, Q, head);
+    else
+        hipLaunchKernelGGL(fk_persistent_kernel<double>, grid, block, 0, s, d_insts, Q, head);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset(const Inst *d_insts, const int32_t *which, int32_t n, const int32_t *n_dev,
+                        unsigned long long *head, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fk_reset_kernel, dim3(blocks_for(n, 64)), dim3(64), 0, s, d_insts, which, n, n_dev, head);
+    return hipGetLastError();
+}
+
+hipError_t launch_update(const Inst *d_insts, const int32_t *which, int32_t n_inst, const int32_t *n_dev,
+                         int32_t max_interior, hipStream_t s)
+{
+    if (n_inst <= 0 || max_interior <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fk_update_kernel, dim3(blocks_for(max_interior, 256), n_inst), dim3(256), 0, s, d_insts,
+                       which, n_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance(const Inst *d_insts, const int32_t *which, int32_t n, const int32_t *n_dev, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fk_advance_kernel, dim3(blocks_for(n, 64)), dim3(64), 0, s, d_insts, which, n, n_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_debug_philox(uint32_t k0, uint32_t k1, const uint4 *ctr, int64_t n, uint4 *out, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fk_debug_philox_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, k0, k1, ctr, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_debug_normals(int precision, const uint2 *words, int64_t n, double2 *z, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    if (precision == 32)
+        hipLaunchKernelGGL(fk_debug_normals_kernel<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, words, n, z);
+    else
+        hipLaunchKernelGGL(fk_debug_normals_kernel<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s, words, n, z);
+    return hipGetLastError();
+}
+
+hipError_t launch_debug_paths(int precision, const Inst *d_inst, const int32_t *nodes, const int64_t *ms, int64_t n,
+                              long long *J, double2 *score, double2 *xj, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    if (precision == 32)
+        hipLaunchKernelGGL(fk_debug_paths_kernel<float>, dim3(blocks_for(n, 64)), dim3(64), 0, s, d_inst, nodes, ms,
+                           n, J, score, xj);
+    else
+        hipLaunchKernelGGL(fk_debug_paths_kernel<double>, dim3(blocks_for(n, 64)), dim3(64), 0, s, d_inst, nodes,
+                           ms, n, J, score, xj);
+    return hipGetLastError();
+}
+
+}  // namespace fkk

@@ -1,0 +1,300 @@
+// fk_problem.cpp -- host-side problem setup (see fk_problem.hpp).
+#include "fk_problem.hpp"
+
+#include <cmath>
+#include <cstring>
+#include <sstream>
+
+namespace fkh {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+const char *last_error_cstr() { return g_last_error.c_str(); }
+
+fk_status fail(fk_status st, const std::string &msg)
+{
+    set_error(msg);
+    return st;
+}
+
+fk_status hip_fail(hipError_t e, const char *what)
+{
+    std::ostringstream os;
+    os << what << ": " << hipGetErrorName(e) << " (" << hipGetErrorString(e) << ")";
+    set_error(os.str());
+    return e == hipErrorOutOfMemory ? FK_ENOMEM : FK_EDEVICE;
+}
+
+double lambda1_bounding_rect(const fk_domain &d)
+{
+    const double a = d.x1 - d.x0, b = d.y1 - d.y0;
+    return M_PI * M_PI * (1.0 / (a * a) + 1.0 / (b * b));
+}
+
+int32_t auto_paths_per_item(int64_t n_interior, int64_t M, int64_t target_items)
+{
+    int64_t p = 4096;
+    while (p > 256 && n_interior * ((M + p - 1) / p) < target_items) p /= 2;
+    const int64_t mcap = ((M + 63) / 64) * 64;
+    if (p > mcap) p = mcap;
+    return (int32_t)p;
+}
+
+static bool finite_all(std::initializer_list<double> v)
+{
+    for (double x : v)
+        if (!std::isfinite(x)) return false;
+    return true;
+}
+
+static fk_status check_bc(const fk_bc &b, bool inner)
+{
+    if (b.kind < FK_BC_ZERO || b.kind > FK_BC_TABLE) return fail(FK_EINVAL, "unknown boundary datum kind");
+    if (b.kind == FK_BC_TABLE) {
+        if (inner) return fail(FK_EINVAL, "TABLE datum is only allowed on the outer boundary");
+        if (!b.table || b.table_len < 2) return fail(FK_EINVAL, "TABLE datum needs table_len >= 2 samples");
+    }
+    for (double c : b.c)
+        if (!std::isfinite(c)) return fail(FK_EINVAL, "boundary datum coefficients must be finite");
+    return FK_OK;
+}
+
+// g at a boundary point on the host (FP64): the grid's boundary values.
+static void host_bc(const HostProblem &P, const fk_bc &B, double x, double y, double &gr, double &gi)
+{
+    const fk_domain &d = P.dom;
+    switch (B.kind) {
+    case FK_BC_PLANE_WAVE: {
+        const double ph = P.par.k * (x * std::cos(B.c[2]) + y * std::sin(B.c[2]));
+        const double c = std::cos(ph), s = std::sin(ph);
+        gr = B.c[0] * c - B.c[1] * s;
+        gi = B.c[0] * s + B.c[1] * c;
+        return;
+    }
+    case FK_BC_BILINEAR:
+        gr = B.c[0] + B.c[2] * x + B.c[4] * y + B.c[6] * x * y;
+        gi = B.c[1] + B.c[3] * x + B.c[5] * y + B.c[7] * x * y;
+        return;
+    case FK_BC_TABLE: {
+        const double a = d.x1 - d.x0, b = d.y1 - d.y0;
+        double s;
+        if (y == d.y0) s = x - d.x0;
+        else if (x == d.x1) s = a + (y - d.y0);
+        else if (y == d.y1) s = a + b + (d.x1 - x);
+        else s = 2.0 * a + b + (d.y1 - y);
+        const int64_t L = (int64_t)P.table.size() / 2;
+        const double u = s / (2.0 * (a + b)) * (double)L;
+        const double fl = std::floor(u), w = u - fl;
+        int64_t i0 = (int64_t)fl % L;
+        if (i0 < 0) i0 += L;
+        const int64_t i1 = (i0 + 1) % L;
+        gr = (1.0 - w) * P.table[2 * i0] + w * P.table[2 * i1];
+        gi = (1.0 - w) * P.table[2 * i0 + 1] + w * P.table[2 * i1 + 1];
+        return;
+    }
+    default:
+        gr = gi = 0.0;
+    }
+}
+
+fk_status setup_problem(const fk_domain *domain, const fk_source *f, const fk_bc *g_outer, const fk_bc *g_inner,
+                        const fk_params *params, HostProblem &P)
+{
+    if (!domain || !params) return fail(FK_EINVAL, "domain and params are required");
+    P.dom = *domain;
+    P.par = *params;
+    if (f) P.src = *f;
+    else std::memset(&P.src, 0, sizeof(P.src));
+    if (g_outer) P.outer = *g_outer;
+    else std::memset(&P.outer, 0, sizeof(P.outer));
+    if (g_inner) P.inner = *g_inner;
+    else std::memset(&P.inner, 0, sizeof(P.inner));
+    const fk_domain &d = P.dom;
+    if (d.kind != FK_DOMAIN_RECT && d.kind != FK_DOMAIN_RECT_MINUS_DISC)
+        return fail(FK_EINVAL, "unknown domain kind");
+    if (!finite_all({d.x0, d.x1, d.y0, d.y1}) || !(d.x1 > d.x0) || !(d.y1 > d.y0))
+        return fail(FK_EINVAL, "rectangle needs finite x0 < x1 and y0 < y1");
+    if (d.nx < 3 || d.ny < 3) return fail(FK_EINVAL, "nx and ny must be at least 3");
+    if ((int64_t)d.nx * d.ny > (int64_t)1 << 28) return fail(FK_EINVAL, "grid too large");
+    if (d.kind == FK_DOMAIN_RECT_MINUS_DISC) {
+        if (!finite_all({d.cx, d.cy, d.r}) || !(d.r > 0.0))
+            return fail(FK_EINVAL, "disc needs a finite centre and r > 0");
+        if (!(d.cx - d.r > d.x0 && d.cx + d.r < d.x1 && d.cy - d.r > d.y0 && d.cy + d.r < d.y1))
+            return fail(FK_EINVAL, "disc must lie strictly inside the rectangle");
+    }
+    if (P.src.kind < FK_SRC_ZERO || P.src.kind > FK_SRC_GAUSSIAN) return fail(FK_EINVAL, "unknown source kind");
+    if (!finite_all({P.src.amp_re, P.src.amp_im, P.src.cx, P.src.cy}))
+        return fail(FK_EINVAL, "source parameters must be finite");
+    if (P.src.kind == FK_SRC_GAUSSIAN && !(P.src.sigma > 0.0 && std::isfinite(P.src.sigma)))
+        return fail(FK_EINVAL, "Gaussian source needs sigma > 0");
+    fk_status st;
+    if ((st = check_bc(P.outer, false)) != FK_OK) return st;
+    if ((st = check_bc(P.inner, true)) != FK_OK) return st;
+    const fk_params &p = P.par;
+    if (!std::isfinite(p.k) || p.k < 0.0) return fail(FK_EINVAL, "k must be finite and >= 0");
+    if (!std::isfinite(p.h) || !(p.h > 0.0)) return fail(FK_EINVAL, "h must be > 0");
+    if (p.M < 2 || p.M > 0xFFFFFFFFll) return fail(FK_EINVAL, "M must be in [2, 2^32)");
+    if (p.precision != 32 && p.precision != 64) return fail(FK_EINVAL, "precision must be 32 or 64");
+    if (p.max_steps < 0) return fail(FK_EINVAL, "max_steps must be >= 0");
+    if (p.paths_per_item < 0 || p.paths_per_item % 64 != 0)
+        return fail(FK_EINVAL, "paths_per_item must be 0 or a positive multiple of 64");
+    if (p.max_iters < 0) return fail(FK_EINVAL, "max_iters must be >= 0");
+
+    P.jmax = p.max_steps > 0 ? p.max_steps : (int64_t)std::ceil(40.0 / (lambda1_bounding_rect(d) * p.h));
+    if (P.jmax < 1 || P.jmax > ((int64_t)1 << 31) - 4) return fail(FK_EINVAL, "step cap out of range (h too small)");
+
+    if (P.outer.kind == FK_BC_TABLE) P.table.assign(P.outer.table, P.outer.table + 2 * P.outer.table_len);
+
+    // node classes and the boundary values of the grid
+    const double dx = (d.x1 - d.x0) / (double)(d.nx - 1), dy = (d.y1 - d.y0) / (double)(d.ny - 1);
+    const size_t nn = P.n_nodes();
+    P.cls.assign(nn, 0);
+    P.grid0.assign(2 * nn, 0.0);
+    P.interior.clear();
+    for (int32_t j = 0; j < d.ny; ++j) {
+        for (int32_t i = 0; i < d.nx; ++i) {
+            const size_t id = (size_t)i + (size_t)d.nx * j;
+            const double x = d.x0 + (double)i * dx, y = d.y0 + (double)j * dy;
+            uint8_t c = 0;
+            if (i == 0 || j == 0 || i == d.nx - 1 || j == d.ny - 1) c = 1;
+            else if (d.kind == FK_DOMAIN_RECT_MINUS_DISC) {
+                const double ex = x - d.cx, ey = y - d.cy;
+                if (ex * ex + ey * ey <= d.r * d.r) c = 2;
+            }
+            P.cls[id] = c;
+            if (c == 0) P.interior.push_back((int32_t)id);
+            else host_bc(P, c == 2 ? P.inner : P.outer, x, y, P.grid0[2 * id], P.grid0[2 * id + 1]);
+        }
+    }
+    const int64_t nint = (int64_t)P.interior.size();
+    P.ppi = p.paths_per_item > 0 ? p.paths_per_item : auto_paths_per_item(nint, p.M, 12000);
+    P.items_per_node = (int32_t)((p.M + P.ppi - 1) / P.ppi);
+    P.n_items = nint * P.items_per_node;
+    return FK_OK;
+}
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+size_t instance_bytes(const HostProblem &P)
+{
+    const size_t nn = P.n_nodes();
+    size_t b = 0;
+    b += align256(nn * sizeof(double2));                 // u64
+    b += align256(nn * sizeof(float2));                  // u32
+    b += align256(P.interior.size() * sizeof(int32_t));  // nodes
+    b += align256((size_t)P.n_items * sizeof(fkd::Slot));
+    b += align256(nn * sizeof(double2));                 // se
+    b += 2 * align256(nn * sizeof(int64_t));             // sum_j, capped
+    b += align256(P.table.size() * sizeof(double));      // table
+    b += align256(sizeof(fkd::DevState));
+    return b;
+}
+
+InstanceBuffers carve(const HostProblem &P, char *base)
+{
+    const size_t nn = P.n_nodes();
+    InstanceBuffers B{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        char *p = base + o;
+        o += align256(bytes);
+        return p;
+    };
+    B.u64 = (double2 *)take(nn * sizeof(double2));
+    B.u32 = (float2 *)take(nn * sizeof(float2));
+    B.nodes = (int32_t *)take(P.interior.size() * sizeof(int32_t));
+    B.slots = (fkd::Slot *)take((size_t)P.n_items * sizeof(fkd::Slot));
+    B.se = (double2 *)take(nn * sizeof(double2));
+    B.sum_j = (int64_t *)take(nn * sizeof(int64_t));
+    B.capped = (int64_t *)take(nn * sizeof(int64_t));
+    B.table = (double2 *)take(P.table.size() * sizeof(double));
+    B.state = (fkd::DevState *)take(sizeof(fkd::DevState));
+    return B;
+}
+
+static void fill_bc(fkd::BCDev &dst, const fk_bc &src, const double2 *table, int64_t len)
+{
+    std::memset(&dst, 0, sizeof(dst));
+    dst.kind = src.kind;
+    if (src.kind == FK_BC_PLANE_WAVE) {
+        dst.c[0] = src.c[0];
+        dst.c[1] = src.c[1];
+        dst.c[2] = std::cos(src.c[2]);
+        dst.c[3] = std::sin(src.c[2]);
+    } else if (src.kind == FK_BC_BILINEAR) {
+        for (int i = 0; i < 8; ++i) dst.c[i] = src.c[i];
+    } else if (src.kind == FK_BC_TABLE) {
+        dst.table = table;
+        dst.len = len;
+    }
+}
+
+fkd::Inst make_inst(const HostProblem &P, const InstanceBuffers &B)
+{
+    fkd::Inst D;
+    std::memset(&D, 0, sizeof(D));
+    const fk_domain &d = P.dom;
+    D.x0 = d.x0; D.x1 = d.x1; D.y0 = d.y0; D.y1 = d.y1;
+    D.dx = (d.x1 - d.x0) / (double)(d.nx - 1);
+    D.dy = (d.y1 - d.y0) / (double)(d.ny - 1);
+    D.idx = 1.0 / D.dx;
+    D.idy = 1.0 / D.dy;
+    D.cx = d.cx; D.cy = d.cy; D.r = d.r; D.r2 = d.r * d.r;
+    D.nx = d.nx; D.ny = d.ny;
+    D.disc = d.kind == FK_DOMAIN_RECT_MINUS_DISC ? 1 : 0;
+    D.n_interior = (int32_t)P.interior.size();
+    D.src_kind = P.src.kind;
+    D.g_unproj = P.par.g_unprojected ? 1 : 0;
+    D.src_re = P.src.amp_re; D.src_im = P.src.amp_im;
+    D.src_cx = P.src.cx; D.src_cy = P.src.cy;
+    D.src_c = P.src.kind == FK_SRC_GAUSSIAN ? 1.0 / (2.0 * P.src.sigma * P.src.sigma) : 0.0;
+    fill_bc(D.outer, P.outer, B.table, (int64_t)P.table.size() / 2);
+    fill_bc(D.inner, P.inner, nullptr, 0);
+    D.k = P.par.k;
+    D.k2 = P.par.k * P.par.k;
+    D.h = P.par.h;
+    D.sigma = std::sqrt(2.0 * P.par.h);
+    D.M = P.par.M;
+    D.jmax = P.jmax;
+    D.key0 = (uint32_t)(P.par.seed & 0xFFFFFFFFull);
+    D.key1 = (uint32_t)(P.par.seed >> 32);
+    D.crn = P.par.crn ? 1 : 0;
+    D.ppi = P.ppi;
+    D.items_per_node = P.items_per_node;
+    D.n_items = P.n_items;
+    D.nodes = B.nodes;
+    D.u64 = B.u64;
+    D.u32 = B.u32;
+    D.slots = B.slots;
+    D.se = B.se;
+    D.node_sum_j = B.sum_j;
+    D.node_capped = B.capped;
+    D.state = B.state;
+    return D;
+}
+
+fk_status upload_instance(const HostProblem &P, const InstanceBuffers &B, hipStream_t s)
+{
+    const size_t nn = P.n_nodes();
+    std::vector<float> g32(2 * nn);
+    for (size_t i = 0; i < 2 * nn; ++i) g32[i] = (float)P.grid0[i];
+    FK_HIP(hipMemcpyAsync(B.u64, P.grid0.data(), nn * sizeof(double2), hipMemcpyHostToDevice, s));
+    FK_HIP(hipMemcpyAsync(B.u32, g32.data(), nn * sizeof(float2), hipMemcpyHostToDevice, s));
+    FK_HIP(hipMemcpyAsync(B.nodes, P.interior.data(), P.interior.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    if (!P.table.empty())
+        FK_HIP(hipMemcpyAsync(B.table, P.table.data(), P.table.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    std::vector<double> zeros(2 * nn, 0.0);
+    std::vector<int64_t> zi(nn, 0);
+    FK_HIP(hipMemcpyAsync(B.se, zeros.data(), nn * sizeof(double2), hipMemcpyHostToDevice, s));
+    FK_HIP(hipMemcpyAsync(B.sum_j, zi.data(), nn * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    FK_HIP(hipMemcpyAsync(B.capped, zi.data(), nn * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    fkd::DevState st;
+    std::memset(&st, 0, sizeof(st));
+    FK_HIP(hipMemcpyAsync(B.state, &st, sizeof(st), hipMemcpyHostToDevice, s));
+    // the staging vectors go out of scope: wait for the copies
+    FK_HIP(hipStreamSynchronize(s));
+    return FK_OK;
+}
+
+}  // namespace fkh

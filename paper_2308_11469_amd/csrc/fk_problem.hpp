@@ -1,0 +1,73 @@
+// fk_problem.hpp -- host-side problem setup shared by the single-instance
+// solver and the batched engine: validation, node classification, boundary
+// values of the grid, work decomposition and the device instance record.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "../../include/fk_helmholtz.h"
+#include "fk_device.hpp"
+
+namespace fkh {
+
+void set_error(const std::string &msg);
+fk_status fail(fk_status st, const std::string &msg);
+fk_status hip_fail(hipError_t e, const char *what);
+
+#define FK_HIP(call)                                                  \
+    do {                                                              \
+        hipError_t e_ = (call);                                       \
+        if (e_ != hipSuccess) return ::fkh::hip_fail(e_, #call);      \
+    } while (0)
+
+struct HostProblem {
+    fk_domain dom{};
+    fk_source src{};
+    fk_bc outer{}, inner{};
+    fk_params par{};
+    std::vector<double> table;        // outer TABLE samples (re, im), copied
+    std::vector<uint8_t> cls;         // 0 interior, 1 rectangle edge, 2 hole
+    std::vector<int32_t> interior;    // interior node ids, grid order
+    std::vector<double> grid0;        // initial grid (re, im): 0 interior, g elsewhere
+    int64_t jmax = 0;
+    int32_t ppi = 0;                  // paths per work item
+    int32_t items_per_node = 0;
+    int64_t n_items = 0;
+    size_t n_nodes() const { return (size_t)dom.nx * (size_t)dom.ny; }
+};
+
+// Validates and prepares a problem.  Returns FK_OK or FK_EINVAL (message set).
+fk_status setup_problem(const fk_domain *domain, const fk_source *f, const fk_bc *g_outer, const fk_bc *g_inner,
+                        const fk_params *params, HostProblem &out);
+
+// Device bytes of one instance's buffers (grids, node list, slots, stats,
+// table, state), each part 256-byte aligned.
+size_t instance_bytes(const HostProblem &P);
+
+// Carves the instance buffers out of base (device, 256-byte aligned) and
+// fills the instance record; uploads nothing.
+struct InstanceBuffers {
+    double2 *u64;
+    float2 *u32;
+    int32_t *nodes;
+    fkd::Slot *slots;
+    double2 *se;
+    int64_t *sum_j, *capped;
+    double2 *table;
+    fkd::DevState *state;
+};
+InstanceBuffers carve(const HostProblem &P, char *base);
+fkd::Inst make_inst(const HostProblem &P, const InstanceBuffers &B);
+
+// Uploads the initial grid (FP64 and FP32 copies), node list, table and a
+// fresh state (iteration 0, u_0 = 0) on stream s.
+fk_status upload_instance(const HostProblem &P, const InstanceBuffers &B, hipStream_t s);
+
+// Paths per work item when the caller leaves it to the library: the largest
+// of 4096, 2048, ... 256 that still yields at least target_items items.
+int32_t auto_paths_per_item(int64_t n_interior, int64_t M, int64_t target_items);
+
+double lambda1_bounding_rect(const fk_domain &d);
+
+}  // namespace fkh

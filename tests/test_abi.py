@@ -1,0 +1,106 @@
+"""The C ABI library loads, exports every symbol that include/fk_helmholtz.h
+declares, and rejects invalid problems on the host (no GPU needed: argument
+validation runs before any device call)."""
+import ctypes as C
+import math
+import os
+import re
+
+import pytest
+
+from paper_2308_11469_amd import build, fkh
+from paper_2308_11469_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "fk_helmholtz.h")).read()
+    return re.findall(r"^(?:fk_status|const char \*)\s*(\w+)\s*\(", txt, flags=re.M)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not build.is_built():
+        build.build()
+    return fkh.lib()
+
+
+def test_header_and_binding_agree():
+    assert sorted(header_functions()) == sorted(fkh.EXPORTS)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in header_functions():
+        assert hasattr(lib, name), name
+
+
+def arena_status(p):
+    m = fkh.Marshalled(p)
+    n = C.c_size_t()
+    st = fkh.lib().fk_helmholtz_arena_bytes(C.byref(m.domain), C.byref(m.outer), C.byref(m.params), C.byref(n))
+    return st, n.value
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nx=2), dict(ny=0), dict(x1=0.0), dict(h=0.0), dict(h=-1e-3), dict(M=1), dict(precision=16),
+    dict(k=float("nan")), dict(k=-1.0), dict(paths_per_item=100),
+])
+def test_invalid_parameters_rejected(lib, bad):
+    p = W.cavity_small()
+    ppi = bad.pop("paths_per_item", 0)
+    p = p.replace(**bad)
+    m = fkh.Marshalled(p, ppi)
+    n = C.c_size_t()
+    st = lib.fk_helmholtz_arena_bytes(C.byref(m.domain), C.byref(m.outer), C.byref(m.params), C.byref(n))
+    assert st == fkh.FK_EINVAL
+    assert lib.fk_helmholtz_last_error().decode()
+
+
+def test_disc_must_be_inside(lib):
+    p = W.scatter_problem(k=2.0, theta=0.0, N=33, M=64, seed=1, table_len=64).replace(r=1.5)
+    assert arena_status(p)[0] == fkh.FK_EINVAL
+    p = W.scatter_problem(k=2.0, theta=0.0, N=33, M=64, seed=1, table_len=64)
+    st, nbytes = arena_status(p)
+    assert st == fkh.FK_OK and nbytes > 33 * 33 * 16
+
+
+def test_table_only_outside(lib):
+    p = W.scatter_problem(k=2.0, theta=0.0, N=33, M=64, seed=1, table_len=64)
+    p.inner = p.outer
+    m = fkh.Marshalled(p)
+    h = C.c_void_p()
+    st = lib.fk_helmholtz_create(*m.args(), None, 0, None, C.byref(h))
+    assert st == fkh.FK_EINVAL and not h.value
+
+
+def test_arena_size_grows_with_grid_and_paths(lib):
+    a = arena_status(W.cavity_small())[1]
+    b = arena_status(W.cavity_65())[1]
+    c = arena_status(W.cavity_source())[1]
+    assert a < b < c
+
+
+def test_step_cap_overflow_rejected(lib):
+    p = W.cavity_small().replace(h=1e-12)
+    assert arena_status(p)[0] == fkh.FK_EINVAL
+
+
+def test_engine_config_validation(lib):
+    cfg = fkh.fk_engine_config()
+    cfg.max_instances = 0
+    cfg.precision = 32
+    cfg.max_grid_nodes = 100
+    cfg.max_items = 100
+    h = C.c_void_p()
+    assert lib.fk_engine_create(C.byref(cfg), None, C.byref(h)) == fkh.FK_EINVAL
+    cfg.max_instances = 4
+    cfg.precision = 48
+    assert lib.fk_engine_create(C.byref(cfg), None, C.byref(h)) == fkh.FK_EINVAL
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    monkeypatch.setattr(fkh, "LIB_PATH", str(tmp_path / "nope.so"))
+    monkeypatch.setattr(fkh, "_lib", None)
+    with pytest.raises(RuntimeError, match="not built"):
+        fkh.lib()

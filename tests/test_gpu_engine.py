@@ -1,0 +1,111 @@
+"""GPU tests of the batched engine (persistent work-stealing kernel replayed
+from a HIP graph): each instance's result is bit-identical alone, in a mix,
+when admitted mid-flight, and to the single-instance solver with the same
+work decomposition; the FP64 engine also matches the oracle."""
+import numpy as np
+import pytest
+
+from oracle import fkmc
+from paper_2308_11469_amd import fkh
+from paper_2308_11469_amd import workloads as W
+
+from gpu_util import assert_fp64_node_parity, interior_values, require_lib, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    require_lib()
+
+
+def mix(precision):
+    a = W.cavity_small().replace(precision=precision, M=640)
+    b = W.Problem(x0=0.0, x1=1.3, y0=0.0, y1=0.7, nx=21, ny=12, k=2.2, h=1e-3, M=300, seed=1003,
+                  outer=W.BC("plane_wave", 1.0, 4.0), precision=precision)
+    c = W.scatter_problem(k=2.0, theta=1.0, N=25, M=200, seed=5007, precision=precision, h=2e-3,
+                          table_len=2048)
+    d = W.cavity_source(precision=precision).replace(nx=13, ny=13, M=128, h=2e-3)
+    return [a, b, c, d]
+
+
+def engine(precision, n=8):
+    return fkh.Engine(n, precision=precision, max_grid_nodes=1 << 16, max_items=1 << 16, max_table=1 << 14,
+                      max_instance_nodes=4096)
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_alone_vs_mix_vs_solver_bit_identical(precision):
+    probs = mix(precision)
+    ticks = 3
+    alone = []
+    for p in probs:
+        e = engine(precision)
+        slot = e.add(p, paths_per_item=128)
+        for _ in range(ticks):
+            e.tick()
+        alone.append(e.get(slot)[0])
+        e.close()
+        s = fkh.Solver(p, paths_per_item=128)
+        s.iterate(ticks)
+        g, _ = s.get()
+        s.close()
+        say("engine alone vs solver", p.name or p.nx, precision)
+        assert np.array_equal(alone[-1], g)
+    e = engine(precision)
+    slots = [e.add(p, paths_per_item=128) for p in probs]
+    for _ in range(ticks):
+        reps = e.tick()
+        assert set(reps) == set(slots)
+    for p, sl, a in zip(probs, slots, alone):
+        assert np.array_equal(e.get(sl)[0], a)
+    e.close()
+
+
+def test_mid_flight_admission_and_slot_reuse():
+    probs = mix(64)
+    e = engine(64, n=3)
+    s0 = e.add(probs[0], paths_per_item=128)
+    s1 = e.add(probs[1], paths_per_item=128)
+    e.tick()
+    s2 = e.add(probs[2], paths_per_item=128)   # admitted while others are mid-solve
+    assert e.add(probs[3]) is None              # no free slot
+    e.tick()
+    e.tick()
+    e.remove(s1)                                # retire; its slot takes the last one
+    s3 = e.add(probs[3], paths_per_item=128)
+    assert s3 == s1
+    e.tick()
+    # reference: each alone for the number of ticks it saw
+    for p, sl, n in ((probs[0], s0, 4), (probs[2], s2, 3), (probs[3], s3, 1)):
+        r = fkh.Solver(p, paths_per_item=128)
+        r.iterate(n)
+        assert np.array_equal(e.get(sl)[0], r.get()[0]), (p.name, n)
+        r.close()
+    e.close()
+
+
+def test_engine_fp64_matches_oracle():
+    probs = mix(64)
+    e = engine(64)
+    slots = [e.add(p) for p in probs]
+    e.tick()
+    for p, sl in zip(probs, slots):
+        g, _ = e.get(sl)
+        orc = fkmc.fk_nodes(p, None, 0)
+        ids = fkmc.interior_ids(p)
+        # exit-step sums: the engine's iterate must come from the same paths
+        assert_fp64_node_parity(interior_values(p, g), orc["sumJ"], orc, p.M, label="engine " + p.name)
+    e.close()
+
+
+def test_engine_memory_admission():
+    # a pool too small for two large instances admits one, then the next after removal
+    p = W.cavity_65().replace(M=256)
+    e = fkh.Engine(4, precision=64, max_grid_nodes=5000, max_items=5000, max_table=0, max_instance_nodes=4225)
+    a = e.add(p)
+    assert a is not None
+    assert e.add(p) is None
+    e.remove(a)
+    assert e.add(p) is not None
+    e.close()
