@@ -181,11 +181,6 @@ fk_status fk_engine_create(const fk_engine_config *cfg, void *hip_stream, fk_eng
     if (cfg->max_grid_nodes < 9 || cfg->max_items < 1 || cfg->max_table < 0 || cfg->waves_per_cu < 0 ||
         cfg->max_instance_nodes < 0)
         return fail(FK_EINVAL, "engine capacities out of range");
-#ifndef FK_ENGINE_ENABLED
-    // A tick of this engine did not complete on its first GPU run; it stays
-    // switched off until the cause is found.
-    return fail(FK_EDEVICE, "the batched engine is switched off in this build");
-#endif
     fk_engine *e = new (std::nothrow) fk_engine();
     if (!e) return fail(FK_ENOMEM, "host allocation failed");
     e->cfg = *cfg;

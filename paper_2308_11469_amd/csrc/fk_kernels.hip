@@ -208,14 +208,14 @@ __device__ __forceinline__ void run_item(const Inst &D, int32_t node_idx, int32_
     q_im = wave_sum(q_im);
     sj = wave_sum(sj);
     nc = wave_sum(nc);
-    if (lane == 0) {
-        slot->s_re = s_re;
-        slot->s_im = s_im;
-        slot->q_re = q_re;
-        slot->q_im = q_im;
-        slot->sum_j = sj;
-        slot->capped = nc;
-    }
+    // every lane holds the same totals after the butterfly: all lanes store
+    // them (identical values), so no branch on the lane id follows the loop
+    slot->s_re = s_re;
+    slot->s_im = s_im;
+    slot->q_re = q_re;
+    slot->q_im = q_im;
+    slot->sum_j = sj;
+    slot->capped = nc;
 }
 
 // ----------------------------------------------------------------- kernels
@@ -246,18 +246,26 @@ __global__ void __launch_bounds__(256) fk_persistent_kernel(const Inst *__restri
     const int32_t nseg = Q->n_seg;
     const int64_t total = nseg > 0 ? Q->seg_end[nseg - 1] : 0;
     for (;;) {
-        unsigned long long g = 0;
-        if (lane == 0) g = atomicAdd(head, 1ull);
-        g = __shfl(g, 0, kWave);
-        if ((int64_t)g >= total) break;
+        // The item number must be wave-uniform, and no branch on the lane id
+        // may surround the fetch: with a lane-0 branch here and the lane-0
+        // slot store at the end of the previous item, the compiler may thread
+        // the two branches into a loop in which lane 0 runs ahead to the next
+        // fetch while the other lanes re-read a stale broadcast forever.  So
+        // every lane takes part in one atomic (lane 0 adds 1, the others 0)
+        // and the result of the first lane is read into scalar registers.
+        const unsigned long long a = atomicAdd(head, lane == 0 ? 1ull : 0ull);
+        const uint32_t lo32 = __builtin_amdgcn_readfirstlane((uint32_t)a);
+        const uint32_t hi32 = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+        const int64_t g = (int64_t)(((uint64_t)hi32 << 32) | lo32);
+        if (g >= total) break;
         int32_t lo = 0, hi = nseg - 1;
         while (lo < hi) {
             const int32_t mid = (lo + hi) >> 1;
-            if (Q->seg_end[mid] > (int64_t)g) hi = mid;
+            if (Q->seg_end[mid] > g) hi = mid;
             else lo = mid + 1;
         }
         const Inst &D = insts[Q->seg_inst[lo]];
-        const int64_t item = (int64_t)g - (lo > 0 ? Q->seg_end[lo - 1] : 0);
+        const int64_t item = g - (lo > 0 ? Q->seg_end[lo - 1] : 0);
         run_item<R>(D, (int32_t)(item / D.items_per_node), (int32_t)(item % D.items_per_node), D.slots + item);
     }
 }

@@ -11,9 +11,7 @@ from paper_2308_11469_amd import workloads as W
 
 from gpu_util import assert_fp64_node_parity, interior_values, require_lib, say
 
-pytestmark = [pytest.mark.gpu,
-              pytest.mark.skip(reason="the engine's first GPU tick did not complete (hang); the engine is "
-                                      "switched off until the cause is found")]
+pytestmark = pytest.mark.gpu
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -96,7 +94,7 @@ def test_engine_fp64_matches_oracle():
         g, _ = e.get(sl)
         orc = fkmc.fk_nodes(p, None, 0)
         ids = fkmc.interior_ids(p)
-        # exit-step sums: the engine's iterate must come from the same paths
+        # means at round-off level (the engine exposes no per-node exit sums)
         assert_fp64_node_parity(interior_values(p, g), orc["sumJ"], orc, p.M, label="engine " + p.name)
     e.close()
 
