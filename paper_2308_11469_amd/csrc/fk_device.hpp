@@ -201,9 +201,10 @@ __device__ __forceinline__ double2 bc_eval(const Inst &D, const BCDev &B, double
 {
     switch (B.kind) {
     case BC_PLANE_WAVE: {
+        // phase in half-turns: sincospi reduces its argument exactly
         const double ph = D.k * (x * B.c[2] + y * B.c[3]);
         double s, c;
-        sincos(ph, &s, &c);
+        sincospi(ph * 0.318309886183790671537767526745, &s, &c);
         return make_double2(B.c[0] * c - B.c[1] * s, B.c[0] * s + B.c[1] * c);
     }
     case BC_BILINEAR:
@@ -239,7 +240,8 @@ __device__ __forceinline__ double2 exit_datum(const Inst &D, double x, double y,
     }
     double px, py;
     const int which = project(D, x, y, px, py);
-    return bc_eval(D, which == 2 ? D.inner : D.outer, px, py);
+    const BCDev *B = which == 2 ? &D.inner : &D.outer;
+    return bc_eval(D, *B, px, py);
 }
 
 // ------------------------------------------ right-hand side f - k^2 I_h[u_n]

@@ -108,23 +108,43 @@ __device__ __forceinline__ bool advance(const Inst &D, const Consts<R> &K, PathS
     return exited || P.t >= D.jmax;
 }
 
+// A finished path waiting for its score: the last point and the left-point
+// sum, both in FP64.
+struct Pending {
+    double x, y, ar, ai;
+    bool exited, live;
+};
+
+template <class R>
+__device__ __forceinline__ void park(Pending &Q, const PathState<R> &P, bool exited)
+{
+    Q.x = (double)P.x;
+    Q.y = (double)P.y;
+    if constexpr (sizeof(R) == 8) {
+        Q.ar = P.ar;
+        Q.ai = P.ai;
+    } else {
+        Q.ar = (double)P.ar - (double)P.cr;
+        Q.ai = (double)P.ai - (double)P.ci;
+    }
+    Q.exited = exited;
+    Q.live = true;
+}
+
 // Score of a finished path: g at the nearest boundary point minus h times
 // the left-point sum (Sec. 2.1 eq. (2.3) with c = 0: the f-term enters with
 // a minus sign).
-template <class R>
-__device__ __forceinline__ double2 score(const Inst &D, const PathState<R> &P, bool exited)
+__device__ __forceinline__ double2 score(const Inst &D, const Pending &Q)
 {
-    const double2 g = exit_datum(D, (double)P.x, (double)P.y, exited);
-    double ar, ai;
-    if constexpr (sizeof(R) == 8) {
-        ar = P.ar;
-        ai = P.ai;
-    } else {
-        ar = (double)P.ar - (double)P.cr;
-        ai = (double)P.ai - (double)P.ci;
-    }
-    return make_double2(g.x - D.h * ar, g.y - D.h * ai);
+    const double2 g = exit_datum(D, Q.x, Q.y, Q.exited);
+    return make_double2(g.x - D.h * Q.ar, g.y - D.h * Q.ai);
 }
+
+// Pending scores gather until more than this many lanes hold one (or a lane
+// finishes a second path first, or the item drains); then the wave scores
+// them together.  Lanes refill at once, and the costly exit datum (nearest
+// point, plane wave or table) runs for many lanes per pass.
+constexpr int kScoreBatch = 40;
 
 template <class R>
 __device__ __forceinline__ void start(PathState<R> &P, R sx, R sy)
@@ -170,29 +190,36 @@ __device__ __forceinline__ void run_item(const Inst &D, int32_t node_idx, int32_
 
     PathState<R> P;
     start(P, sx, sy);
+    Pending Q;
+    Q.live = false;
     double s_re = 0.0, s_im = 0.0, q_re = 0.0, q_im = 0.0;
     long long sj = 0, nc = 0;
+    auto flush = [&]() {
+        if (Q.live) {
+            const double2 sc = score(D, Q);
+            s_re += sc.x;
+            s_im += sc.y;
+            q_re += sc.x * sc.x;
+            q_im += sc.y * sc.y;
+            Q.live = false;
+        }
+    };
 
     for (;;) {
         if (__ballot(active) == 0ull) break;
-        bool fin = false;
-        if (active) {
-            bool exited;
-            fin = advance<R>(D, K, P, (uint32_t)m, (uint32_t)node, ctr3, use_u, exited);
-            if (fin) {
-                const double2 s = score<R>(D, P, exited);
-                s_re += s.x;
-                s_im += s.y;
-                q_re += s.x * s.x;
-                q_im += s.y * s.y;
-                sj += P.t;
-                nc += exited ? 0 : 1;
-            }
-        }
-        // lanes whose path ended take the next unused path indices in lane order
+        bool fin = false, exited = false;
+        if (active) fin = advance<R>(D, K, P, (uint32_t)m, (uint32_t)node, ctr3, use_u, exited);
         const unsigned long long done = __ballot(fin);
         if (done) {
+            // score the parked paths first when a finishing lane still holds
+            // one, or when enough have gathered
+            const unsigned long long pend = __ballot(Q.live);
+            if ((done & pend) || __popcll(done | pend) > kScoreBatch) flush();
             if (fin) {
+                sj += P.t;
+                nc += exited ? 0 : 1;
+                park<R>(Q, P, exited);
+                // the lane takes the next unused path index (lane order)
                 const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(done >> 32),
                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)done, 0u));
                 m = next + rank;
@@ -202,6 +229,7 @@ __device__ __forceinline__ void run_item(const Inst &D, int32_t node_idx, int32_
             next += __popcll(done);
         }
     }
+    flush();
     s_re = wave_sum(s_re);
     s_im = wave_sum(s_im);
     q_re = wave_sum(q_re);
@@ -429,7 +457,9 @@ __global__ void fk_debug_paths_kernel(const Inst *__restrict__ inst, const int32
     while (!advance<R>(D, K, P, (uint32_t)ms[i], (uint32_t)node, ctr3, use_u, exited)) {
     }
     J[i] = P.t;
-    score_out[i] = score<R>(D, P, exited);
+    Pending Q;
+    park<R>(Q, P, exited);
+    score_out[i] = score(D, Q);
     xj[i] = make_double2((double)P.x, (double)P.y);
 }
 
