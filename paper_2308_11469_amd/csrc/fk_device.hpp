@@ -61,6 +61,7 @@ struct DevState {
 struct Inst {
     double x0, x1, y0, y1, dx, dy, idx, idy;
     double cx, cy, r, r2;
+    float x0_rd, x1_ru, y0_rd, y1_ru;                // edges rounded outward to binary32
     int32_t nx, ny, disc, n_interior;
     int32_t src_kind, g_unproj;
     double src_re, src_im, src_cx, src_cy, src_c;   // src_c = 1 / (2 sigma^2)
@@ -84,6 +85,16 @@ struct Inst {
 // Counter-based generator of Salmon, Moraes, Dror and Shaw (SC'11): ten
 // rounds of two 32x32->64 products whose high halves are xor-ed into the
 // other words with the round key; the key is bumped by two Weyl constants.
+// a ^ b ^ k in one VALU op (gfx950 three-input bitwise op, truth table 0x96);
+// k is wave-uniform (a round key) and sits in a scalar register.
+__device__ __forceinline__ uint32_t xor3_uniform(uint32_t a, uint32_t b, uint32_t k)
+{
+    uint32_t r;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(k));
+    return r;
+}
+
+// k0, k1 must be wave-uniform (the instance's key).
 __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                                uint32_t k0, uint32_t k1)
 {
@@ -91,8 +102,8 @@ __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = xor3_uniform((uint32_t)(p1 >> 32), c1, k0);
+        const uint32_t n2 = xor3_uniform((uint32_t)(p0 >> 32), c3, k1);
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;
@@ -143,20 +154,21 @@ __device__ __forceinline__ bool outside64(const Inst &D, double x, double y)
     return false;
 }
 
-// Exit test on an FP32 point.  The rectangle test compares the point
-// (converted exactly to FP64) with the FP64 edges.  The disc test runs in FP32
-// and falls back to FP64 only within a thin band around the circle.
+// Exit test on an FP32 point.  For a binary32 x, x <= x0 exactly iff
+// x <= RD(x0) (x0 rounded down to binary32) and x >= x1 iff x >= RU(x1), so the
+// rectangle test in FP32 against the directed-rounded edges equals the exact
+// test against the FP64 edges.  The disc test runs in FP32 and falls back to
+// FP64 only within a thin band around the circle.
 __device__ __forceinline__ bool outside32(const Inst &D, float x, float y, float cxf, float cyf,
                                           float r2f, float band)
 {
-    const double xd = (double)x, yd = (double)y;
-    if (xd <= D.x0 || xd >= D.x1 || yd <= D.y0 || yd >= D.y1) return true;
+    if (x <= D.x0_rd || x >= D.x1_ru || y <= D.y0_rd || y >= D.y1_ru) return true;
     if (D.disc) {
         const float ex = x - cxf, ey = y - cyf;
         const float d = ex * ex + ey * ey - r2f;
         if (d > band) return false;
         if (d < -band) return true;
-        const double exd = xd - D.cx, eyd = yd - D.cy;
+        const double exd = (double)x - D.cx, eyd = (double)y - D.cy;
         return exd * exd + eyd * eyd <= D.r2;
     }
     return false;
@@ -244,7 +256,7 @@ __device__ __forceinline__ double2 exit_datum(const Inst &D, double x, double y,
     return bc_eval(D, *B, px, py);
 }
 
-// ------------------------------------------ right-hand side f - k^2 I_h[u_n]
+// ------------------------------------------ iterate grid per precision
 
 template <class R> struct Grid;
 template <> struct Grid<double> {
@@ -255,24 +267,5 @@ template <> struct Grid<float> {
     using C2 = float2;
     static __device__ __forceinline__ const float2 *ptr(const Inst &D) { return D.u32; }
 };
-
-// Bilinear interpolation on the cell containing (x, y): p = floor((x-x0)/dx)
-// clamped to [0, nx-2], fractions a, b; lerp in x then in y.
-template <class R, class C2>
-__device__ __forceinline__ void interp(const C2 *__restrict__ u, int nx, int ny, R x0, R y0, R idx, R idy,
-                                       R x, R y, R &vr, R &vi)
-{
-    const R fx = (x - x0) * idx, fy = (y - y0) * idy;
-    int p = (int)fx, q = (int)fy;     // fx, fy >= 0 inside the domain: truncation is floor
-    p = p > nx - 2 ? nx - 2 : (p < 0 ? 0 : p);
-    q = q > ny - 2 ? ny - 2 : (q < 0 ? 0 : q);
-    const R a = fx - (R)p, b = fy - (R)q;
-    const int i00 = p + nx * q;
-    const C2 u00 = u[i00], u10 = u[i00 + 1], u01 = u[i00 + nx], u11 = u[i00 + nx + 1];
-    const R lr0 = u00.x + a * (u10.x - u00.x), li0 = u00.y + a * (u10.y - u00.y);
-    const R lr1 = u01.x + a * (u11.x - u01.x), li1 = u01.y + a * (u11.y - u01.y);
-    vr = lr0 + b * (lr1 - lr0);
-    vi = li0 + b * (li1 - li0);
-}
 
 }  // namespace fkd

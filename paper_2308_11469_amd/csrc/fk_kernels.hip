@@ -19,21 +19,33 @@ namespace fkd {
 
 // Per-precision constants of an instance, hoisted out of the stepping loop.
 template <class R> struct Consts {
-    R x0, y0, idx, idy, sigma, k2, h;
+    R x0, y0, idx, idy, sigma, k2;
     R cxf, cyf, r2f, band;
     R src_re, src_im, src_cx, src_cy, src_c;
-    int nx, ny;
+    R pmax, qmax;       // largest cell index as R (nx - 2, ny - 2)
+    int nx;
+    int jmax;
+    uint32_t row_bytes;  // bytes of one grid row in this precision
+    __amdgpu_buffer_rsrc_t grid;   // buffer resource of the iterate grid
     __device__ explicit Consts(const Inst &D)
         : x0((R)D.x0), y0((R)D.y0), idx((R)D.idx), idy((R)D.idy), sigma((R)D.sigma), k2((R)D.k2),
-          h((R)D.h), cxf((R)D.cx), cyf((R)D.cy), r2f((R)D.r2), band((R)(1e-5 * (D.r + 1.0))),
+          cxf((R)D.cx), cyf((R)D.cy), r2f((R)D.r2), band((R)(1e-5 * (D.r + 1.0))),
           src_re((R)D.src_re), src_im((R)D.src_im), src_cx((R)D.src_cx), src_cy((R)D.src_cy),
-          src_c((R)D.src_c), nx(D.nx), ny(D.ny) {}
+          src_c((R)D.src_c), pmax((R)(D.nx - 2)), qmax((R)(D.ny - 2)), nx(D.nx), jmax((int)D.jmax),
+          row_bytes((uint32_t)D.nx * (uint32_t)(2 * sizeof(R)))
+    {
+        // raw buffer over nx*ny complex values; dword 3 = 0x00020000 for gfx9-family
+        const uint32_t bytes = (uint32_t)D.nx * (uint32_t)D.ny * (uint32_t)(2 * sizeof(R));
+        grid = __builtin_amdgcn_make_buffer_rsrc((void *)Grid<R>::ptr(D), (short)0, (int)bytes, 0x00020000);
+    }
 };
 
+// Path state.  The integral is held in FP64 in both precisions: the FP32 path
+// adds the FP32 sum of each loop trip's (at most two) integrand values to it,
+// so its rounding error does not grow with the path length.
 template <class R> struct PathState {
     R x, y;       // position
-    R ar, ai;     // sum of the integrand over the left points
-    R cr, ci;     // Kahan compensation of ar, ai (FP32 only)
+    double ar, ai;  // sum of the integrand over the left points
     int t;        // steps taken
 };
 
@@ -49,37 +61,71 @@ __device__ __forceinline__ bool is_out(const Inst &D, const Consts<float> &K, fl
     return outside32(D, x, y, K.cxf, K.cyf, K.r2f, K.band);
 }
 
-// integrand f - k^2 I_h[u_n] at the current point, added to the path sum
+// Bilinear interpolation of u_n at (x, y): cell p = floor((x - x0)/dx)
+// clamped to [0, nx-2] (likewise q), fractions a, b; lerp in x then in y.
+// The grid is read with raw buffer loads: the base address stays in scalar
+// registers, the offset is 32-bit, and an offset outside the grid returns
+// zero instead of touching other memory.
+__device__ __forceinline__ float clamp_cell(float v, float hi) { return __builtin_amdgcn_fmed3f(v, 0.0f, hi); }
+__device__ __forceinline__ double clamp_cell(double v, double hi) { return fmin(fmax(v, 0.0), hi); }
+
 template <class R>
-__device__ __forceinline__ void accumulate(const Inst &D, const Consts<R> &K, PathState<R> &P, bool use_u)
+__device__ __forceinline__ void interp_u(const Consts<R> &K, R x, R y, R &vr, R &vi)
 {
-    R fr = (R)0, fi = (R)0;
+    const R fx = (x - K.x0) * K.idx, fy = (y - K.y0) * K.idy;
+    const R pf = clamp_cell(floor(fx), K.pmax);
+    const R qf = clamp_cell(floor(fy), K.qmax);
+    const R a = fx - pf, b = fy - qf;
+    const uint32_t i00 = (uint32_t)pf + (uint32_t)K.nx * (uint32_t)qf;
+    R u00r, u00i, u10r, u10i, u01r, u01i, u11r, u11i;
+    if constexpr (sizeof(R) == 4) {
+        const uint32_t off = i00 * 8u;
+        const auto r0 = __builtin_amdgcn_raw_buffer_load_b128(K.grid, off, 0, 0);
+        const auto r1 = __builtin_amdgcn_raw_buffer_load_b128(K.grid, off + K.row_bytes, 0, 0);
+        u00r = __uint_as_float(r0[0]); u00i = __uint_as_float(r0[1]);
+        u10r = __uint_as_float(r0[2]); u10i = __uint_as_float(r0[3]);
+        u01r = __uint_as_float(r1[0]); u01i = __uint_as_float(r1[1]);
+        u11r = __uint_as_float(r1[2]); u11i = __uint_as_float(r1[3]);
+    } else {
+        const uint32_t off = i00 * 16u;
+        const auto a0 = __builtin_amdgcn_raw_buffer_load_b128(K.grid, off, 0, 0);
+        const auto a1 = __builtin_amdgcn_raw_buffer_load_b128(K.grid, off + 16u, 0, 0);
+        const auto b0 = __builtin_amdgcn_raw_buffer_load_b128(K.grid, off + K.row_bytes, 0, 0);
+        const auto b1 = __builtin_amdgcn_raw_buffer_load_b128(K.grid, off + K.row_bytes + 16u, 0, 0);
+        auto d = [](uint32_t lo, uint32_t hi) {
+            return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+        };
+        u00r = d(a0[0], a0[1]); u00i = d(a0[2], a0[3]);
+        u10r = d(a1[0], a1[1]); u10i = d(a1[2], a1[3]);
+        u01r = d(b0[0], b0[1]); u01i = d(b0[2], b0[3]);
+        u11r = d(b1[0], b1[1]); u11i = d(b1[2], b1[3]);
+    }
+    const R lr0 = u00r + a * (u10r - u00r), li0 = u00i + a * (u10i - u00i);
+    const R lr1 = u01r + a * (u11r - u01r), li1 = u01i + a * (u11i - u01i);
+    vr = lr0 + b * (lr1 - lr0);
+    vi = li0 + b * (li1 - li0);
+}
+
+// integrand f - k^2 I_h[u_n] at the current point
+template <class R>
+__device__ __forceinline__ void rhs(const Inst &D, const Consts<R> &K, R x, R y, bool use_u, R &fr, R &fi)
+{
+    fr = (R)0;
+    fi = (R)0;
     if (D.src_kind == SRC_CONST) {
         fr = K.src_re;
         fi = K.src_im;
     } else if (D.src_kind == SRC_GAUSSIAN) {
-        const R ex = P.x - K.src_cx, ey = P.y - K.src_cy;
+        const R ex = x - K.src_cx, ey = y - K.src_cy;
         const R e = exp_src(-K.src_c * (ex * ex + ey * ey));
         fr = K.src_re * e;
         fi = K.src_im * e;
     }
     if (use_u) {
         R vr, vi;
-        interp<R>(Grid<R>::ptr(D), K.nx, K.ny, K.x0, K.y0, K.idx, K.idy, P.x, P.y, vr, vi);
+        interp_u<R>(K, x, y, vr, vi);
         fr -= K.k2 * vr;
         fi -= K.k2 * vi;
-    }
-    if constexpr (sizeof(R) == 8) {
-        P.ar += fr;
-        P.ai += fi;
-    } else {
-        // Kahan summation of the FP32 path integral
-        const R yr = fr - P.cr, yi = fi - P.ci;
-        const R tr = P.ar + yr, ti = P.ai + yi;
-        P.cr = (tr - P.ar) - yr;
-        P.ci = (ti - P.ai) - yi;
-        P.ar = tr;
-        P.ai = ti;
     }
 }
 
@@ -93,19 +139,25 @@ __device__ __forceinline__ bool advance(const Inst &D, const Consts<R> &K, PathS
     R z0x, z0y, z1x, z1y;
     normals(w.x, w.y, z0x, z0y);
     normals(w.z, w.w, z1x, z1y);
-    accumulate<R>(D, K, P, use_u);
+    R fr, fi;
+    rhs<R>(D, K, P.x, P.y, use_u, fr, fi);
     P.x += K.sigma * z0x;
     P.y += K.sigma * z0y;
     P.t += 1;
     exited = is_out(D, K, P.x, P.y);
-    if (!exited && P.t < D.jmax) {
-        accumulate<R>(D, K, P, use_u);
+    if (!exited && P.t < K.jmax) {
+        R gr, gi;
+        rhs<R>(D, K, P.x, P.y, use_u, gr, gi);
+        fr += gr;
+        fi += gi;
         P.x += K.sigma * z1x;
         P.y += K.sigma * z1y;
         P.t += 1;
         exited = is_out(D, K, P.x, P.y);
     }
-    return exited || P.t >= D.jmax;
+    P.ar += (double)fr;
+    P.ai += (double)fi;
+    return exited || P.t >= K.jmax;
 }
 
 // A finished path waiting for its score: the last point and the left-point
@@ -120,13 +172,8 @@ __device__ __forceinline__ void park(Pending &Q, const PathState<R> &P, bool exi
 {
     Q.x = (double)P.x;
     Q.y = (double)P.y;
-    if constexpr (sizeof(R) == 8) {
-        Q.ar = P.ar;
-        Q.ai = P.ai;
-    } else {
-        Q.ar = (double)P.ar - (double)P.cr;
-        Q.ai = (double)P.ai - (double)P.ci;
-    }
+    Q.ar = P.ar;
+    Q.ai = P.ai;
     Q.exited = exited;
     Q.live = true;
 }
@@ -151,7 +198,7 @@ __device__ __forceinline__ void start(PathState<R> &P, R sx, R sy)
 {
     P.x = sx;
     P.y = sy;
-    P.ar = P.ai = P.cr = P.ci = (R)0;
+    P.ar = P.ai = 0.0;
     P.t = 0;
 }
 

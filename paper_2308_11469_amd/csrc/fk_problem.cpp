@@ -116,7 +116,7 @@ fk_status setup_problem(const fk_domain *domain, const fk_source *f, const fk_bc
     if (!finite_all({d.x0, d.x1, d.y0, d.y1}) || !(d.x1 > d.x0) || !(d.y1 > d.y0))
         return fail(FK_EINVAL, "rectangle needs finite x0 < x1 and y0 < y1");
     if (d.nx < 3 || d.ny < 3) return fail(FK_EINVAL, "nx and ny must be at least 3");
-    if ((int64_t)d.nx * d.ny > (int64_t)1 << 28) return fail(FK_EINVAL, "grid too large");
+    if ((int64_t)d.nx * d.ny > (int64_t)1 << 26) return fail(FK_EINVAL, "grid too large (nx*ny > 2^26)");
     if (d.kind == FK_DOMAIN_RECT_MINUS_DISC) {
         if (!finite_all({d.cx, d.cy, d.r}) || !(d.r > 0.0))
             return fail(FK_EINVAL, "disc needs a finite centre and r > 0");
@@ -241,6 +241,10 @@ fkd::Inst make_inst(const HostProblem &P, const InstanceBuffers &B)
     D.idx = 1.0 / D.dx;
     D.idy = 1.0 / D.dy;
     D.cx = d.cx; D.cy = d.cy; D.r = d.r; D.r2 = d.r * d.r;
+    // binary32 edges rounded outward: largest float <= x0, smallest float >= x1
+    auto rd = [](double v) { float f = (float)v; return (double)f > v ? std::nextafter(f, -INFINITY) : f; };
+    auto ru = [](double v) { float f = (float)v; return (double)f < v ? std::nextafter(f, INFINITY) : f; };
+    D.x0_rd = rd(d.x0); D.x1_ru = ru(d.x1); D.y0_rd = rd(d.y0); D.y1_ru = ru(d.y1);
     D.nx = d.nx; D.ny = d.ny;
     D.disc = d.kind == FK_DOMAIN_RECT_MINUS_DISC ? 1 : 0;
     D.n_interior = (int32_t)P.interior.size();

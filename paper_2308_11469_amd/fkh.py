@@ -28,6 +28,9 @@ _BC = {"zero": 0, "plane_wave": 1, "bilinear": 2, "table": 3}
 
 
 class FkError(RuntimeError):
+    """A status other than FK_OK from the library (FK_EINVAL also raises
+    ValueError subclasses: see FkInvalid)."""
+
     def __init__(self, status, msg):
         super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
         self.status = status
@@ -128,9 +131,14 @@ def lib():
     return _lib
 
 
+class FkInvalid(FkError, ValueError):
+    """FK_EINVAL: the problem description or an argument is invalid."""
+
+
 def _check(st, allow=()):
     if st != FK_OK and st not in allow:
-        raise FkError(st, lib().fk_helmholtz_last_error().decode())
+        cls = FkInvalid if st == FK_EINVAL else FkError
+        raise cls(st, lib().fk_helmholtz_last_error().decode())
     return st
 
 

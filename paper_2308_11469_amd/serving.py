@@ -1,0 +1,223 @@
+"""Continuous-batching request loop over the batched engine.
+
+Requests (Helmholtz instances) arrive over time.  Between engine ticks the
+loop admits waiting requests into free engine slots while the engine's device
+pool can hold their footprint (the engine answers FK_ENOMEM / FK_EBUSY
+otherwise and the request keeps waiting), so requests that arrive while
+others are on the GPU join the next tick and share its persistent launch.
+Each tick advances every resident instance by one fixed-point iteration
+(Sec. 1 eq. (1.4) with alpha = k^2); an instance retires when its change
+falls below max(tol, noise floor) (the sup-norm control of Sec. 3 meeting the
+Monte Carlo noise floor), when it diverges, or at max_iters.  Requests whose
+predicted contraction ratio k^2 / lambda_1 is too close to one are rejected
+at admission: the iteration cannot converge there (Sec. 2.4).
+
+Latency = completion time - arrival time.  The engine is deterministic per
+instance, so each result is bit-identical to the same request solved alone.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass
+from typing import Callable, Dict, List, Optional
+
+import numpy as np
+
+BGK_BETA = 0.5825971579390106   # -zeta(1/2) / sqrt(2 pi)
+
+
+# ------------------------------------------------------------- predictors
+
+_lambda_cache: Dict[tuple, float] = {}
+
+
+def lambda1(p) -> float:
+    """First Dirichlet eigenvalue of -Delta on the problem's domain.
+    Rectangle: pi^2 (1/a^2 + 1/b^2).  Rectangle minus a disc: smallest
+    eigenvalue of the 5-point Laplacian on a 97 x 97 grid of the domain
+    (sparse shift-invert), cached per geometry."""
+    a, b = p.x1 - p.x0, p.y1 - p.y0
+    if p.domain_kind == "rect":
+        return math.pi ** 2 * (1 / a ** 2 + 1 / b ** 2)
+    key = (round(p.x0, 12), round(p.x1, 12), round(p.y0, 12), round(p.y1, 12),
+           round(p.cx, 12), round(p.cy, 12), round(p.r, 12))
+    if key not in _lambda_cache:
+        import scipy.sparse as sp
+        import scipy.sparse.linalg as spla
+        n = 97
+        xs = np.linspace(p.x0, p.x1, n)
+        ys = np.linspace(p.y0, p.y1, n)
+        X, Y = np.meshgrid(xs, ys)
+        inside = np.ones((n, n), bool)
+        inside[0, :] = inside[-1, :] = inside[:, 0] = inside[:, -1] = False
+        inside &= (X - p.cx) ** 2 + (Y - p.cy) ** 2 > p.r ** 2
+        idx = -np.ones((n, n), int)
+        idx[inside] = np.arange(inside.sum())
+        dx, dy = xs[1] - xs[0], ys[1] - ys[0]
+        rows, cols, vals = [], [], []
+        for j, i in zip(*np.nonzero(inside)):
+            r = idx[j, i]
+            rows.append(r); cols.append(r); vals.append(2 / dx ** 2 + 2 / dy ** 2)
+            for jj, ii, w in ((j, i - 1, dx), (j, i + 1, dx), (j - 1, i, dy), (j + 1, i, dy)):
+                if inside[jj, ii]:
+                    rows.append(r); cols.append(idx[jj, ii]); vals.append(-1 / w ** 2)
+        A = sp.csc_matrix((vals, (rows, cols)))
+        _lambda_cache[key] = float(spla.eigsh(A, k=1, sigma=0, which="LM", return_eigenvectors=False)[0])
+    return _lambda_cache[key]
+
+
+def predicted_rho(p) -> float:
+    """Contraction ratio of the iteration as the estimator sees it: k^2 over
+    lambda_1 of the domain enlarged by the discrete-monitoring shift
+    delta = beta sqrt(2h) (outer boundary out by delta, hole in by delta)."""
+    d = BGK_BETA * math.sqrt(2 * p.h)
+    a, b = p.x1 - p.x0, p.y1 - p.y0
+    if p.domain_kind == "rect":
+        lam = math.pi ** 2 * (1 / (a + 2 * d) ** 2 + 1 / (b + 2 * d) ** 2)
+    else:
+        grown = p.replace(x0=p.x0 - d, x1=p.x1 + d, y0=p.y0 - d, y1=p.y1 + d, r=max(p.r - d, 1e-9))
+        lam = lambda1(grown)
+    return p.k ** 2 / lam
+
+
+def exit_time_problem(p, M=1024):
+    """The same domain and grid with k = 0, f = -1, g = 0: one Feynman-Kac
+    step of it estimates E[tau] at every node (Remark 2.5), whose maximum gives
+    the sufficient bound k_*^C = (max E[tau])^(-1/2) (Remark 2.4)."""
+    from .workloads import BC
+    return p.replace(k=0.0, src_kind="const", src_amp=-1.0 + 0j, outer=BC("zero"), inner=BC("zero"),
+                     M=M, crn=False, max_iters=1, tol=0.0)
+
+
+def kstar_cavity(exit_times: np.ndarray) -> float:
+    return 1.0 / math.sqrt(float(np.max(exit_times)))
+
+
+# ----------------------------------------------------------------- server
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float              # seconds after the start of the run
+    problem: object
+    seed_note: str = ""
+
+
+@dataclass
+class Result:
+    rid: int
+    arrival: float
+    admitted: float = math.nan
+    completed: float = math.nan
+    iterations: int = 0
+    outcome: str = ""           # converged | max_iters | diverged | rejected
+    rho: float = math.nan
+    u: Optional[np.ndarray] = None
+    se: Optional[np.ndarray] = None
+    admitted_tick: int = -1
+    path_steps: int = 0
+
+    @property
+    def latency(self) -> float:
+        return self.completed - self.arrival
+
+
+class Server:
+    """Drives an engine (``fkh.Engine`` or any object with add / tick / get /
+    remove) with a stream of requests in wall-clock time."""
+
+    def __init__(self, engine, rho_max: float = 0.98, keep_results: bool = True,
+                 clock: Callable[[], float] = time.perf_counter, sleep: Callable[[float], None] = time.sleep):
+        self.engine = engine
+        self.rho_max = rho_max
+        self.keep = keep_results
+        self.clock = clock
+        self.sleep = sleep
+        self.ticks = 0
+        self.tick_log: List[dict] = []
+
+    def run(self, requests: List[Request], horizon: Optional[float] = None) -> Dict[int, Result]:
+        pending = sorted(requests, key=lambda r: r.arrival)
+        results = {r.rid: Result(r.rid, r.arrival) for r in pending}
+        queue: List[Request] = []          # arrived, waiting for a slot / memory
+        resident: Dict[int, Request] = {}  # slot -> request
+        t0 = self.clock()
+        i = 0
+        while i < len(pending) or queue or resident:
+            now = self.clock() - t0
+            while i < len(pending) and pending[i].arrival <= now:
+                queue.append(pending[i])
+                i += 1
+            if horizon is not None and now > horizon and not resident:
+                break
+            # admission between ticks: FIFO, skipping requests that do not fit yet
+            still = []
+            for req in queue:
+                res = results[req.rid]
+                if math.isnan(res.rho):
+                    res.rho = predicted_rho(req.problem)
+                if res.rho >= self.rho_max:
+                    res.outcome = "rejected"
+                    res.completed = self.clock() - t0
+                    continue
+                try:
+                    slot = self.engine.add(req.problem)
+                except ValueError as ex:       # invalid problem description
+                    res.outcome = "invalid: %s" % ex
+                    res.completed = self.clock() - t0
+                    continue
+                if slot is None:
+                    if not resident:        # does not fit even into an empty engine
+                        res.outcome = "too_large"
+                        res.completed = self.clock() - t0
+                        continue
+                    still.append(req)
+                    continue
+                resident[slot] = req
+                res.admitted = self.clock() - t0
+                res.admitted_tick = self.ticks
+            queue = still
+            if not resident:
+                if i < len(pending):
+                    wait = pending[i].arrival - (self.clock() - t0)
+                    if wait > 0:
+                        self.sleep(wait)
+                continue
+            reps = self.engine.tick()
+            self.ticks += 1
+            now = self.clock() - t0
+            self.tick_log.append(dict(tick=self.ticks, t=now, resident=len(resident), queued=len(queue)))
+            for slot, rep in reps.items():
+                req = resident.get(slot)
+                if req is None:
+                    continue
+                res = results[req.rid]
+                res.iterations = rep["n"]
+                res.path_steps += rep["path_steps"]
+                p = req.problem
+                done = None
+                if rep["diverging"]:
+                    done = "diverged"
+                elif rep["max_du"] < max(p.tol, rep["noise_floor"]):
+                    done = "converged"
+                elif rep["n"] >= p.max_iters:
+                    done = "max_iters"
+                if done:
+                    if self.keep:
+                        res.u, res.se = self.engine.get(slot)
+                    self.engine.remove(slot)
+                    del resident[slot]
+                    res.outcome = done
+                    res.completed = now
+        return results
+
+
+def latency_summary(results: Dict[int, Result], wall: float) -> dict:
+    done = [r for r in results.values() if r.outcome in ("converged", "max_iters", "diverged")]
+    lat = np.array([r.latency for r in done]) if done else np.array([math.nan])
+    return dict(completed=len(done), rejected=sum(r.outcome == "rejected" for r in results.values()),
+                diverged=sum(r.outcome == "diverged" for r in results.values()),
+                p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
+                solves_per_s=len(done) / wall if wall > 0 else math.nan,
+                path_steps=int(sum(r.path_steps for r in done)))
