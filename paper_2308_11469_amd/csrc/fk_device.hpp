@@ -9,13 +9,12 @@
 //   Y_t = y + sqrt(2) W_t,
 // with a new Brownian motion for every n (Remark 2.1).
 //
-// Execution model: one wavefront (64 lanes) owns a work item = (node, chunk
-// of consecutive path indices m).  Each lane runs one path at a time; when a
-// lane's path exits, the lane takes the next unused path index of the chunk
-// (ballot + mbcnt), so lanes never wait for the longest path of a group.
-// Every loop trip draws one Philox block (4 words) and takes two Euler steps.
-// Per-lane sums are FP64; the wave reduces them in a fixed butterfly order
-// into the item's own slot, so results do not depend on scheduling.
+// Execution model: waves take work items (node, chunk of consecutive path
+// indices m) from a queue; the 64 lanes of a wave run paths as one stream,
+// each lane taking the next unused index when its path exits.  Every loop
+// trip draws one Philox block (4 words) and takes two Euler steps.  Scores
+// go into per-node slots as exact integers, so results do not depend on
+// scheduling.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -36,11 +35,17 @@ struct BCDev {
     int64_t len;
 };
 
-// Result slot of one work item: sums over the item's paths.
+// Sums of one interior node over one iteration, as exact integers (added
+// with integer atomics, so their value does not depend on the order):
+// s = sum over paths of the score, held as sum floor(s 2^16) (hi, two's
+// complement) and sum frac(s 2^16) 2^40 (lo); s^2 likewise with scale 1.
 struct Slot {
-    double s_re, s_im, q_re, q_im;   // sum s, sum s^2 (per component)
-    int64_t sum_j;                   // sum of exit-step indices
-    int64_t capped;                  // paths stopped by the step cap
+    unsigned long long s_re_hi, s_re_lo, s_im_hi, s_im_lo;
+    unsigned long long q_re_hi, q_re_lo, q_im_hi, q_im_lo;
+    unsigned long long sum_j;        // sum of exit-step indices
+    unsigned long long capped;       // paths stopped by the step cap
+    unsigned long long overflow;     // scores not representable (|s| >= 2^21 or not finite)
+    unsigned long long pad;
 };
 
 // Per-instance device state written by the update kernel.
@@ -75,7 +80,7 @@ struct Inst {
     const int32_t *nodes;                            // interior node ids
     double2 *u64;                                    // iterate, FP64 master
     float2 *u32;                                     // iterate, FP32 copy
-    Slot *slots;                                     // n_items
+    Slot *slots;                                     // one per interior node
     double2 *se;                                     // per grid node
     int64_t *node_sum_j, *node_capped;               // per grid node
     DevState *state;

@@ -4,8 +4,9 @@
 // a segment table numbers the work items of the active instances (longest
 // expected paths first).  One tick = one fixed-point iteration of every active
 // instance = one replay of a HIP graph captured once at creation:
-//   reset (status + queue head) -> persistent work-stealing path kernel ->
-//   update (all active instances) -> iteration advance -> status copy.
+//   reset (status + queue head) -> path kernel (persistent waves pulling work
+//   items from the queue) -> update (all active instances) -> iteration
+//   advance -> status copy.
 // Admitting or retiring an instance edits the tables between ticks; the graph
 // is never re-captured.  Instance memory comes from one device pool managed by
 // a first-fit allocator; admission fails with FK_ENOMEM when the pool cannot
@@ -125,7 +126,7 @@ static fk_status capture_graph(fk_engine *e)
     FK_HIP(hipStreamBeginCapture(e->cap_stream, hipStreamCaptureModeThreadLocal));
     hipError_t err = fkk::launch_reset(e->d_insts, e->d_active, cap, e->d_n_active, e->d_head, e->cap_stream);
     if (err == hipSuccess)
-        err = fkk::launch_persistent(prec, e->d_insts, e->d_queue, e->d_head, e->n_blocks, e->cap_stream);
+        err = fkk::launch_stream(prec, e->d_insts, e->d_queue, e->d_head, e->n_blocks, e->cap_stream);
     if (err == hipSuccess)
         err = fkk::launch_update(e->d_insts, e->d_active, cap, e->d_n_active, e->max_interior_cap, e->cap_stream);
     if (err == hipSuccess) err = fkk::launch_advance(e->d_insts, e->d_active, cap, e->d_n_active, e->cap_stream);
@@ -192,19 +193,14 @@ fk_status fk_engine_create(const fk_engine_config *cfg, void *hip_stream, fk_eng
         return st;
     };
     hipError_t err;
-    int dev = 0, n_cu = 0;
-    if ((err = hipGetDevice(&dev)) != hipSuccess) return bail(hip_fail(err, "hipGetDevice"));
-    if ((err = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
-        return bail(hip_fail(err, "hipDeviceGetAttribute"));
-    const int wpc = cfg->waves_per_cu > 0 ? cfg->waves_per_cu : 16;
-    e->n_blocks = std::max(1, n_cu * wpc / 4);
+    e->n_blocks = path_kernel_blocks(cfg->waves_per_cu);
     // largest interior count of one instance (sizes the update grid of the graph)
     e->max_interior_cap = cfg->max_instance_nodes > 0 ? cfg->max_instance_nodes : 257 * 257;
     const int32_t cap = cfg->max_instances;
-    // pool: per-node arrays (u64 16, u32 8, nodes 4, se 16, sum_j 8, capped 8),
-    // slots, tables, and 8 alignment paddings per instance
-    e->pool_bytes = (size_t)cfg->max_grid_nodes * 60 + (size_t)cfg->max_items * sizeof(fkd::Slot) +
-                    (size_t)cfg->max_table * 16 + (size_t)cap * 9 * 256;
+    // pool: per-node arrays (u64 16, u32 8, nodes 4, se 16, sum_j 8, capped 8,
+    // slot), tables, and 9 alignment paddings per instance
+    e->pool_bytes = (size_t)cfg->max_grid_nodes * (60 + sizeof(fkd::Slot)) + (size_t)cfg->max_table * 16 +
+                    (size_t)cap * 9 * 256;
     if ((err = hipStreamCreateWithFlags(&e->cap_stream, hipStreamNonBlocking)) != hipSuccess)
         return bail(hip_fail(err, "hipStreamCreateWithFlags"));
     if ((err = hipMalloc((void **)&e->d_insts, cap * sizeof(fkd::Inst))) != hipSuccess ||
@@ -255,6 +251,10 @@ fk_status fk_engine_add(fk_engine *e, const fk_domain *domain, const fk_source *
     if (P.par.precision != e->cfg.precision) return fail(FK_EINVAL, "instance precision differs from the engine's");
     if ((int64_t)P.interior.size() > e->max_interior_cap) return fail(FK_ENOMEM, "instance grid exceeds the engine");
     if (free_slot < 0) return fail(FK_EBUSY, "no free engine slot");
+    int64_t resident_items = 0;
+    for (const SlotInfo &o : e->slots)
+        if (o.used) resident_items += o.P.n_items;
+    if (resident_items + P.n_items > e->cfg.max_items) return fail(FK_ENOMEM, "engine work-item capacity reached");
     const size_t bytes = instance_bytes(P);
     size_t off = 0;
     if (!e->pool.alloc(bytes, off)) return fail(FK_ENOMEM, "engine pool cannot hold the instance now");

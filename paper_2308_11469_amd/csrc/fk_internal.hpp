@@ -10,7 +10,7 @@ struct Inst;
 struct DevState;
 struct Slot;
 
-// Segment table of a batched launch (device): segment s covers the items of
+// Segment table of a path launch (device): segment s covers the items of
 // instance seg_inst[s]; seg_end is the inclusive prefix sum of item counts.
 constexpr int kMaxSlots = 1024;
 struct EngineQueue {
@@ -22,10 +22,8 @@ struct EngineQueue {
 }  // namespace fkd
 
 namespace fkk {
-hipError_t launch_paths(int precision, const fkd::Inst *d_inst, int64_t item_begin, int64_t item_end,
-                        hipStream_t s);
-hipError_t launch_persistent(int precision, const fkd::Inst *d_insts, const fkd::EngineQueue *Q,
-                             unsigned long long *head, int n_blocks, hipStream_t s);
+hipError_t launch_stream(int precision, const fkd::Inst *d_insts, const fkd::EngineQueue *Q,
+                         unsigned long long *head, int n_blocks, hipStream_t s);
 hipError_t launch_reset(const fkd::Inst *d_insts, const int32_t *which, int32_t n, const int32_t *n_dev,
                         unsigned long long *head, hipStream_t s);
 hipError_t launch_update(const fkd::Inst *d_insts, const int32_t *which, int32_t n_inst, const int32_t *n_dev,

@@ -1,9 +1,9 @@
 // fk_kernels.hip -- HIP kernels of the Feynman-Kac Helmholtz path (gfx950).
 //
-//   fk_paths_kernel<R>        one wavefront per work item (node, chunk of paths)
-//   fk_persistent_kernel<R>   batched: waves pull (instance, node, chunk)
-//                             items from a device queue until it is empty
-//   fk_update_kernel          node mean / variance from the item slots, the
+//   fk_stream_kernel<R>       the paths: waves pull (instance, node, chunk)
+//                             items from a device queue until it is empty and
+//                             run their paths as one stream of lanes
+//   fk_update_kernel          node mean / variance from the node slots, the
 //                             fixed-point update of the iterate and the
 //                             per-iteration status (max |du|, sup, max SE,
 //                             path steps, capped and non-finite counts)
@@ -161,19 +161,22 @@ __device__ __forceinline__ bool advance(const Inst &D, const Consts<R> &K, PathS
 }
 
 // A finished path waiting for its score: the last point and the left-point
-// sum, both in FP64.
+// sum (FP64), its exit-step index and the node it belongs to.
 struct Pending {
     double x, y, ar, ai;
+    int32_t t, node_idx;
     bool exited, live;
 };
 
 template <class R>
-__device__ __forceinline__ void park(Pending &Q, const PathState<R> &P, bool exited)
+__device__ __forceinline__ void park(Pending &Q, const PathState<R> &P, bool exited, int32_t node_idx)
 {
     Q.x = (double)P.x;
     Q.y = (double)P.y;
     Q.ar = P.ar;
     Q.ai = P.ai;
+    Q.t = P.t;
+    Q.node_idx = node_idx;
     Q.exited = exited;
     Q.live = true;
 }
@@ -187,8 +190,75 @@ __device__ __forceinline__ double2 score(const Inst &D, const Pending &Q)
     return make_double2(g.x - D.h * Q.ar, g.y - D.h * Q.ai);
 }
 
+// Exact fixed-point split of v * scale into floor (hi) and the fraction in
+// units of 2^-40 (lo).  v * scale and its fraction are exact in binary64, so
+// the same score always gives the same integers, and integer sums do not
+// depend on the order in which paths are added.
+__device__ __forceinline__ void fix_split(double v, double scale, unsigned long long &hi, unsigned long long &lo)
+{
+    const double t = v * scale;
+    const double f = floor(t);
+    hi = (unsigned long long)(long long)f;
+    lo = (unsigned long long)((t - f) * 0x1p40);
+}
+
+// Component i of one path's contribution to its node slot, as an exact
+// integer (the Slot fields in order): 0-3 the score's real and imaginary
+// parts (hi, lo at scale 2^16), 4-7 their squares (hi, lo at scale 1), 8 the
+// exit-step index, 9 capped, 10 overflow.  Scores of magnitude 2^21 or more
+// (and non-finite ones) count as overflow instead: the iteration is then
+// reported as non-finite.
+constexpr int kSlotSums = 11;
+
+__device__ __forceinline__ unsigned long long contribution(int i, double2 sc, bool ok, int32_t J, bool capped)
+{
+    if (i == 8) return (unsigned long long)J;
+    if (i == 9) return capped ? 1ull : 0ull;
+    if (i == 10) return ok ? 0ull : 1ull;
+    if (!ok) return 0ull;
+    const double v = i < 2 ? sc.x : (i < 4 ? sc.y : (i < 6 ? sc.x * sc.x : sc.y * sc.y));
+    unsigned long long hi, lo;
+    fix_split(v, i < 4 ? 0x1p16 : 1.0, hi, lo);
+    return (i & 1) ? lo : hi;
+}
+
+// Scores the parked paths of the wave and adds them to their node sums.
+// Paths of the wave's current node go into the wave's LDS accumulator (exact
+// 64-bit LDS atomics, no return); paths of older nodes, still in flight when
+// the wave moved on, go straight to their node slot in global memory.
+__device__ __forceinline__ void deposit_parked(const Inst &D, Pending &Q, unsigned long long *acc,
+                                               int32_t acc_node)
+{
+    if (Q.live) {
+        const double2 sc = score(D, Q);
+        const bool ok = fabs(sc.x) < 0x1p21 && fabs(sc.y) < 0x1p21;
+        unsigned long long *dst = Q.node_idx == acc_node ? acc : (unsigned long long *)(D.slots + Q.node_idx);
+#pragma unroll 1
+        for (int i = 0; i < kSlotSums; ++i) {
+            const unsigned long long v = contribution(i, sc, ok, Q.t, !Q.exited);
+            if (v != 0ull) atomicAdd(dst + i, v);
+        }
+        Q.live = false;
+    }
+}
+
+// Moves the wave's LDS accumulator into its node's slot (lane i < 11 posts
+// sum i) and clears it.
+__device__ __forceinline__ void flush_acc(const Inst &D, unsigned long long *acc, int32_t acc_node)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    __builtin_amdgcn_wave_barrier();
+    if (acc_node >= 0 && lane < kSlotSums) {
+        const unsigned long long v = __hip_atomic_load(acc + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (v != 0ull) atomicAdd((unsigned long long *)(D.slots + acc_node) + lane, v);
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (lane < 12) acc[lane] = 0ull;
+    __builtin_amdgcn_wave_barrier();
+}
+
 // Pending scores gather until more than this many lanes hold one (or a lane
-// finishes a second path first, or the item drains); then the wave scores
+// finishes a second path first, or the stream drains); then the wave scores
 // them together.  Lanes refill at once, and the costly exit datum (nearest
 // point, plane wave or table) runs for many lanes per pass.
 constexpr int kScoreBatch = 40;
@@ -202,146 +272,151 @@ __device__ __forceinline__ void start(PathState<R> &P, R sx, R sy)
     P.t = 0;
 }
 
-__device__ __forceinline__ double wave_sum(double v)
+// Next item number from the queue head.  Only the first active lane adds 1;
+// every lane takes part in the atomic and the first lane's old value is read
+// into scalar registers, so the value is wave-uniform and no branch on the
+// lane id surrounds the fetch (a lane-0 branch here once let the compiler
+// build a divergent loop in which lanes read a stale broadcast forever).
+__device__ __forceinline__ int64_t fetch_item(unsigned long long *head)
 {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
-}
-__device__ __forceinline__ long long wave_sum(long long v)
-{
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
-}
-
-// One work item: paths [chunk*ppi, min(M, (chunk+1)*ppi)) of interior node
-// node_idx, executed by the calling wavefront; sums land in *slot.
-template <class R>
-__device__ __forceinline__ void run_item(const Inst &D, int32_t node_idx, int32_t chunk, Slot *slot)
-{
+    const unsigned long long ex = __ballot(true);
     const int lane = threadIdx.x & (kWave - 1);
-    const Consts<R> K(D);
-    const int32_t iter = D.state->iter;
-    const bool use_u = D.state->use_u != 0;
-    const uint32_t ctr3 = D.crn ? 0u : (uint32_t)iter;
-    const int32_t node = D.nodes[node_idx];
-    const int32_t gi = node % D.nx, gj = node / D.nx;
-    const R sx = (R)(D.x0 + (double)gi * D.dx);
-    const R sy = (R)(D.y0 + (double)gj * D.dy);
-    const int64_t m_begin = (int64_t)chunk * D.ppi;
-    const int64_t m_end = m_begin + D.ppi < D.M ? m_begin + D.ppi : D.M;
-    int64_t next = m_begin + kWave;
-    int64_t m = m_begin + lane;
-    bool active = m < m_end;
+    const bool first = lane == __ffsll((long long)ex) - 1;
+    const unsigned long long a = atomicAdd(head, first ? 1ull : 0ull);
+    const uint32_t lo32 = __builtin_amdgcn_readfirstlane((uint32_t)a);
+    const uint32_t hi32 = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    return (int64_t)(((uint64_t)hi32 << 32) | lo32);
+}
 
-    PathState<R> P;
-    start(P, sx, sy);
-    Pending Q;
-    Q.live = false;
-    double s_re = 0.0, s_im = 0.0, q_re = 0.0, q_im = 0.0;
-    long long sj = 0, nc = 0;
-    auto flush = [&]() {
-        if (Q.live) {
-            const double2 sc = score(D, Q);
-            s_re += sc.x;
-            s_im += sc.y;
-            q_re += sc.x * sc.x;
-            q_im += sc.y * sc.y;
-            Q.live = false;
-        }
-    };
-
-    for (;;) {
-        if (__ballot(active) == 0ull) break;
-        bool fin = false, exited = false;
-        if (active) fin = advance<R>(D, K, P, (uint32_t)m, (uint32_t)node, ctr3, use_u, exited);
-        const unsigned long long done = __ballot(fin);
-        if (done) {
-            // score the parked paths first when a finishing lane still holds
-            // one, or when enough have gathered
-            const unsigned long long pend = __ballot(Q.live);
-            if ((done & pend) || __popcll(done | pend) > kScoreBatch) flush();
-            if (fin) {
-                sj += P.t;
-                nc += exited ? 0 : 1;
-                park<R>(Q, P, exited);
-                // the lane takes the next unused path index (lane order)
-                const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(done >> 32),
-                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)done, 0u));
-                m = next + rank;
-                if (m < m_end) start(P, sx, sy);
-                else active = false;
-            }
-            next += __popcll(done);
-        }
+// Segment s of the queue holds the items of instance seg_inst[s]; seg_end is
+// the inclusive prefix sum of item counts.  Binary search (wave-uniform).
+__device__ __forceinline__ int32_t find_segment(const EngineQueue *Q, int32_t nseg, int64_t g)
+{
+    int32_t lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (Q->seg_end[mid] > g) hi = mid;
+        else lo = mid + 1;
     }
-    flush();
-    s_re = wave_sum(s_re);
-    s_im = wave_sum(s_im);
-    q_re = wave_sum(q_re);
-    q_im = wave_sum(q_im);
-    sj = wave_sum(sj);
-    nc = wave_sum(nc);
-    // every lane holds the same totals after the butterfly: all lanes store
-    // them (identical values), so no branch on the lane id follows the loop
-    slot->s_re = s_re;
-    slot->s_im = s_im;
-    slot->q_re = q_re;
-    slot->q_im = q_im;
-    slot->sum_j = sj;
-    slot->capped = nc;
+    return lo;
 }
 
-// ----------------------------------------------------------------- kernels
-
+// The path kernel.  Work items (instance, node, chunk of ppi consecutive path
+// indices) are numbered consecutively over the queue's instances; waves take
+// items from an atomic counter until all are taken.  Within a wave the lanes
+// form one stream: a lane whose path ends takes the next unused path index of
+// the wave's current item, and when that item has no index left the wave
+// fetches the next item, so lanes never wait for the slow paths of an item.
+// A wave only mixes items of one instance; at an instance boundary it drains
+// first.  Each path's score goes into its node's slot as exact integers, so
+// the node sums do not depend on which wave, lane or launch ran which path:
+// an instance gives bit-identical results alone, in any batch and for any
+// item size.
 template <class R>
-__global__ void __launch_bounds__(256) fk_paths_kernel(const Inst *__restrict__ inst, int64_t item_begin,
-                                                       int64_t item_end)
+__global__ void __launch_bounds__(256) fk_stream_kernel(const Inst *__restrict__ insts,
+                                                        const EngineQueue *__restrict__ Q,
+                                                        unsigned long long *head)
 {
-    const Inst &D = *inst;
-    const int64_t item = item_begin + (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
-    if (item >= item_end) return;
-    const int32_t node_idx = (int32_t)(item / D.items_per_node);
-    const int32_t chunk = (int32_t)(item % D.items_per_node);
-    run_item<R>(D, node_idx, chunk, D.slots + item);
-}
-
-// Batched work queue.  The items of the active instances are numbered
-// consecutively, instance after instance in the order of seg_inst (longest
-// expected paths first); seg_end[s] is the exclusive prefix end of segment s.
-// Each wave takes the next item number from an atomic counter until all are
-// taken, finds its segment by binary search (wave-uniform) and runs it.
-template <class R>
-__global__ void __launch_bounds__(256) fk_persistent_kernel(const Inst *__restrict__ insts,
-                                                            const EngineQueue *__restrict__ Q,
-                                                            unsigned long long *head)
-{
-    const int lane = threadIdx.x & (kWave - 1);
+    __shared__ unsigned long long lds_acc[4][12];   // one node accumulator per wave
+    unsigned long long *acc = lds_acc[threadIdx.x / kWave];
+    if ((threadIdx.x & (kWave - 1)) < 12) acc[threadIdx.x & (kWave - 1)] = 0ull;
+    __builtin_amdgcn_wave_barrier();
     const int32_t nseg = Q->n_seg;
     const int64_t total = nseg > 0 ? Q->seg_end[nseg - 1] : 0;
+    int64_t carry = -1;    // an item fetched for another instance, run next
     for (;;) {
-        // The item number must be wave-uniform, and no branch on the lane id
-        // may surround the fetch: with a lane-0 branch here and the lane-0
-        // slot store at the end of the previous item, the compiler may thread
-        // the two branches into a loop in which lane 0 runs ahead to the next
-        // fetch while the other lanes re-read a stale broadcast forever.  So
-        // every lane takes part in one atomic (lane 0 adds 1, the others 0)
-        // and the result of the first lane is read into scalar registers.
-        const unsigned long long a = atomicAdd(head, lane == 0 ? 1ull : 0ull);
-        const uint32_t lo32 = __builtin_amdgcn_readfirstlane((uint32_t)a);
-        const uint32_t hi32 = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
-        const int64_t g = (int64_t)(((uint64_t)hi32 << 32) | lo32);
+        int64_t g = carry >= 0 ? carry : fetch_item(head);
+        carry = -1;
         if (g >= total) break;
-        int32_t lo = 0, hi = nseg - 1;
-        while (lo < hi) {
-            const int32_t mid = (lo + hi) >> 1;
-            if (Q->seg_end[mid] > g) hi = mid;
-            else lo = mid + 1;
+        int32_t seg = find_segment(Q, nseg, g);
+        const int32_t inst = Q->seg_inst[seg];
+        const Inst &D = insts[inst];
+        const Consts<R> K(D);
+        const bool use_u = D.state->use_u != 0;
+        const uint32_t ctr3 = D.crn ? 0u : (uint32_t)D.state->iter;
+
+        // wave-uniform pool: path indices [pool_m, pool_end) of one node
+        int64_t pool_m = 0, pool_end = 0;
+        int32_t pool_node_idx = 0, pool_node = 0;
+        int32_t acc_node = -1;   // node whose sums the LDS accumulator holds
+        R pool_sx = (R)0, pool_sy = (R)0;
+        bool more = true;       // the queue may hold further items of this instance
+        auto open_item = [&](int64_t gg) {
+            const int64_t item = gg - (seg > 0 ? Q->seg_end[seg - 1] : 0);
+            pool_node_idx = (int32_t)(item / D.items_per_node);
+            const int64_t chunk = item % D.items_per_node;
+            pool_m = chunk * D.ppi;
+            pool_end = pool_m + D.ppi < D.M ? pool_m + D.ppi : D.M;
+            pool_node = D.nodes[pool_node_idx];
+            const int32_t gi = pool_node % D.nx, gj = pool_node / D.nx;
+            pool_sx = (R)(D.x0 + (double)gi * D.dx);
+            pool_sy = (R)(D.y0 + (double)gj * D.dy);
+            if (pool_node_idx != acc_node) {
+                flush_acc(D, acc, acc_node);
+                acc_node = pool_node_idx;
+            }
+        };
+        open_item(g);
+
+        PathState<R> P;
+        start(P, (R)0, (R)0);
+        Pending Qp;
+        Qp.live = false;
+        bool active = false;
+        int32_t node = 0, node_idx = 0;
+        uint32_t m = 0;
+        auto flush = [&]() { deposit_parked(D, Qp, acc, acc_node); };
+
+        for (;;) {
+            // give every idle lane the next path index, opening items as needed
+            for (;;) {
+                const unsigned long long need = __ballot(!active);
+                if (need == 0ull) break;
+                if (pool_m >= pool_end) {
+                    if (!more) break;
+                    const int64_t g2 = fetch_item(head);
+                    if (g2 >= total) {
+                        more = false;
+                        break;
+                    }
+                    if (Q->seg_inst[find_segment(Q, nseg, g2)] != inst) {
+                        carry = g2;      // another instance: drain this one first
+                        more = false;
+                        break;
+                    }
+                    open_item(g2);
+                    continue;
+                }
+                const int64_t avail = pool_end - pool_m;
+                const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(need >> 32),
+                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
+                if (!active && (int64_t)rank < avail) {
+                    m = (uint32_t)(pool_m + rank);
+                    node = pool_node;
+                    node_idx = pool_node_idx;
+                    start(P, pool_sx, pool_sy);
+                    active = true;
+                }
+                const int64_t taken = (int64_t)__popcll(need);
+                pool_m += taken < avail ? taken : avail;
+            }
+            if (__ballot(active) == 0ull) break;
+            bool fin = false, exited = false;
+            if (active) fin = advance<R>(D, K, P, m, (uint32_t)node, ctr3, use_u, exited);
+            const unsigned long long done = __ballot(fin);
+            if (done) {
+                // score the parked paths first when a finishing lane still
+                // holds one, or when enough have gathered
+                const unsigned long long pend = __ballot(Qp.live);
+                if ((done & pend) || __popcll(done | pend) > kScoreBatch) flush();
+                if (fin) {
+                    park<R>(Qp, P, exited, node_idx);
+                    active = false;
+                }
+            }
         }
-        const Inst &D = insts[Q->seg_inst[lo]];
-        const int64_t item = g - (lo > 0 ? Q->seg_end[lo - 1] : 0);
-        run_item<R>(D, (int32_t)(item / D.items_per_node), (int32_t)(item % D.items_per_node), D.slots + item);
+        flush();
+        flush_acc(D, acc, acc_node);
     }
 }
 
@@ -388,16 +463,16 @@ __global__ void __launch_bounds__(256) fk_update_kernel(const Inst *__restrict__
     const bool use_u = D.state->use_u != 0;
     if (idx < D.n_interior) {
         const int32_t node = D.nodes[idx];
-        const Slot *sl = D.slots + (int64_t)idx * D.items_per_node;
-        double s_re = 0.0, s_im = 0.0, q_re = 0.0, q_im = 0.0;
-        for (int c = 0; c < D.items_per_node; ++c) {
-            s_re += sl[c].s_re;
-            s_im += sl[c].s_im;
-            q_re += sl[c].q_re;
-            q_im += sl[c].q_im;
-            sj += sl[c].sum_j;
-            nc += sl[c].capped;
-        }
+        Slot *sl = D.slots + idx;
+        // exact integer sums of the iteration; the slot is cleared for the next
+        const double s_re = (double)(long long)sl->s_re_hi * 0x1p-16 + (double)sl->s_re_lo * 0x1p-56;
+        const double s_im = (double)(long long)sl->s_im_hi * 0x1p-16 + (double)sl->s_im_lo * 0x1p-56;
+        const double q_re = (double)sl->q_re_hi + (double)sl->q_re_lo * 0x1p-40;
+        const double q_im = (double)sl->q_im_hi + (double)sl->q_im_lo * 0x1p-40;
+        sj = (long long)sl->sum_j;
+        nc = (long long)sl->capped;
+        const unsigned long long ovf = sl->overflow;
+        *sl = Slot{};
         const double Mf = (double)D.M;
         const double mr = s_re / Mf, mi = s_im / Mf;
         const double vr = fmax((q_re - s_re * mr) / (Mf - 1.0), 0.0);
@@ -412,7 +487,7 @@ __global__ void __launch_bounds__(256) fk_update_kernel(const Inst *__restrict__
         du = hypot(mr - old.x, mi - old.y);
         sup = hypot(mr, mi);
         sem = hypot(ser, sei);
-        if (!(isfinite(mr) && isfinite(mi))) {
+        if (ovf != 0ull || !(isfinite(mr) && isfinite(mi))) {
             nf = 1;
             du = HUGE_VAL;
             sup = HUGE_VAL;
@@ -505,7 +580,7 @@ __global__ void fk_debug_paths_kernel(const Inst *__restrict__ inst, const int32
     }
     J[i] = P.t;
     Pending Q;
-    park<R>(Q, P, exited);
+    park<R>(Q, P, exited, 0);
     score_out[i] = score(D, Q);
     xj[i] = make_double2((double)P.x, (double)P.y);
 }
@@ -519,27 +594,14 @@ using namespace fkd;
 
 static int blocks_for(int64_t n, int per) { return (int)((n + per - 1) / per); }
 
-hipError_t launch_paths(int precision, const Inst *d_inst, int64_t item_begin, int64_t item_end, hipStream_t s)
-{
-    const int64_t n = item_end - item_begin;
-    if (n <= 0) return hipSuccess;
-    const int waves = 4;
-    dim3 grid(blocks_for(n, waves)), block(waves * kWave);
-    if (precision == 32)
-        hipLaunchKernelGGL(fk_paths_kernel<float>, grid, block, 0, s, d_inst, item_begin, item_end);
-    else
-        hipLaunchKernelGGL(fk_paths_kernel<double>, grid, block, 0, s, d_inst, item_begin, item_end);
-    return hipGetLastError();
-}
-
-hipError_t launch_persistent(int precision, const Inst *d_insts, const EngineQueue *Q, unsigned long long *head,
-                             int n_blocks, hipStream_t s)
+hipError_t launch_stream(int precision, const Inst *d_insts, const EngineQueue *Q, unsigned long long *head,
+                         int n_blocks, hipStream_t s)
 {
     dim3 grid(n_blocks), block(256);
     if (precision == 32)
-        hipLaunchKernelGGL(fk_persistent_kernel<float>, grid, block, 0, s, d_insts, Q, head);
+        hipLaunchKernelGGL(fk_stream_kernel<float>, grid, block, 0, s, d_insts, Q, head);
     else
-        hipLaunchKernelGGL(fk_persistent_kernel<double>, grid, block, 0, s, d_insts, Q, head);
+        hipLaunchKernelGGL(fk_stream_kernel<double>, grid, block, 0, s, d_insts, Q, head);
     return hipGetLastError();
 }
 

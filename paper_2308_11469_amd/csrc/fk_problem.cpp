@@ -2,8 +2,10 @@
 #include "fk_problem.hpp"
 
 #include <cmath>
+#include <algorithm>
 #include <cstring>
 #include <sstream>
+#include <utility>
 
 namespace fkh {
 
@@ -26,18 +28,33 @@ fk_status hip_fail(hipError_t e, const char *what)
     return e == hipErrorOutOfMemory ? FK_ENOMEM : FK_EDEVICE;
 }
 
+int path_kernel_blocks(int waves_per_cu)
+{
+    int dev = 0, n_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n_cu <= 0)
+        n_cu = 256;
+    const int w = waves_per_cu > 0 ? waves_per_cu : 16;
+    const int b = n_cu * w / 4;
+    return b > 0 ? b : 1;
+}
+
 double lambda1_bounding_rect(const fk_domain &d)
 {
     const double a = d.x1 - d.x0, b = d.y1 - d.y0;
     return M_PI * M_PI * (1.0 / (a * a) + 1.0 / (b * b));
 }
 
-int32_t auto_paths_per_item(int64_t n_interior, int64_t M, int64_t target_items)
+int32_t auto_paths_per_item(int64_t n_interior, int64_t M)
 {
-    int64_t p = 4096;
-    while (p > 256 && n_interior * ((M + p - 1) / p) < target_items) p /= 2;
+    // Lanes stream across items, so items can be small; 256 paths (four per
+    // lane) keep the queue fine-grained without many fetches.  Fewer when an
+    // instance has too few paths in total to fill a few thousand items.
+    int64_t p = 256;
+    while (p > 64 && n_interior * ((M + p - 1) / p) < 4096) p /= 2;
     const int64_t mcap = ((M + 63) / 64) * 64;
     if (p > mcap) p = mcap;
+    (void)n_interior;
     return (int32_t)p;
 }
 
@@ -134,7 +151,7 @@ fk_status setup_problem(const fk_domain *domain, const fk_source *f, const fk_bc
     const fk_params &p = P.par;
     if (!std::isfinite(p.k) || p.k < 0.0) return fail(FK_EINVAL, "k must be finite and >= 0");
     if (!std::isfinite(p.h) || !(p.h > 0.0)) return fail(FK_EINVAL, "h must be > 0");
-    if (p.M < 2 || p.M > 0xFFFFFFFFll) return fail(FK_EINVAL, "M must be in [2, 2^32)");
+    if (p.M < 2 || p.M > (1ll << 20)) return fail(FK_EINVAL, "M must be in [2, 2^20]");
     if (p.precision != 32 && p.precision != 64) return fail(FK_EINVAL, "precision must be 32 or 64");
     if (p.max_steps < 0) return fail(FK_EINVAL, "max_steps must be >= 0");
     if (p.paths_per_item < 0 || p.paths_per_item % 64 != 0)
@@ -167,8 +184,33 @@ fk_status setup_problem(const fk_domain *domain, const fk_source *f, const fk_bc
             else host_bc(P, c == 2 ? P.inner : P.outer, x, y, P.grid0[2 * id], P.grid0[2 * id + 1]);
         }
     }
+    // Work order: nodes with the longest expected paths first, so that the
+    // last items of a launch have short paths and the lanes drain quickly at
+    // the end.  The proxy is the harmonic combination of the 1-D exit times
+    // (x - x0)(x1 - x)/2, (y - y0)(y1 - y)/2 and, with a hole, d_c L/2 for the
+    // distance d_c to the circle.  The order does not change any result: node
+    // sums are exact and independent of which path ran when.
+    {
+        std::vector<std::pair<double, int32_t>> key;
+        key.reserve(P.interior.size());
+        const double L = 0.5 * ((d.x1 - d.x0) + (d.y1 - d.y0));
+        for (int32_t id : P.interior) {
+            const double x = d.x0 + (double)(id % d.nx) * dx, y = d.y0 + (double)(id / d.nx) * dy;
+            double inv = 2.0 / ((x - d.x0) * (d.x1 - x)) + 2.0 / ((y - d.y0) * (d.y1 - y));
+            if (d.kind == FK_DOMAIN_RECT_MINUS_DISC) {
+                const double dc = std::sqrt((x - d.cx) * (x - d.cx) + (y - d.cy) * (y - d.cy)) - d.r;
+                inv += 2.0 / (dc * L);
+            }
+            key.emplace_back(1.0 / inv, id);
+        }
+        std::stable_sort(key.begin(), key.end(),
+                         [](const std::pair<double, int32_t> &a, const std::pair<double, int32_t> &b) {
+                             return a.first > b.first;
+                         });
+        for (size_t i = 0; i < key.size(); ++i) P.interior[i] = key[i].second;
+    }
     const int64_t nint = (int64_t)P.interior.size();
-    P.ppi = p.paths_per_item > 0 ? p.paths_per_item : auto_paths_per_item(nint, p.M, 12000);
+    P.ppi = p.paths_per_item > 0 ? p.paths_per_item : auto_paths_per_item(nint, p.M);
     P.items_per_node = (int32_t)((p.M + P.ppi - 1) / P.ppi);
     P.n_items = nint * P.items_per_node;
     return FK_OK;
@@ -183,7 +225,7 @@ size_t instance_bytes(const HostProblem &P)
     b += align256(nn * sizeof(double2));                 // u64
     b += align256(nn * sizeof(float2));                  // u32
     b += align256(P.interior.size() * sizeof(int32_t));  // nodes
-    b += align256((size_t)P.n_items * sizeof(fkd::Slot));
+    b += align256(P.interior.size() * sizeof(fkd::Slot));
     b += align256(nn * sizeof(double2));                 // se
     b += 2 * align256(nn * sizeof(int64_t));             // sum_j, capped
     b += align256(P.table.size() * sizeof(double));      // table
@@ -204,7 +246,7 @@ InstanceBuffers carve(const HostProblem &P, char *base)
     B.u64 = (double2 *)take(nn * sizeof(double2));
     B.u32 = (float2 *)take(nn * sizeof(float2));
     B.nodes = (int32_t *)take(P.interior.size() * sizeof(int32_t));
-    B.slots = (fkd::Slot *)take((size_t)P.n_items * sizeof(fkd::Slot));
+    B.slots = (fkd::Slot *)take(P.interior.size() * sizeof(fkd::Slot));
     B.se = (double2 *)take(nn * sizeof(double2));
     B.sum_j = (int64_t *)take(nn * sizeof(int64_t));
     B.capped = (int64_t *)take(nn * sizeof(int64_t));
@@ -290,6 +332,10 @@ fk_status upload_instance(const HostProblem &P, const InstanceBuffers &B, hipStr
         FK_HIP(hipMemcpyAsync(B.table, P.table.data(), P.table.size() * sizeof(double), hipMemcpyHostToDevice, s));
     std::vector<double> zeros(2 * nn, 0.0);
     std::vector<int64_t> zi(nn, 0);
+    std::vector<fkd::Slot> zs(P.interior.size());
+    std::memset(zs.data(), 0, zs.size() * sizeof(fkd::Slot));
+    if (!zs.empty())
+        FK_HIP(hipMemcpyAsync(B.slots, zs.data(), zs.size() * sizeof(fkd::Slot), hipMemcpyHostToDevice, s));
     FK_HIP(hipMemcpyAsync(B.se, zeros.data(), nn * sizeof(double2), hipMemcpyHostToDevice, s));
     FK_HIP(hipMemcpyAsync(B.sum_j, zi.data(), nn * sizeof(int64_t), hipMemcpyHostToDevice, s));
     FK_HIP(hipMemcpyAsync(B.capped, zi.data(), nn * sizeof(int64_t), hipMemcpyHostToDevice, s));

@@ -28,7 +28,7 @@ struct HostProblem {
     fk_params par{};
     std::vector<double> table;        // outer TABLE samples (re, im), copied
     std::vector<uint8_t> cls;         // 0 interior, 1 rectangle edge, 2 hole
-    std::vector<int32_t> interior;    // interior node ids, grid order
+    std::vector<int32_t> interior;    // interior node ids, longest expected paths first
     std::vector<double> grid0;        // initial grid (re, im): 0 interior, g elsewhere
     int64_t jmax = 0;
     int32_t ppi = 0;                  // paths per work item
@@ -64,9 +64,11 @@ fkd::Inst make_inst(const HostProblem &P, const InstanceBuffers &B);
 // fresh state (iteration 0, u_0 = 0) on stream s.
 fk_status upload_instance(const HostProblem &P, const InstanceBuffers &B, hipStream_t s);
 
-// Paths per work item when the caller leaves it to the library: the largest
-// of 4096, 2048, ... 256 that still yields at least target_items items.
-int32_t auto_paths_per_item(int64_t n_interior, int64_t M, int64_t target_items);
+// Paths per work item when the caller leaves it to the library.
+int32_t auto_paths_per_item(int64_t n_interior, int64_t M);
+
+// Resident waves of the path kernel: CUs x (waves per CU), in blocks of four.
+int path_kernel_blocks(int waves_per_cu);
 
 double lambda1_bounding_rect(const fk_domain &d);
 

@@ -1,10 +1,11 @@
 // fk_solver.cpp -- single-instance solver behind the C ABI.
 //
 // One fixed-point iteration u_n -> u_{n+1} (Sec. 1 eq. (1.4) with alpha = k^2)
-// is four launches on the solver's stream: reset of the status record, the
-// path kernel (one wavefront per (node, chunk) work item), the update kernel
-// (node statistics, new iterate, status) and the iteration-index advance;
-// then one 64-byte status copy to pinned host memory.  The host applies the
+// is four launches on the solver's stream: reset of the status record and the
+// queue head, the path kernel (waves pull (node, chunk) work items from a
+// one-instance queue), the update kernel (node statistics, new iterate,
+// status) and the iteration-index advance; then one 64-byte status copy to
+// pinned host memory.  The host applies the
 // sup-norm stopping rule (Sec. 3) and the divergence rule.
 #include <cmath>
 #include <cstring>
@@ -27,6 +28,9 @@ struct fk_solver {
     bool own_arena = false;
     InstanceBuffers B{};
     fkd::Inst *d_inst = nullptr;      // device copy of the instance record (in the arena)
+    fkd::EngineQueue *d_queue = nullptr;  // one-segment work queue (in the arena)
+    unsigned long long *d_head = nullptr; // queue head (in the arena)
+    int n_blocks = 0;
     fkd::DevState *h_status = nullptr;  // pinned
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double step_ms_total = 0.0;
@@ -36,7 +40,13 @@ struct fk_solver {
     fk_iter_report last{};
 };
 
-static size_t solver_bytes(const HostProblem &P) { return 256 + ((sizeof(fkd::Inst) + 255) & ~(size_t)255) + instance_bytes(P); }
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// arena: instance record | queue | head | instance buffers
+static size_t solver_bytes(const HostProblem &P)
+{
+    return align256(sizeof(fkd::Inst)) + align256(sizeof(fkd::EngineQueue)) + 256 + instance_bytes(P);
+}
 
 extern "C" {
 
@@ -88,9 +98,13 @@ fk_status fk_helmholtz_create(const fk_domain *domain, const fk_source *f, const
     }
     char *p = s->arena;
     s->d_inst = (fkd::Inst *)p;
-    p += (sizeof(fkd::Inst) + 255) & ~(size_t)255;
+    p += align256(sizeof(fkd::Inst));
+    s->d_queue = (fkd::EngineQueue *)p;
+    p += align256(sizeof(fkd::EngineQueue));
+    s->d_head = (unsigned long long *)p;
     p += 256;
     s->B = carve(s->P, p);
+    s->n_blocks = path_kernel_blocks(0);
     fkd::Inst D = make_inst(s->P, s->B);
     auto cleanup = [&](fk_status code) {
         fk_helmholtz_destroy(s);
@@ -103,6 +117,16 @@ fk_status fk_helmholtz_create(const fk_domain *domain, const fk_source *f, const
     if ((st = upload_instance(s->P, s->B, s->stream)) != FK_OK) return cleanup(st);
     if ((e = hipMemcpyAsync(s->d_inst, &D, sizeof(D), hipMemcpyHostToDevice, s->stream)) != hipSuccess)
         return cleanup(hip_fail(e, "hipMemcpyAsync(inst)"));
+    {
+        fkd::EngineQueue q;
+        std::memset(&q, 0, sizeof(q));
+        q.n_seg = 1;
+        q.seg_end[0] = s->P.n_items;
+        q.seg_inst[0] = 0;
+        if ((e = hipMemcpyAsync(s->d_queue, &q, sizeof(q), hipMemcpyHostToDevice, s->stream)) != hipSuccess ||
+            (e = hipStreamSynchronize(s->stream)) != hipSuccess)
+            return cleanup(hip_fail(e, "hipMemcpyAsync(queue)"));
+    }
     if ((e = hipStreamSynchronize(s->stream)) != hipSuccess) return cleanup(hip_fail(e, "hipStreamSynchronize"));
     *out = s;
     return FK_OK;
@@ -111,9 +135,9 @@ fk_status fk_helmholtz_create(const fk_domain *domain, const fk_source *f, const
 static fk_status run_one(fk_solver *s, fk_iter_report *rep)
 {
     const int prec = s->P.par.precision;
-    FK_HIP(fkk::launch_reset(s->d_inst, nullptr, 1, nullptr, nullptr, s->stream));
+    FK_HIP(fkk::launch_reset(s->d_inst, nullptr, 1, nullptr, s->d_head, s->stream));
     FK_HIP(hipEventRecord(s->ev0, s->stream));
-    FK_HIP(fkk::launch_paths(prec, s->d_inst, 0, s->P.n_items, s->stream));
+    FK_HIP(fkk::launch_stream(prec, s->d_inst, s->d_queue, s->d_head, s->n_blocks, s->stream));
     FK_HIP(hipEventRecord(s->ev1, s->stream));
     FK_HIP(fkk::launch_update(s->d_inst, nullptr, 1, nullptr, (int32_t)s->P.interior.size(), s->stream));
     FK_HIP(fkk::launch_advance(s->d_inst, nullptr, 1, nullptr, s->stream));

@@ -102,7 +102,7 @@ def test_engine_fp64_matches_oracle():
 def test_engine_memory_admission():
     # a pool too small for two large instances admits one, then the next after removal
     p = W.cavity_65().replace(M=256)
-    e = fkh.Engine(4, precision=64, max_grid_nodes=5000, max_items=5000, max_table=0, max_instance_nodes=4225)
+    e = fkh.Engine(4, precision=64, max_grid_nodes=5000, max_items=1 << 20, max_table=0, max_instance_nodes=4225)
     a = e.add(p)
     assert a is not None
     assert e.add(p) is None
