@@ -2,7 +2,7 @@
 
 Default workload (one GPU): the 65x65 unit-square cavity, plane-wave data
 theta = pi/6, k = 2, M = 4096 paths per node, h = 1e-4, FP64, one instance
-on the plain (non-persistent) path kernel.  A step is one fixed-point
+(the single-instance solver, no batching).  A step is one fixed-point
 iteration: Philox normals, Euler-Maruyama paths with exit test and boundary
 datum, the left-point integral of f - k^2 u_n with u_n interpolated from the
 device-resident grid, per-node reduction and the update of the iterate.
@@ -24,12 +24,15 @@ sys.path.insert(0, ROOT)
 
 # MI355X published peaks (vector ALU, non-sparse)
 PEAK_TFLOPS = {64: 78.6, 32: 157.3}
-# Algorithmic floating-point operations per path-step (FMA = 2, compare and
-# transcendental = 1) of the stepping loop with f = 0 and u_n interpolated:
-# uniforms 2, Box-Muller 3.5 (2 transcendentals + 1.5 mul), step 4, exit test
-# 4, cell location 8, complex bilinear lerps 18, integrand and accumulation 4;
-# the FP32 path adds 6 for the compensated (Kahan) integral.
-FLOPS_PER_STEP = {64: 44.0, 32: 50.0}
+# Algorithmic floating-point operations per path-step (FMA = 2, compare,
+# conversion and transcendental = 1) of the stepping loop with f = 0 and u_n
+# interpolated: two uniforms 4 (FP64: convert and scale each) or 2 (FP32: one
+# subtraction each), Box-Muller 7 (log, sqrt, cos, sin and 3 mul for one pair
+# of normals), step 4, exit test 4, cell location 10, complex bilinear lerps
+# 18, integrand 2, left-point sum 1 (FP64) or 1.5 (FP32: half an FP32 add for
+# the trip's two values, then half a conversion and half an FP64 add).
+FLOPS_PER_STEP = {64: 50.0, 32: 48.5}
+KERNEL = {64: "fk_stream_f64", 32: "fk_stream_f32"}
 
 
 def parse():
@@ -40,6 +43,7 @@ def parse():
     ap.add_argument("--k", type=float, default=2.0)
     ap.add_argument("--precision", type=int, default=64, choices=[32, 64])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extras", action="store_true", help="skip the FP32, batched and serving figures")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     return ap.parse_args()
 
@@ -72,6 +76,106 @@ def cpu_baseline(p, target_s):
     return dict(value=steps / t_used, unit="path-steps/s", cores=threads, kind="oracle",
                 sample="%d of %d interior nodes x M=%d paths, one iteration (u_n = exact wave), "
                        "%.3g path-steps in %.1f s" % (done, len(ids), p.M, steps, t_used))
+
+
+def fp32_same_config(k, steps):
+    """The same cavity on the FP32 path: path-steps/s and kernel time."""
+    import torch
+    from paper_2308_11469_amd import fkh
+    from paper_2308_11469_amd import workloads as W
+    s = fkh.Solver(W.cavity_65(k=k, precision=32))
+    s.iterate(2)
+    s.timing(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = [s.iterate(1) for _ in range(steps)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms, n = s.timing()
+    s.close()
+    steps_total = sum(r["path_steps"] for r in reps)
+    return dict(value=steps_total / wall, unit="path-steps/s", ms_per_step=wall / steps * 1e3,
+                kernel_ms_avg=ms / max(n, 1),
+                roofline_frac=FLOPS_PER_STEP[32] * steps_total / (ms / 1e3) / 1e12 / PEAK_TFLOPS[32])
+
+
+def batched_vs_plain(n_sub=16, ticks=2):
+    """Solves/s of the batched FP32 engine (one persistent launch per tick for
+    all instances) against the plain FP64 single-instance path (instances one
+    after another), on every 16th instance of the 256-rectangle workload, at
+    the same iterations (so the same estimator and RMS error up to FP32
+    rounding, which stays below 0.1 SE).  Timed: iterations 1..ticks after
+    the first (iteration 0 has no interpolation)."""
+    import numpy as np
+    import torch
+    from paper_2308_11469_amd import fkh
+    from paper_2308_11469_amd import workloads as W
+    probs = W.rect_batch(256)[::256 // n_sub]
+    nodes = sum(p.nx * p.ny for p in probs)
+    eng = fkh.Engine(len(probs), precision=32, max_grid_nodes=nodes + 4096, max_items=1 << 26,
+                     max_table=16, max_instance_nodes=max(p.nx * p.ny for p in probs))
+    slots = [eng.add(p) for p in probs]
+    eng.tick()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps_b = 0
+    for _ in range(ticks):
+        reps = eng.tick()
+        steps_b += sum(r["path_steps"] for r in reps.values())
+    torch.cuda.synchronize()
+    t_batched = (time.perf_counter() - t0) / ticks
+    err_b = []
+    for p, sl in zip(probs, slots):
+        u, _ = eng.get(sl)
+        err_b.append(np.sqrt(np.mean(np.abs(u - W.exact_solution(p))[1:-1, 1:-1] ** 2)))
+    eng.close()
+    t_plain = 0.0
+    steps_p = 0
+    err_p = []
+    for p in probs:
+        s = fkh.Solver(p.replace(precision=64))
+        s.iterate(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(ticks):
+            steps_p += s.iterate(1)["path_steps"]
+        torch.cuda.synchronize()
+        t_plain += (time.perf_counter() - t0) / ticks
+        u, _ = s.get()
+        err_p.append(np.sqrt(np.mean(np.abs(u - W.exact_solution(p))[1:-1, 1:-1] ** 2)))
+        s.close()
+    return dict(instances=len(probs), ticks_timed=ticks,
+                batched_fp32_s_per_iteration=t_batched, plain_fp64_s_per_iteration=t_plain,
+                solves_per_s_ratio=t_plain / t_batched,
+                batched_path_steps_per_s=steps_b / ticks / t_batched,
+                plain_path_steps_per_s=steps_p / ticks / t_plain,
+                rms_error_batched=float(np.mean(err_b)), rms_error_plain=float(np.mean(err_p)),
+                note="same iteration counts; iterations per solve are equal on both sides")
+
+
+def serving_window(n_requests=12):
+    """The scattering request stream (Poisson arrivals at 200/s, k ~ U[1,4],
+    grids 33..257, M 1024..8192, h = 1e-4, FP32) for its first n_requests
+    arrivals, through the continuous-batching loop; p50/p99 latency of the
+    completed requests and solves/s over the window."""
+    from paper_2308_11469_amd import fkh, serving
+    from paper_2308_11469_amd import workloads as W
+    arrivals, params = W.scatter_stream(n_requests)
+    reqs = []
+    for r, (t, q) in enumerate(zip(arrivals, params)):
+        p = W.scatter_problem(q["k"], q["theta"], q["N"], q["M"], q["seed"], precision=32)
+        reqs.append(serving.Request(r, t, p.replace(max_iters=12, tol=1e-3)))
+    eng = fkh.Engine(8, precision=32, max_grid_nodes=8 * 257 * 257, max_items=1 << 26,
+                     max_table=8 * 4 * 8192, max_instance_nodes=257 * 257)
+    srv = serving.Server(eng, keep_results=False)
+    t0 = time.perf_counter()
+    res = srv.run(reqs)
+    wall = time.perf_counter() - t0
+    eng.close()
+    out = serving.latency_summary(res, wall)
+    out.update(requests=n_requests, wall_s=wall, offered_rate_per_s=200.0,
+               ticks=srv.ticks, max_resident=max((t["resident"] for t in srv.tick_log), default=0))
+    return out
 
 
 def main():
@@ -133,17 +237,21 @@ def main():
         "dtype": "f64" if a.precision == 64 else "f32",
         "data": "synthetic",
         "config": {"workload": "unit-square cavity 65x65, plane wave theta=pi/6, k=%g, M=4096, h=1e-4, "
-                               "single instance, plain path kernel" % a.k,
+                               "single instance" % a.k,
                    "grid": [65, 65], "M": 4096, "h": 1e-4, "k": a.k, "precision": a.precision},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": None,
-                     "kernel": "fk_paths_kernel<%s>" % ("double" if a.precision == 64 else "float"),
+                     "kernel": KERNEL[a.precision],
                      "kernel_ms_avg": avg_kernel_s * 1e3, "flops_per_path_step": FLOPS_PER_STEP[a.precision]},
         "extra": {"solves_per_s": 1.0 / (ms_per_step / 1e3 * solve_iters),
                   "iterations_per_solve": solve_iters,
                   "rms_error_vs_exact": rms,
                   "path_steps_per_iteration": steps_total / a.steps},
     }
+    if not a.no_extras:
+        out["extra"]["fp32_same_config"] = fp32_same_config(a.k, 5)
+        out["extra"]["batched_fp32_vs_plain_fp64"] = batched_vs_plain()
+        out["extra"]["serving_scatter_window"] = serving_window()
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p, a.cpu_seconds)
     print(json.dumps(out), flush=True)

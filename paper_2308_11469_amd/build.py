@@ -21,6 +21,7 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
          # packed FP32 instructions stay off: scalar FP32 code only
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-I" + os.path.join(HERE, "..", "include")]
+FLAGS += os.environ.get("FK_HIPCC_FLAGS", "").split()   # extra compiler options
 
 
 def _compile(src):

@@ -75,11 +75,11 @@ struct Inst {
     int64_t M, jmax;
     uint32_t key0, key1;
     int32_t crn, ppi;                                // ppi: paths per item
-    int32_t items_per_node, pad1;
+    int32_t items_per_node, cells;                   // cells: u32 is the cell-major FP32 copy
     int64_t n_items;
     const int32_t *nodes;                            // interior node ids
     double2 *u64;                                    // iterate, FP64 master
-    float2 *u32;                                     // iterate, FP32 copy
+    float2 *u32;                                     // iterate, FP32 copy (row-major nodes, or cells)
     Slot *slots;                                     // one per interior node
     double2 *se;                                     // per grid node
     int64_t *node_sum_j, *node_capped;               // per grid node
@@ -147,37 +147,6 @@ __device__ __forceinline__ void normals(uint32_t ra, uint32_t rb, float &zx, flo
 }
 
 // ------------------------------------------------------------- geometry
-
-// Exit test on an FP64 point: outside the open rectangle, or in the closed disc.
-__device__ __forceinline__ bool outside64(const Inst &D, double x, double y)
-{
-    if (x <= D.x0 || x >= D.x1 || y <= D.y0 || y >= D.y1) return true;
-    if (D.disc) {
-        const double ex = x - D.cx, ey = y - D.cy;
-        return ex * ex + ey * ey <= D.r2;
-    }
-    return false;
-}
-
-// Exit test on an FP32 point.  For a binary32 x, x <= x0 exactly iff
-// x <= RD(x0) (x0 rounded down to binary32) and x >= x1 iff x >= RU(x1), so the
-// rectangle test in FP32 against the directed-rounded edges equals the exact
-// test against the FP64 edges.  The disc test runs in FP32 and falls back to
-// FP64 only within a thin band around the circle.
-__device__ __forceinline__ bool outside32(const Inst &D, float x, float y, float cxf, float cyf,
-                                          float r2f, float band)
-{
-    if (x <= D.x0_rd || x >= D.x1_ru || y <= D.y0_rd || y >= D.y1_ru) return true;
-    if (D.disc) {
-        const float ex = x - cxf, ey = y - cyf;
-        const float d = ex * ex + ey * ey - r2f;
-        if (d > band) return false;
-        if (d < -band) return true;
-        const double exd = (double)x - D.cx, eyd = (double)y - D.cy;
-        return exd * exd + eyd * eyd <= D.r2;
-    }
-    return false;
-}
 
 // Nearest boundary point of X (FP64).  Outside the rectangle: clamp (outer
 // part).  In the closed disc: radial projection onto the circle.  Inside the

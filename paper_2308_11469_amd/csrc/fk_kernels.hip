@@ -1,6 +1,6 @@
 // fk_kernels.hip -- HIP kernels of the Feynman-Kac Helmholtz path (gfx950).
 //
-//   fk_stream_kernel<R>       the paths: waves pull (instance, node, chunk)
+//   fk_stream_f32 / _f64      the paths: waves pull (instance, node, chunk)
 //                             items from a device queue until it is empty and
 //                             run their paths as one stream of lanes
 //   fk_update_kernel          node mean / variance from the node slots, the
@@ -18,24 +18,51 @@
 namespace fkd {
 
 // Per-precision constants of an instance, hoisted out of the stepping loop.
+// Everything the stepping loop reads is copied here once per instance, so the
+// loop touches no instance memory.
 template <class R> struct Consts {
     R x0, y0, idx, idy, sigma, k2;
+    R ex0, ex1, ey0, ey1;   // rectangle edges for the exit test (FP32: rounded outward)
     R cxf, cyf, r2f, band;
     R src_re, src_im, src_cx, src_cy, src_c;
     R pmax, qmax;       // largest cell index as R (nx - 2, ny - 2)
-    int nx;
     int jmax;
-    uint32_t row_bytes;  // bytes of one grid row in this precision
+    int disc, src_kind;
+    int cells;          // FP32 copy of u_n is cell-major
+    uint32_t key0, key1;
+    // Byte offset of cell (p, q)'s first 16-byte read is p * sx + q * sy; the
+    // second read is at + second.  Row-major nodes: the two reads are the
+    // cell's bottom and top rows (u00 u10 | u01 u11).  Cell-major (FP32 copy
+    // only): one 32-byte block per cell holding the same four corners in the
+    // same order, so both layouts fill the registers identically.
+    uint32_t sx, sy, second;
     __amdgpu_buffer_rsrc_t grid;   // buffer resource of the iterate grid
     __device__ explicit Consts(const Inst &D)
         : x0((R)D.x0), y0((R)D.y0), idx((R)D.idx), idy((R)D.idy), sigma((R)D.sigma), k2((R)D.k2),
           cxf((R)D.cx), cyf((R)D.cy), r2f((R)D.r2), band((R)(1e-5 * (D.r + 1.0))),
           src_re((R)D.src_re), src_im((R)D.src_im), src_cx((R)D.src_cx), src_cy((R)D.src_cy),
-          src_c((R)D.src_c), pmax((R)(D.nx - 2)), qmax((R)(D.ny - 2)), nx(D.nx), jmax((int)D.jmax),
-          row_bytes((uint32_t)D.nx * (uint32_t)(2 * sizeof(R)))
+          src_c((R)D.src_c), pmax((R)(D.nx - 2)), qmax((R)(D.ny - 2)), jmax((int)D.jmax),
+          disc(D.disc), src_kind(D.src_kind), cells(sizeof(R) == 4 && D.cells), key0(D.key0), key1(D.key1)
     {
-        // raw buffer over nx*ny complex values; dword 3 = 0x00020000 for gfx9-family
-        const uint32_t bytes = (uint32_t)D.nx * (uint32_t)D.ny * (uint32_t)(2 * sizeof(R));
+        if (sizeof(R) == 4) {
+            ex0 = (R)D.x0_rd; ex1 = (R)D.x1_ru; ey0 = (R)D.y0_rd; ey1 = (R)D.y1_ru;
+        } else {
+            ex0 = (R)D.x0; ex1 = (R)D.x1; ey0 = (R)D.y0; ey1 = (R)D.y1;
+        }
+        const uint32_t node_bytes = (uint32_t)(2 * sizeof(R));
+        uint32_t bytes;
+        if (cells) {
+            sx = 32u;
+            sy = 32u * (uint32_t)(D.nx - 1);
+            second = 16u;
+            bytes = sy * (uint32_t)(D.ny - 1);
+        } else {
+            sx = node_bytes;
+            sy = node_bytes * (uint32_t)D.nx;
+            second = sy;
+            bytes = sy * (uint32_t)D.ny;
+        }
+        // raw buffer over the grid; dword 3 = 0x00020000 for gfx9-family
         grid = __builtin_amdgcn_make_buffer_rsrc((void *)Grid<R>::ptr(D), (short)0, (int)bytes, 0x00020000);
     }
 };
@@ -52,13 +79,33 @@ template <class R> struct PathState {
 __device__ __forceinline__ double exp_src(double a) { return exp(a); }
 __device__ __forceinline__ float exp_src(float a) { return __builtin_amdgcn_exp2f(a * 1.44269504088896341f); }
 
-__device__ __forceinline__ bool is_out(const Inst &D, const Consts<double> &, double x, double y)
+// Exit test: outside the open rectangle, or in the closed disc.  FP64: the
+// same comparisons as the problem statement.  FP32: for a binary32 x,
+// x <= x0 exactly iff x <= RD(x0) (x0 rounded down to binary32) and x >= x1
+// iff x >= RU(x1), so comparing with the outward-rounded edges equals the
+// exact test against the FP64 edges; the disc test runs in FP32 and falls
+// back to FP64 only within a thin band around the circle.
+__device__ __forceinline__ bool is_out(const Inst &, const Consts<double> &K, double x, double y)
 {
-    return outside64(D, x, y);
+    if (x <= K.ex0 || x >= K.ex1 || y <= K.ey0 || y >= K.ey1) return true;
+    if (K.disc) {
+        const double ex = x - K.cxf, ey = y - K.cyf;
+        return ex * ex + ey * ey <= K.r2f;
+    }
+    return false;
 }
 __device__ __forceinline__ bool is_out(const Inst &D, const Consts<float> &K, float x, float y)
 {
-    return outside32(D, x, y, K.cxf, K.cyf, K.r2f, K.band);
+    if (x <= K.ex0 || x >= K.ex1 || y <= K.ey0 || y >= K.ey1) return true;
+    if (K.disc) {
+        const float ex = x - K.cxf, ey = y - K.cyf;
+        const float d = ex * ex + ey * ey - K.r2f;
+        if (d > K.band) return false;
+        if (d < -K.band) return true;
+        const double exd = (double)x - D.cx, eyd = (double)y - D.cy;
+        return exd * exd + eyd * eyd <= D.r2;
+    }
+    return false;
 }
 
 // Bilinear interpolation of u_n at (x, y): cell p = floor((x - x0)/dx)
@@ -69,92 +116,139 @@ __device__ __forceinline__ bool is_out(const Inst &D, const Consts<float> &K, fl
 __device__ __forceinline__ float clamp_cell(float v, float hi) { return __builtin_amdgcn_fmed3f(v, 0.0f, hi); }
 __device__ __forceinline__ double clamp_cell(double v, double hi) { return fmin(fmax(v, 0.0), hi); }
 
+template <class R> struct Cell {
+    R a, b;          // fractions within the cell
+    uint32_t off;    // byte offset of the cell's first read
+};
+
 template <class R>
-__device__ __forceinline__ void interp_u(const Consts<R> &K, R x, R y, R &vr, R &vi)
+__device__ __forceinline__ Cell<R> locate(const Consts<R> &K, R x, R y)
 {
     const R fx = (x - K.x0) * K.idx, fy = (y - K.y0) * K.idy;
     const R pf = clamp_cell(floor(fx), K.pmax);
     const R qf = clamp_cell(floor(fy), K.qmax);
-    const R a = fx - pf, b = fy - qf;
-    const uint32_t i00 = (uint32_t)pf + (uint32_t)K.nx * (uint32_t)qf;
-    R u00r, u00i, u10r, u10i, u01r, u01i, u11r, u11i;
-    if constexpr (sizeof(R) == 4) {
-        const uint32_t off = i00 * 8u;
-        const auto r0 = __builtin_amdgcn_raw_buffer_load_b128(K.grid, off, 0, 0);
-        const auto r1 = __builtin_amdgcn_raw_buffer_load_b128(K.grid, off + K.row_bytes, 0, 0);
-        u00r = __uint_as_float(r0[0]); u00i = __uint_as_float(r0[1]);
-        u10r = __uint_as_float(r0[2]); u10i = __uint_as_float(r0[3]);
-        u01r = __uint_as_float(r1[0]); u01i = __uint_as_float(r1[1]);
-        u11r = __uint_as_float(r1[2]); u11i = __uint_as_float(r1[3]);
-    } else {
-        const uint32_t off = i00 * 16u;
-        const auto a0 = __builtin_amdgcn_raw_buffer_load_b128(K.grid, off, 0, 0);
-        const auto a1 = __builtin_amdgcn_raw_buffer_load_b128(K.grid, off + 16u, 0, 0);
-        const auto b0 = __builtin_amdgcn_raw_buffer_load_b128(K.grid, off + K.row_bytes, 0, 0);
-        const auto b1 = __builtin_amdgcn_raw_buffer_load_b128(K.grid, off + K.row_bytes + 16u, 0, 0);
-        auto d = [](uint32_t lo, uint32_t hi) {
-            return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
-        };
-        u00r = d(a0[0], a0[1]); u00i = d(a0[2], a0[3]);
-        u10r = d(a1[0], a1[1]); u10i = d(a1[2], a1[3]);
-        u01r = d(b0[0], b0[1]); u01i = d(b0[2], b0[3]);
-        u11r = d(b1[0], b1[1]); u11i = d(b1[2], b1[3]);
-    }
-    const R lr0 = u00r + a * (u10r - u00r), li0 = u00i + a * (u10i - u00i);
-    const R lr1 = u01r + a * (u11r - u01r), li1 = u01i + a * (u11i - u01i);
-    vr = lr0 + b * (lr1 - lr0);
-    vi = li0 + b * (li1 - li0);
+    return Cell<R>{fx - pf, fy - qf, (uint32_t)pf * K.sx + (uint32_t)qf * K.sy};
 }
 
-// integrand f - k^2 I_h[u_n] at the current point
 template <class R>
-__device__ __forceinline__ void rhs(const Inst &D, const Consts<R> &K, R x, R y, bool use_u, R &fr, R &fi)
+__device__ __forceinline__ void lerp(const Cell<R> &c, R u00r, R u00i, R u10r, R u10i, R u01r, R u01i, R u11r,
+                                     R u11i, R &vr, R &vi)
 {
-    fr = (R)0;
-    fi = (R)0;
-    if (D.src_kind == SRC_CONST) {
+    const R lr0 = u00r + c.a * (u10r - u00r), li0 = u00i + c.a * (u10i - u00i);
+    const R lr1 = u01r + c.a * (u11r - u01r), li1 = u01i + c.a * (u11i - u01i);
+    vr = lr0 + c.b * (lr1 - lr0);
+    vi = li0 + c.b * (li1 - li0);
+}
+
+__device__ __forceinline__ auto grid_load(const __amdgpu_buffer_rsrc_t &g, uint32_t off)
+{
+    return __builtin_amdgcn_raw_buffer_load_b128(g, off, 0, 0);
+}
+
+// u_n at two points.  FP32: two 16-byte reads per point (u00 u10 | u01 u11).
+// Large grids miss the vector L1 on nearly every read and the stepping loop is
+// then bound by the rate of L2 requests: the cell-major copy puts a cell's
+// two halves in one line, and issuing them back to back lets the second read
+// join the first one's miss, for one L2 request per step.  Keeping more reads
+// in flight, or waiting between the halves, was measured to cost more
+// requests (the line is evicted or not yet allocated).
+__device__ __forceinline__ void interp_pair(const Consts<float> &K, float x0, float y0, float x1, float y1,
+                                            float &v0r, float &v0i, float &v1r, float &v1i)
+{
+    const Cell<float> c0 = locate(K, x0, y0), c1 = locate(K, x1, y1);
+    // row-major: all four reads in flight at once (the grid is L1-resident
+    // where this layout is chosen); cell-major: the second point's reads
+    // wait for the first point's, so that each cell's two halves reach the
+    // vector L1 back to back and share one L2 request
+    uint32_t o1 = c1.off;
+    const auto a0 = grid_load(K.grid, c0.off);
+    const auto b0 = grid_load(K.grid, c0.off + K.second);
+    if (K.cells) asm volatile("" : "+v"(o1) : "v"(b0[0]));
+    const auto a1 = grid_load(K.grid, o1);
+    const auto b1 = grid_load(K.grid, o1 + K.second);
+    auto f = [](uint32_t w) { return __uint_as_float(w); };
+    lerp(c0, f(a0[0]), f(a0[1]), f(a0[2]), f(a0[3]), f(b0[0]), f(b0[1]), f(b0[2]), f(b0[3]), v0r, v0i);
+    lerp(c1, f(a1[0]), f(a1[1]), f(a1[2]), f(a1[3]), f(b1[0]), f(b1[1]), f(b1[2]), f(b1[3]), v1r, v1i);
+}
+
+// FP64: four 16-byte reads per point, two per row (u00 | u10 and u01 | u11).
+__device__ __forceinline__ void interp_pair(const Consts<double> &K, double x0, double y0, double x1, double y1,
+                                            double &v0r, double &v0i, double &v1r, double &v1i)
+{
+    auto d = [](uint32_t lo, uint32_t hi) {
+        return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+    };
+    const Cell<double> c[2] = {locate(K, x0, y0), locate(K, x1, y1)};
+    double v[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const auto a0 = grid_load(K.grid, c[i].off);
+        const auto a1 = grid_load(K.grid, c[i].off + 16u);
+        const auto b0 = grid_load(K.grid, c[i].off + K.second);
+        const auto b1 = grid_load(K.grid, c[i].off + K.second + 16u);
+        lerp(c[i], d(a0[0], a0[1]), d(a0[2], a0[3]), d(a1[0], a1[1]), d(a1[2], a1[3]), d(b0[0], b0[1]),
+             d(b0[2], b0[3]), d(b1[0], b1[1]), d(b1[2], b1[3]), v[i][0], v[i][1]);
+    }
+    v0r = v[0][0]; v0i = v[0][1];
+    v1r = v[1][0]; v1i = v[1][1];
+}
+
+// source f at a point (the caller branches on K.src_kind != SRC_ZERO)
+template <class R>
+__device__ __forceinline__ void source(const Consts<R> &K, R x, R y, R &fr, R &fi)
+{
+    if (K.src_kind == SRC_CONST) {
         fr = K.src_re;
         fi = K.src_im;
-    } else if (D.src_kind == SRC_GAUSSIAN) {
+    } else {
         const R ex = x - K.src_cx, ey = y - K.src_cy;
         const R e = exp_src(-K.src_c * (ex * ex + ey * ey));
         fr = K.src_re * e;
         fi = K.src_im * e;
     }
-    if (use_u) {
-        R vr, vi;
-        interp_u<R>(K, x, y, vr, vi);
-        fr -= K.k2 * vr;
-        fi -= K.k2 * vi;
-    }
 }
 
 // One Philox block = normals for two increments; takes up to two Euler steps.
-// Returns true when the path is finished (exited or capped).
+// Both points of the trip are computed first, so the gathers of u_n at the
+// two left points are in flight together and overlap the exit tests; the
+// second step counts only if the first did not end the path.  Returns true
+// when the path is finished (exited or capped).
+// The integrand f - k^2 I_h[u_n] is formed as -(k2u v) + f with k2u = k^2,
+// or 0 while u_n = 0 (n = 0): the gather then still runs but adds nothing,
+// so no lane-dependent branch separates the two gathers.
 template <class R>
 __device__ __forceinline__ bool advance(const Inst &D, const Consts<R> &K, PathState<R> &P, uint32_t m,
-                                        uint32_t node, uint32_t ctr3, bool use_u, bool &exited)
+                                        uint32_t node, uint32_t ctr3, R k2u, bool &exited)
 {
-    const uint4 w = philox4x32_10((uint32_t)(P.t >> 1), m, node, ctr3, D.key0, D.key1);
+    const uint4 w = philox4x32_10((uint32_t)(P.t >> 1), m, node, ctr3, K.key0, K.key1);
     R z0x, z0y, z1x, z1y;
     normals(w.x, w.y, z0x, z0y);
     normals(w.z, w.w, z1x, z1y);
-    R fr, fi;
-    rhs<R>(D, K, P.x, P.y, use_u, fr, fi);
-    P.x += K.sigma * z0x;
-    P.y += K.sigma * z0y;
-    P.t += 1;
-    exited = is_out(D, K, P.x, P.y);
-    if (!exited && P.t < K.jmax) {
-        R gr, gi;
-        rhs<R>(D, K, P.x, P.y, use_u, gr, gi);
+    const R x1 = P.x + K.sigma * z0x, y1 = P.y + K.sigma * z0y;
+    const R x2 = x1 + K.sigma * z1x, y2 = y1 + K.sigma * z1y;
+    R v0r, v0i, v1r, v1i;
+    interp_pair(K, P.x, P.y, x1, y1, v0r, v0i, v1r, v1i);
+    R fr = -(k2u * v0r), fi = -(k2u * v0i), gr = -(k2u * v1r), gi = -(k2u * v1i);
+    if (K.src_kind != SRC_ZERO) {
+        R sr, si;
+        source<R>(K, P.x, P.y, sr, si);
+        fr += sr;
+        fi += si;
+        source<R>(K, x1, y1, sr, si);
+        gr += sr;
+        gi += si;
+    }
+    const bool out1 = is_out(D, K, x1, y1);
+    const bool out2 = is_out(D, K, x2, y2);
+    const bool second = !out1 && P.t + 1 < K.jmax;
+    if (second) {
         fr += gr;
         fi += gi;
-        P.x += K.sigma * z1x;
-        P.y += K.sigma * z1y;
-        P.t += 1;
-        exited = is_out(D, K, P.x, P.y);
     }
+    P.x = second ? x2 : x1;
+    P.y = second ? y2 : y1;
+    P.t += second ? 2 : 1;
+    exited = second ? out2 : out1;
     P.ar += (double)fr;
     P.ai += (double)fi;
     return exited || P.t >= K.jmax;
@@ -313,9 +407,8 @@ __device__ __forceinline__ int32_t find_segment(const EngineQueue *Q, int32_t ns
 // an instance gives bit-identical results alone, in any batch and for any
 // item size.
 template <class R>
-__global__ void __launch_bounds__(256) fk_stream_kernel(const Inst *__restrict__ insts,
-                                                        const EngineQueue *__restrict__ Q,
-                                                        unsigned long long *head)
+__device__ __forceinline__ void stream_paths(const Inst *__restrict__ insts, const EngineQueue *__restrict__ Q,
+                                             unsigned long long *head)
 {
     __shared__ unsigned long long lds_acc[4][12];   // one node accumulator per wave
     unsigned long long *acc = lds_acc[threadIdx.x / kWave];
@@ -332,7 +425,7 @@ __global__ void __launch_bounds__(256) fk_stream_kernel(const Inst *__restrict__
         const int32_t inst = Q->seg_inst[seg];
         const Inst &D = insts[inst];
         const Consts<R> K(D);
-        const bool use_u = D.state->use_u != 0;
+        const R k2u = D.state->use_u != 0 ? K.k2 : (R)0;
         const uint32_t ctr3 = D.crn ? 0u : (uint32_t)D.state->iter;
 
         // wave-uniform pool: path indices [pool_m, pool_end) of one node
@@ -402,7 +495,7 @@ __global__ void __launch_bounds__(256) fk_stream_kernel(const Inst *__restrict__
             }
             if (__ballot(active) == 0ull) break;
             bool fin = false, exited = false;
-            if (active) fin = advance<R>(D, K, P, m, (uint32_t)node, ctr3, use_u, exited);
+            if (active) fin = advance<R>(D, K, P, m, (uint32_t)node, ctr3, k2u, exited);
             const unsigned long long done = __ballot(fin);
             if (done) {
                 // score the parked paths first when a finishing lane still
@@ -418,6 +511,27 @@ __global__ void __launch_bounds__(256) fk_stream_kernel(const Inst *__restrict__
         flush();
         flush_acc(D, acc, acc_node);
     }
+}
+
+// Occupancy targets (waves per SIMD) of the two path kernels; they bound the
+// registers the compiler may use.
+#ifndef FK_WAVES_F32
+#define FK_WAVES_F32 4
+#endif
+#ifndef FK_WAVES_F64
+#define FK_WAVES_F64 3
+#endif
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FK_WAVES_F32)))
+fk_stream_f32(const Inst *__restrict__ insts, const EngineQueue *__restrict__ Q, unsigned long long *head)
+{
+    stream_paths<float>(insts, Q, head);
+}
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FK_WAVES_F64)))
+fk_stream_f64(const Inst *__restrict__ insts, const EngineQueue *__restrict__ Q, unsigned long long *head)
+{
+    stream_paths<double>(insts, Q, head);
 }
 
 // Instance lists: `which` (device, optional) names the instances by index
@@ -480,7 +594,19 @@ __global__ void __launch_bounds__(256) fk_update_kernel(const Inst *__restrict__
         const double ser = sqrt(vr / Mf), sei = sqrt(vi / Mf);
         const double2 old = use_u ? D.u64[node] : make_double2(0.0, 0.0);
         D.u64[node] = make_double2(mr, mi);
-        D.u32[node] = make_float2((float)mr, (float)mi);
+        const float2 v32 = make_float2((float)mr, (float)mi);
+        if (D.cells) {
+            // an interior node is a corner of the four cells around it:
+            // corner index 0..3 = (p,q), (p+1,q), (p,q+1), (p+1,q+1)
+            const int i = node % D.nx, j = node / D.nx, cw = D.nx - 1;
+            float2 *c = D.u32;
+            c[4 * ((i - 1) + cw * (j - 1)) + 3] = v32;
+            c[4 * (i + cw * (j - 1)) + 2] = v32;
+            c[4 * ((i - 1) + cw * j) + 1] = v32;
+            c[4 * (i + cw * j) + 0] = v32;
+        } else {
+            D.u32[node] = v32;
+        }
         D.se[node] = make_double2(ser, sei);
         D.node_sum_j[node] = sj;
         D.node_capped[node] = nc;
@@ -568,7 +694,7 @@ __global__ void fk_debug_paths_kernel(const Inst *__restrict__ inst, const int32
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const Inst &D = *inst;
     const Consts<R> K(D);
-    const bool use_u = D.state->use_u != 0;
+    const R k2u = D.state->use_u != 0 ? K.k2 : (R)0;
     const uint32_t ctr3 = D.crn ? 0u : (uint32_t)D.state->iter;
     if (i >= n) return;
     const int32_t node = nodes[i];
@@ -576,7 +702,7 @@ __global__ void fk_debug_paths_kernel(const Inst *__restrict__ inst, const int32
     PathState<R> P;
     start(P, (R)(D.x0 + (double)gi * D.dx), (R)(D.y0 + (double)gj * D.dy));
     bool exited = false;
-    while (!advance<R>(D, K, P, (uint32_t)ms[i], (uint32_t)node, ctr3, use_u, exited)) {
+    while (!advance<R>(D, K, P, (uint32_t)ms[i], (uint32_t)node, ctr3, k2u, exited)) {
     }
     J[i] = P.t;
     Pending Q;
@@ -599,9 +725,9 @@ hipError_t launch_stream(int precision, const Inst *d_insts, const EngineQueue *
 {
     dim3 grid(n_blocks), block(256);
     if (precision == 32)
-        hipLaunchKernelGGL(fk_stream_kernel<float>, grid, block, 0, s, d_insts, Q, head);
+        hipLaunchKernelGGL(fk_stream_f32, grid, block, 0, s, d_insts, Q, head);
     else
-        hipLaunchKernelGGL(fk_stream_kernel<double>, grid, block, 0, s, d_insts, Q, head);
+        hipLaunchKernelGGL(fk_stream_f64, grid, block, 0, s, d_insts, Q, head);
     return hipGetLastError();
 }
 

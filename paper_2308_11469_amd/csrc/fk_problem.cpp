@@ -154,6 +154,8 @@ fk_status setup_problem(const fk_domain *domain, const fk_source *f, const fk_bc
     if (p.M < 2 || p.M > (1ll << 20)) return fail(FK_EINVAL, "M must be in [2, 2^20]");
     if (p.precision != 32 && p.precision != 64) return fail(FK_EINVAL, "precision must be 32 or 64");
     if (p.max_steps < 0) return fail(FK_EINVAL, "max_steps must be >= 0");
+    if (p.gather_layout < FK_GATHER_AUTO || p.gather_layout > FK_GATHER_CELLS)
+        return fail(FK_EINVAL, "gather_layout must be FK_GATHER_AUTO, _NODES or _CELLS");
     if (p.paths_per_item < 0 || p.paths_per_item % 64 != 0)
         return fail(FK_EINVAL, "paths_per_item must be 0 or a positive multiple of 64");
     if (p.max_iters < 0) return fail(FK_EINVAL, "max_iters must be >= 0");
@@ -209,6 +211,16 @@ fk_status setup_problem(const fk_domain *domain, const fk_source *f, const fk_bc
                          });
         for (size_t i = 0; i < key.size(); ++i) P.interior[i] = key[i].second;
     }
+    // The row-major FP32 copy is read as two 16-byte pieces of two rows per
+    // step: cheap while the whole grid stays in the 32 KiB vector L1 cache.
+    // Above that nearly every read misses to L2, and the cell-major copy
+    // halves the L2 requests per step.
+    if (p.gather_layout == FK_GATHER_CELLS) P.cells = 1;
+    else if (p.gather_layout == FK_GATHER_NODES) P.cells = 0;
+    else P.cells = p.precision == 32 && P.n_nodes() * 8 > kL1GatherBytes ? 1 : 0;
+    if (p.precision != 32) P.cells = 0;
+    if (P.cells && P.n_cells() * 32 >= ((size_t)1 << 31))
+        return fail(FK_EINVAL, "grid too large for the cell-major FP32 copy (2 GiB); use FK_GATHER_NODES");
     const int64_t nint = (int64_t)P.interior.size();
     P.ppi = p.paths_per_item > 0 ? p.paths_per_item : auto_paths_per_item(nint, p.M);
     P.items_per_node = (int32_t)((p.M + P.ppi - 1) / P.ppi);
@@ -223,7 +235,7 @@ size_t instance_bytes(const HostProblem &P)
     const size_t nn = P.n_nodes();
     size_t b = 0;
     b += align256(nn * sizeof(double2));                 // u64
-    b += align256(nn * sizeof(float2));                  // u32
+    b += align256(P.gather_floats() * sizeof(float));    // u32
     b += align256(P.interior.size() * sizeof(int32_t));  // nodes
     b += align256(P.interior.size() * sizeof(fkd::Slot));
     b += align256(nn * sizeof(double2));                 // se
@@ -244,7 +256,7 @@ InstanceBuffers carve(const HostProblem &P, char *base)
         return p;
     };
     B.u64 = (double2 *)take(nn * sizeof(double2));
-    B.u32 = (float2 *)take(nn * sizeof(float2));
+    B.u32 = (float2 *)take(P.gather_floats() * sizeof(float));
     B.nodes = (int32_t *)take(P.interior.size() * sizeof(int32_t));
     B.slots = (fkd::Slot *)take(P.interior.size() * sizeof(fkd::Slot));
     B.se = (double2 *)take(nn * sizeof(double2));
@@ -308,6 +320,7 @@ fkd::Inst make_inst(const HostProblem &P, const InstanceBuffers &B)
     D.crn = P.par.crn ? 1 : 0;
     D.ppi = P.ppi;
     D.items_per_node = P.items_per_node;
+    D.cells = P.cells;
     D.n_items = P.n_items;
     D.nodes = B.nodes;
     D.u64 = B.u64;
@@ -320,13 +333,33 @@ fkd::Inst make_inst(const HostProblem &P, const InstanceBuffers &B)
     return D;
 }
 
+void fp32_gather_grid(const HostProblem &P, const double *grid, std::vector<float> &out)
+{
+    const size_t nn = P.n_nodes();
+    out.resize(P.gather_floats());
+    if (!P.cells) {
+        for (size_t i = 0; i < 2 * nn; ++i) out[i] = (float)grid[i];
+        return;
+    }
+    const size_t nx = (size_t)P.dom.nx, ny = (size_t)P.dom.ny;
+    float *c = out.data();
+    for (size_t q = 0; q + 1 < ny; ++q)
+        for (size_t p = 0; p + 1 < nx; ++p) {
+            const size_t corner[4] = {p + nx * q, p + 1 + nx * q, p + nx * (q + 1), p + 1 + nx * (q + 1)};
+            for (int k = 0; k < 4; ++k) {
+                *c++ = (float)grid[2 * corner[k]];
+                *c++ = (float)grid[2 * corner[k] + 1];
+            }
+        }
+}
+
 fk_status upload_instance(const HostProblem &P, const InstanceBuffers &B, hipStream_t s)
 {
     const size_t nn = P.n_nodes();
-    std::vector<float> g32(2 * nn);
-    for (size_t i = 0; i < 2 * nn; ++i) g32[i] = (float)P.grid0[i];
+    std::vector<float> g32;
+    fp32_gather_grid(P, P.grid0.data(), g32);
     FK_HIP(hipMemcpyAsync(B.u64, P.grid0.data(), nn * sizeof(double2), hipMemcpyHostToDevice, s));
-    FK_HIP(hipMemcpyAsync(B.u32, g32.data(), nn * sizeof(float2), hipMemcpyHostToDevice, s));
+    FK_HIP(hipMemcpyAsync(B.u32, g32.data(), g32.size() * sizeof(float), hipMemcpyHostToDevice, s));
     FK_HIP(hipMemcpyAsync(B.nodes, P.interior.data(), P.interior.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     if (!P.table.empty())
         FK_HIP(hipMemcpyAsync(B.table, P.table.data(), P.table.size() * sizeof(double), hipMemcpyHostToDevice, s));

@@ -21,6 +21,13 @@ fk_status hip_fail(hipError_t e, const char *what);
         if (e_ != hipSuccess) return ::fkh::hip_fail(e_, #call);      \
     } while (0)
 
+// Largest row-major FP32 copy of u_n that the automatic gather layout keeps
+// row-major.  The vector L1 cache of a CU holds 32 KiB; measured on the
+// unit square (FP32, M = 1024), row-major is ahead up to 97x97 (75 KB:
+// 2.40e11 against 2.28e11 path-steps/s) and cell-major from 129x129 on
+// (257x257: 2.39e11 against 1.35e11).
+constexpr size_t kL1GatherBytes = 80 * 1024;
+
 struct HostProblem {
     fk_domain dom{};
     fk_source src{};
@@ -34,7 +41,11 @@ struct HostProblem {
     int32_t ppi = 0;                  // paths per work item
     int32_t items_per_node = 0;
     int64_t n_items = 0;
+    int32_t cells = 0;                // FP32 copy of u_n is cell-major
     size_t n_nodes() const { return (size_t)dom.nx * (size_t)dom.ny; }
+    size_t n_cells() const { return (size_t)(dom.nx - 1) * (size_t)(dom.ny - 1); }
+    // floats of the FP32 copy of the iterate
+    size_t gather_floats() const { return cells ? 8 * n_cells() : 2 * n_nodes(); }
 };
 
 // Validates and prepares a problem.  Returns FK_OK or FK_EINVAL (message set).
@@ -63,6 +74,10 @@ fkd::Inst make_inst(const HostProblem &P, const InstanceBuffers &B);
 // Uploads the initial grid (FP64 and FP32 copies), node list, table and a
 // fresh state (iteration 0, u_0 = 0) on stream s.
 fk_status upload_instance(const HostProblem &P, const InstanceBuffers &B, hipStream_t s);
+
+// The FP32 copy of a grid of complex values (re, im interleaved, row-major
+// nodes) in the instance's gather layout.
+void fp32_gather_grid(const HostProblem &P, const double *grid, std::vector<float> &out);
 
 // Paths per work item when the caller leaves it to the library.
 int32_t auto_paths_per_item(int64_t n_interior, int64_t M);

@@ -25,6 +25,7 @@ STATUS_NAMES = {0: "FK_OK", 1: "FK_EINVAL", 2: "FK_ENOMEM", 3: "FK_EDEVICE", 4: 
 _DOMAIN = {"rect": 0, "rect_minus_disc": 1}
 _SRC = {"zero": 0, "const": 1, "gaussian": 2}
 _BC = {"zero": 0, "plane_wave": 1, "bilinear": 2, "table": 3}
+GATHER = {"auto": 0, "nodes": 1, "cells": 2}   # layout of the FP32 copy of u_n (fk_gather_layout)
 
 
 class FkError(RuntimeError):
@@ -56,7 +57,7 @@ class fk_params(C.Structure):
     _fields_ = [("k", C.c_double), ("h", C.c_double), ("M", C.c_int64), ("seed", C.c_uint64),
                 ("precision", C.c_int32), ("max_iters", C.c_int32), ("tol", C.c_double),
                 ("max_steps", C.c_int64), ("crn", C.c_int32), ("g_unprojected", C.c_int32),
-                ("paths_per_item", C.c_int32), ("reserved", C.c_int32)]
+                ("paths_per_item", C.c_int32), ("gather_layout", C.c_int32)]
 
 
 class fk_iter_report(C.Structure):
@@ -151,7 +152,7 @@ def _dptr(a):
 class Marshalled:
     """C structs for one problem description (keeps the table alive)."""
 
-    def __init__(self, p, paths_per_item=0):
+    def __init__(self, p, paths_per_item=0, gather_layout="auto"):
         d = fk_domain()
         d.kind = _DOMAIN[p.domain_kind]
         d.nx, d.ny = int(p.nx), int(p.ny)
@@ -187,6 +188,7 @@ class Marshalled:
         par.crn = 1 if p.crn else 0
         par.g_unprojected = 1 if getattr(p, "g_unprojected", False) else 0
         par.paths_per_item = int(paths_per_item)
+        par.gather_layout = GATHER[gather_layout] if isinstance(gather_layout, str) else int(gather_layout)
         self.domain, self.source, self.outer, self.inner, self.params = d, f, bcs[0], bcs[1], par
 
     def args(self):
@@ -212,10 +214,10 @@ class Solver:
     memory is a PyTorch uint8 tensor (the arena); work runs on PyTorch's
     current HIP stream unless ``stream`` is given."""
 
-    def __init__(self, problem, paths_per_item=0, stream=None):
+    def __init__(self, problem, paths_per_item=0, stream=None, gather_layout="auto"):
         torch = _torch()
         self.problem = problem
-        self.m = Marshalled(problem, paths_per_item)
+        self.m = Marshalled(problem, paths_per_item, gather_layout)
         nbytes = C.c_size_t()
         _check(lib().fk_helmholtz_arena_bytes(C.byref(self.m.domain), C.byref(self.m.outer),
                                               C.byref(self.m.params), C.byref(nbytes)))
@@ -350,10 +352,10 @@ class Engine:
         except Exception:
             pass
 
-    def add(self, problem, paths_per_item=0):
+    def add(self, problem, paths_per_item=0, gather_layout="auto"):
         """Admits an instance; returns its slot, or None when no slot or no
         memory is free right now (FK_EBUSY / FK_ENOMEM)."""
-        m = Marshalled(problem, paths_per_item)
+        m = Marshalled(problem, paths_per_item, gather_layout)
         slot = C.c_int32(-1)
         st = _check(lib().fk_engine_add(self.h, *m.args(), C.byref(slot)), allow=(FK_EBUSY, FK_ENOMEM))
         if st != FK_OK:

@@ -81,6 +81,29 @@ def test_arena_size_grows_with_grid_and_paths(lib):
     assert a < b < c
 
 
+def test_gather_layout_sizes_and_validation(lib):
+    # FP32: cell-major copy is 32 B per cell instead of 8 B per node; FP64
+    # ignores the layout (its paths read the row-major FP64 master)
+    def size(p, layout):
+        m = fkh.Marshalled(p, 0, layout)
+        n = C.c_size_t()
+        st = lib.fk_helmholtz_arena_bytes(C.byref(m.domain), C.byref(m.outer), C.byref(m.params), C.byref(n))
+        return st, n.value
+    p32 = W.cavity_65(precision=32)
+    st_n, nodes = size(p32, "nodes")
+    st_c, cells = size(p32, "cells")
+    assert st_n == st_c == fkh.FK_OK
+    grow = 64 * 64 * 32 - 65 * 65 * 8
+    assert abs((cells - nodes) - grow) <= 256
+    assert size(p32, "auto")[1] == nodes            # 33.8 KB row-major copy fits L1
+    big = p32.replace(nx=129, ny=129)
+    assert size(big, "auto")[1] == size(big, "cells")[1] != size(big, "nodes")[1]
+    p64 = W.cavity_65(precision=64)
+    assert size(p64, "cells")[1] == size(p64, "nodes")[1]
+    for bad in (-1, 3):
+        assert size(p32, bad)[0] == fkh.FK_EINVAL
+
+
 def test_step_cap_overflow_rejected(lib):
     p = W.cavity_small().replace(h=1e-12)
     assert arena_status(p)[0] == fkh.FK_EINVAL
