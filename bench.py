@@ -45,7 +45,25 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP32, batched and serving figures")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run three device-to-device copies of MIB MiB (the reference kernel for "
+                         "scaling HBM byte counters) and exit")
     return ap.parse_args()
+
+
+def calibrate_copy(mib):
+    """Three plain device copies of mib MiB each: a profiler's FETCH_SIZE and
+    WRITE_SIZE for this copy kernel, against the mib MiB it must move each
+    way, give the factor that turns those counters into bytes."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.rand(n, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_mib": mib, "copies": 3, "bytes_read_per_copy": n * 4, "bytes_written_per_copy": n * 4}))
 
 
 def cpu_baseline(p, target_s):
@@ -184,6 +202,9 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % a.gpus, file=sys.stderr)
         sys.exit(2)
+    if a.calibrate_copy:
+        calibrate_copy(a.calibrate_copy)
+        return
     import numpy as np
     import torch
     from paper_2308_11469_amd import build, fkh

@@ -316,17 +316,27 @@ __device__ __forceinline__ unsigned long long contribution(int i, double2 sc, bo
     return (i & 1) ? lo : hi;
 }
 
-// Scores the parked paths of the wave and adds them to their node sums.
-// Paths of the wave's current node go into the wave's LDS accumulator (exact
-// 64-bit LDS atomics, no return); paths of older nodes, still in flight when
-// the wave moved on, go straight to their node slot in global memory.
-__device__ __forceinline__ void deposit_parked(const Inst &D, Pending &Q, unsigned long long *acc,
-                                               int32_t acc_node)
+// A wave's two LDS node accumulators: the node it takes paths from now and
+// the one before, whose long paths may still be running.  A new node reuses
+// the older accumulator after moving its sums to the node's slot.
+struct NodeAcc {
+    unsigned long long *buf[2];
+    int32_t node[2];
+    int cur;
+};
+
+// Scores the parked paths of the wave and adds them to their node sums:
+// exact 64-bit LDS atomics (no return) into the accumulator of the path's
+// node, or, for a path that outlived two node changes of its wave, straight
+// to the node's slot in global memory.
+__device__ __forceinline__ void deposit_parked(const Inst &D, Pending &Q, const NodeAcc &A)
 {
     if (Q.live) {
         const double2 sc = score(D, Q);
         const bool ok = fabs(sc.x) < 0x1p21 && fabs(sc.y) < 0x1p21;
-        unsigned long long *dst = Q.node_idx == acc_node ? acc : (unsigned long long *)(D.slots + Q.node_idx);
+        unsigned long long *dst = Q.node_idx == A.node[0]   ? A.buf[0]
+                                  : Q.node_idx == A.node[1] ? A.buf[1]
+                                                            : (unsigned long long *)(D.slots + Q.node_idx);
 #pragma unroll 1
         for (int i = 0; i < kSlotSums; ++i) {
             const unsigned long long v = contribution(i, sc, ok, Q.t, !Q.exited);
@@ -336,8 +346,8 @@ __device__ __forceinline__ void deposit_parked(const Inst &D, Pending &Q, unsign
     }
 }
 
-// Moves the wave's LDS accumulator into its node's slot (lane i < 11 posts
-// sum i) and clears it.
+// Moves one LDS accumulator into its node's slot (lane i < 11 posts sum i)
+// and clears it.
 __device__ __forceinline__ void flush_acc(const Inst &D, unsigned long long *acc, int32_t acc_node)
 {
     const int lane = threadIdx.x & (kWave - 1);
@@ -410,9 +420,11 @@ template <class R>
 __device__ __forceinline__ void stream_paths(const Inst *__restrict__ insts, const EngineQueue *__restrict__ Q,
                                              unsigned long long *head)
 {
-    __shared__ unsigned long long lds_acc[4][12];   // one node accumulator per wave
-    unsigned long long *acc = lds_acc[threadIdx.x / kWave];
-    if ((threadIdx.x & (kWave - 1)) < 12) acc[threadIdx.x & (kWave - 1)] = 0ull;
+    __shared__ unsigned long long lds_acc[4][2][12];   // two node accumulators per wave
+    NodeAcc A;
+    A.buf[0] = lds_acc[threadIdx.x / kWave][0];
+    A.buf[1] = lds_acc[threadIdx.x / kWave][1];
+    if ((threadIdx.x & (kWave - 1)) < 24) A.buf[0][threadIdx.x & (kWave - 1)] = 0ull;
     __builtin_amdgcn_wave_barrier();
     const int32_t nseg = Q->n_seg;
     const int64_t total = nseg > 0 ? Q->seg_end[nseg - 1] : 0;
@@ -431,7 +443,8 @@ __device__ __forceinline__ void stream_paths(const Inst *__restrict__ insts, con
         // wave-uniform pool: path indices [pool_m, pool_end) of one node
         int64_t pool_m = 0, pool_end = 0;
         int32_t pool_node_idx = 0, pool_node = 0;
-        int32_t acc_node = -1;   // node whose sums the LDS accumulator holds
+        A.node[0] = A.node[1] = -1;
+        A.cur = 0;
         R pool_sx = (R)0, pool_sy = (R)0;
         bool more = true;       // the queue may hold further items of this instance
         auto open_item = [&](int64_t gg) {
@@ -444,9 +457,11 @@ __device__ __forceinline__ void stream_paths(const Inst *__restrict__ insts, con
             const int32_t gi = pool_node % D.nx, gj = pool_node / D.nx;
             pool_sx = (R)(D.x0 + (double)gi * D.dx);
             pool_sy = (R)(D.y0 + (double)gj * D.dy);
-            if (pool_node_idx != acc_node) {
-                flush_acc(D, acc, acc_node);
-                acc_node = pool_node_idx;
+            if (pool_node_idx != A.node[A.cur]) {
+                const int v = 1 - A.cur;
+                flush_acc(D, A.buf[v], A.node[v]);
+                A.node[v] = pool_node_idx;
+                A.cur = v;
             }
         };
         open_item(g);
@@ -458,7 +473,7 @@ __device__ __forceinline__ void stream_paths(const Inst *__restrict__ insts, con
         bool active = false;
         int32_t node = 0, node_idx = 0;
         uint32_t m = 0;
-        auto flush = [&]() { deposit_parked(D, Qp, acc, acc_node); };
+        auto flush = [&]() { deposit_parked(D, Qp, A); };
 
         for (;;) {
             // give every idle lane the next path index, opening items as needed
@@ -509,7 +524,8 @@ __device__ __forceinline__ void stream_paths(const Inst *__restrict__ insts, con
             }
         }
         flush();
-        flush_acc(D, acc, acc_node);
+        flush_acc(D, A.buf[0], A.node[0]);
+        flush_acc(D, A.buf[1], A.node[1]);
     }
 }
 
