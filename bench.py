@@ -33,6 +33,34 @@ PEAK_TFLOPS = {64: 78.6, 32: 157.3}
 # the trip's two values, then half a conversion and half an FP64 add).
 FLOPS_PER_STEP = {64: 50.0, 32: 48.5}
 KERNEL = {64: "fk_stream_f64", 32: "fk_stream_f32"}
+# HBM bytes per launch of the path kernels from FETCH_SIZE / WRITE_SIZE
+# counters (scaled by a plain copy of known size), valid only for the kernel
+# sources they were taken on
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fk_stream_traffic.json")
+KERNEL_SOURCES = ["fk_kernels.hip", "fk_device.hpp", "fk_internal.hpp"]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2308_11469_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """Counter-derived HBM bytes per launch, or None when no measurement
+    exists for these kernel sources and this workload."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    if t.get("source_sha") != kernel_source_hash() or not k or k.get("workload") != workload:
+        return None
+    return k["bytes_per_launch"]
 
 
 def parse():
@@ -244,6 +272,8 @@ def main():
     ms_per_step = wall / a.steps * 1e3
     solve_iters = floor_iter if floor_iter else len(reports)
 
+    workload = ("unit-square cavity 65x65, plane wave theta=pi/6, k=%g, M=4096, h=1e-4, single instance"
+                % a.k)
     out = {
         "metric": "Brownian path-steps/s (Helmholtz solves/s at fixed RMS error reported alongside)",
         "value": value,
@@ -257,11 +287,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if a.precision == 64 else "f32",
         "data": "synthetic",
-        "config": {"workload": "unit-square cavity 65x65, plane wave theta=pi/6, k=%g, M=4096, h=1e-4, "
-                               "single instance" % a.k,
+        "config": {"workload": workload,
                    "grid": [65, 65], "M": 4096, "h": 1e-4, "k": a.k, "precision": a.precision},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak,
+                     "traffic": measured_traffic(KERNEL[a.precision], workload),
                      "kernel": KERNEL[a.precision],
                      "kernel_ms_avg": avg_kernel_s * 1e3, "flops_per_path_step": FLOPS_PER_STEP[a.precision]},
         "extra": {"solves_per_s": 1.0 / (ms_per_step / 1e3 * solve_iters),

@@ -137,10 +137,17 @@ __device__ __forceinline__ void normals(uint32_t ra, uint32_t rb, double &zx, do
 // FP32: 1 + (r >> 9) 2^-23 built from the bits, minus (1 - 2^-24), is the
 // same uniform exactly.  Hardware log2, sqrt, sin and cos; the sin/cos
 // instructions take their argument in revolutions, so 2 pi U needs no multiply.
+// The bit pattern 0x3f800000 | (r >> 9) is the funnel shift of 127 : r right
+// by 9 (one v_alignbit_b32).
+__device__ __forceinline__ float unit_interval_bits(uint32_t r)
+{
+    return __uint_as_float(__builtin_amdgcn_alignbit(127u, r, 9u));
+}
+
 __device__ __forceinline__ void normals(uint32_t ra, uint32_t rb, float &zx, float &zy)
 {
-    const float ua = __uint_as_float(0x3f800000u | (ra >> 9)) - 0x1.fffffep-1f;
-    const float ub = __uint_as_float(0x3f800000u | (rb >> 9)) - 0x1.fffffep-1f;
+    const float ua = unit_interval_bits(ra) - 0x1.fffffep-1f;
+    const float ub = unit_interval_bits(rb) - 0x1.fffffep-1f;
     const float rho = __builtin_amdgcn_sqrtf(-1.38629436111989061f * __builtin_amdgcn_logf(ua));
     zx = rho * __builtin_amdgcn_cosf(ub);
     zy = rho * __builtin_amdgcn_sinf(ub);

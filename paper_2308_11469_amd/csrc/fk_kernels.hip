@@ -127,7 +127,10 @@ __device__ __forceinline__ Cell<R> locate(const Consts<R> &K, R x, R y)
     const R fx = (x - K.x0) * K.idx, fy = (y - K.y0) * K.idy;
     const R pf = clamp_cell(floor(fx), K.pmax);
     const R qf = clamp_cell(floor(fy), K.qmax);
-    return Cell<R>{fx - pf, fy - qf, (uint32_t)pf * K.sx + (uint32_t)qf * K.sy};
+    // p, q < 2^24 and the strides < 2^24 (checked at set-up): full-rate
+    // 24-bit products
+    const uint32_t off = (uint32_t)__umul24((uint32_t)pf, K.sx) + (uint32_t)__umul24((uint32_t)qf, K.sy);
+    return Cell<R>{fx - pf, fy - qf, off};
 }
 
 template <class R>

@@ -134,6 +134,8 @@ fk_status setup_problem(const fk_domain *domain, const fk_source *f, const fk_bc
         return fail(FK_EINVAL, "rectangle needs finite x0 < x1 and y0 < y1");
     if (d.nx < 3 || d.ny < 3) return fail(FK_EINVAL, "nx and ny must be at least 3");
     if ((int64_t)d.nx * d.ny > (int64_t)1 << 26) return fail(FK_EINVAL, "grid too large (nx*ny > 2^26)");
+    // cell offsets are formed with 24-bit integer products
+    if (d.nx > (1 << 19) || d.ny >= (1 << 24)) return fail(FK_EINVAL, "nx must be <= 2^19 and ny < 2^24");
     if (d.kind == FK_DOMAIN_RECT_MINUS_DISC) {
         if (!finite_all({d.cx, d.cy, d.r}) || !(d.r > 0.0))
             return fail(FK_EINVAL, "disc needs a finite centre and r > 0");
