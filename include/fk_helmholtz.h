@@ -120,6 +120,10 @@ typedef struct {
     int32_t gather_layout; /* FP32 stepping: layout of the FP32 copy of u_n
                               that the paths read (fk_gather_layout); the
                               FP64 path always reads the row-major master  */
+    int32_t waves_per_cu;  /* single-instance solver: resident waves of the
+                              path kernel per CU, a multiple of 4 in [4, 32];
+                              0 = 16.  (The engine takes it from its config.) */
+    int32_t reserved;      /* must be 0 */
 } fk_params;
 
 /* Per-iteration report (after the iteration that produced u_n). */

@@ -156,6 +156,9 @@ fk_status setup_problem(const fk_domain *domain, const fk_source *f, const fk_bc
     if (p.M < 2 || p.M > (1ll << 20)) return fail(FK_EINVAL, "M must be in [2, 2^20]");
     if (p.precision != 32 && p.precision != 64) return fail(FK_EINVAL, "precision must be 32 or 64");
     if (p.max_steps < 0) return fail(FK_EINVAL, "max_steps must be >= 0");
+    if (p.waves_per_cu < 0 || p.waves_per_cu > 32 || p.waves_per_cu % 4 != 0)
+        return fail(FK_EINVAL, "waves_per_cu must be 0 or a multiple of 4 in [4, 32]");
+    if (p.reserved != 0) return fail(FK_EINVAL, "fk_params.reserved must be 0");
     if (p.gather_layout < FK_GATHER_AUTO || p.gather_layout > FK_GATHER_CELLS)
         return fail(FK_EINVAL, "gather_layout must be FK_GATHER_AUTO, _NODES or _CELLS");
     if (p.paths_per_item < 0 || p.paths_per_item % 64 != 0)

@@ -104,7 +104,7 @@ fk_status fk_helmholtz_create(const fk_domain *domain, const fk_source *f, const
     s->d_head = (unsigned long long *)p;
     p += 256;
     s->B = carve(s->P, p);
-    s->n_blocks = path_kernel_blocks(0);
+    s->n_blocks = path_kernel_blocks(s->P.par.waves_per_cu);
     fkd::Inst D = make_inst(s->P, s->B);
     auto cleanup = [&](fk_status code) {
         fk_helmholtz_destroy(s);

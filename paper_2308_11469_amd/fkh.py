@@ -57,7 +57,8 @@ class fk_params(C.Structure):
     _fields_ = [("k", C.c_double), ("h", C.c_double), ("M", C.c_int64), ("seed", C.c_uint64),
                 ("precision", C.c_int32), ("max_iters", C.c_int32), ("tol", C.c_double),
                 ("max_steps", C.c_int64), ("crn", C.c_int32), ("g_unprojected", C.c_int32),
-                ("paths_per_item", C.c_int32), ("gather_layout", C.c_int32)]
+                ("paths_per_item", C.c_int32), ("gather_layout", C.c_int32),
+                ("waves_per_cu", C.c_int32), ("reserved", C.c_int32)]
 
 
 class fk_iter_report(C.Structure):
@@ -152,7 +153,7 @@ def _dptr(a):
 class Marshalled:
     """C structs for one problem description (keeps the table alive)."""
 
-    def __init__(self, p, paths_per_item=0, gather_layout="auto"):
+    def __init__(self, p, paths_per_item=0, gather_layout="auto", waves_per_cu=0):
         d = fk_domain()
         d.kind = _DOMAIN[p.domain_kind]
         d.nx, d.ny = int(p.nx), int(p.ny)
@@ -189,6 +190,7 @@ class Marshalled:
         par.g_unprojected = 1 if getattr(p, "g_unprojected", False) else 0
         par.paths_per_item = int(paths_per_item)
         par.gather_layout = GATHER[gather_layout] if isinstance(gather_layout, str) else int(gather_layout)
+        par.waves_per_cu = int(waves_per_cu)
         self.domain, self.source, self.outer, self.inner, self.params = d, f, bcs[0], bcs[1], par
 
     def args(self):
@@ -214,10 +216,10 @@ class Solver:
     memory is a PyTorch uint8 tensor (the arena); work runs on PyTorch's
     current HIP stream unless ``stream`` is given."""
 
-    def __init__(self, problem, paths_per_item=0, stream=None, gather_layout="auto"):
+    def __init__(self, problem, paths_per_item=0, stream=None, gather_layout="auto", waves_per_cu=0):
         torch = _torch()
         self.problem = problem
-        self.m = Marshalled(problem, paths_per_item, gather_layout)
+        self.m = Marshalled(problem, paths_per_item, gather_layout, waves_per_cu)
         nbytes = C.c_size_t()
         _check(lib().fk_helmholtz_arena_bytes(C.byref(self.m.domain), C.byref(self.m.outer),
                                               C.byref(self.m.params), C.byref(nbytes)))

@@ -104,6 +104,17 @@ def test_gather_layout_sizes_and_validation(lib):
         assert size(p32, bad)[0] == fkh.FK_EINVAL
 
 
+@pytest.mark.parametrize("waves", [-4, 2, 6, 36])
+def test_waves_per_cu_validated(lib, waves):
+    m = fkh.Marshalled(W.cavity_small(), 0, "auto", waves)
+    n = C.c_size_t()
+    assert lib.fk_helmholtz_arena_bytes(C.byref(m.domain), C.byref(m.outer), C.byref(m.params),
+                                        C.byref(n)) == fkh.FK_EINVAL
+    m = fkh.Marshalled(W.cavity_small(), 0, "auto", 8)
+    assert lib.fk_helmholtz_arena_bytes(C.byref(m.domain), C.byref(m.outer), C.byref(m.params),
+                                        C.byref(n)) == fkh.FK_OK
+
+
 def test_step_cap_overflow_rejected(lib):
     p = W.cavity_small().replace(h=1e-12)
     assert arena_status(p)[0] == fkh.FK_EINVAL
