@@ -267,7 +267,8 @@ def main():
     ex = W.exact_solution(p)
     ids = np.nonzero(np.abs(se.ravel()) > 0)[0]
     rms = float(np.sqrt(np.mean(np.abs(u.ravel()[ids] - ex.ravel()[ids]) ** 2)))
-    floor_iter = next((r["n"] for r in reports if r["max_du"] < r["noise_floor"]), None)
+    from paper_2308_11469_amd import serving
+    floor_iter = next((r["n"] for r in reports if serving.settled(r)), None)
     s.close()
     ms_per_step = wall / a.steps * 1e3
     solve_iters = floor_iter if floor_iter else len(reports)

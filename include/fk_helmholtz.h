@@ -138,6 +138,11 @@ typedef struct {
     int64_t capped;        /* paths stopped by the step cap                    */
     int64_t nonfinite;     /* nodes whose estimate is not finite               */
     double step_ms;        /* device time of the path kernel (HIP events)      */
+    double noise_ratio;    /* mean over interior nodes of |u_n - u_{n-1}|^2 /
+                              (2 |SE_n|^2), each node's term capped at 4096:
+                              about 1/(1+rho) once the change is Monte Carlo
+                              noise alone (fresh paths), large while the
+                              iterate still contracts                       */
 } fk_iter_report;
 
 typedef struct fk_solver fk_solver;

@@ -251,8 +251,11 @@ def solve(p, max_iters=None, tol=None, nthreads=0, u0=None, n0=0, callback=None)
     the sup norm of the iterate and the change have grown by at least 25%
     (a contraction shrinks the change; the noise floor of fresh paths keeps
     both flat).  Also records the first iteration whose change is below the
-    noise floor 4 max SE.  Returns a dict with the final grid, per-node SE and
-    the per-iteration history."""
+    noise floor 4 max SE, and per iteration the noise ratio: the mean over
+    interior nodes of |u_{n+1} - u_n|^2 / (2 |SE|^2) (each term capped at
+    4096), which is about 1/(1+rho) once the change is the noise of fresh
+    paths alone.  Returns a dict with the final grid, per-node SE and the
+    per-iteration history."""
     max_iters = p.max_iters if max_iters is None else max_iters
     tol = p.tol if tol is None else tol
     ids = interior_ids(p)
@@ -275,7 +278,8 @@ def solve(p, max_iters=None, tol=None, nthreads=0, u0=None, n0=0, callback=None)
             back = hist[-5]
             diverging = sup >= 1.25 * back["sup"] and du >= 1.25 * back["max_du"]
         rec = dict(n=it, max_du=du, sup=sup, noise_floor=floor, sumJ=int(est["sumJ"].sum()),
-                   capped=int(est["capped"].sum()), diverging=bool(diverging))
+                   capped=int(est["capped"].sum()), diverging=bool(diverging),
+                   noise_ratio=noise_ratio(est["mean"] - old_int, se))
         hist.append(rec)
         if callback:
             callback(rec, new)
@@ -291,6 +295,18 @@ def solve(p, max_iters=None, tol=None, nthreads=0, u0=None, n0=0, callback=None)
     below = [h["n"] for h in hist if h["max_du"] < h["noise_floor"]]
     return dict(u=u, se=se_grid, history=hist, diverged=diverged,
                 noise_floor_iter=below[0] if below else None)
+
+
+def noise_ratio(du, se):
+    """Mean over nodes of min(|du|^2 / (2 |SE|^2), 4096), nodes with SE = 0
+    left out (0 when there are none).  du and se complex per node, se as
+    SE_re + i SE_im."""
+    du = np.asarray(du)
+    s2 = np.asarray(se).real ** 2 + np.asarray(se).imag ** 2
+    ok = (s2 > 0) & np.isfinite(np.abs(du))
+    if not ok.any():
+        return 0.0
+    return float(np.mean(np.minimum(np.abs(du[ok]) ** 2 / (2.0 * s2[ok]), 4096.0)))
 
 
 def threads() -> int:

@@ -58,7 +58,11 @@ struct DevState {
     unsigned long long path_steps;
     unsigned long long capped;
     unsigned long long nonfinite;
-    int32_t pad[2];
+    // sum over nodes of min(|du|^2 / (2 |SE|^2), 4096) in units of 2^-20
+    // (exact integers: independent of the order of addition), and the
+    // number of nodes with a non-zero SE
+    unsigned long long ratio_fx;
+    unsigned long long ratio_n;
 };
 
 // Everything a work item needs about its instance (device memory, read

@@ -341,6 +341,7 @@ fk_status fk_engine_tick(fk_engine *e, fk_iter_report *reports, uint8_t *active_
         r.capped = (int64_t)h.capped;
         r.nonfinite = (int64_t)h.nonfinite;
         r.step_ms = ms;
+    r.noise_ratio = h.ratio_n ? (double)h.ratio_fx * 0x1p-20 / (double)h.ratio_n : 0.0;
         bool div = !(std::isfinite(du) && std::isfinite(sup)) || r.nonfinite > 0;
         const size_t nh = S.hist_du.size();
         if (!div && nh >= 5) div = sup >= 1.25 * S.hist_sup[nh - 5] && du >= 1.25 * S.hist_du[nh - 5];

@@ -571,6 +571,8 @@ __global__ void fk_reset_kernel(const Inst *__restrict__ insts, const int32_t *_
     st->path_steps = 0ull;
     st->capped = 0ull;
     st->nonfinite = 0ull;
+    st->ratio_fx = 0ull;
+    st->ratio_n = 0ull;
 }
 
 __device__ __forceinline__ unsigned long long bits_of(double v)
@@ -592,7 +594,7 @@ __global__ void __launch_bounds__(256) fk_update_kernel(const Inst *__restrict__
     if ((int64_t)blockIdx.x * blockDim.x >= D.n_interior) return;
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     double du = 0.0, sup = 0.0, sem = 0.0;
-    long long sj = 0, nc = 0, nf = 0;
+    long long sj = 0, nc = 0, nf = 0, rq = 0, rn = 0;
     const bool use_u = D.state->use_u != 0;
     if (idx < D.n_interior) {
         const int32_t node = D.nodes[idx];
@@ -632,6 +634,13 @@ __global__ void __launch_bounds__(256) fk_update_kernel(const Inst *__restrict__
         du = hypot(mr - old.x, mi - old.y);
         sup = hypot(mr, mi);
         sem = hypot(ser, sei);
+        // change against its Monte Carlo noise: |du|^2 / (2 |SE|^2)
+        const double s2 = ser * ser + sei * sei;
+        const double d2 = (mr - old.x) * (mr - old.x) + (mi - old.y) * (mi - old.y);
+        if (s2 > 0.0 && isfinite(d2)) {
+            rq = (long long)(fmin(d2 / (2.0 * s2), 4096.0) * 0x1p20);
+            rn = 1;
+        }
         if (ovf != 0ull || !(isfinite(mr) && isfinite(mi))) {
             nf = 1;
             du = HUGE_VAL;
@@ -640,7 +649,7 @@ __global__ void __launch_bounds__(256) fk_update_kernel(const Inst *__restrict__
     }
     // block reduction: waves by shuffles, then across the block's waves
     __shared__ double r_du[4], r_sup[4], r_se[4];
-    __shared__ long long r_sj[4], r_nc[4], r_nf[4];
+    __shared__ long long r_sj[4], r_nc[4], r_nf[4], r_rq[4], r_rn[4];
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
         du = fmax(du, __shfl_xor(du, o, kWave));
@@ -649,18 +658,20 @@ __global__ void __launch_bounds__(256) fk_update_kernel(const Inst *__restrict__
         sj += __shfl_xor(sj, o, kWave);
         nc += __shfl_xor(nc, o, kWave);
         nf += __shfl_xor(nf, o, kWave);
+        rq += __shfl_xor(rq, o, kWave);
+        rn += __shfl_xor(rn, o, kWave);
     }
     const int w = threadIdx.x / kWave;
     if ((threadIdx.x & (kWave - 1)) == 0) {
         r_du[w] = du; r_sup[w] = sup; r_se[w] = sem;
-        r_sj[w] = sj; r_nc[w] = nc; r_nf[w] = nf;
+        r_sj[w] = sj; r_nc[w] = nc; r_nf[w] = nf; r_rq[w] = rq; r_rn[w] = rn;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         const int nw = blockDim.x / kWave;
         for (int i = 1; i < nw; ++i) {
             du = fmax(du, r_du[i]); sup = fmax(sup, r_sup[i]); sem = fmax(sem, r_se[i]);
-            sj += r_sj[i]; nc += r_nc[i]; nf += r_nf[i];
+            sj += r_sj[i]; nc += r_nc[i]; nf += r_nf[i]; rq += r_rq[i]; rn += r_rn[i];
         }
         DevState *st = D.state;
         atomicMax(&st->max_du, bits_of(du));
@@ -669,6 +680,8 @@ __global__ void __launch_bounds__(256) fk_update_kernel(const Inst *__restrict__
         atomicAdd(&st->path_steps, (unsigned long long)sj);
         atomicAdd(&st->capped, (unsigned long long)nc);
         atomicAdd(&st->nonfinite, (unsigned long long)nf);
+        atomicAdd(&st->ratio_fx, (unsigned long long)rq);
+        atomicAdd(&st->ratio_n, (unsigned long long)rn);
     }
 }
 

@@ -163,6 +163,7 @@ static fk_status run_one(fk_solver *s, fk_iter_report *rep)
     r.capped = (int64_t)h.capped;
     r.nonfinite = (int64_t)h.nonfinite;
     r.step_ms = ms;
+    r.noise_ratio = h.ratio_n ? (double)h.ratio_fx * 0x1p-20 / (double)h.ratio_n : 0.0;
     bool div = !(std::isfinite(du) && std::isfinite(sup)) || r.nonfinite > 0;
     const size_t nh = s->hist_du.size();
     if (!div && nh >= 5)

@@ -64,7 +64,8 @@ class fk_params(C.Structure):
 class fk_iter_report(C.Structure):
     _fields_ = [("n", C.c_int32), ("diverging", C.c_int32), ("max_du", C.c_double), ("sup", C.c_double),
                 ("max_se", C.c_double), ("noise_floor", C.c_double), ("path_steps", C.c_int64),
-                ("capped", C.c_int64), ("nonfinite", C.c_int64), ("step_ms", C.c_double)]
+                ("capped", C.c_int64), ("nonfinite", C.c_int64), ("step_ms", C.c_double),
+                ("noise_ratio", C.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -328,6 +329,7 @@ class Engine:
     def __init__(self, max_instances, precision=32, max_grid_nodes=1 << 22, max_items=1 << 22,
                  max_table=1 << 20, waves_per_cu=0, max_instance_nodes=0, stream=None):
         cfg = fk_engine_config()
+        self.max_instances = int(max_instances)
         cfg.max_instances = int(max_instances)
         cfg.precision = int(precision)
         cfg.max_grid_nodes = int(max_grid_nodes)

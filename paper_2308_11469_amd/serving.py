@@ -6,9 +6,19 @@ pool can hold their footprint (the engine answers FK_ENOMEM / FK_EBUSY
 otherwise and the request keeps waiting), so requests that arrive while
 others are on the GPU join the next tick and share its persistent launch.
 Each tick advances every resident instance by one fixed-point iteration
-(Sec. 1 eq. (1.4) with alpha = k^2); an instance retires when its change
-falls below max(tol, noise floor) (the sup-norm control of Sec. 3 meeting the
-Monte Carlo noise floor), when it diverges, or at max_iters.  Requests whose
+(Sec. 1 eq. (1.4) with alpha = k^2); an instance retires when its sup-norm
+change falls below tol (the control of Sec. 3), when the change is down to
+Monte Carlo noise (``settled``), when it diverges, or at max_iters.
+
+With fresh paths every iteration (Remark 2.1) the change never reaches a
+small tol: once the deterministic contraction has died out it is the noise
+of two independent estimates.  The engine reports R = mean over nodes of
+|du|^2 / (2 |SE|^2).  Noise alone (e_{n+1} = K e_n + xi, xi fresh each
+iteration) gives R between 1/(1 + rho) and 1 -- near 1 in practice, since
+independent per-node noise lies mostly in modes that K barely propagates --
+and a deterministic change d adds |d|^2 / (2 SE^2).  An instance settles
+when R < 9/8: the remaining deterministic change is below about half a
+standard error (root mean square over the nodes).  Requests whose
 predicted contraction ratio k^2 / lambda_1 is too close to one are rejected
 at admission: the iteration cannot converge there (Sec. 2.4).
 
@@ -81,6 +91,15 @@ def predicted_rho(p) -> float:
     return p.k ** 2 / lam
 
 
+SETTLE_RATIO = 1.125
+
+
+def settled(rep: dict) -> bool:
+    """The change of this iteration is down to Monte Carlo noise (see the
+    module docstring); never at the first iteration."""
+    return rep["n"] >= 2 and rep["noise_ratio"] < SETTLE_RATIO
+
+
 def exit_time_problem(p, M=1024):
     """The same domain and grid with k = 0, f = -1, g = 0: one Feynman-Kac
     step of it estimates E[tau] at every node (Remark 2.5), whose maximum gives
@@ -100,8 +119,14 @@ def kstar_cavity(exit_times: np.ndarray) -> float:
 class Request:
     rid: int
     arrival: float              # seconds after the start of the run
-    problem: object
+    problem: object             # or None with ``make`` given
     seed_note: str = ""
+    make: Optional[Callable[[], object]] = None   # builds the problem when first needed
+
+    def get_problem(self):
+        if self.problem is None and self.make is not None:
+            self.problem = self.make()
+        return self.problem
 
 
 @dataclass
@@ -128,12 +153,15 @@ class Server:
     remove) with a stream of requests in wall-clock time."""
 
     def __init__(self, engine, rho_max: float = 0.98, keep_results: bool = True,
-                 clock: Callable[[], float] = time.perf_counter, sleep: Callable[[float], None] = time.sleep):
+                 clock: Callable[[], float] = time.perf_counter, sleep: Callable[[float], None] = time.sleep,
+                 max_queue: Optional[int] = None, on_tick: Optional[Callable[[dict], None]] = None):
         self.engine = engine
         self.rho_max = rho_max
         self.keep = keep_results
         self.clock = clock
         self.sleep = sleep
+        self.max_queue = max_queue      # waiting requests beyond this are turned away (queue_full)
+        self.on_tick = on_tick
         self.ticks = 0
         self.tick_log: List[dict] = []
 
@@ -151,18 +179,23 @@ class Server:
                 i += 1
             if horizon is not None and now > horizon and not resident:
                 break
-            # admission between ticks: FIFO, skipping requests that do not fit yet
+            # admission between ticks: FIFO, skipping requests that do not fit
+            # yet (no scan while every engine slot is taken)
             still = []
-            for req in queue:
+            cap = getattr(self.engine, "max_instances", None)
+            for qi, req in enumerate(queue):
+                if cap is not None and len(resident) >= cap:
+                    still.extend(queue[qi:])
+                    break
                 res = results[req.rid]
                 if math.isnan(res.rho):
-                    res.rho = predicted_rho(req.problem)
+                    res.rho = predicted_rho(req.get_problem())
                 if res.rho >= self.rho_max:
                     res.outcome = "rejected"
                     res.completed = self.clock() - t0
                     continue
                 try:
-                    slot = self.engine.add(req.problem)
+                    slot = self.engine.add(req.get_problem())
                 except ValueError as ex:       # invalid problem description
                     res.outcome = "invalid: %s" % ex
                     res.completed = self.clock() - t0
@@ -178,6 +211,13 @@ class Server:
                 res.admitted = self.clock() - t0
                 res.admitted_tick = self.ticks
             queue = still
+            if self.max_queue is not None and len(queue) > self.max_queue:
+                # the waiting room is full: the latest arrivals are turned away
+                for req in queue[self.max_queue:]:
+                    res = results[req.rid]
+                    res.outcome = "queue_full"
+                    res.completed = self.clock() - t0
+                queue = queue[:self.max_queue]
             if not resident:
                 if i < len(pending):
                     wait = pending[i].arrival - (self.clock() - t0)
@@ -187,7 +227,10 @@ class Server:
             reps = self.engine.tick()
             self.ticks += 1
             now = self.clock() - t0
-            self.tick_log.append(dict(tick=self.ticks, t=now, resident=len(resident), queued=len(queue)))
+            self.tick_log.append(dict(tick=self.ticks, t=now, resident=len(resident), queued=len(queue),
+                                      arrived=i))
+            if self.on_tick is not None:
+                self.on_tick(self.tick_log[-1])
             for slot, rep in reps.items():
                 req = resident.get(slot)
                 if req is None:
@@ -195,11 +238,11 @@ class Server:
                 res = results[req.rid]
                 res.iterations = rep["n"]
                 res.path_steps += rep["path_steps"]
-                p = req.problem
+                p = req.get_problem()
                 done = None
                 if rep["diverging"]:
                     done = "diverged"
-                elif rep["max_du"] < max(p.tol, rep["noise_floor"]):
+                elif rep["max_du"] < p.tol or settled(rep):
                     done = "converged"
                 elif rep["n"] >= p.max_iters:
                     done = "max_iters"
@@ -213,11 +256,25 @@ class Server:
         return results
 
 
-def latency_summary(results: Dict[int, Result], wall: float) -> dict:
-    done = [r for r in results.values() if r.outcome in ("converged", "max_iters", "diverged")]
+def latency_summary(results: Dict[int, Result], wall: float, tick_log: Optional[List[dict]] = None) -> dict:
+    """Completed solves (converged, max_iters or diverged), their p50 / p99
+    latency, solves/s over the wall time, turned-away requests by reason and,
+    given the tick log, the growth of the waiting queue (requests per second,
+    least-squares slope while requests were still arriving)."""
+    vals = list(results.values())
+    done = [r for r in vals if r.outcome in ("converged", "max_iters", "diverged")]
     lat = np.array([r.latency for r in done]) if done else np.array([math.nan])
-    return dict(completed=len(done), rejected=sum(r.outcome == "rejected" for r in results.values()),
-                diverged=sum(r.outcome == "diverged" for r in results.values()),
-                p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
-                solves_per_s=len(done) / wall if wall > 0 else math.nan,
-                path_steps=int(sum(r.path_steps for r in done)))
+    out = dict(completed=len(done), rejected=sum(r.outcome == "rejected" for r in vals),
+               queue_full=sum(r.outcome == "queue_full" for r in vals),
+               too_large=sum(r.outcome == "too_large" for r in vals),
+               diverged=sum(r.outcome == "diverged" for r in vals),
+               max_iters=sum(r.outcome == "max_iters" for r in vals),
+               p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
+               solves_per_s=len(done) / wall if wall > 0 else math.nan,
+               path_steps=int(sum(r.path_steps for r in done)))
+    if tick_log:
+        last_arrival = max(r.arrival for r in vals)
+        pts = [(t["t"], t["queued"]) for t in tick_log if t["t"] <= last_arrival]
+        out["queue_growth_per_s"] = (float(np.polyfit([a for a, _ in pts], [b for _, b in pts], 1)[0])
+                                     if len(pts) >= 2 else None)
+    return out

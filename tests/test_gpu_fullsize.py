@@ -1,0 +1,120 @@
+"""Parity at the full sizes the benchmark, the batched engine and the serving
+loop run, in the same launch configuration (persistent stream kernel, the
+library's own item size and gather layout).
+
+The oracle cannot redo a whole iteration at these sizes, so it recomputes a
+seeded sample of nodes one by one from the same u_n: FP64 node means within
+1e-12 of the score scale, exit-step sums bit-exact.  The FP32 path is checked
+at every interior node against the FP64 path on the same streams and the
+same u_n: within 0.1 standard errors.
+"""
+import numpy as np
+import pytest
+
+from oracle import fkmc
+from paper_2308_11469_amd import fkh
+from paper_2308_11469_amd import workloads as W
+
+from gpu_util import assert_fp64_node_parity, interior_values, require_lib, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    require_lib()
+
+
+def sample(p, n, seed):
+    ids = fkmc.interior_ids(p)
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(ids, size=min(n, len(ids)), replace=False)).astype(np.int32)
+
+
+def oracle_sampled(p, s64, u_prev, it, n_nodes, label):
+    """s64 holds u_{it+1} computed from u_prev (None for u_0 = 0)."""
+    g, _ = s64.get()
+    sj, _ = s64.node_stats()
+    ids = sample(p, n_nodes, 100 + it)
+    orc = fkmc.fk_nodes(p, u_prev, it, ids)
+    say(label, "oracle nodes", len(ids))
+    assert_fp64_node_parity(g.ravel()[ids], sj[ids], orc, p.M, label=label)
+
+
+def fp32_within_tenth_se(p, g64, se64, g32, label):
+    d = np.abs(interior_values(p, g32) - interior_values(p, g64))
+    se = np.abs(interior_values(p, se64))
+    r = d / se
+    say(label, "FP32 vs FP64: max %.4f SE, rms %.4f SE over %d nodes" % (r.max(), np.sqrt(np.mean(r ** 2)), r.size))
+    assert np.all(d <= 0.1 * se)
+
+
+@pytest.mark.parametrize("k", [2.0, 4.0])
+def test_cavity65_fp64_bench_configuration(k):
+    # the benchmark's workload: 65x65, M = 4096, h = 1e-4, FP64
+    p = W.cavity_65(k=k, precision=64)
+    s = fkh.Solver(p)
+    s.iterate(1)
+    u1, _ = s.get()
+    s.iterate(1)
+    oracle_sampled(p, s, u1, 1, 24, "cavity65 k=%g" % k)
+    s.close()
+
+
+def test_gaussian_source_129_fp32_against_fp64_and_oracle():
+    # 129x129, complex Gaussian source, k = 3.5, M = 16384, h = 5e-5
+    p = W.cavity_source(precision=64)
+    s64 = fkh.Solver(p)
+    s32 = fkh.Solver(p.replace(precision=32))
+    prev = None
+    for it in range(2):
+        s64.iterate(1)
+        if it > 0:
+            s32.set_iterate(prev, it)
+        s32.iterate(1)
+        g64, se64 = s64.get()
+        g32, _ = s32.get()
+        fp32_within_tenth_se(p, g64, se64, g32, "source129 it %d" % it)
+        if it == 1:
+            oracle_sampled(p, s64, prev, 1, 12, "source129")
+        prev = g64
+    s64.close()
+    s32.close()
+
+
+def test_largest_batch_rectangle_engine_fp32():
+    # the largest-grid instance of the 256-rectangle batch (244 x 252) through
+    # the FP32 engine, against the FP64 solver and the oracle
+    p = W.rect_batch(256)[0]
+    assert (p.nx, p.ny) == (244, 252)
+    eng = fkh.Engine(1, precision=32, max_grid_nodes=p.nx * p.ny + 1024, max_items=1 << 24,
+                     max_table=16, max_instance_nodes=p.nx * p.ny)
+    slot = eng.add(p)
+    eng.tick()
+    g32, _ = eng.get(slot)
+    eng.close()
+    p64 = p.replace(precision=64)
+    s64 = fkh.Solver(p64)
+    s64.iterate(1)
+    g64, se64 = s64.get()
+    fp32_within_tenth_se(p64, g64, se64, g32, "rect000 it 0")
+    s64.iterate(1)
+    oracle_sampled(p64, s64, g64, 1, 8, "rect000")
+    s64.close()
+
+
+def test_scattering_257_fp32_against_fp64_and_oracle():
+    # a serving request at the largest grid: disc domain, outer data from the
+    # series table, M = 8192
+    p = W.scatter_problem(k=2.5, theta=0.3, N=257, M=8192, seed=5000, precision=64)
+    s64 = fkh.Solver(p)
+    s32 = fkh.Solver(p.replace(precision=32))
+    s64.iterate(1)
+    s32.iterate(1)
+    g64, se64 = s64.get()
+    g32, _ = s32.get()
+    fp32_within_tenth_se(p, g64, se64, g32, "scatter257 it 0")
+    s64.iterate(1)
+    oracle_sampled(p, s64, g64, 1, 8, "scatter257")
+    s64.close()
+    s32.close()

@@ -107,13 +107,18 @@ def test_node_estimates_fp64_per_iteration(name):
     ids = fkmc.interior_ids(p)
     u = None
     for it in range(3):
-        s.iterate(1)
+        rep = s.iterate(1)
         g, se = s.get()
         sj, cp = s.node_stats()
         orc = fkmc.fk_nodes(p, u, it)
         assert_fp64_node_parity(interior_values(p, g), sj[ids], orc, p.M, label="%s it %d" % (name, it))
         se_o = orc["se"]
         assert np.allclose(interior_values(p, se), se_o, rtol=1e-8, atol=1e-14)
+        # the reported noise ratio is the oracle's statistic of the GPU's own
+        # iterates, up to its 2^-20 fixed-point resolution per node
+        old = np.zeros(len(ids), complex) if u is None else interior_values(p, u)
+        r_host = fkmc.noise_ratio(interior_values(p, g) - old, interior_values(p, se))
+        assert abs(rep["noise_ratio"] - r_host) <= 2.0 ** -20 + 1e-12 * r_host, (rep["noise_ratio"], r_host)
         # the next oracle step starts from the GPU's iterate (same u_n on both sides)
         u = g
     s.close()

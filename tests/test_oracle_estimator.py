@@ -18,7 +18,11 @@ Each test checks the oracle against something other than itself:
   finite-difference solve on the BGK-enlarged square, and the sqrt(h) decay
   of the error against the exact plane wave;
 * Remark 2.1: the exit-time law does not depend on n; common random numbers
-  reproduce exit steps exactly.
+  reproduce exit steps exactly;
+* the noise ratio R = mean |du|^2 / (2 |SE|^2): fresh paths leave the
+  stationary noise of an AR(1) chain e_{n+1} = K e_n + xi, for which R lies
+  between 1/(1+rho) and 1; common random numbers leave no noise, and R falls
+  like rho^(2n).
 """
 import math
 
@@ -199,3 +203,18 @@ def test_divergence_flagged_above_kmax():
     # a convergent wavenumber under the same noise is not flagged
     ok = fkmc.solve(p.replace(k=4.0, crn=False, max_iters=40))
     assert not ok["diverged"] and len(ok["history"]) == 40
+
+
+def test_noise_ratio_follows_the_noise_model():
+    p = W.cavity_small().replace(k=3.0, M=500, max_iters=40)
+    d = cf.bgk_beta() * math.sqrt(2 * p.h)
+    rho_eff = 9.0 / cf.lambda1_rect(1 + 2 * d, 1 + 2 * d)
+    res = fkmc.solve(p)
+    R = np.array([h["noise_ratio"] for h in res["history"]])
+    assert R[0] > 100 and R[1] > 5          # the first changes are the contraction itself
+    tail = R[10:].mean()
+    assert 1 / (1 + rho_eff) - 0.05 < tail < 1.1, (tail, rho_eff)
+    # common random numbers: no fresh noise, the change contracts away
+    crn = fkmc.solve(p.replace(k=2.0, crn=True, max_iters=14))
+    Rc = [h["noise_ratio"] for h in crn["history"]]
+    assert Rc[-1] < 1e-6 and Rc[-1] < Rc[6] < Rc[2]

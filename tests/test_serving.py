@@ -25,8 +25,8 @@ class VirtualClock:
 
 class ScriptedEngine:
     """Slots and a byte pool like the real engine; each instance reports
-    max_du = 0.5^n and a noise floor of 0.01, so it converges after 7 ticks
-    unless max_iters stops it first.  A tick costs `dt` virtual seconds."""
+    max_du = 0.5^n and a noise ratio of 0.9 + 20 * 0.5^n, which settles
+    (below 9/8) after 7 ticks unless max_iters stops it first.  A tick costs `dt` virtual seconds."""
 
     def __init__(self, clock, slots=3, pool=10_000, dt=0.05):
         self.clock, self.slots, self.pool, self.dt = clock, slots, pool, dt
@@ -51,8 +51,8 @@ class ScriptedEngine:
         for s, (p, n) in list(self.res.items()):
             n += 1
             self.res[s] = (p, n)
-            out[s] = dict(n=n, max_du=0.5 ** n, noise_floor=0.01, diverging=int(p.k > 100),
-                          path_steps=1000)
+            out[s] = dict(n=n, max_du=0.5 ** n, noise_floor=0.01, noise_ratio=0.9 + 20 * 0.5 ** n,
+                          diverging=int(p.k > 100), path_steps=1000)
         return out
 
     def get(self, slot):
@@ -119,6 +119,30 @@ def test_too_large_and_rejected_by_rho():
     assert res[2].outcome == "converged"
 
 
+def test_bounded_queue_turns_away_and_reports_growth():
+    # 3 slots, queue of 2: of 10 simultaneous arrivals 3 are admitted, 2 wait,
+    # 5 are turned away at arrival; the waiting ones are served later
+    reqs = [req(i, 0.0) for i in range(10)]
+    clk = VirtualClock()
+    eng = ScriptedEngine(clk, slots=3)
+    ticks = []
+    srv = serving.Server(eng, clock=clk, sleep=clk.sleep, max_queue=2, on_tick=ticks.append)
+    res = srv.run(reqs)
+    out = [res[i].outcome for i in range(10)]
+    assert out.count("queue_full") == 5 and out.count("converged") == 5
+    assert all(res[i].outcome == "queue_full" for i in range(5, 10))
+    assert ticks == srv.tick_log and ticks[0]["arrived"] == 10
+    s = serving.latency_summary(res, wall=clk.t, tick_log=srv.tick_log)
+    assert s["queue_full"] == 5 and s["completed"] == 5
+    # a stream arriving faster than it is served: the queue grows
+    reqs = [req(i, 0.02 * i) for i in range(30)]
+    clk = VirtualClock()
+    srv = serving.Server(ScriptedEngine(clk, slots=1), clock=clk, sleep=clk.sleep)
+    res = srv.run(reqs)
+    s = serving.latency_summary(res, wall=clk.t, tick_log=srv.tick_log)
+    assert s["queue_growth_per_s"] > 10
+
+
 def test_max_iters_and_divergence_retire():
     reqs = [req(0, 0.0, max_iters=3)]
     srv, eng, res = run(reqs)
@@ -129,6 +153,12 @@ def test_max_iters_and_divergence_retire():
     srv.sleep = eng.clock.sleep
     out = srv.run([req(0, 0.0, k=200.0)])
     assert out[0].outcome == "diverged"
+
+
+def test_settled_rule():
+    assert not serving.settled(dict(n=1, noise_ratio=0.0))      # first change is the iterate itself
+    assert serving.settled(dict(n=2, noise_ratio=1.1))
+    assert not serving.settled(dict(n=5, noise_ratio=1.2))
 
 
 def test_predicted_rho_rectangle_and_disc():
