@@ -127,15 +127,79 @@ __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
 // U(r) = (2 (r >> 9) + 1) 2^-24 in (0, 1), exact in binary32 and binary64.
 // Box-Muller: z = sqrt(-2 ln U(ra)) (cos 2 pi U(rb), sin 2 pi U(rb)).
 
-__device__ __forceinline__ void normals(uint32_t ra, uint32_t rb, double &zx, double &zy)
+// FP64.  U = j 2^-24 with j = (r >> 8) | 1 odd, 1 <= j < 2^24, so ln U and
+// sincos(2 pi U) only ever see 2^23 arguments; two small tables in LDS (built
+// once per block by init_f64_tables) and short polynomials give them in far
+// fewer operations than the general library functions, to about 1 ulp.
+struct F64Tables {
+    double2 sc[512];   // (sin, cos)(pi i / 256)
+    double2 lg[256];   // (ln c, 1 / c) for c = (i + 128) / 256
+};
+
+// Every thread of the block calls this; the caller synchronises the block.
+__device__ __forceinline__ void init_f64_tables(F64Tables &T)
 {
-    const double ua = (double)((ra >> 8) | 1u) * 0x1p-24;
-    const double ub = (double)((rb >> 8) | 1u) * 0x1p-24;
-    const double rho = sqrt(-2.0 * log(ua));
-    double s, c;
-    sincospi(2.0 * ub, &s, &c);
-    zx = rho * c;
-    zy = rho * s;
+    for (int i = threadIdx.x; i < 512; i += blockDim.x) {
+        double sn, cs;
+        sincospi((double)i * 0x1p-8, &sn, &cs);
+        T.sc[i] = make_double2(sn, cs);
+    }
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) {
+        const double c = (double)(i + 128) * 0x1p-8;
+        T.lg[i] = make_double2(log(c), 1.0 / c);
+    }
+}
+
+// ln(j 2^-24).  j 2^-24 = 2^n y with y in [2/3, 4/3); y = c (1 + r) with
+// c = k/256 the table point nearest y, so |r| < 2^-9 / c < 0.003 and y - c is
+// exact; ln(1 + r) by its Taylor series to r^7 (the next term is below 1e-21).
+// Near U = 1 the table point is c = 1 (ln c = 0, n = 0) and ln U is ln(1 + r)
+// alone, without cancellation.  n ln 2 in two parts (Cody-Waite split: the
+// high part has trailing zero bits, so n * ln2_hi is exact).
+__device__ __forceinline__ double ln_uniform(uint32_t j, const F64Tables &T)
+{
+    int e = 31 - __clz((int)j);
+    double y = ldexp((double)j, -e);
+    if (y >= 4.0 / 3.0) {
+        y *= 0.5;
+        e += 1;
+    }
+    const int k = (int)(y * 256.0 + 0.5);
+    const double2 t = T.lg[k - 128];
+    const double r = (y - (double)k * 0x1p-8) * t.y;
+    double q = 1.0 / 7.0;
+    q = fma(r, q, -1.0 / 6.0);
+    q = fma(r, q, 1.0 / 5.0);
+    q = fma(r, q, -0.25);
+    q = fma(r, q, 1.0 / 3.0);
+    q = fma(r, q, -0.5);
+    const double l1p = fma(r, r * q, r);
+    const double n = (double)(e - 24);
+    const double ln2_hi = 6.93147180369123816490e-01, ln2_lo = 1.90821492927058770002e-10;
+    return fma(n, ln2_hi, fma(n, ln2_lo, t.x + l1p));
+}
+
+// (sin, cos)(pi j 2^-23) = (sin, cos)(pi (jh 2^-8 + x/pi)) with jh = j >> 15
+// from the table and x = pi (j mod 2^15) 2^-23 in [0, 0.0123): sin x to x^7
+// and cos x - 1 to x^6 (next terms below 2e-20), then the addition formulas.
+__device__ __forceinline__ void sincospi_uniform(uint32_t j, const F64Tables &T, double &sn, double &cs)
+{
+    const double2 t = T.sc[j >> 15];
+    const double x = (double)(j & 0x7FFFu) * 3.7450702829239286e-07;   // pi 2^-23
+    const double x2 = x * x;
+    const double s1 = fma(x * x2, fma(x2, fma(x2, -1.0 / 5040.0, 1.0 / 120.0), -1.0 / 6.0), x);
+    const double c1 = x2 * fma(x2, fma(x2, -1.0 / 720.0, 1.0 / 24.0), -0.5);
+    sn = fma(t.y, s1, fma(t.x, c1, t.x));
+    cs = fma(-t.x, s1, fma(t.y, c1, t.y));
+}
+
+__device__ __forceinline__ void normals(uint32_t ra, uint32_t rb, const F64Tables &T, double &zx, double &zy)
+{
+    const double rho = sqrt(-2.0 * ln_uniform((ra >> 8) | 1u, T));
+    double sn, cs;
+    sincospi_uniform((rb >> 8) | 1u, T, sn, cs);
+    zx = rho * cs;
+    zy = rho * sn;
 }
 
 // FP32: 1 + (r >> 9) 2^-23 built from the bits, minus (1 - 2^-24), is the
@@ -148,7 +212,9 @@ __device__ __forceinline__ float unit_interval_bits(uint32_t r)
     return __uint_as_float(__builtin_amdgcn_alignbit(127u, r, 9u));
 }
 
-__device__ __forceinline__ void normals(uint32_t ra, uint32_t rb, float &zx, float &zy)
+struct NoTables {};
+
+__device__ __forceinline__ void normals(uint32_t ra, uint32_t rb, const NoTables &, float &zx, float &zy)
 {
     const float ua = unit_interval_bits(ra) - 0x1.fffffep-1f;
     const float ub = unit_interval_bits(rb) - 0x1.fffffep-1f;

@@ -18,6 +18,17 @@
 namespace fkd {
 
 // Per-precision constants of an instance, hoisted out of the stepping loop.
+// The normals' lookup tables per precision (FP64 only; they live in LDS).
+template <class R> struct TablesOf { using type = F64Tables; };
+template <> struct TablesOf<float> { using type = NoTables; };
+
+// Builds the block's tables; every thread of the block must call it.
+template <class R> __device__ __forceinline__ void setup_tables(typename TablesOf<R>::type &T)
+{
+    if constexpr (sizeof(R) == 8) init_f64_tables(T);
+    __syncthreads();
+}
+
 // Everything the stepping loop reads is copied here once per instance, so the
 // loop touches no instance memory.
 template <class R> struct Consts {
@@ -30,6 +41,7 @@ template <class R> struct Consts {
     int disc, src_kind;
     int cells;          // FP32 copy of u_n is cell-major
     uint32_t key0, key1;
+    const typename TablesOf<R>::type *tab;   // the block's normals tables
     // Byte offset of cell (p, q)'s first 16-byte read is p * sx + q * sy; the
     // second read is at + second.  Row-major nodes: the two reads are the
     // cell's bottom and top rows (u00 u10 | u01 u11).  Cell-major (FP32 copy
@@ -37,12 +49,13 @@ template <class R> struct Consts {
     // same order, so both layouts fill the registers identically.
     uint32_t sx, sy, second;
     __amdgpu_buffer_rsrc_t grid;   // buffer resource of the iterate grid
-    __device__ explicit Consts(const Inst &D)
+    __device__ Consts(const Inst &D, const typename TablesOf<R>::type *T)
         : x0((R)D.x0), y0((R)D.y0), idx((R)D.idx), idy((R)D.idy), sigma((R)D.sigma), k2((R)D.k2),
           cxf((R)D.cx), cyf((R)D.cy), r2f((R)D.r2), band((R)(1e-5 * (D.r + 1.0))),
           src_re((R)D.src_re), src_im((R)D.src_im), src_cx((R)D.src_cx), src_cy((R)D.src_cy),
           src_c((R)D.src_c), pmax((R)(D.nx - 2)), qmax((R)(D.ny - 2)), jmax((int)D.jmax),
-          disc(D.disc), src_kind(D.src_kind), cells(sizeof(R) == 4 && D.cells), key0(D.key0), key1(D.key1)
+          disc(D.disc), src_kind(D.src_kind), cells(sizeof(R) == 4 && D.cells), key0(D.key0), key1(D.key1),
+          tab(T)
     {
         if (sizeof(R) == 4) {
             ex0 = (R)D.x0_rd; ex1 = (R)D.x1_ru; ey0 = (R)D.y0_rd; ey1 = (R)D.y1_ru;
@@ -225,8 +238,8 @@ __device__ __forceinline__ bool advance(const Inst &D, const Consts<R> &K, PathS
 {
     const uint4 w = philox4x32_10((uint32_t)(P.t >> 1), m, node, ctr3, K.key0, K.key1);
     R z0x, z0y, z1x, z1y;
-    normals(w.x, w.y, z0x, z0y);
-    normals(w.z, w.w, z1x, z1y);
+    normals(w.x, w.y, *K.tab, z0x, z0y);
+    normals(w.z, w.w, *K.tab, z1x, z1y);
     const R x1 = P.x + K.sigma * z0x, y1 = P.y + K.sigma * z0y;
     const R x2 = x1 + K.sigma * z1x, y2 = y1 + K.sigma * z1y;
     R v0r, v0i, v1r, v1i;
@@ -423,6 +436,8 @@ template <class R>
 __device__ __forceinline__ void stream_paths(const Inst *__restrict__ insts, const EngineQueue *__restrict__ Q,
                                              unsigned long long *head)
 {
+    __shared__ typename TablesOf<R>::type tables;
+    setup_tables<R>(tables);
     __shared__ unsigned long long lds_acc[4][2][12];   // two node accumulators per wave
     NodeAcc A;
     A.buf[0] = lds_acc[threadIdx.x / kWave][0];
@@ -439,7 +454,7 @@ __device__ __forceinline__ void stream_paths(const Inst *__restrict__ insts, con
         int32_t seg = find_segment(Q, nseg, g);
         const int32_t inst = Q->seg_inst[seg];
         const Inst &D = insts[inst];
-        const Consts<R> K(D);
+        const Consts<R> K(D, &tables);
         const R k2u = D.state->use_u != 0 ? K.k2 : (R)0;
         const uint32_t ctr3 = D.crn ? 0u : (uint32_t)D.state->iter;
 
@@ -710,10 +725,12 @@ __global__ void fk_debug_philox_kernel(uint32_t k0, uint32_t k1, const uint4 *__
 template <class R>
 __global__ void fk_debug_normals_kernel(const uint2 *__restrict__ words, int64_t n, double2 *__restrict__ z)
 {
+    __shared__ typename TablesOf<R>::type tables;
+    setup_tables<R>(tables);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     R zx, zy;
-    normals(words[i].x, words[i].y, zx, zy);
+    normals(words[i].x, words[i].y, tables, zx, zy);
     z[i] = make_double2((double)zx, (double)zy);
 }
 
@@ -723,9 +740,11 @@ __global__ void fk_debug_paths_kernel(const Inst *__restrict__ inst, const int32
                                       const int64_t *__restrict__ ms, int64_t n, long long *__restrict__ J,
                                       double2 *__restrict__ score_out, double2 *__restrict__ xj)
 {
+    __shared__ typename TablesOf<R>::type tables;
+    setup_tables<R>(tables);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const Inst &D = *inst;
-    const Consts<R> K(D);
+    const Consts<R> K(D, &tables);
     const R k2u = D.state->use_u != 0 ? K.k2 : (R)0;
     const uint32_t ctr3 = D.crn ? 0u : (uint32_t)D.state->iter;
     if (i >= n) return;
