@@ -95,12 +95,15 @@ typedef struct {
     int64_t table_len;
 } fk_bc;
 
-/* Layout of the FP32 copy of the iterate read by the bilinear gather.
- * NODES: row-major nodes, 8 B per node (the cell's two rows are two reads).
+/* Layout of the copy of the iterate read by the bilinear gather.
+ * NODES: row-major nodes (the cell's two rows are two cache lines); the
+ *        FP32 path reads an FP32 copy (8 B per node), the FP64 path the
+ *        FP64 master itself.
  * CELLS: per cell (p, q) the four corners u(p,q), u(p+1,q), u(p,q+1),
- *        u(p+1,q+1) in one 32-byte block, 32 B per cell (one read, 4x the
- *        bytes).  AUTO: NODES while the row-major copy fits the vector L1
- *        cache, CELLS above.  The interpolated values are identical. */
+ *        u(p+1,q+1) in one block: 32 B per cell (FP32) or 64 B (FP64), one
+ *        cache line per step, 4x the bytes.
+ * AUTO:  NODES while the row-major data fit the vector L1 cache (80 KiB),
+ *        CELLS above.  The interpolated values are identical. */
 typedef enum { FK_GATHER_AUTO = 0, FK_GATHER_NODES = 1, FK_GATHER_CELLS = 2 } fk_gather_layout;
 
 typedef struct {
@@ -117,9 +120,8 @@ typedef struct {
     int32_t crn;           /* 1: same paths every iteration (counter n -> 0)  */
     int32_t g_unprojected; /* verification variant: g at X_J itself           */
     int32_t paths_per_item;/* paths per wavefront work item; 0 = auto         */
-    int32_t gather_layout; /* FP32 stepping: layout of the FP32 copy of u_n
-                              that the paths read (fk_gather_layout); the
-                              FP64 path always reads the row-major master  */
+    int32_t gather_layout; /* layout of the copy of u_n that the paths read
+                              (fk_gather_layout)                           */
     int32_t waves_per_cu;  /* single-instance solver: resident waves of the
                               path kernel per CU, a multiple of 4 in [4, 32];
                               0 = 16.  (The engine takes it from its config.) */

@@ -6,9 +6,9 @@ iterates):
 
 - ``paths_per_item`` (P): paths per work item.  Small items balance better,
   large ones mean fewer queue fetches and fewer node-accumulator flushes;
-- ``gather_layout``: row-major or cell-major FP32 copy of u_n (FP32 only).
-  Row-major is cheaper while the grid stays in the vector L1 cache, cell-major
-  needs one L2 request per step instead of about two once it does not;
+- ``gather_layout``: row-major or cell-major copy of u_n.  Row-major is
+  cheaper while the grid stays in the vector L1 cache, cell-major needs one
+  L2 request per step instead of about two once it does not;
 - ``waves_per_cu``: resident waves of the persistent launch per CU.
 
 For a problem the tuner times one fixed-point iteration per candidate on a
@@ -28,15 +28,14 @@ from . import fkh
 PPI = (64, 128, 256, 512, 1024)
 AUTO = dict(paths_per_item=0, gather_layout="auto", waves_per_cu=0)   # the library's own choice
 WAVES = (8, 12, 16)
-LAYOUTS32 = ("nodes", "cells")
+LAYOUTS = ("nodes", "cells")
 
 
 def candidates(problem, ppi=PPI, waves=WAVES):
     """Every (paths_per_item, gather_layout, waves_per_cu) worth timing."""
     mcap = ((int(problem.M) + 63) // 64) * 64
     ps = [p for p in ppi if p <= mcap] or [64]
-    layouts = LAYOUTS32 if int(problem.precision) == 32 else ("nodes",)
-    return [dict(paths_per_item=p, gather_layout=l, waves_per_cu=w) for p in ps for l in layouts for w in waves]
+    return [dict(paths_per_item=p, gather_layout=l, waves_per_cu=w) for p in ps for l in LAYOUTS for w in waves]
 
 
 def shape_key(problem):

@@ -79,11 +79,14 @@ struct Inst {
     int64_t M, jmax;
     uint32_t key0, key1;
     int32_t crn, ppi;                                // ppi: paths per item
-    int32_t items_per_node, cells;                   // cells: u32 is the cell-major FP32 copy
+    int32_t items_per_node, cells;                   // cells: the gather copy is cell-major
+    int32_t prec, pad1;                              // 32 or 64: the instance's stepping precision
     int64_t n_items;
     const int32_t *nodes;                            // interior node ids
     double2 *u64;                                    // iterate, FP64 master
-    float2 *u32;                                     // iterate, FP32 copy (row-major nodes, or cells)
+    void *gather;                                    // copy of u_n the paths read: FP32 row-major nodes
+                                                     // or cells (FP32 path), FP64 cells (FP64 path with
+                                                     // cells); unused by the FP64 row-major path
     Slot *slots;                                     // one per interior node
     double2 *se;                                     // per grid node
     int64_t *node_sum_j, *node_capped;               // per grid node
@@ -312,11 +315,14 @@ __device__ __forceinline__ double2 exit_datum(const Inst &D, double x, double y,
 template <class R> struct Grid;
 template <> struct Grid<double> {
     using C2 = double2;
-    static __device__ __forceinline__ const double2 *ptr(const Inst &D) { return D.u64; }
+    static __device__ __forceinline__ const double2 *ptr(const Inst &D)
+    {
+        return D.cells ? (const double2 *)D.gather : D.u64;
+    }
 };
 template <> struct Grid<float> {
     using C2 = float2;
-    static __device__ __forceinline__ const float2 *ptr(const Inst &D) { return D.u32; }
+    static __device__ __forceinline__ const float2 *ptr(const Inst &D) { return (const float2 *)D.gather; }
 };
 
 }  // namespace fkd

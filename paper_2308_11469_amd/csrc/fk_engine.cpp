@@ -197,10 +197,10 @@ fk_status fk_engine_create(const fk_engine_config *cfg, void *hip_stream, fk_eng
     // largest interior count of one instance (sizes the update grid of the graph)
     e->max_interior_cap = cfg->max_instance_nodes > 0 ? cfg->max_instance_nodes : 257 * 257;
     const int32_t cap = cfg->max_instances;
-    // pool: per-node arrays (u64 16, FP32 copy up to 32 when cell-major,
-    // nodes 4, se 16, sum_j 8, capped 8, slot), tables, and 9 alignment
-    // paddings per instance
-    e->pool_bytes = (size_t)cfg->max_grid_nodes * (84 + sizeof(fkd::Slot)) + (size_t)cfg->max_table * 16 +
+    // pool: per-node arrays (u64 16, gather copy up to 64 when FP64
+    // cell-major, nodes 4, se 16, sum_j 8, capped 8, slot), tables, and 9
+    // alignment paddings per instance
+    e->pool_bytes = (size_t)cfg->max_grid_nodes * (116 + sizeof(fkd::Slot)) + (size_t)cfg->max_table * 16 +
                     (size_t)cap * 9 * 256;
     if ((err = hipStreamCreateWithFlags(&e->cap_stream, hipStreamNonBlocking)) != hipSuccess)
         return bail(hip_fail(err, "hipStreamCreateWithFlags"));

@@ -39,7 +39,7 @@ template <class R> struct Consts {
     R pmax, qmax;       // largest cell index as R (nx - 2, ny - 2)
     int jmax;
     int disc, src_kind;
-    int cells;          // FP32 copy of u_n is cell-major
+    int cells;          // the gather copy of u_n is cell-major
     uint32_t key0, key1;
     const typename TablesOf<R>::type *tab;   // the block's normals tables
     // Byte offset of cell (p, q)'s first 16-byte read is p * sx + q * sy; the
@@ -54,7 +54,7 @@ template <class R> struct Consts {
           cxf((R)D.cx), cyf((R)D.cy), r2f((R)D.r2), band((R)(1e-5 * (D.r + 1.0))),
           src_re((R)D.src_re), src_im((R)D.src_im), src_cx((R)D.src_cx), src_cy((R)D.src_cy),
           src_c((R)D.src_c), pmax((R)(D.nx - 2)), qmax((R)(D.ny - 2)), jmax((int)D.jmax),
-          disc(D.disc), src_kind(D.src_kind), cells(sizeof(R) == 4 && D.cells), key0(D.key0), key1(D.key1),
+          disc(D.disc), src_kind(D.src_kind), cells(D.cells), key0(D.key0), key1(D.key1),
           tab(T)
     {
         if (sizeof(R) == 4) {
@@ -65,9 +65,9 @@ template <class R> struct Consts {
         const uint32_t node_bytes = (uint32_t)(2 * sizeof(R));
         uint32_t bytes;
         if (cells) {
-            sx = 32u;
-            sy = 32u * (uint32_t)(D.nx - 1);
-            second = 16u;
+            sx = 4u * node_bytes;                 // one cell: four corners
+            sy = sx * (uint32_t)(D.nx - 1);
+            second = 2u * node_bytes;             // the top two corners
             bytes = sy * (uint32_t)(D.ny - 1);
         } else {
             sx = node_bytes;
@@ -187,26 +187,31 @@ __device__ __forceinline__ void interp_pair(const Consts<float> &K, float x0, fl
     lerp(c1, f(a1[0]), f(a1[1]), f(a1[2]), f(a1[3]), f(b1[0]), f(b1[1]), f(b1[2]), f(b1[3]), v1r, v1i);
 }
 
-// FP64: four 16-byte reads per point, two per row (u00 | u10 and u01 | u11).
+// FP64: four 16-byte reads per point, u00 | u10 at the cell offset and
+// u01 | u11 at + second (the next row, or the cell block's second half).
+// As for FP32, the cell-major copy keeps a cell in one line, and the second
+// point's reads wait for the first point's.
 __device__ __forceinline__ void interp_pair(const Consts<double> &K, double x0, double y0, double x1, double y1,
                                             double &v0r, double &v0i, double &v1r, double &v1i)
 {
     auto d = [](uint32_t lo, uint32_t hi) {
         return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
     };
-    const Cell<double> c[2] = {locate(K, x0, y0), locate(K, x1, y1)};
-    double v[2][2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const auto a0 = grid_load(K.grid, c[i].off);
-        const auto a1 = grid_load(K.grid, c[i].off + 16u);
-        const auto b0 = grid_load(K.grid, c[i].off + K.second);
-        const auto b1 = grid_load(K.grid, c[i].off + K.second + 16u);
-        lerp(c[i], d(a0[0], a0[1]), d(a0[2], a0[3]), d(a1[0], a1[1]), d(a1[2], a1[3]), d(b0[0], b0[1]),
-             d(b0[2], b0[3]), d(b1[0], b1[1]), d(b1[2], b1[3]), v[i][0], v[i][1]);
-    }
-    v0r = v[0][0]; v0i = v[0][1];
-    v1r = v[1][0]; v1i = v[1][1];
+    const Cell<double> c0 = locate(K, x0, y0), c1 = locate(K, x1, y1);
+    uint32_t o1 = c1.off;
+    const auto a00 = grid_load(K.grid, c0.off);
+    const auto a01 = grid_load(K.grid, c0.off + 16u);
+    const auto b00 = grid_load(K.grid, c0.off + K.second);
+    const auto b01 = grid_load(K.grid, c0.off + K.second + 16u);
+    if (K.cells) asm volatile("" : "+v"(o1) : "v"(b01[0]));
+    const auto a10 = grid_load(K.grid, o1);
+    const auto a11 = grid_load(K.grid, o1 + 16u);
+    const auto b10 = grid_load(K.grid, o1 + K.second);
+    const auto b11 = grid_load(K.grid, o1 + K.second + 16u);
+    lerp(c0, d(a00[0], a00[1]), d(a00[2], a00[3]), d(a01[0], a01[1]), d(a01[2], a01[3]), d(b00[0], b00[1]),
+         d(b00[2], b00[3]), d(b01[0], b01[1]), d(b01[2], b01[3]), v0r, v0i);
+    lerp(c1, d(a10[0], a10[1]), d(a10[2], a10[3]), d(a11[0], a11[1]), d(a11[2], a11[3]), d(b10[0], b10[1]),
+         d(b10[2], b10[3]), d(b11[0], b11[1]), d(b11[2], b11[3]), v1r, v1i);
 }
 
 // source f at a point (the caller branches on K.src_kind != SRC_ZERO)
@@ -630,18 +635,29 @@ __global__ void __launch_bounds__(256) fk_update_kernel(const Inst *__restrict__
         const double ser = sqrt(vr / Mf), sei = sqrt(vi / Mf);
         const double2 old = use_u ? D.u64[node] : make_double2(0.0, 0.0);
         D.u64[node] = make_double2(mr, mi);
-        const float2 v32 = make_float2((float)mr, (float)mi);
-        if (D.cells) {
-            // an interior node is a corner of the four cells around it:
-            // corner index 0..3 = (p,q), (p+1,q), (p,q+1), (p+1,q+1)
-            const int i = node % D.nx, j = node / D.nx, cw = D.nx - 1;
-            float2 *c = D.u32;
-            c[4 * ((i - 1) + cw * (j - 1)) + 3] = v32;
-            c[4 * (i + cw * (j - 1)) + 2] = v32;
-            c[4 * ((i - 1) + cw * j) + 1] = v32;
-            c[4 * (i + cw * j) + 0] = v32;
-        } else {
-            D.u32[node] = v32;
+        // the gather copy: an interior node is a corner of the four cells
+        // around it (corner index 0..3 = (p,q), (p+1,q), (p,q+1), (p+1,q+1))
+        const int gi = node % D.nx, gj = node / D.nx, cw = D.nx - 1;
+        const int c00 = 4 * (gi + cw * gj), c10 = 4 * ((gi - 1) + cw * gj);
+        const int c01 = 4 * (gi + cw * (gj - 1)), c11 = 4 * ((gi - 1) + cw * (gj - 1));
+        if (D.prec == 32) {
+            const float2 v32 = make_float2((float)mr, (float)mi);
+            float2 *c = (float2 *)D.gather;
+            if (D.cells) {
+                c[c11 + 3] = v32;
+                c[c01 + 2] = v32;
+                c[c10 + 1] = v32;
+                c[c00 + 0] = v32;
+            } else {
+                c[node] = v32;
+            }
+        } else if (D.cells) {
+            const double2 v64 = make_double2(mr, mi);
+            double2 *c = (double2 *)D.gather;
+            c[c11 + 3] = v64;
+            c[c01 + 2] = v64;
+            c[c10 + 1] = v64;
+            c[c00 + 0] = v64;
         }
         D.se[node] = make_double2(ser, sei);
         D.node_sum_j[node] = sj;

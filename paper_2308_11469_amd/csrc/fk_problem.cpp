@@ -220,12 +220,12 @@ fk_status setup_problem(const fk_domain *domain, const fk_source *f, const fk_bc
     // step: cheap while the whole grid stays in the 32 KiB vector L1 cache.
     // Above that nearly every read misses to L2, and the cell-major copy
     // halves the L2 requests per step.
+    const size_t node_bytes = p.precision == 32 ? 8 : 16;
     if (p.gather_layout == FK_GATHER_CELLS) P.cells = 1;
     else if (p.gather_layout == FK_GATHER_NODES) P.cells = 0;
-    else P.cells = p.precision == 32 && P.n_nodes() * 8 > kL1GatherBytes ? 1 : 0;
-    if (p.precision != 32) P.cells = 0;
-    if (P.cells && P.n_cells() * 32 >= ((size_t)1 << 31))
-        return fail(FK_EINVAL, "grid too large for the cell-major FP32 copy (2 GiB); use FK_GATHER_NODES");
+    else P.cells = P.n_nodes() * node_bytes > kL1GatherBytes ? 1 : 0;
+    if (P.cells && P.n_cells() * 4 * node_bytes >= ((size_t)1 << 31))
+        return fail(FK_EINVAL, "grid too large for the cell-major copy (2 GiB); use FK_GATHER_NODES");
     const int64_t nint = (int64_t)P.interior.size();
     P.ppi = p.paths_per_item > 0 ? p.paths_per_item : auto_paths_per_item(nint, p.M);
     P.items_per_node = (int32_t)((p.M + P.ppi - 1) / P.ppi);
@@ -240,7 +240,7 @@ size_t instance_bytes(const HostProblem &P)
     const size_t nn = P.n_nodes();
     size_t b = 0;
     b += align256(nn * sizeof(double2));                 // u64
-    b += align256(P.gather_floats() * sizeof(float));    // u32
+    b += align256(P.gather_bytes());                     // gather copy
     b += align256(P.interior.size() * sizeof(int32_t));  // nodes
     b += align256(P.interior.size() * sizeof(fkd::Slot));
     b += align256(nn * sizeof(double2));                 // se
@@ -261,7 +261,7 @@ InstanceBuffers carve(const HostProblem &P, char *base)
         return p;
     };
     B.u64 = (double2 *)take(nn * sizeof(double2));
-    B.u32 = (float2 *)take(P.gather_floats() * sizeof(float));
+    B.gather = take(P.gather_bytes());
     B.nodes = (int32_t *)take(P.interior.size() * sizeof(int32_t));
     B.slots = (fkd::Slot *)take(P.interior.size() * sizeof(fkd::Slot));
     B.se = (double2 *)take(nn * sizeof(double2));
@@ -329,7 +329,8 @@ fkd::Inst make_inst(const HostProblem &P, const InstanceBuffers &B)
     D.n_items = P.n_items;
     D.nodes = B.nodes;
     D.u64 = B.u64;
-    D.u32 = B.u32;
+    D.gather = B.gather;
+    D.prec = P.par.precision;
     D.slots = B.slots;
     D.se = B.se;
     D.node_sum_j = B.sum_j;
@@ -338,33 +339,45 @@ fkd::Inst make_inst(const HostProblem &P, const InstanceBuffers &B)
     return D;
 }
 
-void fp32_gather_grid(const HostProblem &P, const double *grid, std::vector<float> &out)
+void gather_copy(const HostProblem &P, const double *grid, std::vector<uint8_t> &out)
 {
-    const size_t nn = P.n_nodes();
-    out.resize(P.gather_floats());
+    out.assign(P.gather_bytes(), 0);
+    if (out.empty()) return;
+    const size_t nx = (size_t)P.dom.nx, ny = (size_t)P.dom.ny;
+    const bool f32 = P.par.precision == 32;
+    auto put = [&](size_t at, size_t node) {   // at: complex slot index in out
+        if (f32) {
+            float *f = (float *)out.data();
+            f[2 * at] = (float)grid[2 * node];
+            f[2 * at + 1] = (float)grid[2 * node + 1];
+        } else {
+            double *d = (double *)out.data();
+            d[2 * at] = grid[2 * node];
+            d[2 * at + 1] = grid[2 * node + 1];
+        }
+    };
     if (!P.cells) {
-        for (size_t i = 0; i < 2 * nn; ++i) out[i] = (float)grid[i];
+        for (size_t i = 0; i < nx * ny; ++i) put(i, i);
         return;
     }
-    const size_t nx = (size_t)P.dom.nx, ny = (size_t)P.dom.ny;
-    float *c = out.data();
+    // cell (p, q): corners u(p,q), u(p+1,q), u(p,q+1), u(p+1,q+1)
+    size_t at = 0;
     for (size_t q = 0; q + 1 < ny; ++q)
         for (size_t p = 0; p + 1 < nx; ++p) {
-            const size_t corner[4] = {p + nx * q, p + 1 + nx * q, p + nx * (q + 1), p + 1 + nx * (q + 1)};
-            for (int k = 0; k < 4; ++k) {
-                *c++ = (float)grid[2 * corner[k]];
-                *c++ = (float)grid[2 * corner[k] + 1];
-            }
+            put(at++, p + nx * q);
+            put(at++, p + 1 + nx * q);
+            put(at++, p + nx * (q + 1));
+            put(at++, p + 1 + nx * (q + 1));
         }
 }
 
 fk_status upload_instance(const HostProblem &P, const InstanceBuffers &B, hipStream_t s)
 {
     const size_t nn = P.n_nodes();
-    std::vector<float> g32;
-    fp32_gather_grid(P, P.grid0.data(), g32);
+    std::vector<uint8_t> g;
+    gather_copy(P, P.grid0.data(), g);
     FK_HIP(hipMemcpyAsync(B.u64, P.grid0.data(), nn * sizeof(double2), hipMemcpyHostToDevice, s));
-    FK_HIP(hipMemcpyAsync(B.u32, g32.data(), g32.size() * sizeof(float), hipMemcpyHostToDevice, s));
+    if (!g.empty()) FK_HIP(hipMemcpyAsync(B.gather, g.data(), g.size(), hipMemcpyHostToDevice, s));
     FK_HIP(hipMemcpyAsync(B.nodes, P.interior.data(), P.interior.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     if (!P.table.empty())
         FK_HIP(hipMemcpyAsync(B.table, P.table.data(), P.table.size() * sizeof(double), hipMemcpyHostToDevice, s));

@@ -21,8 +21,8 @@ fk_status hip_fail(hipError_t e, const char *what);
         if (e_ != hipSuccess) return ::fkh::hip_fail(e_, #call);      \
     } while (0)
 
-// Largest row-major FP32 copy of u_n that the automatic gather layout keeps
-// row-major.  The vector L1 cache of a CU holds 32 KiB; measured on the
+// Largest row-major copy of u_n (FP32 copy, or the FP64 master) that the
+// automatic gather layout keeps row-major.  The vector L1 cache of a CU holds 32 KiB; measured on the
 // unit square (FP32, M = 1024), row-major is ahead up to 97x97 (75 KB:
 // 2.40e11 against 2.28e11 path-steps/s) and cell-major from 129x129 on
 // (257x257: 2.39e11 against 1.35e11).
@@ -44,8 +44,14 @@ struct HostProblem {
     int32_t cells = 0;                // FP32 copy of u_n is cell-major
     size_t n_nodes() const { return (size_t)dom.nx * (size_t)dom.ny; }
     size_t n_cells() const { return (size_t)(dom.nx - 1) * (size_t)(dom.ny - 1); }
-    // floats of the FP32 copy of the iterate
-    size_t gather_floats() const { return cells ? 8 * n_cells() : 2 * n_nodes(); }
+    // bytes of the gather copy of the iterate: FP32 row-major 8 per node or
+    // cells 32 per cell; FP64 cells 64 per cell; none for FP64 row-major
+    // (those paths read the FP64 master)
+    size_t gather_bytes() const
+    {
+        if (par.precision == 32) return cells ? 32 * n_cells() : 8 * n_nodes();
+        return cells ? 64 * n_cells() : 0;
+    }
 };
 
 // Validates and prepares a problem.  Returns FK_OK or FK_EINVAL (message set).
@@ -60,7 +66,7 @@ size_t instance_bytes(const HostProblem &P);
 // fills the instance record; uploads nothing.
 struct InstanceBuffers {
     double2 *u64;
-    float2 *u32;
+    void *gather;
     int32_t *nodes;
     fkd::Slot *slots;
     double2 *se;
@@ -75,9 +81,10 @@ fkd::Inst make_inst(const HostProblem &P, const InstanceBuffers &B);
 // fresh state (iteration 0, u_0 = 0) on stream s.
 fk_status upload_instance(const HostProblem &P, const InstanceBuffers &B, hipStream_t s);
 
-// The FP32 copy of a grid of complex values (re, im interleaved, row-major
-// nodes) in the instance's gather layout.
-void fp32_gather_grid(const HostProblem &P, const double *grid, std::vector<float> &out);
+// The gather copy (bytes, gather_bytes() of them) of a grid of complex
+// values (re, im interleaved, row-major nodes) in the instance's precision
+// and layout.
+void gather_copy(const HostProblem &P, const double *grid, std::vector<uint8_t> &out);
 
 // Paths per work item when the caller leaves it to the library.
 int32_t auto_paths_per_item(int64_t n_interior, int64_t M);

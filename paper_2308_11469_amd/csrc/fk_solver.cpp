@@ -243,14 +243,14 @@ fk_status fk_helmholtz_set_iterate(fk_solver *s, const double *u_reim, int32_t n
             full[2 * i] = s->P.grid0[2 * i];
             full[2 * i + 1] = s->P.grid0[2 * i + 1];
         }
-    std::vector<float> f32;
-    fp32_gather_grid(s->P, full.data(), f32);
+    std::vector<uint8_t> gc;
+    gather_copy(s->P, full.data(), gc);
     fkd::DevState st;
     std::memset(&st, 0, sizeof(st));
     st.iter = n;
     st.use_u = 1;
     FK_HIP(hipMemcpyAsync(s->B.u64, full.data(), nn * sizeof(double2), hipMemcpyHostToDevice, s->stream));
-    FK_HIP(hipMemcpyAsync(s->B.u32, f32.data(), f32.size() * sizeof(float), hipMemcpyHostToDevice, s->stream));
+    if (!gc.empty()) FK_HIP(hipMemcpyAsync(s->B.gather, gc.data(), gc.size(), hipMemcpyHostToDevice, s->stream));
     FK_HIP(hipMemcpyAsync(s->B.state, &st, sizeof(st), hipMemcpyHostToDevice, s->stream));
     FK_HIP(hipStreamSynchronize(s->stream));
     s->iter = n;

@@ -25,7 +25,7 @@ STATUS_NAMES = {0: "FK_OK", 1: "FK_EINVAL", 2: "FK_ENOMEM", 3: "FK_EDEVICE", 4: 
 _DOMAIN = {"rect": 0, "rect_minus_disc": 1}
 _SRC = {"zero": 0, "const": 1, "gaussian": 2}
 _BC = {"zero": 0, "plane_wave": 1, "bilinear": 2, "table": 3}
-GATHER = {"auto": 0, "nodes": 1, "cells": 2}   # layout of the FP32 copy of u_n (fk_gather_layout)
+GATHER = {"auto": 0, "nodes": 1, "cells": 2}   # layout of the gathered copy of u_n (fk_gather_layout)
 
 
 class FkError(RuntimeError):

@@ -13,7 +13,7 @@ def test_candidates_cover_the_grid_and_respect_M():
     assert len(c) == len(autotune.PPI) * 2 * len(autotune.WAVES)
     assert {x["gather_layout"] for x in c} == {"nodes", "cells"}
     p64 = W.cavity_65(precision=64)
-    assert {x["gather_layout"] for x in autotune.candidates(p64)} == {"nodes"}
+    assert {x["gather_layout"] for x in autotune.candidates(p64)} == {"nodes", "cells"}
     small = W.cavity_small().replace(M=100)          # items never exceed M rounded up to 64
     assert max(x["paths_per_item"] for x in autotune.candidates(small)) == 128
 

@@ -175,12 +175,13 @@ def test_paths_per_item_does_not_change_results(precision):
 
 # ------------------------------------------------------------ FP32 path
 
+@pytest.mark.parametrize("precision", [32, 64])
 @pytest.mark.parametrize("name", ["cavity_9x9", "disc_33", "aniso_23x7"])
-def test_fp32_gather_layouts_bit_identical(name):
-    # the cell-major and row-major FP32 copies hold the same values and the
+def test_gather_layouts_bit_identical(name, precision):
+    # the cell-major and row-major copies hold the same values and the
     # kernel reads them into the same registers: identical iterates, also
     # after an iterate set from the host
-    p = _cases()[name].replace(precision=32, M=512)
+    p = _cases()[name].replace(precision=precision, M=512)
     runs = []
     for layout in ("nodes", "cells"):
         say("layout", name, layout)
