@@ -156,62 +156,73 @@ __device__ __forceinline__ void lerp(const Cell<R> &c, R u00r, R u00i, R u10r, R
     vi = li0 + c.b * (li1 - li0);
 }
 
-__device__ __forceinline__ auto grid_load(const __amdgpu_buffer_rsrc_t &g, uint32_t off)
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ u32x4 grid_load(const __amdgpu_buffer_rsrc_t &g, uint32_t off)
 {
     return __builtin_amdgcn_raw_buffer_load_b128(g, off, 0, 0);
 }
 
-// u_n at two points.  FP32: two 16-byte reads per point (u00 u10 | u01 u11).
-// Large grids miss the vector L1 on nearly every read and the stepping loop is
-// then bound by the rate of L2 requests: the cell-major copy puts a cell's
-// two halves in one line, and issuing them back to back lets the second read
-// join the first one's miss, for one L2 request per step.  Keeping more reads
-// in flight, or waiting between the halves, was measured to cost more
-// requests (the line is evicted or not yet allocated).
-__device__ __forceinline__ void interp_pair(const Consts<float> &K, float x0, float y0, float x1, float y1,
-                                            float &v0r, float &v0i, float &v1r, float &v1i)
+// Reads of u_n at one point: its cell, and the 16-byte reads in flight.
+// FP32: u00 u10 | u01 u11 (two reads); FP64: u00 | u10 | u01 | u11 (four).
+// The top pair sits at + second: the next row, or the second half of the
+// cell's block in the cell-major copy.
+template <class R> struct CellReads;
+template <> struct CellReads<float> {
+    Cell<float> c;
+    u32x4 a, b;
+};
+template <> struct CellReads<double> {
+    Cell<double> c;
+    u32x4 a0, a1, b0, b1;
+};
+
+// Large grids miss the vector L1 on nearly every read, and the stepping loop
+// is then bound by the rate of L2 requests.  In the cell-major copy a cell's
+// reads share one line: issued back to back, the later reads join the first
+// one's miss, for one L2 request per step.  Any instruction or wait the
+// scheduler puts between them was measured to cost extra requests (the line
+// is not yet allocated, or already evicted), so the reads of a cell are
+// fenced off from the scheduler.
+__device__ __forceinline__ void issue_reads(const Consts<float> &K, uint32_t off, CellReads<float> &r)
 {
-    const Cell<float> c0 = locate(K, x0, y0), c1 = locate(K, x1, y1);
-    // row-major: all four reads in flight at once (the grid is L1-resident
-    // where this layout is chosen); cell-major: the second point's reads
-    // wait for the first point's, so that each cell's two halves reach the
-    // vector L1 back to back and share one L2 request
-    uint32_t o1 = c1.off;
-    const auto a0 = grid_load(K.grid, c0.off);
-    const auto b0 = grid_load(K.grid, c0.off + K.second);
-    if (K.cells) asm volatile("" : "+v"(o1) : "v"(b0[0]));
-    const auto a1 = grid_load(K.grid, o1);
-    const auto b1 = grid_load(K.grid, o1 + K.second);
-    auto f = [](uint32_t w) { return __uint_as_float(w); };
-    lerp(c0, f(a0[0]), f(a0[1]), f(a0[2]), f(a0[3]), f(b0[0]), f(b0[1]), f(b0[2]), f(b0[3]), v0r, v0i);
-    lerp(c1, f(a1[0]), f(a1[1]), f(a1[2]), f(a1[3]), f(b1[0]), f(b1[1]), f(b1[2]), f(b1[3]), v1r, v1i);
+    __builtin_amdgcn_sched_barrier(0);
+    r.a = grid_load(K.grid, off);
+    r.b = grid_load(K.grid, off + K.second);
+    __builtin_amdgcn_sched_barrier(0);
+}
+__device__ __forceinline__ void issue_reads(const Consts<double> &K, uint32_t off, CellReads<double> &r)
+{
+    r.a0 = grid_load(K.grid, off);
+    r.a1 = grid_load(K.grid, off + 16u);
+    r.b0 = grid_load(K.grid, off + K.second);
+    r.b1 = grid_load(K.grid, off + K.second + 16u);
 }
 
-// FP64: four 16-byte reads per point, u00 | u10 at the cell offset and
-// u01 | u11 at + second (the next row, or the cell block's second half).
-// As for FP32, the cell-major copy keeps a cell in one line, and the second
-// point's reads wait for the first point's.
-__device__ __forceinline__ void interp_pair(const Consts<double> &K, double x0, double y0, double x1, double y1,
-                                            double &v0r, double &v0i, double &v1r, double &v1i)
+// In the cell-major copy the second point's reads are issued only once the
+// first point's have returned, so that at most one cell per lane is in
+// flight (two in flight were measured to cost more L2 requests).
+__device__ __forceinline__ void after_reads(uint32_t &off, const CellReads<float> &r)
+{
+    asm volatile("" : "+v"(off) : "v"(r.b[0]));
+}
+__device__ __forceinline__ void after_reads(uint32_t &off, const CellReads<double> &r)
+{
+    asm volatile("" : "+v"(off) : "v"(r.b1[0]));
+}
+
+__device__ __forceinline__ void value(const CellReads<float> &r, float &vr, float &vi)
+{
+    auto f = [](uint32_t w) { return __uint_as_float(w); };
+    lerp(r.c, f(r.a[0]), f(r.a[1]), f(r.a[2]), f(r.a[3]), f(r.b[0]), f(r.b[1]), f(r.b[2]), f(r.b[3]), vr, vi);
+}
+__device__ __forceinline__ void value(const CellReads<double> &r, double &vr, double &vi)
 {
     auto d = [](uint32_t lo, uint32_t hi) {
         return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
     };
-    const Cell<double> c0 = locate(K, x0, y0), c1 = locate(K, x1, y1);
-    uint32_t o1 = c1.off;
-    const auto a00 = grid_load(K.grid, c0.off);
-    const auto a01 = grid_load(K.grid, c0.off + 16u);
-    const auto b00 = grid_load(K.grid, c0.off + K.second);
-    const auto b01 = grid_load(K.grid, c0.off + K.second + 16u);
-    if (K.cells) asm volatile("" : "+v"(o1) : "v"(b01[0]));
-    const auto a10 = grid_load(K.grid, o1);
-    const auto a11 = grid_load(K.grid, o1 + 16u);
-    const auto b10 = grid_load(K.grid, o1 + K.second);
-    const auto b11 = grid_load(K.grid, o1 + K.second + 16u);
-    lerp(c0, d(a00[0], a00[1]), d(a00[2], a00[3]), d(a01[0], a01[1]), d(a01[2], a01[3]), d(b00[0], b00[1]),
-         d(b00[2], b00[3]), d(b01[0], b01[1]), d(b01[2], b01[3]), v0r, v0i);
-    lerp(c1, d(a10[0], a10[1]), d(a10[2], a10[3]), d(a11[0], a11[1]), d(a11[2], a11[3]), d(b10[0], b10[1]),
-         d(b10[2], b10[3]), d(b11[0], b11[1]), d(b11[2], b11[3]), v1r, v1i);
+    lerp(r.c, d(r.a0[0], r.a0[1]), d(r.a0[2], r.a0[3]), d(r.a1[0], r.a1[1]), d(r.a1[2], r.a1[3]),
+         d(r.b0[0], r.b0[1]), d(r.b0[2], r.b0[3]), d(r.b1[0], r.b1[1]), d(r.b1[2], r.b1[3]), vr, vi);
 }
 
 // source f at a point (the caller branches on K.src_kind != SRC_ZERO)
@@ -241,14 +252,25 @@ template <class R>
 __device__ __forceinline__ bool advance(const Inst &D, const Consts<R> &K, PathState<R> &P, uint32_t m,
                                         uint32_t node, uint32_t ctr3, R k2u, bool &exited)
 {
+    // Both points' reads are issued after the normals.  (Issuing the
+    // current point's before the Philox block was measured slower on large
+    // grids in FP32 and spills registers in FP64.)
+    CellReads<R> g0, g1;
     const uint4 w = philox4x32_10((uint32_t)(P.t >> 1), m, node, ctr3, K.key0, K.key1);
     R z0x, z0y, z1x, z1y;
     normals(w.x, w.y, *K.tab, z0x, z0y);
     normals(w.z, w.w, *K.tab, z1x, z1y);
     const R x1 = P.x + K.sigma * z0x, y1 = P.y + K.sigma * z0y;
     const R x2 = x1 + K.sigma * z1x, y2 = y1 + K.sigma * z1y;
+    g0.c = locate(K, P.x, P.y);
+    g1.c = locate(K, x1, y1);
+    issue_reads(K, g0.c.off, g0);
+    uint32_t o1 = g1.c.off;
+    if (K.cells) after_reads(o1, g0);
+    issue_reads(K, o1, g1);
     R v0r, v0i, v1r, v1i;
-    interp_pair(K, P.x, P.y, x1, y1, v0r, v0i, v1r, v1i);
+    value(g0, v0r, v0i);
+    value(g1, v1r, v1i);
     R fr = -(k2u * v0r), fi = -(k2u * v0i), gr = -(k2u * v1r), gi = -(k2u * v1i);
     if (K.src_kind != SRC_ZERO) {
         R sr, si;
@@ -341,9 +363,9 @@ __device__ __forceinline__ unsigned long long contribution(int i, double2 sc, bo
 // the one before, whose long paths may still be running.  A new node reuses
 // the older accumulator after moving its sums to the node's slot.
 struct NodeAcc {
-    unsigned long long *buf[2];
-    int32_t node[2];
-    int cur;
+    unsigned long long *buf0, *buf1;
+    int32_t node0, node1;
+    int cur;                        // 0: node0 is the current node, 1: node1
 };
 
 // Scores the parked paths of the wave and adds them to their node sums:
@@ -355,9 +377,9 @@ __device__ __forceinline__ void deposit_parked(const Inst &D, Pending &Q, const 
     if (Q.live) {
         const double2 sc = score(D, Q);
         const bool ok = fabs(sc.x) < 0x1p21 && fabs(sc.y) < 0x1p21;
-        unsigned long long *dst = Q.node_idx == A.node[0]   ? A.buf[0]
-                                  : Q.node_idx == A.node[1] ? A.buf[1]
-                                                            : (unsigned long long *)(D.slots + Q.node_idx);
+        unsigned long long *dst = Q.node_idx == A.node0   ? A.buf0
+                                  : Q.node_idx == A.node1 ? A.buf1
+                                                          : (unsigned long long *)(D.slots + Q.node_idx);
 #pragma unroll 1
         for (int i = 0; i < kSlotSums; ++i) {
             const unsigned long long v = contribution(i, sc, ok, Q.t, !Q.exited);
@@ -445,9 +467,9 @@ __device__ __forceinline__ void stream_paths(const Inst *__restrict__ insts, con
     setup_tables<R>(tables);
     __shared__ unsigned long long lds_acc[4][2][12];   // two node accumulators per wave
     NodeAcc A;
-    A.buf[0] = lds_acc[threadIdx.x / kWave][0];
-    A.buf[1] = lds_acc[threadIdx.x / kWave][1];
-    if ((threadIdx.x & (kWave - 1)) < 24) A.buf[0][threadIdx.x & (kWave - 1)] = 0ull;
+    A.buf0 = lds_acc[threadIdx.x / kWave][0];
+    A.buf1 = lds_acc[threadIdx.x / kWave][1];
+    if ((threadIdx.x & (kWave - 1)) < 24) A.buf0[threadIdx.x & (kWave - 1)] = 0ull;
     __builtin_amdgcn_wave_barrier();
     const int32_t nseg = Q->n_seg;
     const int64_t total = nseg > 0 ? Q->seg_end[nseg - 1] : 0;
@@ -466,7 +488,7 @@ __device__ __forceinline__ void stream_paths(const Inst *__restrict__ insts, con
         // wave-uniform pool: path indices [pool_m, pool_end) of one node
         int64_t pool_m = 0, pool_end = 0;
         int32_t pool_node_idx = 0, pool_node = 0;
-        A.node[0] = A.node[1] = -1;
+        A.node0 = A.node1 = -1;
         A.cur = 0;
         R pool_sx = (R)0, pool_sy = (R)0;
         bool more = true;       // the queue may hold further items of this instance
@@ -480,11 +502,15 @@ __device__ __forceinline__ void stream_paths(const Inst *__restrict__ insts, con
             const int32_t gi = pool_node % D.nx, gj = pool_node / D.nx;
             pool_sx = (R)(D.x0 + (double)gi * D.dx);
             pool_sy = (R)(D.y0 + (double)gj * D.dy);
-            if (pool_node_idx != A.node[A.cur]) {
-                const int v = 1 - A.cur;
-                flush_acc(D, A.buf[v], A.node[v]);
-                A.node[v] = pool_node_idx;
-                A.cur = v;
+            // a new node takes the older accumulator (wave-uniform branch)
+            if (A.cur == 0 && pool_node_idx != A.node0) {
+                flush_acc(D, A.buf1, A.node1);
+                A.node1 = pool_node_idx;
+                A.cur = 1;
+            } else if (A.cur == 1 && pool_node_idx != A.node1) {
+                flush_acc(D, A.buf0, A.node0);
+                A.node0 = pool_node_idx;
+                A.cur = 0;
             }
         };
         open_item(g);
@@ -547,8 +573,8 @@ __device__ __forceinline__ void stream_paths(const Inst *__restrict__ insts, con
             }
         }
         flush();
-        flush_acc(D, A.buf[0], A.node[0]);
-        flush_acc(D, A.buf[1], A.node[1]);
+        flush_acc(D, A.buf0, A.node0);
+        flush_acc(D, A.buf1, A.node1);
     }
 }
 
