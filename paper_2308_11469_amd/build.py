@@ -20,6 +20,10 @@ ARCH = os.environ.get("FK_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
          # packed FP32 instructions stay off: scalar FP32 code only
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # multiply-adds are fused only within one expression, never across
+         # statements: the path kernel is compiled per feature set, and every
+         # variant must round an instance's arithmetic the same way
+         "-ffp-contract=on",
          "-Wall", "-Wno-unused-function", "-I" + os.path.join(HERE, "..", "include")]
 FLAGS += os.environ.get("FK_HIPCC_FLAGS", "").split()   # extra compiler options
 

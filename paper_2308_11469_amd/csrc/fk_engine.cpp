@@ -3,12 +3,14 @@
 // Device-resident tables hold, per slot, the instance record and its status;
 // a segment table numbers the work items of the active instances (longest
 // expected paths first).  One tick = one fixed-point iteration of every active
-// instance = one replay of a HIP graph captured once at creation:
+// instance = one replay of a HIP graph captured at creation:
 //   reset (status + queue head) -> path kernel (persistent waves pulling work
 //   items from the queue) -> update (all active instances) -> iteration
 //   advance -> status copy.
-// Admitting or retiring an instance edits the tables between ticks; the graph
-// is never re-captured.  Instance memory comes from one device pool managed by
+// One graph is captured per set of optional path-kernel features (hole,
+// source term); a tick replays the one for the union of the active
+// instances' features.  Admitting or retiring an instance edits the tables
+// between ticks; the graphs are never re-captured.  Instance memory comes from one device pool managed by
 // a first-fit allocator; admission fails with FK_ENOMEM when the pool cannot
 // hold the instance's footprint, so callers admit by HBM footprint.
 #include <algorithm>
@@ -110,8 +112,8 @@ struct fk_engine {
     PoolAllocator pool;
     bool tables_dirty = true;
     int32_t n_active = 0;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph[4] = {};         // per feature set of the path kernel
+    hipGraphExec_t exec[4] = {};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double kernel_ms_total = 0.0;
     int64_t launches = 0;
@@ -119,14 +121,14 @@ struct fk_engine {
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-static fk_status capture_graph(fk_engine *e)
+static fk_status capture_graph(fk_engine *e, int features)
 {
     const int prec = e->cfg.precision;
     const int32_t cap = e->cfg.max_instances;
     FK_HIP(hipStreamBeginCapture(e->cap_stream, hipStreamCaptureModeThreadLocal));
     hipError_t err = fkk::launch_reset(e->d_insts, e->d_active, cap, e->d_n_active, e->d_head, e->cap_stream);
     if (err == hipSuccess)
-        err = fkk::launch_stream(prec, e->d_insts, e->d_queue, e->d_head, e->n_blocks, e->cap_stream);
+        err = fkk::launch_stream(prec, features, e->d_insts, e->d_queue, e->d_head, e->n_blocks, e->cap_stream);
     if (err == hipSuccess)
         err = fkk::launch_update(e->d_insts, e->d_active, cap, e->d_n_active, e->max_interior_cap, e->cap_stream);
     if (err == hipSuccess) err = fkk::launch_advance(e->d_insts, e->d_active, cap, e->d_n_active, e->cap_stream);
@@ -140,8 +142,8 @@ static fk_status capture_graph(fk_engine *e)
         return hip_fail(err, "engine graph capture");
     }
     if (end != hipSuccess) return hip_fail(end, "hipStreamEndCapture");
-    e->graph = g;
-    FK_HIP(hipGraphInstantiate(&e->exec, g, nullptr, nullptr, 0));
+    e->graph[features] = g;
+    FK_HIP(hipGraphInstantiate(&e->exec[features], g, nullptr, nullptr, 0));
     return FK_OK;
 }
 
@@ -228,8 +230,10 @@ fk_status fk_engine_create(const fk_engine_config *cfg, void *hip_stream, fk_eng
     if ((err = hipEventCreate(&e->ev0)) != hipSuccess || (err = hipEventCreate(&e->ev1)) != hipSuccess)
         return bail(hip_fail(err, "hipEventCreate"));
     e->pool.reset(e->pool_bytes);
-    fk_status st = capture_graph(e);
-    if (st != FK_OK) return bail(st);
+    for (int f = 0; f < 4; ++f) {
+        fk_status st = capture_graph(e, f);
+        if (st != FK_OK) return bail(st);
+    }
     e->tables_dirty = false;
     *out = e;
     return FK_OK;
@@ -314,8 +318,10 @@ fk_status fk_engine_tick(fk_engine *e, fk_iter_report *reports, uint8_t *active_
         FK_HIP(hipMemcpyAsync(e->d_queue, e->h_queue, sizeof(fkd::EngineQueue), hipMemcpyHostToDevice, s));
         e->tables_dirty = false;
     }
+    int features = 0;
+    for (int32_t a = 0; a < e->n_active; ++a) features |= e->slots[e->h_active[a]].P.features();
     FK_HIP(hipEventRecord(e->ev0, s));
-    FK_HIP(hipGraphLaunch(e->exec, s));
+    FK_HIP(hipGraphLaunch(e->exec[features], s));
     FK_HIP(hipEventRecord(e->ev1, s));
     FK_HIP(hipStreamSynchronize(s));
     float ms = 0.0f;
@@ -388,8 +394,10 @@ fk_status fk_engine_destroy(fk_engine *e)
     if (!e) return FK_OK;
     if (e->user_stream) (void)hipStreamSynchronize(e->user_stream);
     if (e->cap_stream) (void)hipStreamSynchronize(e->cap_stream);
-    if (e->exec) (void)hipGraphExecDestroy(e->exec);
-    if (e->graph) (void)hipGraphDestroy(e->graph);
+    for (int f = 0; f < 4; ++f) {
+        if (e->exec[f]) (void)hipGraphExecDestroy(e->exec[f]);
+        if (e->graph[f]) (void)hipGraphDestroy(e->graph[f]);
+    }
     if (e->ev0) (void)hipEventDestroy(e->ev0);
     if (e->ev1) (void)hipEventDestroy(e->ev1);
     (void)hipFree(e->d_insts);

@@ -1,6 +1,6 @@
 // fk_kernels.hip -- HIP kernels of the Feynman-Kac Helmholtz path (gfx950).
 //
-//   fk_stream_f32 / _f64      the paths: waves pull (instance, node, chunk)
+//   fk_stream_f32 / _f64<F>   the paths: waves pull (instance, node, chunk)
 //                             items from a device queue until it is empty and
 //                             run their paths as one stream of lanes
 //   fk_update_kernel          node mean / variance from the node slots, the
@@ -18,6 +18,13 @@
 namespace fkd {
 
 // Per-precision constants of an instance, hoisted out of the stepping loop.
+// Optional parts of the stepping loop.  The path kernel is compiled per set
+// of features; an instance runs in any kernel whose set contains its own
+// (the run-time checks stay), and a kernel without a feature carries neither
+// its code nor its constants across the loop.
+constexpr int kFeatDisc = 1;     // the domain has a hole
+constexpr int kFeatSource = 2;   // f is not zero
+
 // The normals' lookup tables per precision (FP64 only; they live in LDS).
 template <class R> struct TablesOf { using type = F64Tables; };
 template <> struct TablesOf<float> { using type = NoTables; };
@@ -98,19 +105,21 @@ __device__ __forceinline__ float exp_src(float a) { return __builtin_amdgcn_exp2
 // iff x >= RU(x1), so comparing with the outward-rounded edges equals the
 // exact test against the FP64 edges; the disc test runs in FP32 and falls
 // back to FP64 only within a thin band around the circle.
+template <int F>
 __device__ __forceinline__ bool is_out(const Inst &, const Consts<double> &K, double x, double y)
 {
     if (x <= K.ex0 || x >= K.ex1 || y <= K.ey0 || y >= K.ey1) return true;
-    if (K.disc) {
+    if ((F & kFeatDisc) && K.disc) {
         const double ex = x - K.cxf, ey = y - K.cyf;
         return ex * ex + ey * ey <= K.r2f;
     }
     return false;
 }
+template <int F>
 __device__ __forceinline__ bool is_out(const Inst &D, const Consts<float> &K, float x, float y)
 {
     if (x <= K.ex0 || x >= K.ex1 || y <= K.ey0 || y >= K.ey1) return true;
-    if (K.disc) {
+    if ((F & kFeatDisc) && K.disc) {
         const float ex = x - K.cxf, ey = y - K.cyf;
         const float d = ex * ex + ey * ey - K.r2f;
         if (d > K.band) return false;
@@ -248,7 +257,7 @@ __device__ __forceinline__ void source(const Consts<R> &K, R x, R y, R &fr, R &f
 // The integrand f - k^2 I_h[u_n] is formed as -(k2u v) + f with k2u = k^2,
 // or 0 while u_n = 0 (n = 0): the gather then still runs but adds nothing,
 // so no lane-dependent branch separates the two gathers.
-template <class R>
+template <class R, int F>
 __device__ __forceinline__ bool advance(const Inst &D, const Consts<R> &K, PathState<R> &P, uint32_t m,
                                         uint32_t node, uint32_t ctr3, R k2u, bool &exited)
 {
@@ -272,7 +281,7 @@ __device__ __forceinline__ bool advance(const Inst &D, const Consts<R> &K, PathS
     value(g0, v0r, v0i);
     value(g1, v1r, v1i);
     R fr = -(k2u * v0r), fi = -(k2u * v0i), gr = -(k2u * v1r), gi = -(k2u * v1i);
-    if (K.src_kind != SRC_ZERO) {
+    if ((F & kFeatSource) && K.src_kind != SRC_ZERO) {
         R sr, si;
         source<R>(K, P.x, P.y, sr, si);
         fr += sr;
@@ -281,8 +290,8 @@ __device__ __forceinline__ bool advance(const Inst &D, const Consts<R> &K, PathS
         gr += sr;
         gi += si;
     }
-    const bool out1 = is_out(D, K, x1, y1);
-    const bool out2 = is_out(D, K, x2, y2);
+    const bool out1 = is_out<F>(D, K, x1, y1);
+    const bool out2 = is_out<F>(D, K, x2, y2);
     const bool second = !out1 && P.t + 1 < K.jmax;
     if (second) {
         fr += gr;
@@ -459,7 +468,7 @@ __device__ __forceinline__ int32_t find_segment(const EngineQueue *Q, int32_t ns
 // the node sums do not depend on which wave, lane or launch ran which path:
 // an instance gives bit-identical results alone, in any batch and for any
 // item size.
-template <class R>
+template <class R, int F>
 __device__ __forceinline__ void stream_paths(const Inst *__restrict__ insts, const EngineQueue *__restrict__ Q,
                                              unsigned long long *head)
 {
@@ -559,7 +568,7 @@ __device__ __forceinline__ void stream_paths(const Inst *__restrict__ insts, con
             }
             if (__ballot(active) == 0ull) break;
             bool fin = false, exited = false;
-            if (active) fin = advance<R>(D, K, P, m, (uint32_t)node, ctr3, k2u, exited);
+            if (active) fin = advance<R, F>(D, K, P, m, (uint32_t)node, ctr3, k2u, exited);
             const unsigned long long done = __ballot(fin);
             if (done) {
                 // score the parked paths first when a finishing lane still
@@ -587,16 +596,18 @@ __device__ __forceinline__ void stream_paths(const Inst *__restrict__ insts, con
 #define FK_WAVES_F64 3
 #endif
 
+template <int F>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FK_WAVES_F32)))
 fk_stream_f32(const Inst *__restrict__ insts, const EngineQueue *__restrict__ Q, unsigned long long *head)
 {
-    stream_paths<float>(insts, Q, head);
+    stream_paths<float, F>(insts, Q, head);
 }
 
+template <int F>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FK_WAVES_F64)))
 fk_stream_f64(const Inst *__restrict__ insts, const EngineQueue *__restrict__ Q, unsigned long long *head)
 {
-    stream_paths<double>(insts, Q, head);
+    stream_paths<double, F>(insts, Q, head);
 }
 
 // Instance lists: `which` (device, optional) names the instances by index
@@ -795,7 +806,7 @@ __global__ void fk_debug_paths_kernel(const Inst *__restrict__ inst, const int32
     PathState<R> P;
     start(P, (R)(D.x0 + (double)gi * D.dx), (R)(D.y0 + (double)gj * D.dy));
     bool exited = false;
-    while (!advance<R>(D, K, P, (uint32_t)ms[i], (uint32_t)node, ctr3, k2u, exited)) {
+    while (!advance<R, kFeatDisc | kFeatSource>(D, K, P, (uint32_t)ms[i], (uint32_t)node, ctr3, k2u, exited)) {
     }
     J[i] = P.t;
     Pending Q;
@@ -813,14 +824,26 @@ using namespace fkd;
 
 static int blocks_for(int64_t n, int per) { return (int)((n + per - 1) / per); }
 
-hipError_t launch_stream(int precision, const Inst *d_insts, const EngineQueue *Q, unsigned long long *head,
-                         int n_blocks, hipStream_t s)
+template <int F>
+static void launch_stream_f(int precision, dim3 grid, dim3 block, const Inst *d_insts, const EngineQueue *Q,
+                            unsigned long long *head, hipStream_t s)
+{
+    if (precision == 32)
+        hipLaunchKernelGGL(fk_stream_f32<F>, grid, block, 0, s, d_insts, Q, head);
+    else
+        hipLaunchKernelGGL(fk_stream_f64<F>, grid, block, 0, s, d_insts, Q, head);
+}
+
+hipError_t launch_stream(int precision, int features, const Inst *d_insts, const EngineQueue *Q,
+                         unsigned long long *head, int n_blocks, hipStream_t s)
 {
     dim3 grid(n_blocks), block(256);
-    if (precision == 32)
-        hipLaunchKernelGGL(fk_stream_f32, grid, block, 0, s, d_insts, Q, head);
-    else
-        hipLaunchKernelGGL(fk_stream_f64, grid, block, 0, s, d_insts, Q, head);
+    switch (features & (kFeatDisc | kFeatSource)) {
+    case 0: launch_stream_f<0>(precision, grid, block, d_insts, Q, head, s); break;
+    case kFeatDisc: launch_stream_f<kFeatDisc>(precision, grid, block, d_insts, Q, head, s); break;
+    case kFeatSource: launch_stream_f<kFeatSource>(precision, grid, block, d_insts, Q, head, s); break;
+    default: launch_stream_f<kFeatDisc | kFeatSource>(precision, grid, block, d_insts, Q, head, s); break;
+    }
     return hipGetLastError();
 }
 
