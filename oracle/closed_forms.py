@@ -9,11 +9,13 @@ import math
 import numpy as np
 
 
-def plane_wave(k, theta, x, y, amp=1.0):
-    """amp exp(i k (x cos theta + y sin theta)): solves Delta u + k^2 u = 0
-    everywhere, so with its own trace as Dirichlet datum it is the exact
-    solution in any cavity (Sec. 1, the incident field)."""
-    return amp * np.exp(1j * k * (np.asarray(x) * math.cos(theta) + np.asarray(y) * math.sin(theta)))
+def plane_wave(k, theta, x, y, amp=1.0, damping=0.0):
+    """amp exp(i kappa (x cos theta + y sin theta)) with kappa^2 = k^2 + i p:
+    solves Delta u + (k^2 + i p) u = 0 everywhere, so with its own trace as
+    Dirichlet datum it is the exact solution in any cavity (Sec. 1, the
+    incident field; Sec. 2.2 with damping p)."""
+    kappa = k if damping == 0.0 else complex(np.sqrt(complex(k * k, damping)))
+    return amp * np.exp(1j * kappa * (np.asarray(x) * math.cos(theta) + np.asarray(y) * math.sin(theta)))
 
 
 def disc_scattered(k, a, theta, x, y, nterms=50):

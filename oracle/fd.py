@@ -67,13 +67,14 @@ def laplacian(p):
 
 
 def direct(p, dense=False) -> np.ndarray:
-    """Direct 5-point solve of (Delta_h + k^2) u = f; returns the full complex
-    grid (ny, nx) with Dirichlet values on edge and hole nodes."""
+    """Direct 5-point solve of (Delta_h + k^2 + i p) u = f (p the damping of
+    Sec. 2.2, eq. (2.4)); returns the full complex grid (ny, nx) with
+    Dirichlet values on edge and hole nodes."""
     L, ids, B = laplacian(p)
     full = fkmc.boundary_grid(p)
     f = source_grid(p).ravel()[ids]
     rhs = f - B @ full.ravel()
-    A = (L + (p.k ** 2) * sp.identity(L.shape[0], format="csc")).astype(complex)
+    A = (L.astype(complex) + complex(p.k ** 2, p.damping) * sp.identity(L.shape[0], format="csc"))
     if dense:
         sol = np.linalg.solve(A.toarray(), rhs)
     else:
@@ -84,17 +85,21 @@ def direct(p, dense=False) -> np.ndarray:
 
 
 def neumann(p, n_iters, u0=None):
-    """Iterates of Delta_h u_{n+1} = f - k^2 u_n (Dirichlet g), u_0 = 0 unless
-    given.  Returns the list [u_1, ..., u_n_iters] of full grids."""
+    """Iterates of (Delta_h - (alpha - k^2)) u_{n+1} = f - (alpha + i p) u_n
+    (Dirichlet g; alpha = k^2 and p = 0 unless the problem sets them: the
+    FD form of the iteration of Sec. 2.2), u_0 = 0 unless given.  Returns the
+    list [u_1, ..., u_n_iters] of full grids."""
     L, ids, B = laplacian(p)
-    lu = spla.splu(L.tocsc())
+    alpha = p.k ** 2 if p.alpha is None else p.alpha
+    c = alpha - p.k ** 2
+    lu = spla.splu((L - c * sp.identity(L.shape[0], format="csc")).tocsc())
     full = fkmc.boundary_grid(p)
     f = source_grid(p).ravel()[ids]
     bterm = B @ full.ravel()
     u_int = np.zeros(len(ids), dtype=complex) if u0 is None else np.asarray(u0).ravel()[ids].astype(complex)
     out = []
     for _ in range(n_iters):
-        rhs = f - p.k ** 2 * u_int - bterm
+        rhs = f - complex(alpha, p.damping) * u_int - bterm
         u_int = lu.solve(rhs.real) + 1j * lu.solve(rhs.imag)
         g = full.copy()
         g.ravel()[ids] = u_int

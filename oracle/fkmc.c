@@ -22,6 +22,14 @@
  *     with Y_t = y + sqrt(2) W_t (eq. (2.2)).
  *   - Every iterate n uses a new, independent Brownian motion (Remark 2.1);
  *     the counter of the random-number generator therefore contains n.
+ *   - General shift alpha >= k^2 and damping p (Sec. 2.2, eq. (2.4) with
+ *     the iteration (2.6)-(2.8) written for the partial sums U_n): the
+ *     equation Delta u + (k^2 + i p) u = f becomes
+ *       Delta U_{n+1} - (alpha - k^2) U_{n+1} = f - (alpha + i p) U_n,
+ *     and the Feynman-Kac formula of eq. (2.3) with c = alpha - k^2 gives
+ *       U_{n+1}(y) = E[e^{-c tau} g(Y_tau)]
+ *                    - E[int_0^tau e^{-c s} (f - (alpha + i p) U_n)(Y_s) ds].
+ *     alpha = k^2, p = 0 is the iteration above.
  *
  * Discretisation (the readings where the paper is silent):
  *   - Euler-Maruyama: X_0 = y, X_{t+1} = X_t + sqrt(2h) (z_x, z_y).
@@ -36,8 +44,11 @@
  *     boundary counts as outside), capped at jmax.  The boundary datum is taken
  *     at the nearest boundary point of X_J.
  *   - Integral: left-point rule over the J increments,
- *     s = g(Pi X_J) - h sum_{t<J} (f - k^2 I_h[u_n])(X_t),
+ *     s = e^{-c J h} g(Pi X_J) - h sum_{t<J} e^{-c t h} (f - (alpha + i p) I_h[u_n])(X_t),
  *     where I_h is bilinear interpolation of the grid of u_n.
+ *   - Plane-wave data: amp exp(i kappa (x cos theta + y sin theta)) with
+ *     kappa = sqrt(k^2 + i p) (principal root), the plane wave that solves
+ *     the damped equation; kappa = k when p = 0.
  */
 #include <math.h>
 #include <stdint.h>
@@ -80,6 +91,8 @@ typedef struct {
     int64_t jmax;
     int32_t crn;
     int32_t g_unprojected; /* test variant: g taken at X_J itself */
+    double alpha;          /* shift, >= k^2 */
+    double p;              /* damping */
 } orc_problem;
 
 /* --------------------------------------------------------------- Philox -- */
@@ -211,8 +224,18 @@ static void bc_eval(const orc_problem *P, const orc_bc *B, double x, double y, d
 {
     switch (B->kind) {
     case ORC_BC_PLANE_WAVE: {
-        double ph = P->k * (x * cos(B->c[2]) + y * sin(B->c[2]));
-        double cr = cos(ph), si = sin(ph);
+        /* kappa = sqrt(k^2 + i p): kr = sqrt((|k^2 + i p| + k^2) / 2),
+         * ki = p / (2 kr); kappa = k when p = 0 */
+        double kr = P->k, ki = 0.0;
+        if (P->p != 0.0) {
+            const double k2 = P->k * P->k;
+            const double mod = sqrt(k2 * k2 + P->p * P->p);
+            kr = sqrt(0.5 * (mod + k2));
+            ki = P->p / (2.0 * kr);
+        }
+        const double sx = x * cos(B->c[2]) + y * sin(B->c[2]);
+        const double ph = kr * sx, decay = exp(-ki * sx);
+        double cr = cos(ph) * decay, si = sin(ph) * decay;
         g[0] = B->c[0] * cr - B->c[1] * si;
         g[1] = B->c[0] * si + B->c[1] * cr;
         return;
@@ -310,7 +333,7 @@ void orc_path(const orc_problem *P, const double *u, int32_t n, int32_t node_id,
               double s[2], int64_t *J_out, int32_t *capped, double xJ[2])
 {
     const double sigma = sqrt(2.0 * P->h);
-    const double k2 = P->k * P->k;
+    const double c = P->alpha - P->k * P->k;     /* killing rate, >= 0 */
     uint32_t key[2] = {(uint32_t)(P->seed & 0xFFFFFFFFu), (uint32_t)(P->seed >> 32)};
     uint32_t ctr[4], r[4];
     double X[2];
@@ -331,12 +354,13 @@ void orc_path(const orc_problem *P, const double *u, int32_t n, int32_t node_id,
             orc_box_muller(r[0], r[1], z);
         else
             orc_box_muller(r[2], r[3], z);
-        /* left-point value of the right-hand side f - k^2 u_n at X_t */
+        /* left-point value of e^{-c s} (f - (alpha + i p) u_n) at X_t, s = t h */
         double f[2], un[2] = {0.0, 0.0};
         source_eval(P, X[0], X[1], f);
         if (u) orc_interp(P, u, X[0], X[1], un);
-        acc[0] += f[0] - k2 * un[0];
-        acc[1] += f[1] - k2 * un[1];
+        const double w = exp(-c * (double)t * P->h);
+        acc[0] += w * (f[0] - (P->alpha * un[0] - P->p * un[1]));
+        acc[1] += w * (f[1] - (P->alpha * un[1] + P->p * un[0]));
         X[0] = X[0] + sigma * z[0];
         X[1] = X[1] + sigma * z[1];
         t += 1;
@@ -353,8 +377,9 @@ void orc_path(const orc_problem *P, const double *u, int32_t n, int32_t node_id,
         int which = orc_project(P, X[0], X[1], pr);
         orc_g(P, which, pr[0], pr[1], g);
     }
-    s[0] = g[0] - P->h * acc[0];
-    s[1] = g[1] - P->h * acc[1];
+    const double wJ = exp(-c * (double)t * P->h);
+    s[0] = wJ * g[0] - P->h * acc[0];
+    s[1] = wJ * g[1] - P->h * acc[1];
     *J_out = t;
     *capped = exited ? 0 : 1;
     xJ[0] = X[0];

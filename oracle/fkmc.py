@@ -35,7 +35,8 @@ class _Problem(C.Structure):
                 ("src_cy", C.c_double), ("src_sigma", C.c_double),
                 ("outer", _BC), ("inner", _BC),
                 ("k", C.c_double), ("h", C.c_double), ("M", C.c_int64), ("seed", C.c_uint64),
-                ("jmax", C.c_int64), ("crn", C.c_int32), ("g_unprojected", C.c_int32)]
+                ("jmax", C.c_int64), ("crn", C.c_int32), ("g_unprojected", C.c_int32),
+                ("alpha", C.c_double), ("p", C.c_double)]
 
 
 _lib = None
@@ -119,6 +120,8 @@ class Handle:
         s.jmax = int(p.jmax) if p.jmax else jmax_auto(p)
         s.crn = 1 if p.crn else 0
         s.g_unprojected = 1 if getattr(p, "g_unprojected", False) else 0
+        s.alpha = p.k * p.k if p.alpha is None else float(p.alpha)
+        s.p = float(p.damping)
         self.s = s
         self.ref = C.byref(s)
 

@@ -77,6 +77,11 @@ class Problem:
     outer: BC = field(default_factory=BC)
     inner: BC = field(default_factory=BC)
     k: float = 0.0
+    # shift alpha >= k^2 of the iteration (None: k^2) and damping p of
+    # Delta u + (k^2 + i p) u = f (Sec. 2.2); plane-wave data then use the
+    # wavenumber sqrt(k^2 + i p)
+    alpha: Optional[float] = None
+    damping: float = 0.0
     h: float = 1e-3
     M: int = 64
     seed: int = 1
@@ -98,10 +103,13 @@ class Problem:
 
 # ----------------------------------------------------------------- exact data
 
-def plane_wave(k: float, theta: float, x, y, amp: complex = 1.0):
-    """``amp * exp(i k (x cos theta + y sin theta))``: an entire solution of
-    Delta u + k^2 u = 0 (the incident field of Sec. 1)."""
-    return amp * np.exp(1j * k * (np.asarray(x) * math.cos(theta) + np.asarray(y) * math.sin(theta)))
+def plane_wave(k: float, theta: float, x, y, amp: complex = 1.0, damping: float = 0.0):
+    """``amp * exp(i kappa (x cos theta + y sin theta))`` with kappa =
+    sqrt(k^2 + i p) (principal root; kappa = k when p = 0): an entire solution
+    of Delta u + (k^2 + i p) u = 0 (the incident field of Sec. 1, damped as in
+    Sec. 2.2)."""
+    kappa = k if damping == 0.0 else complex(np.sqrt(complex(k * k, damping)))
+    return amp * np.exp(1j * kappa * (np.asarray(x) * math.cos(theta) + np.asarray(y) * math.sin(theta)))
 
 
 def disc_scattered(k: float, a: float, theta: float, x, y, nterms: int = 50, amp: complex = 1.0):
@@ -157,7 +165,9 @@ def exact_solution(p: Problem) -> Optional[np.ndarray]:
     if p.src_kind != "zero":
         return None
     if p.domain_kind == RECT and p.outer.kind == "plane_wave":
-        return plane_wave(p.k, p.outer.theta, X, Y, p.outer.amp)
+        return plane_wave(p.k, p.outer.theta, X, Y, p.outer.amp, p.damping)
+    if p.damping != 0.0:
+        return None
     if p.domain_kind == RECT_MINUS_DISC and p.outer.kind == "table" and p.inner.kind == "plane_wave":
         inc_amp = -p.inner.amp
         return disc_scattered(p.k, p.r, p.inner.theta, X - p.cx, Y - p.cy, amp=inc_amp)

@@ -19,6 +19,11 @@ Each test checks the oracle against something other than itself:
   of the error against the exact plane wave;
 * Remark 2.1: the exit-time law does not depend on n; common random numbers
   reproduce exit steps exactly;
+* shift alpha > k^2 and damping p (Sec. 2.2): one step from the exact
+  damped plane wave within the discrete Dynkin bound (|alpha + i p| in place
+  of k^2, |kappa|^2 = |k^2 + i p| for the interpolation error); the whole
+  iteration against the damped FD solve on the BGK-enlarged square; common
+  random numbers contract at |alpha + i p| / (lambda_1 + alpha - k^2);
 * the noise ratio R = mean |du|^2 / (2 |SE|^2): fresh paths leave the
   stationary noise of an AR(1) chain e_{n+1} = K e_n + xi, for which R lies
   between 1/(1+rho) and 1; common random numbers leave no noise, and R falls
@@ -121,10 +126,11 @@ def bgk_fd_prediction(p, N=257):
     import scipy.interpolate as si
     d = cf.bgk_beta() * math.sqrt(2 * p.h)
     q = W.Problem(x0=p.x0 - d, x1=p.x1 + d, y0=p.y0 - d, y1=p.y1 + d, nx=N, ny=N, k=p.k,
-                  outer=W.BC("table"))
+                  damping=p.damping, outer=W.BC("table"))
     L = 4 * 8192
     px, py = W.perimeter_points(q.x0, q.x1, q.y0, q.y1, L)
-    q.outer.table = cf.plane_wave(p.k, p.outer.theta, np.clip(px, p.x0, p.x1), np.clip(py, p.y0, p.y1))
+    q.outer.table = cf.plane_wave(p.k, p.outer.theta, np.clip(px, p.x0, p.x1), np.clip(py, p.y0, p.y1),
+                                  damping=p.damping)
     u = fd.direct(q)
     xs = np.linspace(q.x0, q.x1, N)
     fr = si.RectBivariateSpline(xs, xs, u.real)
@@ -218,3 +224,64 @@ def test_noise_ratio_follows_the_noise_model():
     crn = fkmc.solve(p.replace(k=2.0, crn=True, max_iters=14))
     Rc = [h["noise_ratio"] for h in crn["history"]]
     assert Rc[-1] < 1e-6 and Rc[-1] < Rc[6] < Rc[2]
+
+
+def test_shift_and_damping_one_step_within_dynkin_bound():
+    # one step of  Delta U - (alpha - k^2) U = f - (alpha + i p) U_n  from the
+    # exact damped plane wave, datum at X_J: only the time rule (|alpha + i p|^2
+    # h / 2 per unit time) and the interpolation (|alpha + i p| |kappa|^2 dx^2 / 8)
+    # are left, each at most max|u| per unit of E[hJ]
+    k, th, h, alpha, damp = 3.0, math.pi / 6, 2.5e-4, 13.0, 2.5
+    p = W.Problem(nx=33, ny=33, k=k, alpha=alpha, damping=damp, h=h, M=3000, seed=23,
+                  outer=W.BC("plane_wave", 1.0 + 0j, th), g_unprojected=True)
+    xs = np.arange(33) / 32
+    X, Y = np.meshgrid(xs, xs)
+    u = cf.plane_wave(k, th, X, Y, damping=damp)
+    ids = [node_id(p, 16, 16), node_id(p, 8, 20), node_id(p, 25, 5)]
+    est = fkmc.fk_nodes(p, u, 3, ids)
+    a = abs(complex(alpha, damp))
+    kap2 = abs(complex(k * k, damp))
+    umax = np.max(np.abs(u))
+    for c, nid in enumerate(ids):
+        ehj = h * est["sumJ"][c] / p.M
+        bound = ehj * umax * (a * kap2 * (1 / 32) ** 2 / 8 + a * a * h / 2)
+        d = est["mean"][c] - u.ravel()[nid]
+        assert abs(d.real) <= 4 * est["se"][c].real + bound
+        assert abs(d.imag) <= 4 * est["se"][c].imag + bound
+    # a step that ignored the discount would drift by (alpha - k^2) E[tau] |u|
+    # (about 0.2 here), far outside the bound.  The damped wave is a fixed
+    # point for every alpha, so it is the damping that a wrong coefficient
+    # shows: without it the same step from the same iterate lands elsewhere
+    off = fkmc.fk_nodes(p.replace(damping=0.0), u, 3, ids)
+    assert np.max(np.abs(off["mean"] - u.ravel()[ids])) > 0.1
+
+
+def test_shift_and_damping_iteration_against_bgk_model():
+    p = W.cavity_small().replace(alpha=7.0, damping=2.0, max_iters=12)
+    res = fkmc.solve(p)
+    assert not res["diverged"]
+    ids = fkmc.interior_ids(p)
+    u = res["u"].ravel()[ids]
+    se = np.abs(res["se"].ravel()[ids])
+    pred = bgk_fd_prediction(p)
+    a = abs(complex(7.0, 2.0))
+    rho = a / (cf.lambda1h_rect(9, 9, 1, 1) + 7.0 - p.k ** 2)
+    se_eff = se / math.sqrt(1 - rho ** 2)
+    umax = np.max(np.abs(W.exact_solution(p)))
+    b_x = a * abs(complex(p.k ** 2, 2.0)) * umax * 0.0737 * (2 / 64) / 8 / (1 - rho)
+    assert np.all(np.abs(u - pred) <= 4.5 * se_eff + b_x)
+    ex = W.exact_solution(p).ravel()[ids]
+    assert np.all(np.abs(u - ex) <= np.abs(pred - ex) + 4.5 * se_eff + b_x)
+    # the damped solution differs from the undamped one by far more than that
+    assert np.max(np.abs(ex - W.exact_solution(p.replace(damping=0.0)).ravel()[ids])) > 0.1
+
+
+def test_crn_contraction_with_shift_and_damping():
+    k, alpha, damp = 2.0, 7.0, 3.0
+    p = W.cavity_small().replace(M=2000, crn=True, max_iters=12, k=k, alpha=alpha, damping=damp)
+    res = fkmc.solve(p)
+    du = [hh["max_du"] for hh in res["history"]]
+    ratios = [du[i + 1] / du[i] for i in range(3, 8)]
+    d = cf.bgk_beta() * math.sqrt(2 * p.h)
+    rho_eff = abs(complex(alpha, damp)) / (cf.lambda1_rect(1 + 2 * d, 1 + 2 * d) + alpha - k * k)
+    assert all(0.6 * rho_eff < r < 1.4 * rho_eff for r in ratios), (ratios, rho_eff)

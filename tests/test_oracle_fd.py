@@ -62,6 +62,35 @@ def test_neumann_series_diverges_above_lambda1():
     assert d[-1] > 1e3 * d[0]
 
 
+def test_damped_direct_second_order_to_damped_plane_wave():
+    # Delta u + (k^2 + i p) u = 0 with the damped plane wave as data
+    errs = []
+    for N in (9, 17, 33, 65):
+        p = cavity(N, k=3.0).replace(damping=2.5)
+        u = fd.direct(p)
+        ex = cf.plane_wave(3.0, math.pi / 6, *np.meshgrid(np.linspace(0, 1, N), np.linspace(0, 1, N)),
+                           damping=2.5)
+        errs.append(np.max(np.abs(u - ex)))
+    rates = [errs[i] / errs[i + 1] for i in range(3)]
+    assert all(3.6 < r < 4.4 for r in rates), rates
+    # the data really are damped: the wave decays along its direction
+    assert abs(ex[-1, -1]) < 0.8 * abs(ex[0, 0])
+
+
+def test_neumann_with_shift_and_damping_contracts_at_its_spectral_radius():
+    # (Delta_h - (alpha - k^2)) u_{n+1} = f - (alpha + i p) u_n: mode m is
+    # multiplied by -(alpha + i p) / (lambda_m + alpha - k^2); the smallest
+    # lambda_m dominates
+    k, alpha, damp = 2.0, 7.0, 3.0
+    p = cavity(17, k=k).replace(alpha=alpha, damping=damp)
+    its = fd.neumann(p, 80)
+    assert np.max(np.abs(its[-1] - fd.direct(p))) < 1e-12
+    lam = cf.lambda1h_rect(17, 17, 1, 1)
+    rho = abs(complex(alpha, damp)) / (lam + alpha - k * k)
+    d = [np.max(np.abs(its[i + 1] - its[i])) for i in range(len(its) - 1)]
+    assert abs(d[10] / d[9] - rho) < 1e-6
+
+
 def test_dst_iterate_equals_lu_iterate():
     p = cavity(33, k=2.0).replace(x1=1.5, nx=49, src_kind="gaussian", src_amp=1 + 0.5j,
                                   src_cx=0.3, src_cy=0.6, src_sigma=0.05)
