@@ -126,6 +126,16 @@ typedef struct {
                               path kernel per CU, a multiple of 4 in [4, 32];
                               0 = 16.  (The engine takes it from its config.) */
     int32_t reserved;      /* must be 0 */
+    double alpha;          /* shift of the iteration, >= k^2; 0 = k^2.  With
+                              damping p the equation is
+                              Delta u + (k^2 + i p) u = f and the iteration
+                              Delta U_{n+1} - (alpha - k^2) U_{n+1}
+                                = f - (alpha + i p) U_n  (Sec. 2.2, the
+                              partial sums of (2.6)-(2.8)); each step is a
+                              Feynman-Kac solve with killing rate
+                              alpha - k^2                                   */
+    double damping;        /* p >= 0; plane-wave data then use the wavenumber
+                              sqrt(k^2 + i p)                               */
 } fk_params;
 
 /* Per-iteration report (after the iteration that produced u_n). */

@@ -24,13 +24,24 @@ namespace fkd {
 
 constexpr int kWave = 64;
 
+// Optional parts of the path code.  The path kernel is compiled per set of
+// features; an instance runs in any kernel whose set contains its own (the
+// run-time checks stay), and a kernel without a feature carries neither its
+// code nor its constants.
+constexpr int kFeatDisc = 1;     // the domain has a hole
+constexpr int kFeatSource = 2;   // f is not zero
+constexpr int kFeatGeneral = 4;  // a shift alpha != k^2 or a damping p (discount, complex coefficient,
+                                 // damped plane-wave data)
+constexpr int kFeatAll = kFeatDisc | kFeatSource | kFeatGeneral;
+
 enum : int32_t { BC_ZERO = 0, BC_PLANE_WAVE = 1, BC_BILINEAR = 2, BC_TABLE = 3 };
 enum : int32_t { SRC_ZERO = 0, SRC_CONST = 1, SRC_GAUSSIAN = 2 };
 
 struct BCDev {
     int32_t kind;
     int32_t pad;
-    double c[8];            // PLANE_WAVE: amp_re, amp_im, cos th, sin th; BILINEAR: c0..c3
+    double c[8];            // PLANE_WAVE: amp_re, amp_im, cos th, sin th, kappa_re, kappa_im;
+                            // BILINEAR: c0..c3
     const double2 *table;   // TABLE samples (device)
     int64_t len;
 };
@@ -76,6 +87,7 @@ struct Inst {
     double src_re, src_im, src_cx, src_cy, src_c;   // src_c = 1 / (2 sigma^2)
     BCDev outer, inner;
     double k, k2, h, sigma;                          // sigma = sqrt(2 h)
+    double alpha, damp, q;                           // shift, damping p, q = exp(-(alpha - k^2) h)
     int64_t M, jmax;
     uint32_t key0, key1;
     int32_t crn, ppi;                                // ppi: paths per item
@@ -263,14 +275,22 @@ __device__ __forceinline__ int project(const Inst &D, double x, double y, double
 }
 
 // Boundary datum at a point (FP64, once per path).
+template <int F>
 __device__ __forceinline__ double2 bc_eval(const Inst &D, const BCDev &B, double x, double y)
 {
     switch (B.kind) {
     case BC_PLANE_WAVE: {
+        // amp exp(i kappa s), s = x cos th + y sin th, kappa = kr + i ki;
         // phase in half-turns: sincospi reduces its argument exactly
-        const double ph = D.k * (x * B.c[2] + y * B.c[3]);
+        const double sd = x * B.c[2] + y * B.c[3];
+        const double ph = B.c[4] * sd;
         double s, c;
         sincospi(ph * 0.318309886183790671537767526745, &s, &c);
+        if ((F & kFeatGeneral) && B.c[5] != 0.0) {
+            const double decay = exp(-B.c[5] * sd);
+            s *= decay;
+            c *= decay;
+        }
         return make_double2(B.c[0] * c - B.c[1] * s, B.c[0] * s + B.c[1] * c);
     }
     case BC_BILINEAR:
@@ -298,16 +318,17 @@ __device__ __forceinline__ double2 bc_eval(const Inst &D, const BCDev &B, double
 }
 
 // Score datum g at the end of a path whose last point is (x, y).
+template <int F>
 __device__ __forceinline__ double2 exit_datum(const Inst &D, double x, double y, bool exited)
 {
     if (D.g_unproj) {
         const bool outer = x <= D.x0 || x >= D.x1 || y <= D.y0 || y >= D.y1;
-        return bc_eval(D, (outer || !exited) ? D.outer : D.inner, x, y);
+        return bc_eval<F>(D, (outer || !exited) ? D.outer : D.inner, x, y);
     }
     double px, py;
     const int which = project(D, x, y, px, py);
     const BCDev *B = which == 2 ? &D.inner : &D.outer;
-    return bc_eval(D, *B, px, py);
+    return bc_eval<F>(D, *B, px, py);
 }
 
 // ------------------------------------------ iterate grid per precision

@@ -8,7 +8,7 @@
 //   items from the queue) -> update (all active instances) -> iteration
 //   advance -> status copy.
 // One graph is captured per set of optional path-kernel features (hole,
-// source term); a tick replays the one for the union of the active
+// source term, shift or damping); a tick replays the one for the union of the active
 // instances' features.  Admitting or retiring an instance edits the tables
 // between ticks; the graphs are never re-captured.  Instance memory comes from one device pool managed by
 // a first-fit allocator; admission fails with FK_ENOMEM when the pool cannot
@@ -112,8 +112,8 @@ struct fk_engine {
     PoolAllocator pool;
     bool tables_dirty = true;
     int32_t n_active = 0;
-    hipGraph_t graph[4] = {};         // per feature set of the path kernel
-    hipGraphExec_t exec[4] = {};
+    hipGraph_t graph[8] = {};         // per feature set of the path kernel
+    hipGraphExec_t exec[8] = {};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double kernel_ms_total = 0.0;
     int64_t launches = 0;
@@ -230,7 +230,7 @@ fk_status fk_engine_create(const fk_engine_config *cfg, void *hip_stream, fk_eng
     if ((err = hipEventCreate(&e->ev0)) != hipSuccess || (err = hipEventCreate(&e->ev1)) != hipSuccess)
         return bail(hip_fail(err, "hipEventCreate"));
     e->pool.reset(e->pool_bytes);
-    for (int f = 0; f < 4; ++f) {
+    for (int f = 0; f < 8; ++f) {
         fk_status st = capture_graph(e, f);
         if (st != FK_OK) return bail(st);
     }
@@ -394,7 +394,7 @@ fk_status fk_engine_destroy(fk_engine *e)
     if (!e) return FK_OK;
     if (e->user_stream) (void)hipStreamSynchronize(e->user_stream);
     if (e->cap_stream) (void)hipStreamSynchronize(e->cap_stream);
-    for (int f = 0; f < 4; ++f) {
+    for (int f = 0; f < 8; ++f) {
         if (e->exec[f]) (void)hipGraphExecDestroy(e->exec[f]);
         if (e->graph[f]) (void)hipGraphDestroy(e->graph[f]);
     }

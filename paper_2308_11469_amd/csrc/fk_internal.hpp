@@ -22,7 +22,8 @@ struct EngineQueue {
 }  // namespace fkd
 
 namespace fkk {
-// features: bit 0 some instance has a hole, bit 1 some instance has a source
+// features: bit 0 some instance has a hole, bit 1 a source term, bit 2 a
+// shift alpha != k^2 or a damping
 hipError_t launch_stream(int precision, int features, const fkd::Inst *d_insts, const fkd::EngineQueue *Q,
                          unsigned long long *head, int n_blocks, hipStream_t s);
 hipError_t launch_reset(const fkd::Inst *d_insts, const int32_t *which, int32_t n, const int32_t *n_dev,

@@ -18,13 +18,6 @@
 namespace fkd {
 
 // Per-precision constants of an instance, hoisted out of the stepping loop.
-// Optional parts of the stepping loop.  The path kernel is compiled per set
-// of features; an instance runs in any kernel whose set contains its own
-// (the run-time checks stay), and a kernel without a feature carries neither
-// its code nor its constants across the loop.
-constexpr int kFeatDisc = 1;     // the domain has a hole
-constexpr int kFeatSource = 2;   // f is not zero
-
 // The normals' lookup tables per precision (FP64 only; they live in LDS).
 template <class R> struct TablesOf { using type = F64Tables; };
 template <> struct TablesOf<float> { using type = NoTables; };
@@ -47,6 +40,10 @@ template <class R> struct Consts {
     int jmax;
     int disc, src_kind;
     int cells;          // the gather copy of u_n is cell-major
+    double q;           // discount per step, e^{-(alpha - k^2) h}
+    R alpha, damp;      // coefficient alpha + i p of the iterate
+    int general;        // this instance has a shift or damping (else it
+                        // takes the plain arithmetic, bit for bit)
     uint32_t key0, key1;
     const typename TablesOf<R>::type *tab;   // the block's normals tables
     // Byte offset of cell (p, q)'s first 16-byte read is p * sx + q * sy; the
@@ -61,7 +58,9 @@ template <class R> struct Consts {
           cxf((R)D.cx), cyf((R)D.cy), r2f((R)D.r2), band((R)(1e-5 * (D.r + 1.0))),
           src_re((R)D.src_re), src_im((R)D.src_im), src_cx((R)D.src_cx), src_cy((R)D.src_cy),
           src_c((R)D.src_c), pmax((R)(D.nx - 2)), qmax((R)(D.ny - 2)), jmax((int)D.jmax),
-          disc(D.disc), src_kind(D.src_kind), cells(D.cells), key0(D.key0), key1(D.key1),
+          disc(D.disc), src_kind(D.src_kind), cells(D.cells), q(D.q), alpha((R)D.alpha), damp((R)D.damp),
+          general(D.alpha != D.k2 || D.damp != 0.0),
+          key0(D.key0), key1(D.key1),
           tab(T)
     {
         if (sizeof(R) == 4) {
@@ -93,6 +92,7 @@ template <class R> struct Consts {
 template <class R> struct PathState {
     R x, y;       // position
     double ar, ai;  // sum of the integrand over the left points
+    double w;     // discount e^{-(alpha - k^2) t h} at the current point (1 without a shift)
     int t;        // steps taken
 };
 
@@ -254,12 +254,19 @@ __device__ __forceinline__ void source(const Consts<R> &K, R x, R y, R &fr, R &f
 // two left points are in flight together and overlap the exit tests; the
 // second step counts only if the first did not end the path.  Returns true
 // when the path is finished (exited or capped).
-// The integrand f - k^2 I_h[u_n] is formed as -(k2u v) + f with k2u = k^2,
-// or 0 while u_n = 0 (n = 0): the gather then still runs but adds nothing,
-// so no lane-dependent branch separates the two gathers.
+// The integrand f - (alpha + i p) I_h[u_n] is formed as -(cu v) + f with the
+// coefficient cu = alpha + i p (k^2 without a shift or damping), or 0 while
+// u_n = 0 (n = 0): the gather then still runs but adds nothing, so no
+// lane-dependent branch separates the two gathers.  With a shift the
+// values at step t carry the discount e^{-(alpha - k^2) t h}, kept in FP64 and
+// advanced by the factor q = e^{-(alpha - k^2) h} per step.
+template <class R> struct Coef {
+    R re, im;
+};
+
 template <class R, int F>
 __device__ __forceinline__ bool advance(const Inst &D, const Consts<R> &K, PathState<R> &P, uint32_t m,
-                                        uint32_t node, uint32_t ctr3, R k2u, bool &exited)
+                                        uint32_t node, uint32_t ctr3, Coef<R> cu, bool &exited)
 {
     // Both points' reads are issued after the normals.  (Issuing the
     // current point's before the Philox block was measured slower on large
@@ -280,7 +287,19 @@ __device__ __forceinline__ bool advance(const Inst &D, const Consts<R> &K, PathS
     R v0r, v0i, v1r, v1i;
     value(g0, v0r, v0i);
     value(g1, v1r, v1i);
-    R fr = -(k2u * v0r), fi = -(k2u * v0i), gr = -(k2u * v1r), gi = -(k2u * v1i);
+    R fr, fi, gr, gi;
+    const bool general = (F & kFeatGeneral) && K.general;
+    if (general) {
+        fr = -(cu.re * v0r - cu.im * v0i);
+        fi = -(cu.re * v0i + cu.im * v0r);
+        gr = -(cu.re * v1r - cu.im * v1i);
+        gi = -(cu.re * v1i + cu.im * v1r);
+    } else {
+        fr = -(cu.re * v0r);
+        fi = -(cu.re * v0i);
+        gr = -(cu.re * v1r);
+        gi = -(cu.re * v1i);
+    }
     if ((F & kFeatSource) && K.src_kind != SRC_ZERO) {
         R sr, si;
         source<R>(K, P.x, P.y, sr, si);
@@ -293,16 +312,28 @@ __device__ __forceinline__ bool advance(const Inst &D, const Consts<R> &K, PathS
     const bool out1 = is_out<F>(D, K, x1, y1);
     const bool out2 = is_out<F>(D, K, x2, y2);
     const bool second = !out1 && P.t + 1 < K.jmax;
-    if (second) {
-        fr += gr;
-        fi += gi;
+    if (general) {
+        // each value with its own discount, summed in FP64
+        const double w1 = P.w * K.q;
+        P.ar += P.w * (double)fr;
+        P.ai += P.w * (double)fi;
+        if (second) {
+            P.ar += w1 * (double)gr;
+            P.ai += w1 * (double)gi;
+        }
+        P.w = second ? w1 * K.q : w1;
+    } else {
+        if (second) {
+            fr += gr;
+            fi += gi;
+        }
+        P.ar += (double)fr;
+        P.ai += (double)fi;
     }
     P.x = second ? x2 : x1;
     P.y = second ? y2 : y1;
     P.t += second ? 2 : 1;
     exited = second ? out2 : out1;
-    P.ar += (double)fr;
-    P.ai += (double)fi;
     return exited || P.t >= K.jmax;
 }
 
@@ -310,6 +341,7 @@ __device__ __forceinline__ bool advance(const Inst &D, const Consts<R> &K, PathS
 // sum (FP64), its exit-step index and the node it belongs to.
 struct Pending {
     double x, y, ar, ai;
+    double wj;            // discount at the exit step
     int32_t t, node_idx;
     bool exited, live;
 };
@@ -321,18 +353,24 @@ __device__ __forceinline__ void park(Pending &Q, const PathState<R> &P, bool exi
     Q.y = (double)P.y;
     Q.ar = P.ar;
     Q.ai = P.ai;
+    Q.wj = P.w;
     Q.t = P.t;
     Q.node_idx = node_idx;
     Q.exited = exited;
     Q.live = true;
 }
 
-// Score of a finished path: g at the nearest boundary point minus h times
-// the left-point sum (Sec. 2.1 eq. (2.3) with c = 0: the f-term enters with
-// a minus sign).
+// Score of a finished path: the discounted datum g at the nearest boundary
+// point minus h times the (discounted) left-point sum (Sec. 2.1 eq. (2.3)
+// with killing rate c = alpha - k^2: the f-term enters with a minus sign).
+template <int F>
 __device__ __forceinline__ double2 score(const Inst &D, const Pending &Q)
 {
-    const double2 g = exit_datum(D, Q.x, Q.y, Q.exited);
+    const double2 g = exit_datum<F>(D, Q.x, Q.y, Q.exited);
+    // an instance without shift or damping scores exactly as in the kernels
+    // without the feature (no multiply by the unit discount)
+    if ((F & kFeatGeneral) && (D.alpha != D.k2 || D.damp != 0.0))
+        return make_double2(Q.wj * g.x - D.h * Q.ar, Q.wj * g.y - D.h * Q.ai);
     return make_double2(g.x - D.h * Q.ar, g.y - D.h * Q.ai);
 }
 
@@ -381,10 +419,11 @@ struct NodeAcc {
 // exact 64-bit LDS atomics (no return) into the accumulator of the path's
 // node, or, for a path that outlived two node changes of its wave, straight
 // to the node's slot in global memory.
+template <int F>
 __device__ __forceinline__ void deposit_parked(const Inst &D, Pending &Q, const NodeAcc &A)
 {
     if (Q.live) {
-        const double2 sc = score(D, Q);
+        const double2 sc = score<F>(D, Q);
         const bool ok = fabs(sc.x) < 0x1p21 && fabs(sc.y) < 0x1p21;
         unsigned long long *dst = Q.node_idx == A.node0   ? A.buf0
                                   : Q.node_idx == A.node1 ? A.buf1
@@ -425,6 +464,7 @@ __device__ __forceinline__ void start(PathState<R> &P, R sx, R sy)
     P.x = sx;
     P.y = sy;
     P.ar = P.ai = 0.0;
+    P.w = 1.0;
     P.t = 0;
 }
 
@@ -491,7 +531,10 @@ __device__ __forceinline__ void stream_paths(const Inst *__restrict__ insts, con
         const int32_t inst = Q->seg_inst[seg];
         const Inst &D = insts[inst];
         const Consts<R> K(D, &tables);
-        const R k2u = D.state->use_u != 0 ? K.k2 : (R)0;
+        const bool use_u = D.state->use_u != 0;
+        Coef<R> cu;
+        cu.re = use_u ? ((F & kFeatGeneral) ? K.alpha : K.k2) : (R)0;
+        cu.im = use_u && (F & kFeatGeneral) ? K.damp : (R)0;
         const uint32_t ctr3 = D.crn ? 0u : (uint32_t)D.state->iter;
 
         // wave-uniform pool: path indices [pool_m, pool_end) of one node
@@ -531,7 +574,7 @@ __device__ __forceinline__ void stream_paths(const Inst *__restrict__ insts, con
         bool active = false;
         int32_t node = 0, node_idx = 0;
         uint32_t m = 0;
-        auto flush = [&]() { deposit_parked(D, Qp, A); };
+        auto flush = [&]() { deposit_parked<F>(D, Qp, A); };
 
         for (;;) {
             // give every idle lane the next path index, opening items as needed
@@ -568,7 +611,7 @@ __device__ __forceinline__ void stream_paths(const Inst *__restrict__ insts, con
             }
             if (__ballot(active) == 0ull) break;
             bool fin = false, exited = false;
-            if (active) fin = advance<R, F>(D, K, P, m, (uint32_t)node, ctr3, k2u, exited);
+            if (active) fin = advance<R, F>(D, K, P, m, (uint32_t)node, ctr3, cu, exited);
             const unsigned long long done = __ballot(fin);
             if (done) {
                 // score the parked paths first when a finishing lane still
@@ -798,7 +841,10 @@ __global__ void fk_debug_paths_kernel(const Inst *__restrict__ inst, const int32
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const Inst &D = *inst;
     const Consts<R> K(D, &tables);
-    const R k2u = D.state->use_u != 0 ? K.k2 : (R)0;
+    const bool use_u = D.state->use_u != 0;
+    Coef<R> cu;
+    cu.re = use_u ? K.alpha : (R)0;
+    cu.im = use_u ? K.damp : (R)0;
     const uint32_t ctr3 = D.crn ? 0u : (uint32_t)D.state->iter;
     if (i >= n) return;
     const int32_t node = nodes[i];
@@ -806,12 +852,12 @@ __global__ void fk_debug_paths_kernel(const Inst *__restrict__ inst, const int32
     PathState<R> P;
     start(P, (R)(D.x0 + (double)gi * D.dx), (R)(D.y0 + (double)gj * D.dy));
     bool exited = false;
-    while (!advance<R, kFeatDisc | kFeatSource>(D, K, P, (uint32_t)ms[i], (uint32_t)node, ctr3, k2u, exited)) {
+    while (!advance<R, kFeatAll>(D, K, P, (uint32_t)ms[i], (uint32_t)node, ctr3, cu, exited)) {
     }
     J[i] = P.t;
     Pending Q;
     park<R>(Q, P, exited, 0);
-    score_out[i] = score(D, Q);
+    score_out[i] = score<kFeatAll>(D, Q);
     xj[i] = make_double2((double)P.x, (double)P.y);
 }
 
@@ -838,11 +884,15 @@ hipError_t launch_stream(int precision, int features, const Inst *d_insts, const
                          unsigned long long *head, int n_blocks, hipStream_t s)
 {
     dim3 grid(n_blocks), block(256);
-    switch (features & (kFeatDisc | kFeatSource)) {
+    switch (features & kFeatAll) {
     case 0: launch_stream_f<0>(precision, grid, block, d_insts, Q, head, s); break;
-    case kFeatDisc: launch_stream_f<kFeatDisc>(precision, grid, block, d_insts, Q, head, s); break;
-    case kFeatSource: launch_stream_f<kFeatSource>(precision, grid, block, d_insts, Q, head, s); break;
-    default: launch_stream_f<kFeatDisc | kFeatSource>(precision, grid, block, d_insts, Q, head, s); break;
+    case 1: launch_stream_f<1>(precision, grid, block, d_insts, Q, head, s); break;
+    case 2: launch_stream_f<2>(precision, grid, block, d_insts, Q, head, s); break;
+    case 3: launch_stream_f<3>(precision, grid, block, d_insts, Q, head, s); break;
+    case 4: launch_stream_f<4>(precision, grid, block, d_insts, Q, head, s); break;
+    case 5: launch_stream_f<5>(precision, grid, block, d_insts, Q, head, s); break;
+    case 6: launch_stream_f<6>(precision, grid, block, d_insts, Q, head, s); break;
+    default: launch_stream_f<7>(precision, grid, block, d_insts, Q, head, s); break;
     }
     return hipGetLastError();
 }

@@ -159,6 +159,9 @@ fk_status setup_problem(const fk_domain *domain, const fk_source *f, const fk_bc
     if (p.waves_per_cu < 0 || p.waves_per_cu > 32 || p.waves_per_cu % 4 != 0)
         return fail(FK_EINVAL, "waves_per_cu must be 0 or a multiple of 4 in [4, 32]");
     if (p.reserved != 0) return fail(FK_EINVAL, "fk_params.reserved must be 0");
+    if (!std::isfinite(p.alpha) || (p.alpha != 0.0 && p.alpha < p.k * p.k))
+        return fail(FK_EINVAL, "alpha must be 0 (meaning k^2) or >= k^2");
+    if (!std::isfinite(p.damping) || p.damping < 0.0) return fail(FK_EINVAL, "damping must be finite and >= 0");
     if (p.gather_layout < FK_GATHER_AUTO || p.gather_layout > FK_GATHER_CELLS)
         return fail(FK_EINVAL, "gather_layout must be FK_GATHER_AUTO, _NODES or _CELLS");
     if (p.paths_per_item < 0 || p.paths_per_item % 64 != 0)
@@ -272,7 +275,7 @@ InstanceBuffers carve(const HostProblem &P, char *base)
     return B;
 }
 
-static void fill_bc(fkd::BCDev &dst, const fk_bc &src, const double2 *table, int64_t len)
+static void fill_bc(fkd::BCDev &dst, const fk_bc &src, const double2 *table, int64_t len, const fk_params &par)
 {
     std::memset(&dst, 0, sizeof(dst));
     dst.kind = src.kind;
@@ -281,6 +284,16 @@ static void fill_bc(fkd::BCDev &dst, const fk_bc &src, const double2 *table, int
         dst.c[1] = src.c[1];
         dst.c[2] = std::cos(src.c[2]);
         dst.c[3] = std::sin(src.c[2]);
+        // wavenumber kappa = sqrt(k^2 + i p) (principal root; k when p = 0)
+        double kr = par.k, ki = 0.0;
+        if (par.damping != 0.0) {
+            const double k2 = par.k * par.k;
+            const double mod = std::sqrt(k2 * k2 + par.damping * par.damping);
+            kr = std::sqrt(0.5 * (mod + k2));
+            ki = par.damping / (2.0 * kr);
+        }
+        dst.c[4] = kr;
+        dst.c[5] = ki;
     } else if (src.kind == FK_BC_BILINEAR) {
         for (int i = 0; i < 8; ++i) dst.c[i] = src.c[i];
     } else if (src.kind == FK_BC_TABLE) {
@@ -312,10 +325,13 @@ fkd::Inst make_inst(const HostProblem &P, const InstanceBuffers &B)
     D.src_re = P.src.amp_re; D.src_im = P.src.amp_im;
     D.src_cx = P.src.cx; D.src_cy = P.src.cy;
     D.src_c = P.src.kind == FK_SRC_GAUSSIAN ? 1.0 / (2.0 * P.src.sigma * P.src.sigma) : 0.0;
-    fill_bc(D.outer, P.outer, B.table, (int64_t)P.table.size() / 2);
-    fill_bc(D.inner, P.inner, nullptr, 0);
+    fill_bc(D.outer, P.outer, B.table, (int64_t)P.table.size() / 2, P.par);
+    fill_bc(D.inner, P.inner, nullptr, 0, P.par);
     D.k = P.par.k;
     D.k2 = P.par.k * P.par.k;
+    D.alpha = P.alpha();
+    D.damp = P.par.damping;
+    D.q = std::exp(-(D.alpha - D.k2) * P.par.h);
     D.h = P.par.h;
     D.sigma = std::sqrt(2.0 * P.par.h);
     D.M = P.par.M;

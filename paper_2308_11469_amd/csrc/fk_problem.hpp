@@ -43,11 +43,14 @@ struct HostProblem {
     int64_t n_items = 0;
     int32_t cells = 0;                // the gather copy of u_n is cell-major
     // optional parts of the stepping loop this instance needs (bit 0 a hole,
-    // bit 1 a source term); the path kernel is compiled per set
+    // bit 1 a source term, bit 2 a shift alpha != k^2 or damping); the path
+    // kernel is compiled per set
     int features() const
     {
-        return (dom.kind == FK_DOMAIN_RECT_MINUS_DISC ? 1 : 0) | (src.kind != FK_SRC_ZERO ? 2 : 0);
+        return (dom.kind == FK_DOMAIN_RECT_MINUS_DISC ? 1 : 0) | (src.kind != FK_SRC_ZERO ? 2 : 0) |
+               (alpha() != par.k * par.k || par.damping != 0.0 ? 4 : 0);
     }
+    double alpha() const { return par.alpha == 0.0 ? par.k * par.k : par.alpha; }
     size_t n_nodes() const { return (size_t)dom.nx * (size_t)dom.ny; }
     size_t n_cells() const { return (size_t)(dom.nx - 1) * (size_t)(dom.ny - 1); }
     // bytes of the gather copy of the iterate: FP32 row-major 8 per node or

@@ -58,7 +58,8 @@ class fk_params(C.Structure):
                 ("precision", C.c_int32), ("max_iters", C.c_int32), ("tol", C.c_double),
                 ("max_steps", C.c_int64), ("crn", C.c_int32), ("g_unprojected", C.c_int32),
                 ("paths_per_item", C.c_int32), ("gather_layout", C.c_int32),
-                ("waves_per_cu", C.c_int32), ("reserved", C.c_int32)]
+                ("waves_per_cu", C.c_int32), ("reserved", C.c_int32),
+                ("alpha", C.c_double), ("damping", C.c_double)]
 
 
 class fk_iter_report(C.Structure):
@@ -192,6 +193,8 @@ class Marshalled:
         par.paths_per_item = int(paths_per_item)
         par.gather_layout = GATHER[gather_layout] if isinstance(gather_layout, str) else int(gather_layout)
         par.waves_per_cu = int(waves_per_cu)
+        par.alpha = 0.0 if getattr(p, "alpha", None) is None else float(p.alpha)
+        par.damping = float(getattr(p, "damping", 0.0))
         self.domain, self.source, self.outer, self.inner, self.params = d, f, bcs[0], bcs[1], par
 
     def args(self):

@@ -78,7 +78,9 @@ def lambda1(p) -> float:
 
 
 def predicted_rho(p) -> float:
-    """Contraction ratio of the iteration as the estimator sees it: k^2 over
+    """Contraction ratio of the iteration as the estimator sees it:
+    |alpha + i p| / (lambda_1 + alpha - k^2) (k^2 / lambda_1 without shift or
+    damping; the iteration of Sec. 2.2 multiplies the first mode by this), with
     lambda_1 of the domain enlarged by the discrete-monitoring shift
     delta = beta sqrt(2h) (outer boundary out by delta, hole in by delta)."""
     d = BGK_BETA * math.sqrt(2 * p.h)
@@ -88,7 +90,8 @@ def predicted_rho(p) -> float:
     else:
         grown = p.replace(x0=p.x0 - d, x1=p.x1 + d, y0=p.y0 - d, y1=p.y1 + d, r=max(p.r - d, 1e-9))
         lam = lambda1(grown)
-    return p.k ** 2 / lam
+    alpha = p.k ** 2 if getattr(p, "alpha", None) is None else p.alpha
+    return abs(complex(alpha, getattr(p, "damping", 0.0))) / (lam + alpha - p.k ** 2)
 
 
 SETTLE_RATIO = 1.125

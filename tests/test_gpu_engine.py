@@ -26,7 +26,9 @@ def mix(precision):
     c = W.scatter_problem(k=2.0, theta=1.0, N=25, M=200, seed=5007, precision=precision, h=2e-3,
                           table_len=2048)
     d = W.cavity_source(precision=precision).replace(nx=13, ny=13, M=128, h=2e-3)
-    return [a, b, c, d]
+    # the general iteration (shift and damping) in the same launch as the rest
+    e = W.cavity_small().replace(precision=precision, M=256, alpha=6.0, damping=1.0, seed=17)
+    return [a, b, c, d, e]
 
 
 def engine(precision, n=8):

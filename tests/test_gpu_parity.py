@@ -67,8 +67,14 @@ def _cases():
                     outer=W.BC("bilinear", coeffs=(0.3 + 1j, 2.0, -1j, 0.5)))
     capped = c1.replace(jmax=7)
     crn = c1.replace(crn=True)
+    # the general cavity iteration: shift alpha > k^2 and damping p (discount,
+    # complex coefficient, damped plane-wave data), also with a source and a hole
+    general = c1.replace(alpha=7.0, damping=2.0)
+    general_src_disc = disc.replace(alpha=9.0, damping=1.5, src_kind="gaussian", src_amp=0.5 - 1j,
+                                    src_cx=0.4, src_cy=-0.3, src_sigma=0.2)
     return {"cavity_9x9": c1, "gaussian_17": gauss, "disc_33": disc, "aniso_23x7": aniso,
-            "bilinear_unprojected": bil, "capped_jmax7": capped, "crn": crn}
+            "bilinear_unprojected": bil, "capped_jmax7": capped, "crn": crn,
+            "general_9x9": general, "general_src_disc_33": general_src_disc}
 
 
 @pytest.mark.parametrize("name", list(_cases().keys()))
@@ -99,7 +105,8 @@ def test_single_paths_bit_exact_exit_steps(name):
 
 # --------------------------------------------------- node estimates (FP64)
 
-@pytest.mark.parametrize("name", ["cavity_9x9", "gaussian_17", "disc_33", "aniso_23x7", "crn"])
+@pytest.mark.parametrize("name", ["cavity_9x9", "gaussian_17", "disc_33", "aniso_23x7", "crn", "general_9x9",
+                                  "general_src_disc_33"])
 def test_node_estimates_fp64_per_iteration(name):
     p = _cases()[name]
     say("nodes fp64", name)
@@ -197,7 +204,7 @@ def test_gather_layouts_bit_identical(name, precision):
     for a, b in zip(*runs):
         assert np.array_equal(a, b)
 
-@pytest.mark.parametrize("name", ["cavity_9x9", "gaussian_17", "disc_33"])
+@pytest.mark.parametrize("name", ["cavity_9x9", "gaussian_17", "disc_33", "general_9x9", "general_src_disc_33"])
 def test_fp32_within_tenth_of_standard_error(name):
     p = _cases()[name].replace(M=2048)
     say("fp32 vs fp64", name)

@@ -166,6 +166,10 @@ def test_predicted_rho_rectangle_and_disc():
     rho = serving.predicted_rho(p)
     assert 0.8 < rho < 0.84                   # k^2 / lambda_1 of the BGK-enlarged square
     assert serving.predicted_rho(p.replace(k=4.6)) > 1
+    # with a shift and damping: |alpha + i p| / (lambda_1 + alpha - k^2)
+    lam_sq = serving.predicted_rho(p.replace(k=1.0)) ** -1
+    g = p.replace(k=1.0, alpha=4.0, damping=3.0)
+    assert serving.predicted_rho(g) == pytest.approx(5.0 / (lam_sq + 3.0))
     q = W.scatter_problem(k=3.0, theta=0.0, N=65, M=64, seed=1, h=1e-4, table_len=64)
     lam = serving.lambda1(q)
     assert 12.5 < lam < 13.5                  # [-1,1]^2 minus the r = 0.25 disc
