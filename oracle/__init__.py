@@ -15,11 +15,18 @@ Contents
     paths of ``y + sqrt(2) W``, first exit, boundary datum at the nearest
     boundary point, left-point integral of ``f - k^2 u_n`` and per-node mean and
     variance (Sec. 2.1 eq. (2.3); Sec. 2.2; Remark 2.1), plus the fixed-point
-    loop with its stopping and divergence rules (Sec. 3).
+    loop with its stopping and divergence rules (Sec. 3).  With a reflecting
+    edge (Sec. 2.3): mirrored steps, the local time on the edge and the Robin
+    coupling d_n U_{n+1} = i k U_n + g2.
 ``fd.py``
     Five-point finite differences: the direct Helmholtz solve and the
     Neumann-series iterate ``u_{n+1} = Delta_h^{-1}(f - k^2 u_n)`` whose
     convergence is governed by the spectral radius of ``G`` (Sec. 2.4).
+``fd_mixed.py``
+    Finite differences with a reflecting (Neumann / Robin) edge around an
+    absorbing hole: mean exit time and mean local time (Table 1), the direct
+    Robin solve, the annular iteration and the spectral radius of its matrix
+    (Sec. 2.4).
 ``closed_forms.py``
     Exact solutions that pin the above: plane waves, the sound-soft disc
     series, the exit-time (torsion) series of Remark 2.5 and ``lambda_1``.

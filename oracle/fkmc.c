@@ -30,6 +30,14 @@
  *       U_{n+1}(y) = E[e^{-c tau} g(Y_tau)]
  *                    - E[int_0^tau e^{-c s} (f - (alpha + i p) U_n)(Y_s) ds].
  *     alpha = k^2, p = 0 is the iteration above.
+ *   - Reflecting outer boundary (Sec. 2.1 eqs. (2.1)-(2.3) with a Neumann
+ *     part; the annular iteration of Sec. 2.3): the hole is absorbing
+ *     (u = phi there), the rectangle's edge carries the Robin condition
+ *     d_n u - i k u = g2.  The partial sums of the iteration of Sec. 2.3
+ *     satisfy d_n U_{n+1} = i k U_n + g2 on the edge (for g2 = 0 the
+ *     conditions on v_n and w_n written there), and the Feynman-Kac formula
+ *     with the reflected diffusion dY = sqrt(2) dW - n dxi and its local time
+ *     xi adds  + E[int_0^tau e^{-c s} (i k U_n + g2)(Y_s) dxi_s]  to U_{n+1}.
  *
  * Discretisation (the readings where the paper is silent):
  *   - Euler-Maruyama: X_0 = y, X_{t+1} = X_t + sqrt(2h) (z_x, z_y).
@@ -49,6 +57,15 @@
  *   - Plane-wave data: amp exp(i kappa (x cos theta + y sin theta)) with
  *     kappa = sqrt(k^2 + i p) (principal root), the plane wave that solves
  *     the damped equation; kappa = k when p = 0.
+ *   - Reflection (a reading: the paper gives no discretisation of the
+ *     reflected diffusion): after each Euler step a coordinate that left the
+ *     rectangle is mirrored back across the face it crossed, and the local
+ *     time grows by the length of the mirror move, 2 x (overshoot); the
+ *     local-time integrand (i k I_h[u_n] + g2) is taken at the foot of the
+ *     move on the face (the mirrored point with that coordinate set to the
+ *     face) and discounted to the end of the step.  Then the step is
+ *     absorbed when the point lies in the closed hole.  Every edge node of
+ *     the grid is an unknown.
  */
 #include <math.h>
 #include <stdint.h>
@@ -60,15 +77,20 @@
 
 /* ---------------------------------------------------------------- types -- */
 
-enum { ORC_RECT = 0, ORC_RECT_MINUS_DISC = 1 };
+enum { ORC_RECT = 0, ORC_RECT_MINUS_DISC = 1, ORC_RECT_MINUS_BOX = 2 };
 enum { ORC_SRC_ZERO = 0, ORC_SRC_CONST = 1, ORC_SRC_GAUSSIAN = 2 };
-enum { ORC_BC_ZERO = 0, ORC_BC_PLANE_WAVE = 1, ORC_BC_BILINEAR = 2, ORC_BC_TABLE = 3 };
+enum { ORC_BC_ZERO = 0, ORC_BC_PLANE_WAVE = 1, ORC_BC_BILINEAR = 2, ORC_BC_TABLE = 3,
+       ORC_BC_PLANE_WAVE_ROBIN = 4 };
 
 /* Boundary datum.  PLANE_WAVE: c = (amp_re, amp_im, theta) and
  * g = amp exp(i k (x cos theta + y sin theta)).  BILINEAR: c holds the complex
  * coefficients (c0, c1, c2, c3), g = c0 + c1 x + c2 y + c3 x y.  TABLE: samples
  * (re, im interleaved) at equal arclength steps round the rectangle,
- * counter-clockwise from (x0, y0), linearly interpolated and periodic. */
+ * counter-clockwise from (x0, y0), linearly interpolated and periodic.
+ * PLANE_WAVE_ROBIN (reflecting edge only): the Robin datum
+ * g2 = d_n w - i k w of the plane wave w of PLANE_WAVE, so that w itself
+ * solves the Robin problem; on a reflecting edge every other kind gives g2
+ * directly. */
 typedef struct {
     int32_t kind;
     int32_t pad;
@@ -93,6 +115,9 @@ typedef struct {
     int32_t g_unprojected; /* test variant: g taken at X_J itself */
     double alpha;          /* shift, >= k^2 */
     double p;              /* damping */
+    double ry;             /* RECT_MINUS_BOX: the hole is [cx-r, cx+r] x [cy-ry, cy+ry] */
+    int32_t reflect;       /* 1: the rectangle's edge reflects (Robin datum outer) */
+    int32_t pad2;
 } orc_problem;
 
 /* --------------------------------------------------------------- Philox -- */
@@ -151,28 +176,81 @@ void orc_node_xy(const orc_problem *P, int32_t node_id, double xy[2])
     xy[1] = P->y0 + (double)j * grid_dy(P);
 }
 
+/* The closed hole: the disc of radius r at (cx, cy), or the box
+ * [cx - r, cx + r] x [cy - ry, cy + ry]. */
 static int in_hole(const orc_problem *P, double x, double y)
 {
-    if (P->domain_kind != ORC_RECT_MINUS_DISC) return 0;
-    double ex = x - P->cx, ey = y - P->cy;
-    return ex * ex + ey * ey <= P->r * P->r;
+    if (P->domain_kind == ORC_RECT_MINUS_DISC) {
+        double ex = x - P->cx, ey = y - P->cy;
+        return ex * ex + ey * ey <= P->r * P->r;
+    }
+    if (P->domain_kind == ORC_RECT_MINUS_BOX)
+        return x >= P->cx - P->r && x <= P->cx + P->r && y >= P->cy - P->ry && y <= P->cy + P->ry;
+    return 0;
 }
 
-/* The open domain: strictly inside the rectangle and strictly outside the disc. */
+/* A point outside the domain: for an absorbing edge, outside the open
+ * rectangle or in the closed hole; for a reflecting edge (whose points
+ * belong to the domain), in the closed hole. */
 int orc_outside(const orc_problem *P, double x, double y)
 {
-    if (x <= P->x0 || x >= P->x1 || y <= P->y0 || y >= P->y1) return 1;
+    if (!P->reflect && (x <= P->x0 || x >= P->x1 || y <= P->y0 || y >= P->y1)) return 1;
     return in_hole(P, x, y);
 }
 
-/* 0 interior, 1 on the rectangle edge, 2 in the closed disc. */
+/* A grid node in the closed hole.  For the box, nodes within 1e-9 of a
+ * grid step of its edges count as on them, so that a box whose edges are
+ * meant to lie on grid lines keeps its edge nodes whatever the rounding of
+ * x0 + i dx. */
+static int node_in_hole(const orc_problem *P, double x, double y)
+{
+    if (P->domain_kind != ORC_RECT_MINUS_BOX) return in_hole(P, x, y);
+    const double ex = 1e-9 * grid_dx(P), ey = 1e-9 * grid_dy(P);
+    return x >= P->cx - P->r - ex && x <= P->cx + P->r + ex && y >= P->cy - P->ry - ey
+        && y <= P->cy + P->ry + ey;
+}
+
+/* 0 unknown (interior, or on a reflecting edge), 1 on an absorbing edge,
+ * 2 in the closed hole. */
 int orc_node_class(const orc_problem *P, int32_t node_id)
 {
     int32_t i = node_id % P->nx, j = node_id / P->nx;
-    if (i == 0 || j == 0 || i == P->nx - 1 || j == P->ny - 1) return 1;
     double xy[2];
     orc_node_xy(P, node_id, xy);
-    return in_hole(P, xy[0], xy[1]) ? 2 : 0;
+    if (node_in_hole(P, xy[0], xy[1])) return 2;
+    if (!P->reflect && (i == 0 || j == 0 || i == P->nx - 1 || j == P->ny - 1)) return 1;
+    return 0;
+}
+
+/* Nearest point of the hole's boundary to (x, y), and its distance. */
+static double hole_project(const orc_problem *P, double x, double y, double p[2])
+{
+    if (P->domain_kind == ORC_RECT_MINUS_DISC) {
+        double ex = x - P->cx, ey = y - P->cy;
+        double d = sqrt(ex * ex + ey * ey);
+        if (d > 0.0) {
+            p[0] = P->cx + P->r * ex / d;
+            p[1] = P->cy + P->r * ey / d;
+        } else {
+            p[0] = P->cx + P->r;
+            p[1] = P->cy;
+        }
+        return fabs(d - P->r);
+    }
+    double bx0 = P->cx - P->r, bx1 = P->cx + P->r, by0 = P->cy - P->ry, by1 = P->cy + P->ry;
+    if (in_hole(P, x, y)) {
+        /* inside the box: the nearest face */
+        double dd[4] = {x - bx0, bx1 - x, y - by0, by1 - y};
+        int e = 0;
+        for (int c = 1; c < 4; ++c)
+            if (dd[c] < dd[e]) e = c;
+        p[0] = e == 0 ? bx0 : (e == 1 ? bx1 : x);
+        p[1] = e == 2 ? by0 : (e == 3 ? by1 : y);
+        return dd[e];
+    }
+    p[0] = x < bx0 ? bx0 : (x > bx1 ? bx1 : x);
+    p[1] = y < by0 ? by0 : (y > by1 ? by1 : y);
+    return hypot(x - p[0], y - p[1]);
 }
 
 /* Nearest boundary point of X.  Outside the rectangle: clamp into it (outer
@@ -181,32 +259,30 @@ int orc_node_class(const orc_problem *P, int32_t node_id)
  * edges and the circle.  Returns 1 for the outer boundary, 2 for the circle. */
 int orc_project(const orc_problem *P, double x, double y, double p[2])
 {
+    const int hole = P->domain_kind != ORC_RECT;
+    if (P->reflect) {
+        /* the Dirichlet part is the hole's boundary alone */
+        hole_project(P, x, y, p);
+        return 2;
+    }
     if (x <= P->x0 || x >= P->x1 || y <= P->y0 || y >= P->y1) {
         p[0] = x < P->x0 ? P->x0 : (x > P->x1 ? P->x1 : x);
         p[1] = y < P->y0 ? P->y0 : (y > P->y1 ? P->y1 : y);
         return 1;
     }
-    double ex = x - P->cx, ey = y - P->cy;
-    double d = sqrt(ex * ex + ey * ey);
-    int disc = P->domain_kind == ORC_RECT_MINUS_DISC;
-    if (!(disc && d <= P->r)) {
+    if (!(hole && in_hole(P, x, y))) {
         double dd[4] = {x - P->x0, P->x1 - x, y - P->y0, P->y1 - y};
         int e = 0;
         for (int c = 1; c < 4; ++c)
             if (dd[c] < dd[e]) e = c;
-        if (!disc || dd[e] <= d - P->r) {
+        double hp[2];
+        if (!hole || dd[e] <= hole_project(P, x, y, hp)) {
             p[0] = e == 0 ? P->x0 : (e == 1 ? P->x1 : x);
             p[1] = e == 2 ? P->y0 : (e == 3 ? P->y1 : y);
             return 1;
         }
     }
-    if (d > 0.0) {
-        p[0] = P->cx + P->r * ex / d;
-        p[1] = P->cy + P->r * ey / d;
-    } else {
-        p[0] = P->cx + P->r;
-        p[1] = P->cy;
-    }
+    hole_project(P, x, y, p);
     return 2;
 }
 
@@ -220,26 +296,37 @@ static double perimeter_s(const orc_problem *P, double x, double y)
     return 2.0 * a + b + (P->y1 - y);
 }
 
+/* kappa = sqrt(k^2 + i p): kr = sqrt((|k^2 + i p| + k^2) / 2),
+ * ki = p / (2 kr); kappa = k when p = 0 */
+static void kappa_of(const orc_problem *P, double *kr, double *ki)
+{
+    *kr = P->k;
+    *ki = 0.0;
+    if (P->p != 0.0) {
+        const double k2 = P->k * P->k;
+        const double mod = sqrt(k2 * k2 + P->p * P->p);
+        *kr = sqrt(0.5 * (mod + k2));
+        *ki = P->p / (2.0 * *kr);
+    }
+}
+
+static void plane_wave_eval(const orc_problem *P, const orc_bc *B, double x, double y, double g[2])
+{
+    double kr, ki;
+    kappa_of(P, &kr, &ki);
+    const double sx = x * cos(B->c[2]) + y * sin(B->c[2]);
+    const double ph = kr * sx, decay = exp(-ki * sx);
+    double cr = cos(ph) * decay, si = sin(ph) * decay;
+    g[0] = B->c[0] * cr - B->c[1] * si;
+    g[1] = B->c[0] * si + B->c[1] * cr;
+}
+
 static void bc_eval(const orc_problem *P, const orc_bc *B, double x, double y, double g[2])
 {
     switch (B->kind) {
-    case ORC_BC_PLANE_WAVE: {
-        /* kappa = sqrt(k^2 + i p): kr = sqrt((|k^2 + i p| + k^2) / 2),
-         * ki = p / (2 kr); kappa = k when p = 0 */
-        double kr = P->k, ki = 0.0;
-        if (P->p != 0.0) {
-            const double k2 = P->k * P->k;
-            const double mod = sqrt(k2 * k2 + P->p * P->p);
-            kr = sqrt(0.5 * (mod + k2));
-            ki = P->p / (2.0 * kr);
-        }
-        const double sx = x * cos(B->c[2]) + y * sin(B->c[2]);
-        const double ph = kr * sx, decay = exp(-ki * sx);
-        double cr = cos(ph) * decay, si = sin(ph) * decay;
-        g[0] = B->c[0] * cr - B->c[1] * si;
-        g[1] = B->c[0] * si + B->c[1] * cr;
+    case ORC_BC_PLANE_WAVE:
+        plane_wave_eval(P, B, x, y, g);
         return;
-    }
     case ORC_BC_BILINEAR:
         g[0] = B->c[0] + B->c[2] * x + B->c[4] * y + B->c[6] * x * y;
         g[1] = B->c[1] + B->c[3] * x + B->c[5] * y + B->c[7] * x * y;
@@ -263,14 +350,38 @@ static void bc_eval(const orc_problem *P, const orc_bc *B, double x, double y, d
     }
 }
 
-/* g at a boundary point; which = 1 outer rectangle, 2 circle. */
+/* g at a boundary point; which = 1 outer rectangle, 2 hole. */
 void orc_g(const orc_problem *P, int which, double x, double y, double g[2])
 {
     bc_eval(P, which == 2 ? &P->inner : &P->outer, x, y, g);
 }
 
+/* Robin datum g2 of a reflecting edge at a point of face `face` (0: x = x0,
+ * 1: x = x1, 2: y = y0, 3: y = y1).  For PLANE_WAVE_ROBIN, with the plane
+ * wave w = amp exp(i kappa d.x), d = (cos theta, sin theta) and the outward
+ * normal n of the face: d_n w = i kappa (d.n) w, so
+ * g2 = d_n w - i k w = i (kappa (d.n) - k) w. */
+void orc_robin(const orc_problem *P, int face, double x, double y, double g[2])
+{
+    if (P->outer.kind != ORC_BC_PLANE_WAVE_ROBIN) {
+        bc_eval(P, &P->outer, x, y, g);
+        return;
+    }
+    const double dn = face == 0 ? -cos(P->outer.c[2])
+                    : face == 1 ? cos(P->outer.c[2])
+                    : face == 2 ? -sin(P->outer.c[2]) : sin(P->outer.c[2]);
+    double kr, ki, w[2];
+    kappa_of(P, &kr, &ki);
+    plane_wave_eval(P, &P->outer, x, y, w);
+    /* i (kappa dn - k) = -ki dn + i (kr dn - k) */
+    const double ar = -ki * dn, ai = kr * dn - P->k;
+    g[0] = ar * w[0] - ai * w[1];
+    g[1] = ar * w[1] + ai * w[0];
+}
+
 /* Grid values that the iterate carries on non-interior nodes for n >= 1:
- * g on the rectangle edge, the inner datum's own formula on hole nodes. */
+ * g on an absorbing rectangle edge, the inner datum's own formula on hole
+ * nodes (a reflecting edge's nodes are unknowns). */
 void orc_fill_boundary(const orc_problem *P, double *u)
 {
     int64_t nn = (int64_t)P->nx * P->ny;
@@ -325,6 +436,60 @@ static void source_eval(const orc_problem *P, double x, double y, double f[2])
 
 /* ----------------------------------------------------------- one path -- */
 
+/* Local-time integrand (i k I_h[u_n] + g2) at a foot point on face `face`
+ * (u == NULL: u_n = 0). */
+static void local_time_integrand(const orc_problem *P, const double *u, int face, double x, double y,
+                                 double out[2])
+{
+    double un[2] = {0.0, 0.0}, g2[2];
+    if (u) orc_interp(P, u, x, y, un);
+    orc_robin(P, face, x, y, g2);
+    out[0] = -P->k * un[1] + g2[0];
+    out[1] = P->k * un[0] + g2[1];
+}
+
+/* Mirrors X (the point after step t) back into the rectangle across the
+ * faces it crossed and adds, per crossed face, the local-time increment
+ * dxi = 2 x overshoot times the discounted integrand at the foot of the
+ * move to lt.  One mirror per coordinate suffices: the rectangle is wider
+ * than any single step (checked at set-up). */
+static void reflect_step(const orc_problem *P, const double *u, int64_t t, double X[2], double lt[2])
+{
+    double dxi_x = 0.0, dxi_y = 0.0;
+    int fx = -1, fy = -1;
+    if (X[0] < P->x0) {
+        dxi_x = 2.0 * (P->x0 - X[0]);
+        X[0] = 2.0 * P->x0 - X[0];
+        fx = 0;
+    } else if (X[0] > P->x1) {
+        dxi_x = 2.0 * (X[0] - P->x1);
+        X[0] = 2.0 * P->x1 - X[0];
+        fx = 1;
+    }
+    if (X[1] < P->y0) {
+        dxi_y = 2.0 * (P->y0 - X[1]);
+        X[1] = 2.0 * P->y0 - X[1];
+        fy = 2;
+    } else if (X[1] > P->y1) {
+        dxi_y = 2.0 * (X[1] - P->y1);
+        X[1] = 2.0 * P->y1 - X[1];
+        fy = 3;
+    }
+    if (fx < 0 && fy < 0) return;
+    const double w = exp(-(P->alpha - P->k * P->k) * (double)t * P->h);
+    double v[2];
+    if (fx >= 0) {
+        local_time_integrand(P, u, fx, fx == 0 ? P->x0 : P->x1, X[1], v);
+        lt[0] += w * dxi_x * v[0];
+        lt[1] += w * dxi_x * v[1];
+    }
+    if (fy >= 0) {
+        local_time_integrand(P, u, fy, X[0], fy == 2 ? P->y0 : P->y1, v);
+        lt[0] += w * dxi_y * v[0];
+        lt[1] += w * dxi_y * v[1];
+    }
+}
+
 /* Simulates path m from node node_id for the Poisson step that produces
  * u_{n+1} from u_n (u == NULL means u_n = 0 everywhere, the start u_0).
  * Writes the score s (re, im), the exit-step index J, whether the cap was
@@ -339,6 +504,7 @@ void orc_path(const orc_problem *P, const double *u, int32_t n, int32_t node_id,
     double X[2];
     orc_node_xy(P, node_id, X);
     double acc[2] = {0.0, 0.0};
+    double lt[2] = {0.0, 0.0};   /* local-time integral (reflecting edge) */
     int64_t t = 0;
     int exited = 0;
     for (;;) {
@@ -364,6 +530,7 @@ void orc_path(const orc_problem *P, const double *u, int32_t n, int32_t node_id,
         X[0] = X[0] + sigma * z[0];
         X[1] = X[1] + sigma * z[1];
         t += 1;
+        if (P->reflect) reflect_step(P, u, t, X, lt);
         if (orc_outside(P, X[0], X[1])) { exited = 1; break; }
         if (t >= P->jmax) break;
     }
@@ -378,8 +545,8 @@ void orc_path(const orc_problem *P, const double *u, int32_t n, int32_t node_id,
         orc_g(P, which, pr[0], pr[1], g);
     }
     const double wJ = exp(-c * (double)t * P->h);
-    s[0] = wJ * g[0] - P->h * acc[0];
-    s[1] = wJ * g[1] - P->h * acc[1];
+    s[0] = wJ * g[0] - P->h * acc[0] + lt[0];
+    s[1] = wJ * g[1] - P->h * acc[1] + lt[1];
     *J_out = t;
     *capped = exited ? 0 : 1;
     xJ[0] = X[0];

@@ -16,9 +16,9 @@ import numpy as np
 
 from . import build as _build
 
-_KIND_DOMAIN = {"rect": 0, "rect_minus_disc": 1}
+_KIND_DOMAIN = {"rect": 0, "rect_minus_disc": 1, "rect_minus_box": 2}
 _KIND_SRC = {"zero": 0, "const": 1, "gaussian": 2}
-_KIND_BC = {"zero": 0, "plane_wave": 1, "bilinear": 2, "table": 3}
+_KIND_BC = {"zero": 0, "plane_wave": 1, "bilinear": 2, "table": 3, "plane_wave_robin": 4}
 
 
 class _BC(C.Structure):
@@ -36,7 +36,8 @@ class _Problem(C.Structure):
                 ("outer", _BC), ("inner", _BC),
                 ("k", C.c_double), ("h", C.c_double), ("M", C.c_int64), ("seed", C.c_uint64),
                 ("jmax", C.c_int64), ("crn", C.c_int32), ("g_unprojected", C.c_int32),
-                ("alpha", C.c_double), ("p", C.c_double)]
+                ("alpha", C.c_double), ("p", C.c_double),
+                ("ry", C.c_double), ("reflect", C.c_int32), ("pad2", C.c_int32)]
 
 
 _lib = None
@@ -65,6 +66,7 @@ def lib():
         L.orc_project.argtypes = [pp, C.c_double, C.c_double, dp]
         L.orc_project.restype = C.c_int
         L.orc_g.argtypes = [pp, C.c_int, C.c_double, C.c_double, dp]
+        L.orc_robin.argtypes = [pp, C.c_int, C.c_double, C.c_double, dp]
         L.orc_fill_boundary.argtypes = [pp, dp]
         L.orc_interp.argtypes = [pp, dp, C.c_double, C.c_double, dp]
         L.orc_path.argtypes = [pp, dp, C.c_int32, C.c_int32, C.c_int64, dp, i64p, i32p, dp]
@@ -82,7 +84,10 @@ def _dptr(a):
 def jmax_auto(p) -> int:
     """Step cap: ceil(40 / (lambda_1 h)) with lambda_1 = pi^2 (1/a^2 + 1/b^2) of
     the bounding rectangle (a lower bound for lambda_1 of the holed domain), so
-    that P(tau > cap) is about e^-40."""
+    that P(tau > cap) is about e^-40.  No such bound holds with a reflecting
+    edge: those problems state their cap."""
+    if getattr(p, "reflect", False):
+        raise ValueError("a reflecting edge needs an explicit jmax")
     a, b = p.x1 - p.x0, p.y1 - p.y0
     lam = math.pi ** 2 * (1.0 / a ** 2 + 1.0 / b ** 2)
     return int(math.ceil(40.0 / (lam * p.h)))
@@ -106,7 +111,7 @@ class Handle:
             bc = getattr(p, name)
             dst = getattr(s, name)
             dst.kind = _KIND_BC[bc.kind]
-            if bc.kind == "plane_wave":
+            if bc.kind in ("plane_wave", "plane_wave_robin"):
                 dst.c[0], dst.c[1], dst.c[2] = complex(bc.amp).real, complex(bc.amp).imag, bc.theta
             elif bc.kind == "bilinear":
                 for i, z in enumerate(bc.coeffs):
@@ -122,6 +127,8 @@ class Handle:
         s.g_unprojected = 1 if getattr(p, "g_unprojected", False) else 0
         s.alpha = p.k * p.k if p.alpha is None else float(p.alpha)
         s.p = float(p.damping)
+        s.ry = float(getattr(p, "ry", 0.0))
+        s.reflect = 1 if getattr(p, "reflect", False) else 0
         self.s = s
         self.ref = C.byref(s)
 
@@ -152,7 +159,8 @@ def box_muller(ra: int, rb: int):
 # ----------------------------------------------------------- geometry
 
 def node_classes(p) -> np.ndarray:
-    """0 interior, 1 rectangle edge, 2 hole (closed disc); shape (ny, nx)."""
+    """0 unknown (interior, or on a reflecting edge), 1 absorbing rectangle
+    edge, 2 hole (closed disc or box); shape (ny, nx)."""
     H = Handle(p)
     cls = np.array([lib().orc_node_class(H.ref, i) for i in range(p.nx * p.ny)], dtype=np.int32)
     return cls.reshape(p.ny, p.nx)
@@ -175,6 +183,14 @@ def project(p, x, y):
 def g_at(p, which, x, y) -> complex:
     out = (C.c_double * 2)()
     lib().orc_g(Handle(p).ref, int(which), float(x), float(y), out)
+    return complex(out[0], out[1])
+
+
+def robin(p, face, x, y) -> complex:
+    """Robin datum g2 of a reflecting edge at a point of face 0..3
+    (x = x0, x = x1, y = y0, y = y1)."""
+    out = (C.c_double * 2)()
+    lib().orc_robin(Handle(p).ref, int(face), float(x), float(y), out)
     return complex(out[0], out[1])
 
 

@@ -19,6 +19,12 @@ plane-wave scattering by a sound-soft obstacle of Sec. 1):
 * ``rect_batch``     256 rectangles with random sides, grids, k, theta, M.
 * ``scatter_stream`` sound-soft disc r = 0.25 in [-1, 1]^2 with exact outer
                      Dirichlet data from the Hankel series, Poisson arrivals.
+* ``annulus_shape1`` / ``annulus_shape3`` / ``annulus_fig2``  the annular
+                     problems of Sec. 2.3 and Sec. 3: a rectangle whose edge
+                     carries the Robin condition d_n u - i k u = 0 (reflected
+                     paths with local time) around an absorbing hole with
+                     u = -exp(-i k x); the geometries of the paper's shapes 1
+                     and 3 and of its finite-difference example.
 """
 from __future__ import annotations
 
@@ -31,16 +37,20 @@ import numpy as np
 
 RECT = "rect"
 RECT_MINUS_DISC = "rect_minus_disc"
+RECT_MINUS_BOX = "rect_minus_box"
 
 
 @dataclass
 class BC:
-    """Dirichlet datum on one boundary part.
+    """Datum on one boundary part: the Dirichlet value, or on a reflecting
+    edge the Robin datum g2 of d_n u - i k u = g2.
 
     kind: ``zero``; ``plane_wave`` (``amp * exp(i k (x cos theta + y sin theta))``
     with the problem's k); ``bilinear`` (``c0 + c1 x + c2 y + c3 x y`` with complex
     ``coeffs``, harmonic); ``table`` (complex samples at equal arclength steps
-    round the rectangle, counter-clockwise from ``(x0, y0)``; outer boundary only).
+    round the rectangle, counter-clockwise from ``(x0, y0)``; outer boundary only);
+    ``plane_wave_robin`` (reflecting edge only: the Robin datum of the plane
+    wave of ``plane_wave``, so that the plane wave solves the Robin problem).
     """
     kind: str = "zero"
     amp: complex = 1.0 + 0.0j
@@ -54,7 +64,11 @@ class Problem:
     """One Helmholtz instance  Delta u + k^2 u = f in Omega, u = g on dOmega.
 
     Omega is the open rectangle ``(x0, x1) x (y0, y1)``, minus the closed disc
-    of radius ``r`` at ``(cx, cy)`` when ``domain_kind == 'rect_minus_disc'``.
+    of radius ``r`` at ``(cx, cy)`` when ``domain_kind == 'rect_minus_disc'``,
+    or minus the closed box ``[cx - r, cx + r] x [cy - ry, cy + ry]`` when
+    ``domain_kind == 'rect_minus_box'``.  With ``reflect`` the rectangle's
+    edge belongs to the domain and carries the Robin condition
+    ``d_n u - i k u = g2`` (``outer`` gives g2); the hole stays Dirichlet.
     The grid has ``nx * ny`` nodes including the edges; node ``(i, j)`` has id
     ``i + nx * j``.
     """
@@ -66,6 +80,8 @@ class Problem:
     cx: float = 0.0
     cy: float = 0.0
     r: float = 0.0
+    ry: float = 0.0
+    reflect: bool = False
     nx: int = 9
     ny: int = 9
     # source f: 'zero' | 'const' (src_amp) | 'gaussian' (src_amp * exp(-|x-c|^2 / (2 sigma^2)))
@@ -242,6 +258,48 @@ def scatter_problem(k: float, theta: float, N: int, M: int, seed: int, precision
                    outer=BC("table", table=tab.astype(np.complex128)),
                    inner=BC("plane_wave", -1.0 + 0j, theta), precision=precision,
                    max_iters=40, tol=1e-3)
+
+
+def _annulus(name, x0, x1, y0, y1, hole, nx, ny, k, h, M, jmax, precision, seed):
+    """Rectangle with a reflecting (Robin) edge around an absorbing hole;
+    inner datum u = -exp(-i k x) (the plane wave of amplitude -1 and
+    direction theta = pi), Robin datum g2 = 0 (Sec. 2.3)."""
+    kind, cx, cy, r, ry = hole
+    return Problem(name=name, domain_kind=kind, x0=x0, x1=x1, y0=y0, y1=y1, cx=cx, cy=cy, r=r, ry=ry,
+                   reflect=True, nx=nx, ny=ny, k=k, h=h, M=M, seed=seed, jmax=jmax,
+                   outer=BC("zero"), inner=BC("plane_wave", -1.0 + 0j, math.pi),
+                   precision=precision, max_iters=30, tol=0.0)
+
+
+def annulus_shape1(k: float = 1.5, n: int = 61, M: int = 4096, h: float = 1e-4, precision: int = 64,
+                   seed: int = 11) -> Problem:
+    """The paper's shape 1: the square [-0.3, 0.3]^2 with the circular hole of
+    radius 0.15 at the origin; n x n grid.  Step cap 40 x 0.25 / h: the
+    mean exit time is at most about 0.03 here."""
+    return _annulus("annulus_shape1_k%g_n%d" % (k, n), -0.3, 0.3, -0.3, 0.3,
+                    (RECT_MINUS_DISC, 0.0, 0.0, 0.15, 0.0), n, n, k, h, M, int(math.ceil(10.0 / h)),
+                    precision, seed)
+
+
+def annulus_shape3(k: float = 0.5, nx: int = 41, ny: int = 65, M: int = 4096, h: float = 1e-4,
+                   precision: int = 64, seed: int = 13) -> Problem:
+    """The paper's shape 3: the rectangle [-0.5, 0.5] x [-0.8, 0.8] with the
+    rectangular hole [-0.05, 0.05] x [-0.4, 0.4]; nx x ny grid (41 x 65
+    puts the hole's edges on grid lines).  Step cap 40 x 1.6 / h: the mean
+    exit time is at most about 0.2 here."""
+    return _annulus("annulus_shape3_k%g_%dx%d" % (k, nx, ny), -0.5, 0.5, -0.8, 0.8,
+                    (RECT_MINUS_BOX, 0.0, 0.0, 0.05, 0.4), nx, ny, k, h, M, int(math.ceil(64.0 / h)),
+                    precision, seed)
+
+
+def annulus_fig2(k: float = 0.8, n: int = 21, M: int = 4096, h: float = 1e-4, precision: int = 64,
+                 seed: int = 17) -> Problem:
+    """The finite-difference example of Sec. 2.4: the square [-0.5, 0.5]^2
+    with the square hole [-0.15, 0.15]^2; n x n grid (21: grid step 0.05,
+    the hole's edges on grid lines)."""
+    return _annulus("annulus_fig2_k%g_n%d" % (k, n), -0.5, 0.5, -0.5, 0.5,
+                    (RECT_MINUS_BOX, 0.0, 0.0, 0.15, 0.15), n, n, k, h, M, int(math.ceil(20.0 / h)),
+                    precision, seed)
 
 
 def scatter_stream(n: int = 400, rate: float = 200.0, seed: int = 5, precision: int = 32):
