@@ -9,19 +9,32 @@
  *   the sequence of Poisson problems  Delta u_{n+1} = f - k^2 u_n,
  *   u_{n+1} = g on dOmega, u_0 = 0 (the shift alpha = k^2 of eq. (1.4); the
  *   partial sums in the proof of Theorem 2.2).  Each Poisson step is solved at
- *   every interior grid node y by the Feynman-Kac formula of Sec. 2.1 eq. (2.3)
+ *   every unknown grid node y by the Feynman-Kac formula of Sec. 2.1 eq. (2.3)
  *   with c = 0:  u_{n+1}(y) = E[g(Y_tau)] - E[int_0^tau (f - k^2 u_n)(Y_t) dt],
  *   Y = y + sqrt(2) W, averaged over M paths that are independent for every n
  *   (Remark 2.1).  The iteration converges when k^2 is below the first
  *   Dirichlet eigenvalue (Sec. 2.4, Remark 2.4); it is stopped by the
  *   sup-norm change (Sec. 3).
  *
+ *   With a reflecting edge (the annular problem of Sec. 2.3) the rectangle's
+ *   edge carries the Robin condition d_n u - i k u = g2 and only the hole is
+ *   absorbing: Y is the diffusion reflected at the edge, dY = sqrt(2) dW -
+ *   n dxi with local time xi (Sec. 2.1 eqs. (2.1)-(2.3)), and each step adds
+ *   E[int_0^tau e^{-(alpha - k^2) t} (i k u_n + g2)(Y_t) dxi_t] (the partial
+ *   sums of the iteration of Sec. 2.3 satisfy d_n u_{n+1} = i k u_n + g2).
+ *   The sufficient condition for convergence is alpha E[tau] + k E[xi] < 1
+ *   (Theorem 2.3).
+ *
  * Discretisation: Euler-Maruyama with step h; normals by Box-Muller from
  * Philox4x32-10 words, key = seed, counter = (t/2, path m, node id, n) (n
  * replaced by 0 when crn != 0); uniform U(r) = (2 (r >> 9) + 1) 2^-24; exit at
  * the first step outside the open domain, boundary datum at the nearest
  * boundary point; left-point rule for the integral; u_n read by bilinear
- * interpolation of the grid.
+ * interpolation of the grid.  Reflecting edge: after each step a coordinate
+ * that left the rectangle is mirrored back across the face it crossed; the
+ * local time grows by twice the overshoot, and the local-time integrand is
+ * taken at the foot of the mirror move on the face, discounted to the end of
+ * the step; the step is absorbed when the point lies in the closed hole.
  *
  * Conventions for every entry point:
  *   - Grids are row-major nx * ny, node (i, j) at index i + nx * j, x fastest;
@@ -57,15 +70,27 @@ typedef enum {
 } fk_status;
 
 /* Omega: the open rectangle (x0,x1) x (y0,y1); for RECT_MINUS_DISC also
- * minus the closed disc of radius r at (cx, cy), which must lie strictly
- * inside the rectangle.  nx, ny >= 3 nodes per side, edges included. */
-typedef enum { FK_DOMAIN_RECT = 0, FK_DOMAIN_RECT_MINUS_DISC = 1 } fk_domain_kind;
+ * minus the closed disc of radius r at (cx, cy); for RECT_MINUS_BOX minus the
+ * closed box [cx - r, cx + r] x [cy - ry, cy + ry].  The hole must lie
+ * strictly inside the rectangle.  nx, ny >= 3 nodes per side, edges
+ * included.  A grid node within 1e-9 grid steps of the box counts as in it
+ * (so a box drawn on grid lines keeps its edge nodes whatever the rounding
+ * of x0 + i dx).
+ *
+ * edge: ABSORBING, u = g_outer on the rectangle's edge (Dirichlet); or
+ * REFLECTING, d_n u - i k u = g_outer on the edge (Robin, Sec. 2.3): the
+ * edge nodes are unknowns, the paths are reflected there and only the hole
+ * absorbs them, so a reflecting edge needs a hole, an explicit step cap
+ * (fk_params.max_steps) and sides longer than 6 sqrt(2 h). */
+typedef enum { FK_DOMAIN_RECT = 0, FK_DOMAIN_RECT_MINUS_DISC = 1, FK_DOMAIN_RECT_MINUS_BOX = 2 } fk_domain_kind;
+typedef enum { FK_EDGE_ABSORBING = 0, FK_EDGE_REFLECTING = 1 } fk_edge_kind;
 typedef struct {
     int32_t kind;
     int32_t nx, ny;
-    int32_t reserved;
+    int32_t edge;          /* fk_edge_kind */
     double x0, x1, y0, y1;
     double cx, cy, r;
+    double ry;             /* RECT_MINUS_BOX: half-height of the box */
 } fk_domain;
 
 /* Source f: ZERO; CONST f = amp; GAUSSIAN f = amp exp(-|x-c|^2 / (2 sigma^2)). */
@@ -76,17 +101,25 @@ typedef struct {
     double amp_re, amp_im, cx, cy, sigma;
 } fk_source;
 
-/* Dirichlet datum on one boundary part.
- *   PLANE_WAVE  c = {amp_re, amp_im, theta}: g = amp exp(i k (x cos th + y sin th))
+/* Datum on one boundary part: the Dirichlet value g, or on a reflecting
+ * edge the Robin datum g2 of d_n u - i k u = g2.
+ *   PLANE_WAVE  c = {amp_re, amp_im, theta}: g = amp exp(i kappa (x cos th + y sin th)),
+ *               kappa = sqrt(k^2 + i p) (k without damping)
  *   BILINEAR    c = {c0re, c0im, c1re, c1im, c2re, c2im, c3re, c3im}:
  *               g = c0 + c1 x + c2 y + c3 x y
  *   TABLE       (outer boundary only) table_len complex samples (re, im
  *               interleaved; host pointer, copied at create) at equal
  *               arclength steps round the rectangle, counter-clockwise from
  *               (x0, y0), linearly interpolated, periodic.
- * On hole nodes (inside the disc) the grid carries the inner datum's own
- * formula (a smooth extension); TABLE is not allowed there. */
-typedef enum { FK_BC_ZERO = 0, FK_BC_PLANE_WAVE = 1, FK_BC_BILINEAR = 2, FK_BC_TABLE = 3 } fk_bc_kind;
+ *   PLANE_WAVE_ROBIN  (reflecting edge only) c as PLANE_WAVE: the Robin
+ *               datum of that plane wave w, g2 = d_n w - i k w
+ *               = i (kappa (n . (cos th, sin th)) - k) w with n the face's
+ *               outward normal, so that w solves the Robin problem.
+ * On hole nodes the grid carries the inner datum's own formula (a smooth
+ * extension); TABLE and PLANE_WAVE_ROBIN are not allowed there. */
+typedef enum {
+    FK_BC_ZERO = 0, FK_BC_PLANE_WAVE = 1, FK_BC_BILINEAR = 2, FK_BC_TABLE = 3, FK_BC_PLANE_WAVE_ROBIN = 4
+} fk_bc_kind;
 typedef struct {
     int32_t kind;
     int32_t reserved;
@@ -116,7 +149,8 @@ typedef struct {
     int32_t max_iters;     /* for fk_helmholtz_solve                          */
     double tol;            /* stop when max |u_{n+1} - u_n| < tol (0: never)  */
     int64_t max_steps;     /* step cap per path; 0 = ceil(40/(lambda1 h)),
-                              lambda1 of the bounding rectangle              */
+                              lambda1 of the bounding rectangle (absorbing
+                              edge only: a reflecting edge needs it set)     */
     int32_t crn;           /* 1: same paths every iteration (counter n -> 0)  */
     int32_t g_unprojected; /* verification variant: g at X_J itself           */
     int32_t paths_per_item;/* paths per wavefront work item; 0 = auto         */
@@ -142,15 +176,15 @@ typedef struct {
 typedef struct {
     int32_t n;             /* iterations completed (index of the iterate)     */
     int32_t diverging;     /* divergence rule fired at this iteration          */
-    double max_du;         /* max over interior nodes |u_n - u_{n-1}|          */
-    double sup;            /* max over interior nodes |u_n|                    */
+    double max_du;         /* max over unknown nodes |u_n - u_{n-1}|           */
+    double sup;            /* max over unknown nodes |u_n|                     */
     double max_se;         /* max node standard error (|SE_re + i SE_im|)      */
     double noise_floor;    /* 4 * max_se                                       */
     int64_t path_steps;    /* sum of exit-step indices over all paths          */
     int64_t capped;        /* paths stopped by the step cap                    */
     int64_t nonfinite;     /* nodes whose estimate is not finite               */
     double step_ms;        /* device time of the path kernel (HIP events)      */
-    double noise_ratio;    /* mean over interior nodes of |u_n - u_{n-1}|^2 /
+    double noise_ratio;    /* mean over unknown nodes of |u_n - u_{n-1}|^2 /
                               (2 |SE_n|^2), each node's term capped at 4096:
                               about 1/(1+rho) once the change is Monte Carlo
                               noise alone (fresh paths), large while the
@@ -164,19 +198,22 @@ typedef struct fk_solver fk_solver;
 fk_status fk_helmholtz_arena_bytes(const fk_domain *domain, const fk_bc *g_outer,
                                    const fk_params *params, size_t *bytes);
 
-/* Validates the problem, classifies the grid nodes (interior, rectangle edge,
- * hole), uploads the boundary data and sets u_0 = 0.  device_arena: device
- * memory of at least fk_helmholtz_arena_bytes bytes, 256-byte aligned, owned
- * by the caller and kept alive until destroy; NULL makes the library allocate
- * (and free) its own.  FK_EINVAL: bad geometry, nx or ny < 3, h <= 0, M < 2,
- * precision not 32/64, disc not strictly inside, TABLE as inner datum or
- * table_len < 2.  FK_ENOMEM: arena too small. */
+/* Validates the problem, classifies the grid nodes (unknown: interior or on
+ * a reflecting edge; absorbing edge; hole), uploads the boundary data and
+ * sets u_0 = 0.  device_arena: device memory of at least
+ * fk_helmholtz_arena_bytes bytes, 256-byte aligned, owned by the caller and
+ * kept alive until destroy; NULL makes the library allocate (and free) its
+ * own.  FK_EINVAL: bad geometry, nx or ny < 3, h <= 0, M < 2, precision not
+ * 32/64, hole not strictly inside, TABLE or PLANE_WAVE_ROBIN as inner datum,
+ * PLANE_WAVE_ROBIN on an absorbing edge, table_len < 2, a reflecting edge
+ * without a hole, without max_steps, with g_unprojected or with a side not
+ * longer than 6 sqrt(2 h).  FK_ENOMEM: arena too small. */
 fk_status fk_helmholtz_create(const fk_domain *domain, const fk_source *f, const fk_bc *g_outer,
                               const fk_bc *g_inner, const fk_params *params, void *device_arena,
                               size_t arena_bytes, void *hip_stream, fk_solver **out);
 
 /* Runs n_iters fixed-point iterations on the device (u_n -> u_{n+1}: one
- * Feynman-Kac solve at every interior node, then the update of the iterate)
+ * Feynman-Kac solve at every unknown node, then the update of the iterate)
  * and fills *last (may be NULL) with the report of the last one.  Returns
  * FK_EDIVERGED as soon as the divergence rule fires: the change is not
  * finite, or five iterations apart both max |u| and max |du| grew by 25%. */
@@ -187,17 +224,17 @@ fk_status fk_helmholtz_iterate(fk_solver *s, int32_t n_iters, fk_iter_report *la
 fk_status fk_helmholtz_solve(fk_solver *s, fk_iter_report *final_report);
 
 /* Copies the current iterate u_n (nx*ny complex) and, if se_reim is not NULL,
- * the per-node standard errors (SE_re, SE_im; 0 on non-interior nodes) of the
- * last iteration.  on_device != 0: the pointers are device pointers. */
+ * the per-node standard errors (SE_re, SE_im; 0 on nodes that are not
+ * unknowns) of the last iteration.  on_device != 0: the pointers are device pointers. */
 fk_status fk_helmholtz_get(fk_solver *s, double *u_reim, double *se_reim, int32_t on_device);
 
 /* Per-node sum of exit-step indices and capped-path counts of the last
- * iteration (nx*ny each, host pointers; 0 on non-interior nodes). */
+ * iteration (nx*ny each, host pointers; 0 on nodes that are not unknowns). */
 fk_status fk_helmholtz_node_stats(fk_solver *s, int64_t *sum_j, int64_t *capped);
 
-/* Replaces the iterate by u_reim (nx*ny complex, host or device) on interior
+/* Replaces the iterate by u_reim (nx*ny complex, host or device) on unknown
  * nodes and sets the iteration index to n (the next iteration uses counter
- * word n).  Boundary and hole nodes keep their data.  Used to resume from a
+ * word n).  Absorbing-edge and hole nodes keep their data.  Used to resume from a
  * checkpoint and to feed the same u_n to another implementation. */
 fk_status fk_helmholtz_set_iterate(fk_solver *s, const double *u_reim, int32_t n, int32_t on_device);
 

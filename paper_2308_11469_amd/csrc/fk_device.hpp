@@ -28,20 +28,23 @@ constexpr int kWave = 64;
 // features; an instance runs in any kernel whose set contains its own (the
 // run-time checks stay), and a kernel without a feature carries neither its
 // code nor its constants.
-constexpr int kFeatDisc = 1;     // the domain has a hole
+constexpr int kFeatDisc = 1;     // the domain has a hole (disc or box)
 constexpr int kFeatSource = 2;   // f is not zero
 constexpr int kFeatGeneral = 4;  // a shift alpha != k^2 or a damping p (discount, complex coefficient,
                                  // damped plane-wave data)
-constexpr int kFeatAll = kFeatDisc | kFeatSource | kFeatGeneral;
+constexpr int kFeatReflect = 8;  // the rectangle's edge reflects (Robin condition, local time); always
+                                 // with a hole
+constexpr int kFeatAll = kFeatDisc | kFeatSource | kFeatGeneral | kFeatReflect;
 
-enum : int32_t { BC_ZERO = 0, BC_PLANE_WAVE = 1, BC_BILINEAR = 2, BC_TABLE = 3 };
+enum : int32_t { BC_ZERO = 0, BC_PLANE_WAVE = 1, BC_BILINEAR = 2, BC_TABLE = 3, BC_PLANE_WAVE_ROBIN = 4 };
+enum : int32_t { HOLE_NONE = 0, HOLE_DISC = 1, HOLE_BOX = 2 };
 enum : int32_t { SRC_ZERO = 0, SRC_CONST = 1, SRC_GAUSSIAN = 2 };
 
 struct BCDev {
     int32_t kind;
     int32_t pad;
-    double c[8];            // PLANE_WAVE: amp_re, amp_im, cos th, sin th, kappa_re, kappa_im;
-                            // BILINEAR: c0..c3
+    double c[8];            // PLANE_WAVE (and PLANE_WAVE_ROBIN): amp_re, amp_im, cos th, sin th,
+                            // kappa_re, kappa_im; BILINEAR: c0..c3
     const double2 *table;   // TABLE samples (device)
     int64_t len;
 };
@@ -81,12 +84,15 @@ struct DevState {
 struct Inst {
     double x0, x1, y0, y1, dx, dy, idx, idy;
     double cx, cy, r, r2;
+    double bx0, bx1, by0, by1;                       // box hole
     float x0_rd, x1_ru, y0_rd, y1_ru;                // edges rounded outward to binary32
-    int32_t nx, ny, disc, n_interior;
+    float bx0_ru, bx1_rd, by0_ru, by1_rd;            // box edges rounded inward to binary32
+    int32_t nx, ny, hole, n_interior;                // hole: HOLE_NONE / _DISC / _BOX
+    int32_t reflect, pad0;                           // 1: the rectangle's edge reflects
     int32_t src_kind, g_unproj;
     double src_re, src_im, src_cx, src_cy, src_c;   // src_c = 1 / (2 sigma^2)
     BCDev outer, inner;
-    double k, k2, h, sigma;                          // sigma = sqrt(2 h)
+    double k, k2, h, ih, sigma;                      // ih = 1 / h, sigma = sqrt(2 h)
     double alpha, damp, q;                           // shift, damping p, q = exp(-(alpha - k^2) h)
     int64_t M, jmax;
     uint32_t key0, key1;
@@ -240,38 +246,94 @@ __device__ __forceinline__ void normals(uint32_t ra, uint32_t rb, const NoTables
 
 // ------------------------------------------------------------- geometry
 
-// Nearest boundary point of X (FP64).  Outside the rectangle: clamp (outer
-// part).  In the closed disc: radial projection onto the circle.  Inside the
-// domain (a path stopped by the cap): the nearest of the four edges and the
-// circle.  Returns 1 for the outer boundary, 2 for the circle.
+// The closed hole (FP64, the problem's own comparisons).
+__device__ __forceinline__ bool in_hole(const Inst &D, double x, double y)
+{
+    if (D.hole == HOLE_DISC) {
+        const double ex = x - D.cx, ey = y - D.cy;
+        return ex * ex + ey * ey <= D.r2;
+    }
+    if (D.hole == HOLE_BOX) return x >= D.bx0 && x <= D.bx1 && y >= D.by0 && y <= D.by1;
+    return false;
+}
+
+// Nearest point of the hole's boundary and its distance.  Disc: radial
+// projection.  Box: from inside, the nearest face; from outside, the clamp.
+__device__ __forceinline__ double hole_project(const Inst &D, double x, double y, double &px, double &py)
+{
+    if (D.hole == HOLE_DISC) {
+        const double ex = x - D.cx, ey = y - D.cy;
+        const double d = sqrt(ex * ex + ey * ey);
+        if (d > 0.0) {
+            px = D.cx + D.r * ex / d;
+            py = D.cy + D.r * ey / d;
+        } else {
+            px = D.cx + D.r;
+            py = D.cy;
+        }
+        return fabs(d - D.r);
+    }
+    if (in_hole(D, x, y)) {
+        double dd[4] = {x - D.bx0, D.bx1 - x, y - D.by0, D.by1 - y};
+        int e = 0;
+        for (int c = 1; c < 4; ++c)
+            if (dd[c] < dd[e]) e = c;
+        px = e == 0 ? D.bx0 : (e == 1 ? D.bx1 : x);
+        py = e == 2 ? D.by0 : (e == 3 ? D.by1 : y);
+        return dd[e];
+    }
+    px = fmin(fmax(x, D.bx0), D.bx1);
+    py = fmin(fmax(y, D.by0), D.by1);
+    return hypot(x - px, y - py);
+}
+
+// Nearest point of the Dirichlet boundary to X (FP64).  With a reflecting
+// edge that is the hole's boundary alone.  Otherwise: outside the rectangle,
+// the clamp (outer part); in the closed hole, its projection; inside the
+// domain (a path stopped by the cap), the nearest of the four edges and the
+// hole.  Returns 1 for the outer boundary, 2 for the hole.
 __device__ __forceinline__ int project(const Inst &D, double x, double y, double &px, double &py)
 {
+    if (D.reflect) {
+        hole_project(D, x, y, px, py);
+        return 2;
+    }
     if (x <= D.x0 || x >= D.x1 || y <= D.y0 || y >= D.y1) {
         px = fmin(fmax(x, D.x0), D.x1);
         py = fmin(fmax(y, D.y0), D.y1);
         return 1;
     }
-    const double ex = x - D.cx, ey = y - D.cy;
-    const double d = sqrt(ex * ex + ey * ey);
-    if (!(D.disc && d <= D.r)) {
+    if (!(D.hole && in_hole(D, x, y))) {
         double dd[4] = {x - D.x0, D.x1 - x, y - D.y0, D.y1 - y};
         int e = 0;
         for (int c = 1; c < 4; ++c)
             if (dd[c] < dd[e]) e = c;
-        if (!D.disc || dd[e] <= d - D.r) {
+        double hx, hy;
+        if (!D.hole || dd[e] <= hole_project(D, x, y, hx, hy)) {
             px = e == 0 ? D.x0 : (e == 1 ? D.x1 : x);
             py = e == 2 ? D.y0 : (e == 3 ? D.y1 : y);
             return 1;
         }
     }
-    if (d > 0.0) {
-        px = D.cx + D.r * ex / d;
-        py = D.cy + D.r * ey / d;
-    } else {
-        px = D.cx + D.r;
-        py = D.cy;
-    }
+    hole_project(D, x, y, px, py);
     return 2;
+}
+
+// The plane wave amp exp(i kappa s), s = x cos th + y sin th, kappa = kr + i ki.
+template <int F>
+__device__ __forceinline__ double2 plane_wave(const BCDev &B, double x, double y)
+{
+    // phase in half-turns: sincospi reduces its argument exactly
+    const double sd = x * B.c[2] + y * B.c[3];
+    const double ph = B.c[4] * sd;
+    double s, c;
+    sincospi(ph * 0.318309886183790671537767526745, &s, &c);
+    if ((F & kFeatGeneral) && B.c[5] != 0.0) {
+        const double decay = exp(-B.c[5] * sd);
+        s *= decay;
+        c *= decay;
+    }
+    return make_double2(B.c[0] * c - B.c[1] * s, B.c[0] * s + B.c[1] * c);
 }
 
 // Boundary datum at a point (FP64, once per path).
@@ -279,20 +341,8 @@ template <int F>
 __device__ __forceinline__ double2 bc_eval(const Inst &D, const BCDev &B, double x, double y)
 {
     switch (B.kind) {
-    case BC_PLANE_WAVE: {
-        // amp exp(i kappa s), s = x cos th + y sin th, kappa = kr + i ki;
-        // phase in half-turns: sincospi reduces its argument exactly
-        const double sd = x * B.c[2] + y * B.c[3];
-        const double ph = B.c[4] * sd;
-        double s, c;
-        sincospi(ph * 0.318309886183790671537767526745, &s, &c);
-        if ((F & kFeatGeneral) && B.c[5] != 0.0) {
-            const double decay = exp(-B.c[5] * sd);
-            s *= decay;
-            c *= decay;
-        }
-        return make_double2(B.c[0] * c - B.c[1] * s, B.c[0] * s + B.c[1] * c);
-    }
+    case BC_PLANE_WAVE:
+        return plane_wave<F>(B, x, y);
     case BC_BILINEAR:
         return make_double2(B.c[0] + B.c[2] * x + B.c[4] * y + B.c[6] * x * y,
                             B.c[1] + B.c[3] * x + B.c[5] * y + B.c[7] * x * y);
@@ -317,11 +367,28 @@ __device__ __forceinline__ double2 bc_eval(const Inst &D, const BCDev &B, double
     }
 }
 
+// Robin datum g2 of a reflecting edge at a point of face `face` (0: x = x0,
+// 1: x = x1, 2: y = y0, 3: y = y1).  PLANE_WAVE_ROBIN: for the plane wave w
+// of direction d, d_n w = i kappa (d . n) w on a face with outward normal n,
+// so g2 = d_n w - i k w = i (kappa (d . n) - k) w.  Any other kind is g2
+// itself.
+template <int F>
+__device__ __forceinline__ double2 robin_datum(const Inst &D, int face, double x, double y)
+{
+    const BCDev &B = D.outer;
+    if (B.kind != BC_PLANE_WAVE_ROBIN) return bc_eval<F>(D, B, x, y);
+    const double dn = face == 0 ? -B.c[2] : (face == 1 ? B.c[2] : (face == 2 ? -B.c[3] : B.c[3]));
+    const double2 w = plane_wave<F>(B, x, y);
+    // i (kappa dn - k) = -ki dn + i (kr dn - k)
+    const double ar = -B.c[5] * dn, ai = B.c[4] * dn - D.k;
+    return make_double2(ar * w.x - ai * w.y, ar * w.y + ai * w.x);
+}
+
 // Score datum g at the end of a path whose last point is (x, y).
 template <int F>
 __device__ __forceinline__ double2 exit_datum(const Inst &D, double x, double y, bool exited)
 {
-    if (D.g_unproj) {
+    if (D.g_unproj && !D.reflect) {
         const bool outer = x <= D.x0 || x >= D.x1 || y <= D.y0 || y >= D.y1;
         return bc_eval<F>(D, (outer || !exited) ? D.outer : D.inner, x, y);
     }

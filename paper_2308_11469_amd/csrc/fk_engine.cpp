@@ -8,7 +8,7 @@
 //   items from the queue) -> update (all active instances) -> iteration
 //   advance -> status copy.
 // One graph is captured per set of optional path-kernel features (hole,
-// source term, shift or damping); a tick replays the one for the union of the active
+// source term, shift or damping, reflecting edge); a tick replays the one for the union of the active
 // instances' features.  Admitting or retiring an instance edits the tables
 // between ticks; the graphs are never re-captured.  Instance memory comes from one device pool managed by
 // a first-fit allocator; admission fails with FK_ENOMEM when the pool cannot
@@ -112,14 +112,18 @@ struct fk_engine {
     PoolAllocator pool;
     bool tables_dirty = true;
     int32_t n_active = 0;
-    hipGraph_t graph[8] = {};         // per feature set of the path kernel
-    hipGraphExec_t exec[8] = {};
+    hipGraph_t graph[16] = {};        // per feature set of the path kernel
+    hipGraphExec_t exec[16] = {};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double kernel_ms_total = 0.0;
     int64_t launches = 0;
 };
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Feature sets that occur: a reflecting edge (bit 3) always comes with a
+// hole (bit 0), so a union of instances' sets with bit 3 has bit 0 too.
+static bool valid_feature_set(int f) { return (f & 8) == 0 || (f & 1) != 0; }
 
 static fk_status capture_graph(fk_engine *e, int features)
 {
@@ -230,7 +234,8 @@ fk_status fk_engine_create(const fk_engine_config *cfg, void *hip_stream, fk_eng
     if ((err = hipEventCreate(&e->ev0)) != hipSuccess || (err = hipEventCreate(&e->ev1)) != hipSuccess)
         return bail(hip_fail(err, "hipEventCreate"));
     e->pool.reset(e->pool_bytes);
-    for (int f = 0; f < 8; ++f) {
+    for (int f = 0; f < 16; ++f) {
+        if (!valid_feature_set(f)) continue;
         fk_status st = capture_graph(e, f);
         if (st != FK_OK) return bail(st);
     }
@@ -394,7 +399,7 @@ fk_status fk_engine_destroy(fk_engine *e)
     if (!e) return FK_OK;
     if (e->user_stream) (void)hipStreamSynchronize(e->user_stream);
     if (e->cap_stream) (void)hipStreamSynchronize(e->cap_stream);
-    for (int f = 0; f < 8; ++f) {
+    for (int f = 0; f < 16; ++f) {
         if (e->exec[f]) (void)hipGraphExecDestroy(e->exec[f]);
         if (e->graph[f]) (void)hipGraphDestroy(e->graph[f]);
     }

@@ -35,10 +35,16 @@ template <class R> struct Consts {
     R x0, y0, idx, idy, sigma, k2;
     R ex0, ex1, ey0, ey1;   // rectangle edges for the exit test (FP32: rounded outward)
     R cxf, cyf, r2f, band;
+    R hx0, hx1, hy0, hy1;   // box hole for the exit test (FP32: rounded inward)
+    R rx0, rx1, ry0, ry1;   // reflecting faces
+    R kk;                   // k (the Robin coupling i k u_n on a reflecting edge)
+    double ih;              // 1 / h
     R src_re, src_im, src_cx, src_cy, src_c;
     R pmax, qmax;       // largest cell index as R (nx - 2, ny - 2)
     int jmax;
-    int disc, src_kind;
+    int hole, src_kind;
+    int reflect;        // the rectangle's edge reflects
+    int robin_g2;       // the Robin datum g2 is not zero
     int cells;          // the gather copy of u_n is cell-major
     double q;           // discount per step, e^{-(alpha - k^2) h}
     R alpha, damp;      // coefficient alpha + i p of the iterate
@@ -56,17 +62,21 @@ template <class R> struct Consts {
     __device__ Consts(const Inst &D, const typename TablesOf<R>::type *T)
         : x0((R)D.x0), y0((R)D.y0), idx((R)D.idx), idy((R)D.idy), sigma((R)D.sigma), k2((R)D.k2),
           cxf((R)D.cx), cyf((R)D.cy), r2f((R)D.r2), band((R)(1e-5 * (D.r + 1.0))),
+          rx0((R)D.x0), rx1((R)D.x1), ry0((R)D.y0), ry1((R)D.y1), kk((R)D.k), ih(D.ih),
           src_re((R)D.src_re), src_im((R)D.src_im), src_cx((R)D.src_cx), src_cy((R)D.src_cy),
           src_c((R)D.src_c), pmax((R)(D.nx - 2)), qmax((R)(D.ny - 2)), jmax((int)D.jmax),
-          disc(D.disc), src_kind(D.src_kind), cells(D.cells), q(D.q), alpha((R)D.alpha), damp((R)D.damp),
+          hole(D.hole), src_kind(D.src_kind), reflect(D.reflect), robin_g2(D.outer.kind != BC_ZERO),
+          cells(D.cells), q(D.q), alpha((R)D.alpha), damp((R)D.damp),
           general(D.alpha != D.k2 || D.damp != 0.0),
           key0(D.key0), key1(D.key1),
           tab(T)
     {
         if (sizeof(R) == 4) {
             ex0 = (R)D.x0_rd; ex1 = (R)D.x1_ru; ey0 = (R)D.y0_rd; ey1 = (R)D.y1_ru;
+            hx0 = (R)D.bx0_ru; hx1 = (R)D.bx1_rd; hy0 = (R)D.by0_ru; hy1 = (R)D.by1_rd;
         } else {
             ex0 = (R)D.x0; ex1 = (R)D.x1; ey0 = (R)D.y0; ey1 = (R)D.y1;
+            hx0 = (R)D.bx0; hx1 = (R)D.bx1; hy0 = (R)D.by0; hy1 = (R)D.by1;
         }
         const uint32_t node_bytes = (uint32_t)(2 * sizeof(R));
         uint32_t bytes;
@@ -99,27 +109,31 @@ template <class R> struct PathState {
 __device__ __forceinline__ double exp_src(double a) { return exp(a); }
 __device__ __forceinline__ float exp_src(float a) { return __builtin_amdgcn_exp2f(a * 1.44269504088896341f); }
 
-// Exit test: outside the open rectangle, or in the closed disc.  FP64: the
-// same comparisons as the problem statement.  FP32: for a binary32 x,
-// x <= x0 exactly iff x <= RD(x0) (x0 rounded down to binary32) and x >= x1
-// iff x >= RU(x1), so comparing with the outward-rounded edges equals the
-// exact test against the FP64 edges; the disc test runs in FP32 and falls
+// Exit test: outside the open rectangle (unless its edge reflects), or in
+// the closed hole.  FP64: the same comparisons as the problem statement.
+// FP32: for a binary32 x, x <= x0 exactly iff x <= RD(x0) (x0 rounded down
+// to binary32) and x >= x1 iff x >= RU(x1), so comparing with the
+// outward-rounded edges equals the exact test against the FP64 edges (the
+// box's edges likewise rounded inward); the disc test runs in FP32 and falls
 // back to FP64 only within a thin band around the circle.
 template <int F>
 __device__ __forceinline__ bool is_out(const Inst &, const Consts<double> &K, double x, double y)
 {
-    if (x <= K.ex0 || x >= K.ex1 || y <= K.ey0 || y >= K.ey1) return true;
-    if ((F & kFeatDisc) && K.disc) {
+    if (!((F & kFeatReflect) && K.reflect) && (x <= K.ex0 || x >= K.ex1 || y <= K.ey0 || y >= K.ey1))
+        return true;
+    if ((F & kFeatDisc) && K.hole == HOLE_DISC) {
         const double ex = x - K.cxf, ey = y - K.cyf;
         return ex * ex + ey * ey <= K.r2f;
     }
+    if ((F & kFeatDisc) && K.hole == HOLE_BOX) return x >= K.hx0 && x <= K.hx1 && y >= K.hy0 && y <= K.hy1;
     return false;
 }
 template <int F>
 __device__ __forceinline__ bool is_out(const Inst &D, const Consts<float> &K, float x, float y)
 {
-    if (x <= K.ex0 || x >= K.ex1 || y <= K.ey0 || y >= K.ey1) return true;
-    if ((F & kFeatDisc) && K.disc) {
+    if (!((F & kFeatReflect) && K.reflect) && (x <= K.ex0 || x >= K.ex1 || y <= K.ey0 || y >= K.ey1))
+        return true;
+    if ((F & kFeatDisc) && K.hole == HOLE_DISC) {
         const float ex = x - K.cxf, ey = y - K.cyf;
         const float d = ex * ex + ey * ey - K.r2f;
         if (d > K.band) return false;
@@ -127,7 +141,43 @@ __device__ __forceinline__ bool is_out(const Inst &D, const Consts<float> &K, fl
         const double exd = (double)x - D.cx, eyd = (double)y - D.cy;
         return exd * exd + eyd * eyd <= D.r2;
     }
+    if ((F & kFeatDisc) && K.hole == HOLE_BOX) return x >= K.hx0 && x <= K.hx1 && y >= K.hy0 && y <= K.hy1;
     return false;
+}
+
+// Reflection at the rectangle's faces (edge that reflects): a coordinate
+// past a face is mirrored back across it, and the local time grows by the
+// length of the mirror move, twice the overshoot.  The rectangle is wider
+// than any single step (checked at set-up), so one mirror per coordinate
+// lands inside.  face: 0 x = x0, 1 x = x1, 2 y = y0, 3 y = y1, -1 none.
+template <class R> struct Mirror {
+    R lx, ly;     // local-time increments of the x and y faces
+    int fx, fy;   // the faces crossed
+};
+
+template <class R>
+__device__ __forceinline__ Mirror<R> reflect(const Consts<R> &K, R &x, R &y)
+{
+    Mirror<R> m{(R)0, (R)0, -1, -1};
+    if (x < K.rx0) {
+        m.lx = (R)2 * (K.rx0 - x);
+        x = (R)2 * K.rx0 - x;
+        m.fx = 0;
+    } else if (x > K.rx1) {
+        m.lx = (R)2 * (x - K.rx1);
+        x = (R)2 * K.rx1 - x;
+        m.fx = 1;
+    }
+    if (y < K.ry0) {
+        m.ly = (R)2 * (K.ry0 - y);
+        y = (R)2 * K.ry0 - y;
+        m.fy = 2;
+    } else if (y > K.ry1) {
+        m.ly = (R)2 * (y - K.ry1);
+        y = (R)2 * K.ry1 - y;
+        m.fy = 3;
+    }
+    return m;
 }
 
 // Bilinear interpolation of u_n at (x, y): cell p = floor((x - x0)/dx)
@@ -262,7 +312,35 @@ __device__ __forceinline__ void source(const Consts<R> &K, R x, R y, R &fr, R &f
 // advanced by the factor q = e^{-(alpha - k^2) h} per step.
 template <class R> struct Coef {
     R re, im;
+    R ik;         // k while u_n != 0 (the Robin coupling i k u_n), else 0
 };
+
+// Local-time term of one mirror move (reflecting edge): the integrand
+// i k I_h[u_n] + g2 at the foot of the move on face `face`, times the
+// increment dxi and the discount w at the end of the step.  It enters the
+// score with a plus sign; it is folded into the left-point sum, which the
+// score multiplies by -h, as -w dxi (...) / h.
+template <class R, int F>
+__device__ __forceinline__ void local_time_term(const Inst &D, const Consts<R> &K, int face, R fx, R fy, R dxi,
+                                                double w, R ik, PathState<R> &P)
+{
+    CellReads<R> g;
+    g.c = locate(K, fx, fy);
+    issue_reads(K, g.c.off, g);
+    R vr, vi;
+    value(g, vr, vi);
+    double gr = -(double)(ik * vi), gi = (double)(ik * vr);
+    if (K.robin_g2) {
+        const double xf = face == 0 ? D.x0 : (face == 1 ? D.x1 : (double)fx);
+        const double yf = face == 2 ? D.y0 : (face == 3 ? D.y1 : (double)fy);
+        const double2 g2 = robin_datum<F>(D, face, xf, yf);
+        gr += g2.x;
+        gi += g2.y;
+    }
+    const double c = w * (double)dxi * K.ih;
+    P.ar -= c * gr;
+    P.ai -= c * gi;
+}
 
 template <class R, int F>
 __device__ __forceinline__ bool advance(const Inst &D, const Consts<R> &K, PathState<R> &P, uint32_t m,
@@ -276,8 +354,13 @@ __device__ __forceinline__ bool advance(const Inst &D, const Consts<R> &K, PathS
     R z0x, z0y, z1x, z1y;
     normals(w.x, w.y, *K.tab, z0x, z0y);
     normals(w.z, w.w, *K.tab, z1x, z1y);
-    const R x1 = P.x + K.sigma * z0x, y1 = P.y + K.sigma * z0y;
-    const R x2 = x1 + K.sigma * z1x, y2 = y1 + K.sigma * z1y;
+    R x1 = P.x + K.sigma * z0x, y1 = P.y + K.sigma * z0y;
+    // a reflecting edge mirrors each step back into the rectangle
+    const bool refl = (F & kFeatReflect) && K.reflect;
+    Mirror<R> m1{(R)0, (R)0, -1, -1}, m2{(R)0, (R)0, -1, -1};
+    if (refl) m1 = reflect(K, x1, y1);
+    R x2 = x1 + K.sigma * z1x, y2 = y1 + K.sigma * z1y;
+    if (refl) m2 = reflect(K, x2, y2);
     g0.c = locate(K, P.x, P.y);
     g1.c = locate(K, x1, y1);
     issue_reads(K, g0.c.off, g0);
@@ -312,6 +395,23 @@ __device__ __forceinline__ bool advance(const Inst &D, const Consts<R> &K, PathS
     const bool out1 = is_out<F>(D, K, x1, y1);
     const bool out2 = is_out<F>(D, K, x2, y2);
     const bool second = !out1 && P.t + 1 < K.jmax;
+    if ((F & kFeatReflect) && refl && (m1.fx >= 0 || m1.fy >= 0 || (second && (m2.fx >= 0 || m2.fy >= 0)))) {
+        // local time of the step(s) taken: up to one mirror move per face
+        // and step, each at the end-of-step discount
+        const double w1 = general ? P.w * K.q : 1.0;
+        const double w2 = general ? w1 * K.q : 1.0;
+#pragma unroll 1
+        for (int c = 0; c < 4; ++c) {
+            const bool s2 = c >= 2;
+            const Mirror<R> &m = s2 ? m2 : m1;
+            const int face = (c & 1) ? m.fy : m.fx;
+            if (face < 0 || (s2 && !second)) continue;
+            const R px = s2 ? x2 : x1, py = s2 ? y2 : y1;
+            const R fx = face == 0 ? K.rx0 : (face == 1 ? K.rx1 : px);
+            const R fy = face == 2 ? K.ry0 : (face == 3 ? K.ry1 : py);
+            local_time_term<R, F>(D, K, face, fx, fy, (c & 1) ? m.ly : m.lx, s2 ? w2 : w1, cu.ik, P);
+        }
+    }
     if (general) {
         // each value with its own discount, summed in FP64
         const double w1 = P.w * K.q;
@@ -535,6 +635,7 @@ __device__ __forceinline__ void stream_paths(const Inst *__restrict__ insts, con
         Coef<R> cu;
         cu.re = use_u ? ((F & kFeatGeneral) ? K.alpha : K.k2) : (R)0;
         cu.im = use_u && (F & kFeatGeneral) ? K.damp : (R)0;
+        cu.ik = use_u ? K.kk : (R)0;
         const uint32_t ctr3 = D.crn ? 0u : (uint32_t)D.state->iter;
 
         // wave-uniform pool: path indices [pool_m, pool_end) of one node
@@ -715,29 +816,24 @@ __global__ void __launch_bounds__(256) fk_update_kernel(const Inst *__restrict__
         const double ser = sqrt(vr / Mf), sei = sqrt(vi / Mf);
         const double2 old = use_u ? D.u64[node] : make_double2(0.0, 0.0);
         D.u64[node] = make_double2(mr, mi);
-        // the gather copy: an interior node is a corner of the four cells
-        // around it (corner index 0..3 = (p,q), (p+1,q), (p,q+1), (p+1,q+1))
+        // the gather copy: a node is corner dp + 2 dq of cell (gi - dp, gj - dq)
+        // for each of the (up to four) cells around it that exist (corner
+        // index 0..3 = (p,q), (p+1,q), (p,q+1), (p+1,q+1)); an unknown node on
+        // a reflecting edge has two, a corner one
         const int gi = node % D.nx, gj = node / D.nx, cw = D.nx - 1;
-        const int c00 = 4 * (gi + cw * gj), c10 = 4 * ((gi - 1) + cw * gj);
-        const int c01 = 4 * (gi + cw * (gj - 1)), c11 = 4 * ((gi - 1) + cw * (gj - 1));
-        if (D.prec == 32) {
-            const float2 v32 = make_float2((float)mr, (float)mi);
-            float2 *c = (float2 *)D.gather;
-            if (D.cells) {
-                c[c11 + 3] = v32;
-                c[c01 + 2] = v32;
-                c[c10 + 1] = v32;
-                c[c00 + 0] = v32;
-            } else {
-                c[node] = v32;
-            }
+        if (D.prec == 32 && !D.cells) {
+            ((float2 *)D.gather)[node] = make_float2((float)mr, (float)mi);
         } else if (D.cells) {
-            const double2 v64 = make_double2(mr, mi);
-            double2 *c = (double2 *)D.gather;
-            c[c11 + 3] = v64;
-            c[c01 + 2] = v64;
-            c[c10 + 1] = v64;
-            c[c00 + 0] = v64;
+#pragma unroll
+            for (int cq = 1; cq >= 0; --cq)
+#pragma unroll
+                for (int cp = 1; cp >= 0; --cp) {
+                    const int p = gi - cp, q = gj - cq;
+                    if (p < 0 || p > D.nx - 2 || q < 0 || q > D.ny - 2) continue;
+                    const int at = 4 * (p + cw * q) + cp + 2 * cq;
+                    if (D.prec == 32) ((float2 *)D.gather)[at] = make_float2((float)mr, (float)mi);
+                    else ((double2 *)D.gather)[at] = make_double2(mr, mi);
+                }
         }
         D.se[node] = make_double2(ser, sei);
         D.node_sum_j[node] = sj;
@@ -845,6 +941,7 @@ __global__ void fk_debug_paths_kernel(const Inst *__restrict__ inst, const int32
     Coef<R> cu;
     cu.re = use_u ? K.alpha : (R)0;
     cu.im = use_u ? K.damp : (R)0;
+    cu.ik = use_u ? K.kk : (R)0;
     const uint32_t ctr3 = D.crn ? 0u : (uint32_t)D.state->iter;
     if (i >= n) return;
     const int32_t node = nodes[i];
@@ -884,6 +981,7 @@ hipError_t launch_stream(int precision, int features, const Inst *d_insts, const
                          unsigned long long *head, int n_blocks, hipStream_t s)
 {
     dim3 grid(n_blocks), block(256);
+    // a reflecting edge comes with a hole: the sets with bit 3 all have bit 0
     switch (features & kFeatAll) {
     case 0: launch_stream_f<0>(precision, grid, block, d_insts, Q, head, s); break;
     case 1: launch_stream_f<1>(precision, grid, block, d_insts, Q, head, s); break;
@@ -892,7 +990,11 @@ hipError_t launch_stream(int precision, int features, const Inst *d_insts, const
     case 4: launch_stream_f<4>(precision, grid, block, d_insts, Q, head, s); break;
     case 5: launch_stream_f<5>(precision, grid, block, d_insts, Q, head, s); break;
     case 6: launch_stream_f<6>(precision, grid, block, d_insts, Q, head, s); break;
-    default: launch_stream_f<7>(precision, grid, block, d_insts, Q, head, s); break;
+    case 7: launch_stream_f<7>(precision, grid, block, d_insts, Q, head, s); break;
+    case 9: launch_stream_f<9>(precision, grid, block, d_insts, Q, head, s); break;
+    case 11: launch_stream_f<11>(precision, grid, block, d_insts, Q, head, s); break;
+    case 13: launch_stream_f<13>(precision, grid, block, d_insts, Q, head, s); break;
+    default: launch_stream_f<15>(precision, grid, block, d_insts, Q, head, s); break;
     }
     return hipGetLastError();
 }

@@ -65,16 +65,31 @@ static bool finite_all(std::initializer_list<double> v)
     return true;
 }
 
-static fk_status check_bc(const fk_bc &b, bool inner)
+static fk_status check_bc(const fk_bc &b, bool inner, bool reflecting_edge)
 {
-    if (b.kind < FK_BC_ZERO || b.kind > FK_BC_TABLE) return fail(FK_EINVAL, "unknown boundary datum kind");
+    if (b.kind < FK_BC_ZERO || b.kind > FK_BC_PLANE_WAVE_ROBIN) return fail(FK_EINVAL, "unknown boundary datum kind");
     if (b.kind == FK_BC_TABLE) {
         if (inner) return fail(FK_EINVAL, "TABLE datum is only allowed on the outer boundary");
         if (!b.table || b.table_len < 2) return fail(FK_EINVAL, "TABLE datum needs table_len >= 2 samples");
     }
+    if (b.kind == FK_BC_PLANE_WAVE_ROBIN && (inner || !reflecting_edge))
+        return fail(FK_EINVAL, "PLANE_WAVE_ROBIN is a Robin datum: only for a reflecting edge");
     for (double c : b.c)
         if (!std::isfinite(c)) return fail(FK_EINVAL, "boundary datum coefficients must be finite");
     return FK_OK;
+}
+
+// kappa = sqrt(k^2 + i p), the principal root (k when p = 0)
+static void kappa_of(const fk_params &par, double &kr, double &ki)
+{
+    kr = par.k;
+    ki = 0.0;
+    if (par.damping != 0.0) {
+        const double k2 = par.k * par.k;
+        const double mod = std::sqrt(k2 * k2 + par.damping * par.damping);
+        kr = std::sqrt(0.5 * (mod + k2));
+        ki = par.damping / (2.0 * kr);
+    }
 }
 
 // g at a boundary point on the host (FP64): the grid's boundary values.
@@ -83,8 +98,12 @@ static void host_bc(const HostProblem &P, const fk_bc &B, double x, double y, do
     const fk_domain &d = P.dom;
     switch (B.kind) {
     case FK_BC_PLANE_WAVE: {
-        const double ph = P.par.k * (x * std::cos(B.c[2]) + y * std::sin(B.c[2]));
-        const double c = std::cos(ph), s = std::sin(ph);
+        // amp exp(i kappa s): the damped plane wave when p != 0
+        double kr, ki;
+        kappa_of(P.par, kr, ki);
+        const double sd = x * std::cos(B.c[2]) + y * std::sin(B.c[2]);
+        const double ph = kr * sd, decay = std::exp(-ki * sd);
+        const double c = std::cos(ph) * decay, s = std::sin(ph) * decay;
         gr = B.c[0] * c - B.c[1] * s;
         gi = B.c[0] * s + B.c[1] * c;
         return;
@@ -128,8 +147,10 @@ fk_status setup_problem(const fk_domain *domain, const fk_source *f, const fk_bc
     if (g_inner) P.inner = *g_inner;
     else std::memset(&P.inner, 0, sizeof(P.inner));
     const fk_domain &d = P.dom;
-    if (d.kind != FK_DOMAIN_RECT && d.kind != FK_DOMAIN_RECT_MINUS_DISC)
+    if (d.kind != FK_DOMAIN_RECT && d.kind != FK_DOMAIN_RECT_MINUS_DISC && d.kind != FK_DOMAIN_RECT_MINUS_BOX)
         return fail(FK_EINVAL, "unknown domain kind");
+    if (d.edge != FK_EDGE_ABSORBING && d.edge != FK_EDGE_REFLECTING)
+        return fail(FK_EINVAL, "edge must be FK_EDGE_ABSORBING or FK_EDGE_REFLECTING");
     if (!finite_all({d.x0, d.x1, d.y0, d.y1}) || !(d.x1 > d.x0) || !(d.y1 > d.y0))
         return fail(FK_EINVAL, "rectangle needs finite x0 < x1 and y0 < y1");
     if (d.nx < 3 || d.ny < 3) return fail(FK_EINVAL, "nx and ny must be at least 3");
@@ -142,14 +163,32 @@ fk_status setup_problem(const fk_domain *domain, const fk_source *f, const fk_bc
         if (!(d.cx - d.r > d.x0 && d.cx + d.r < d.x1 && d.cy - d.r > d.y0 && d.cy + d.r < d.y1))
             return fail(FK_EINVAL, "disc must lie strictly inside the rectangle");
     }
+    if (d.kind == FK_DOMAIN_RECT_MINUS_BOX) {
+        if (!finite_all({d.cx, d.cy, d.r, d.ry}) || !(d.r > 0.0) || !(d.ry > 0.0))
+            return fail(FK_EINVAL, "box hole needs a finite centre and half-sides r, ry > 0");
+        if (!(d.cx - d.r > d.x0 && d.cx + d.r < d.x1 && d.cy - d.ry > d.y0 && d.cy + d.ry < d.y1))
+            return fail(FK_EINVAL, "box must lie strictly inside the rectangle");
+    }
+    const bool reflecting = d.edge == FK_EDGE_REFLECTING;
+    if (reflecting) {
+        if (d.kind == FK_DOMAIN_RECT)
+            return fail(FK_EINVAL, "a reflecting edge needs a hole (the paths are absorbed only there)");
+        if (params->max_steps <= 0) return fail(FK_EINVAL, "a reflecting edge needs an explicit max_steps");
+        if (params->g_unprojected) return fail(FK_EINVAL, "g_unprojected is not defined with a reflecting edge");
+        // the largest normal step is sqrt(-2 ln 2^-24) sqrt(2h) < 5.8 sqrt(2h):
+        // one mirror per coordinate brings any step back into the rectangle
+        const double smax = 6.0 * std::sqrt(2.0 * params->h);
+        if (!(d.x1 - d.x0 > smax && d.y1 - d.y0 > smax))
+            return fail(FK_EINVAL, "a reflecting edge needs sides longer than 6 sqrt(2 h)");
+    }
     if (P.src.kind < FK_SRC_ZERO || P.src.kind > FK_SRC_GAUSSIAN) return fail(FK_EINVAL, "unknown source kind");
     if (!finite_all({P.src.amp_re, P.src.amp_im, P.src.cx, P.src.cy}))
         return fail(FK_EINVAL, "source parameters must be finite");
     if (P.src.kind == FK_SRC_GAUSSIAN && !(P.src.sigma > 0.0 && std::isfinite(P.src.sigma)))
         return fail(FK_EINVAL, "Gaussian source needs sigma > 0");
     fk_status st;
-    if ((st = check_bc(P.outer, false)) != FK_OK) return st;
-    if ((st = check_bc(P.inner, true)) != FK_OK) return st;
+    if ((st = check_bc(P.outer, false, reflecting)) != FK_OK) return st;
+    if ((st = check_bc(P.inner, true, reflecting)) != FK_OK) return st;
     const fk_params &p = P.par;
     if (!std::isfinite(p.k) || p.k < 0.0) return fail(FK_EINVAL, "k must be finite and >= 0");
     if (!std::isfinite(p.h) || !(p.h > 0.0)) return fail(FK_EINVAL, "h must be > 0");
@@ -179,16 +218,21 @@ fk_status setup_problem(const fk_domain *domain, const fk_source *f, const fk_bc
     P.cls.assign(nn, 0);
     P.grid0.assign(2 * nn, 0.0);
     P.interior.clear();
+    // a node within 1e-9 grid steps of the box counts as in it
+    const double tx = 1e-9 * dx, ty = 1e-9 * dy;
     for (int32_t j = 0; j < d.ny; ++j) {
         for (int32_t i = 0; i < d.nx; ++i) {
             const size_t id = (size_t)i + (size_t)d.nx * j;
             const double x = d.x0 + (double)i * dx, y = d.y0 + (double)j * dy;
             uint8_t c = 0;
-            if (i == 0 || j == 0 || i == d.nx - 1 || j == d.ny - 1) c = 1;
-            else if (d.kind == FK_DOMAIN_RECT_MINUS_DISC) {
+            if (d.kind == FK_DOMAIN_RECT_MINUS_DISC) {
                 const double ex = x - d.cx, ey = y - d.cy;
                 if (ex * ex + ey * ey <= d.r * d.r) c = 2;
+            } else if (d.kind == FK_DOMAIN_RECT_MINUS_BOX) {
+                if (x >= d.cx - d.r - tx && x <= d.cx + d.r + tx && y >= d.cy - d.ry - ty && y <= d.cy + d.ry + ty)
+                    c = 2;
             }
+            if (c == 0 && !reflecting && (i == 0 || j == 0 || i == d.nx - 1 || j == d.ny - 1)) c = 1;
             P.cls[id] = c;
             if (c == 0) P.interior.push_back((int32_t)id);
             else host_bc(P, c == 2 ? P.inner : P.outer, x, y, P.grid0[2 * id], P.grid0[2 * id + 1]);
@@ -198,7 +242,8 @@ fk_status setup_problem(const fk_domain *domain, const fk_source *f, const fk_bc
     // last items of a launch have short paths and the lanes drain quickly at
     // the end.  The proxy is the harmonic combination of the 1-D exit times
     // (x - x0)(x1 - x)/2, (y - y0)(y1 - y)/2 and, with a hole, d_c L/2 for the
-    // distance d_c to the circle.  The order does not change any result: node
+    // distance d_c to the hole; with a reflecting edge (no exit there) the
+    // distance to the hole alone.  The order does not change any result: node
     // sums are exact and independent of which path ran when.
     {
         std::vector<std::pair<double, int32_t>> key;
@@ -206,12 +251,23 @@ fk_status setup_problem(const fk_domain *domain, const fk_source *f, const fk_bc
         const double L = 0.5 * ((d.x1 - d.x0) + (d.y1 - d.y0));
         for (int32_t id : P.interior) {
             const double x = d.x0 + (double)(id % d.nx) * dx, y = d.y0 + (double)(id / d.nx) * dy;
-            double inv = 2.0 / ((x - d.x0) * (d.x1 - x)) + 2.0 / ((y - d.y0) * (d.y1 - y));
+            double dc = 0.0;
             if (d.kind == FK_DOMAIN_RECT_MINUS_DISC) {
-                const double dc = std::sqrt((x - d.cx) * (x - d.cx) + (y - d.cy) * (y - d.cy)) - d.r;
-                inv += 2.0 / (dc * L);
+                dc = std::sqrt((x - d.cx) * (x - d.cx) + (y - d.cy) * (y - d.cy)) - d.r;
+            } else if (d.kind == FK_DOMAIN_RECT_MINUS_BOX) {
+                const double ox = std::fmax(std::fabs(x - d.cx) - d.r, 0.0);
+                const double oy = std::fmax(std::fabs(y - d.cy) - d.ry, 0.0);
+                dc = std::hypot(ox, oy);
             }
-            key.emplace_back(1.0 / inv, id);
+            double k;
+            if (reflecting) {
+                k = dc;
+            } else {
+                double inv = 2.0 / ((x - d.x0) * (d.x1 - x)) + 2.0 / ((y - d.y0) * (d.y1 - y));
+                if (d.kind != FK_DOMAIN_RECT) inv += 2.0 / (dc * L);
+                k = 1.0 / inv;
+            }
+            key.emplace_back(k, id);
         }
         std::stable_sort(key.begin(), key.end(),
                          [](const std::pair<double, int32_t> &a, const std::pair<double, int32_t> &b) {
@@ -279,19 +335,14 @@ static void fill_bc(fkd::BCDev &dst, const fk_bc &src, const double2 *table, int
 {
     std::memset(&dst, 0, sizeof(dst));
     dst.kind = src.kind;
-    if (src.kind == FK_BC_PLANE_WAVE) {
+    if (src.kind == FK_BC_PLANE_WAVE || src.kind == FK_BC_PLANE_WAVE_ROBIN) {
         dst.c[0] = src.c[0];
         dst.c[1] = src.c[1];
         dst.c[2] = std::cos(src.c[2]);
         dst.c[3] = std::sin(src.c[2]);
         // wavenumber kappa = sqrt(k^2 + i p) (principal root; k when p = 0)
-        double kr = par.k, ki = 0.0;
-        if (par.damping != 0.0) {
-            const double k2 = par.k * par.k;
-            const double mod = std::sqrt(k2 * k2 + par.damping * par.damping);
-            kr = std::sqrt(0.5 * (mod + k2));
-            ki = par.damping / (2.0 * kr);
-        }
+        double kr, ki;
+        kappa_of(par, kr, ki);
         dst.c[4] = kr;
         dst.c[5] = ki;
     } else if (src.kind == FK_BC_BILINEAR) {
@@ -313,12 +364,17 @@ fkd::Inst make_inst(const HostProblem &P, const InstanceBuffers &B)
     D.idx = 1.0 / D.dx;
     D.idy = 1.0 / D.dy;
     D.cx = d.cx; D.cy = d.cy; D.r = d.r; D.r2 = d.r * d.r;
+    D.bx0 = d.cx - d.r; D.bx1 = d.cx + d.r; D.by0 = d.cy - d.ry; D.by1 = d.cy + d.ry;
     // binary32 edges rounded outward: largest float <= x0, smallest float >= x1
     auto rd = [](double v) { float f = (float)v; return (double)f > v ? std::nextafter(f, -INFINITY) : f; };
     auto ru = [](double v) { float f = (float)v; return (double)f < v ? std::nextafter(f, INFINITY) : f; };
     D.x0_rd = rd(d.x0); D.x1_ru = ru(d.x1); D.y0_rd = rd(d.y0); D.y1_ru = ru(d.y1);
+    // box: x >= bx0 exactly iff x >= RU(bx0) for a binary32 x, x <= bx1 iff x <= RD(bx1)
+    D.bx0_ru = ru(D.bx0); D.bx1_rd = rd(D.bx1); D.by0_ru = ru(D.by0); D.by1_rd = rd(D.by1);
     D.nx = d.nx; D.ny = d.ny;
-    D.disc = d.kind == FK_DOMAIN_RECT_MINUS_DISC ? 1 : 0;
+    D.hole = d.kind == FK_DOMAIN_RECT_MINUS_DISC ? fkd::HOLE_DISC
+           : (d.kind == FK_DOMAIN_RECT_MINUS_BOX ? fkd::HOLE_BOX : fkd::HOLE_NONE);
+    D.reflect = P.reflect() ? 1 : 0;
     D.n_interior = (int32_t)P.interior.size();
     D.src_kind = P.src.kind;
     D.g_unproj = P.par.g_unprojected ? 1 : 0;
@@ -333,6 +389,7 @@ fkd::Inst make_inst(const HostProblem &P, const InstanceBuffers &B)
     D.damp = P.par.damping;
     D.q = std::exp(-(D.alpha - D.k2) * P.par.h);
     D.h = P.par.h;
+    D.ih = 1.0 / P.par.h;
     D.sigma = std::sqrt(2.0 * P.par.h);
     D.M = P.par.M;
     D.jmax = P.jmax;

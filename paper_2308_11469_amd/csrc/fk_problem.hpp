@@ -34,8 +34,8 @@ struct HostProblem {
     fk_bc outer{}, inner{};
     fk_params par{};
     std::vector<double> table;        // outer TABLE samples (re, im), copied
-    std::vector<uint8_t> cls;         // 0 interior, 1 rectangle edge, 2 hole
-    std::vector<int32_t> interior;    // interior node ids, longest expected paths first
+    std::vector<uint8_t> cls;         // 0 unknown (interior or reflecting edge), 1 absorbing edge, 2 hole
+    std::vector<int32_t> interior;    // unknown node ids, longest expected paths first
     std::vector<double> grid0;        // initial grid (re, im): 0 interior, g elsewhere
     int64_t jmax = 0;
     int32_t ppi = 0;                  // paths per work item
@@ -43,13 +43,14 @@ struct HostProblem {
     int64_t n_items = 0;
     int32_t cells = 0;                // the gather copy of u_n is cell-major
     // optional parts of the stepping loop this instance needs (bit 0 a hole,
-    // bit 1 a source term, bit 2 a shift alpha != k^2 or damping); the path
-    // kernel is compiled per set
+    // bit 1 a source term, bit 2 a shift alpha != k^2 or damping, bit 3 a
+    // reflecting edge); the path kernel is compiled per set
     int features() const
     {
-        return (dom.kind == FK_DOMAIN_RECT_MINUS_DISC ? 1 : 0) | (src.kind != FK_SRC_ZERO ? 2 : 0) |
-               (alpha() != par.k * par.k || par.damping != 0.0 ? 4 : 0);
+        return (dom.kind != FK_DOMAIN_RECT ? 1 : 0) | (src.kind != FK_SRC_ZERO ? 2 : 0) |
+               (alpha() != par.k * par.k || par.damping != 0.0 ? 4 : 0) | (reflect() ? 8 : 0);
     }
+    bool reflect() const { return dom.edge == FK_EDGE_REFLECTING; }
     double alpha() const { return par.alpha == 0.0 ? par.k * par.k : par.alpha; }
     size_t n_nodes() const { return (size_t)dom.nx * (size_t)dom.ny; }
     size_t n_cells() const { return (size_t)(dom.nx - 1) * (size_t)(dom.ny - 1); }

@@ -22,9 +22,9 @@ FK_OK, FK_EINVAL, FK_ENOMEM, FK_EDEVICE, FK_EDIVERGED, FK_ENOTCONVERGED, FK_EBUS
 STATUS_NAMES = {0: "FK_OK", 1: "FK_EINVAL", 2: "FK_ENOMEM", 3: "FK_EDEVICE", 4: "FK_EDIVERGED",
                 5: "FK_ENOTCONVERGED", 6: "FK_EBUSY"}
 
-_DOMAIN = {"rect": 0, "rect_minus_disc": 1}
+_DOMAIN = {"rect": 0, "rect_minus_disc": 1, "rect_minus_box": 2}
 _SRC = {"zero": 0, "const": 1, "gaussian": 2}
-_BC = {"zero": 0, "plane_wave": 1, "bilinear": 2, "table": 3}
+_BC = {"zero": 0, "plane_wave": 1, "bilinear": 2, "table": 3, "plane_wave_robin": 4}
 GATHER = {"auto": 0, "nodes": 1, "cells": 2}   # layout of the gathered copy of u_n (fk_gather_layout)
 
 
@@ -38,9 +38,9 @@ class FkError(RuntimeError):
 
 
 class fk_domain(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("reserved", C.c_int32),
+    _fields_ = [("kind", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("edge", C.c_int32),
                 ("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
-                ("cx", C.c_double), ("cy", C.c_double), ("r", C.c_double)]
+                ("cx", C.c_double), ("cy", C.c_double), ("r", C.c_double), ("ry", C.c_double)]
 
 
 class fk_source(C.Structure):
@@ -161,6 +161,8 @@ class Marshalled:
         d.nx, d.ny = int(p.nx), int(p.ny)
         d.x0, d.x1, d.y0, d.y1 = p.x0, p.x1, p.y0, p.y1
         d.cx, d.cy, d.r = p.cx, p.cy, p.r
+        d.ry = float(getattr(p, "ry", 0.0))
+        d.edge = 1 if getattr(p, "reflect", False) else 0
         f = fk_source()
         f.kind = _SRC[p.src_kind]
         a = complex(p.src_amp)
@@ -170,7 +172,7 @@ class Marshalled:
         for bc in (p.outer, p.inner):
             b = fk_bc()
             b.kind = _BC[bc.kind]
-            if bc.kind == "plane_wave":
+            if bc.kind in ("plane_wave", "plane_wave_robin"):
                 amp = complex(bc.amp)
                 b.c[0], b.c[1], b.c[2] = amp.real, amp.imag, bc.theta
             elif bc.kind == "bilinear":

@@ -140,3 +140,41 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(fkh, "_lib", None)
     with pytest.raises(RuntimeError, match="not built"):
         fkh.lib()
+
+
+@pytest.mark.parametrize("bad", ["no_hole", "no_step_cap", "unprojected", "robin_on_absorbing_edge",
+                                 "robin_inner", "box_outside", "box_flat", "sides_vs_step"])
+def test_reflecting_edge_and_box_validation(lib, bad):
+    p = W.annulus_shape3(nx=21, ny=33)
+    if bad == "no_hole":
+        p = p.replace(domain_kind="rect")
+    elif bad == "no_step_cap":
+        p = p.replace(jmax=0)
+    elif bad == "unprojected":
+        p = p.replace(g_unprojected=True)
+    elif bad == "robin_on_absorbing_edge":
+        p = p.replace(reflect=False, outer=W.BC("plane_wave_robin", 1.0, 0.3))
+    elif bad == "robin_inner":
+        p = p.replace(inner=W.BC("plane_wave_robin", 1.0, 0.3))
+    elif bad == "box_outside":
+        p = p.replace(ry=0.9)
+    elif bad == "box_flat":
+        p = p.replace(ry=0.0)
+    elif bad == "sides_vs_step":
+        # 6 sqrt(2 h) = 0.85 with h = 0.01: longer than the 0.8-wide side
+        p = p.replace(h=0.01, x0=-0.4, x1=0.4)
+    if bad == "robin_inner":
+        # the inner datum is checked at create (validation precedes any device call)
+        m = fkh.Marshalled(p)
+        h = C.c_void_p()
+        assert lib.fk_helmholtz_create(*m.args(), None, 0, None, C.byref(h)) == fkh.FK_EINVAL and not h.value
+        return
+    assert arena_status(p)[0] == fkh.FK_EINVAL, bad
+
+
+def test_annulus_workloads_accepted(lib):
+    for p in (W.annulus_shape1(), W.annulus_shape3(), W.annulus_fig2(),
+              W.annulus_shape1().replace(outer=W.BC("plane_wave_robin", 1.0, 0.4),
+                                         inner=W.BC("plane_wave", 1.0, 0.4), alpha=3.0, damping=0.5)):
+        st, nbytes = arena_status(p)
+        assert st == fkh.FK_OK, (p.name, fkh.lib().fk_helmholtz_last_error())
