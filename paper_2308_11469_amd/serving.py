@@ -82,7 +82,12 @@ def predicted_rho(p) -> float:
     |alpha + i p| / (lambda_1 + alpha - k^2) (k^2 / lambda_1 without shift or
     damping; the iteration of Sec. 2.2 multiplies the first mode by this), with
     lambda_1 of the domain enlarged by the discrete-monitoring shift
-    delta = beta sqrt(2h) (outer boundary out by delta, hole in by delta)."""
+    delta = beta sqrt(2h) (outer boundary out by delta, hole in by delta).
+    Absorbing edge only: with a reflecting edge there is no such closed form
+    (NaN; the sufficient bound of Theorem 2.3 comes from the estimators
+    ``exit_time_problem`` and ``local_time_problem``)."""
+    if getattr(p, "reflect", False):
+        return math.nan
     d = BGK_BETA * math.sqrt(2 * p.h)
     a, b = p.x1 - p.x0, p.y1 - p.y0
     if p.domain_kind == "rect":
@@ -106,14 +111,42 @@ def settled(rep: dict) -> bool:
 def exit_time_problem(p, M=1024):
     """The same domain and grid with k = 0, f = -1, g = 0: one Feynman-Kac
     step of it estimates E[tau] at every node (Remark 2.5), whose maximum gives
-    the sufficient bound k_*^C = (max E[tau])^(-1/2) (Remark 2.4)."""
+    the sufficient bound k_*^C = (max E[tau])^(-1/2) (Remark 2.4).  With a
+    reflecting edge (g2 = 0 there) it is the mean exit time of the reflected
+    diffusion, which Theorem 2.3 uses."""
     from .workloads import BC
-    return p.replace(k=0.0, src_kind="const", src_amp=-1.0 + 0j, outer=BC("zero"), inner=BC("zero"),
-                     M=M, crn=False, max_iters=1, tol=0.0)
+    return p.replace(k=0.0, alpha=None, damping=0.0, src_kind="const", src_amp=-1.0 + 0j, outer=BC("zero"),
+                     inner=BC("zero"), M=M, crn=False, max_iters=1, tol=0.0)
 
 
 def kstar_cavity(exit_times: np.ndarray) -> float:
     return 1.0 / math.sqrt(float(np.max(exit_times)))
+
+
+def local_time_problem(p, M=1024):
+    """For a reflecting edge: the same domain and grid with k = 0, f = 0,
+    u = 0 on the hole and Robin datum g2 = 1 (d_n L = 1 on the edge): one
+    Feynman-Kac step of it estimates the mean local time E[xi] on the edge at
+    every node (the remark after Theorem 2.3)."""
+    from .workloads import BC
+    return p.replace(k=0.0, alpha=None, damping=0.0, src_kind="zero", outer=BC("bilinear", coeffs=(1.0 + 0j, 0j, 0j, 0j)),
+                     inner=BC("zero"), M=M, crn=False, max_iters=1, tol=0.0)
+
+
+def khat_annulus(exit_time, local_time):
+    """Largest k with alpha = k^2 meeting alpha E[tau] + k E[xi] < 1 at a
+    point: (-E[xi] + sqrt(E[xi]^2 + 4 E[tau])) / (2 E[tau]) (the remark after
+    Theorem 2.3); k_*^A is its minimum over the domain."""
+    E = np.asarray(exit_time, dtype=float)
+    L = np.asarray(local_time, dtype=float)
+    return (-L + np.sqrt(L * L + 4.0 * E)) / (2.0 * E)
+
+
+def theorem23_bound(p, sup_exit_time, sup_local_time) -> float:
+    """alpha sup E[tau] + k sup E[xi]: below one, the annular iteration
+    converges (Theorem 2.3, a sufficient condition)."""
+    alpha = p.k ** 2 if getattr(p, "alpha", None) is None else p.alpha
+    return alpha * sup_exit_time + p.k * sup_local_time
 
 
 # ----------------------------------------------------------------- server

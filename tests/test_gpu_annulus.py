@@ -1,0 +1,127 @@
+"""GPU: the annular problems of Sec. 2.3 / Table 1 on the path kernels.
+
+* The mean exit time and mean local time of the reflected diffusion
+  (estimated by one Feynman-Kac step each, k = 0) agree node by node with
+  finite differences on the hole shrunk by the continuity correction of the
+  once-per-step exit test.
+* Extrapolated to h -> 0 (the exit bias is O(sqrt h)), their suprema give
+  Table 1's sup E[tau], sup E[xi] and k_*^A for shapes 1 and 3.
+* At the k values Table 1 tests, N = 30 iterations converge to the FD
+  solution of the Robin problem where the table says "converges" and move
+  away from it where it says "diverges"."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import closed_forms as CF
+from oracle import fd_mixed as FM
+from oracle import fkmc
+from paper_2308_11469_amd import fkh, serving
+from paper_2308_11469_amd import workloads as W
+
+from gpu_util import require_lib, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    require_lib()
+
+
+def shrunk(p, h):
+    d = CF.bgk_beta() * math.sqrt(2.0 * h)
+    return p.replace(r=p.r - d, ry=max(p.ry - d, 0.0) if p.ry else 0.0)
+
+
+def one_step(p):
+    s = fkh.Solver(p)
+    s.iterate(1)
+    u, se = s.get()
+    s.close()
+    return u.real, se.real
+
+
+@pytest.mark.parametrize("shape", ["shape1", "shape3"])
+def test_exit_and_local_time_maps_match_fd(shape):
+    h = 4e-5
+    if shape == "shape1":
+        base = W.annulus_shape1(n=13, h=h, precision=32)
+        fine, step = W.annulus_shape1(n=121), 10
+    else:
+        base = W.annulus_shape3(nx=21, ny=33, h=h, precision=32)
+        fine, step = W.annulus_shape3(nx=161, ny=257), 8
+    ids = fkmc.interior_ids(base)
+    fid = (ids % base.nx) * step + fine.nx * ((ids // base.nx) * step)
+    for which in ("exit_time", "local_time"):
+        mk = serving.exit_time_problem if which == "exit_time" else serving.local_time_problem
+        E, se = one_step(mk(base, M=8192))
+        ref = (FM.exit_time if which == "exit_time" else FM.local_time)(shrunk(fine, h)).ravel()[fid]
+        z = (E.ravel()[ids] - ref) / se.ravel()[ids]
+        say(shape, which, "max |z| %.2f, max rel %.4f" % (np.abs(z).max(), np.max(np.abs(E.ravel()[ids] - ref) / ref)))
+        assert np.all(np.abs(E.ravel()[ids] - ref) <= 4.5 * se.ravel()[ids] + 0.015 * ref)
+
+
+def corner_mean(u, p):
+    return float(np.mean([u[0, 0], u[0, -1], u[-1, 0], u[-1, -1]]))
+
+
+@pytest.mark.parametrize("shape,table", [("shape1", (0.03, 0.46, 1.93)), ("shape3", (0.20, 1.24, 0.72))])
+def test_table1_suprema_and_kstar_from_gpu(shape, table):
+    # the suprema sit at the rectangle's four corners (farthest from the
+    # hole, by symmetry equal); E(h) = E_0 + c sqrt(h) + O(h): from h and h/4,
+    # E_0 ~ 2 E(h/4) - E(h)
+    est = {}
+    for which in ("exit_time", "local_time"):
+        vals = []
+        for h in (4e-5, 1e-5):
+            if shape == "shape1":
+                p = W.annulus_shape1(n=7, h=h, precision=32)
+            else:
+                p = W.annulus_shape3(nx=11, ny=17, h=h, precision=32)
+            mk = serving.exit_time_problem if which == "exit_time" else serving.local_time_problem
+            u, se = one_step(mk(p, M=1 << 18))
+            vals.append(corner_mean(u, p))
+        est[which] = 2.0 * vals[1] - vals[0]
+        say(shape, which, "E(4e-5) %.5f E(1e-5) %.5f -> %.5f" % (vals[0], vals[1], est[which]))
+    ks = float(serving.khat_annulus(est["exit_time"], est["local_time"]))
+    say(shape, "k_*^A %.4f (Table 1: %s)" % (ks, table))
+    assert round(est["exit_time"], 2) == table[0]
+    assert round(est["local_time"], 2) == table[1]
+    assert round(ks, 2) == table[2]
+
+
+# Table 1: tested k, and whether the sum of 30 iterates converged
+TABLE1 = {"shape1": [(1.50, True), (1.93, True), (1.94, True), (2.90, False)],
+          "shape3": [(0.50, True), (0.72, True), (0.73, True), (1.07, False)]}
+
+
+@pytest.mark.parametrize("shape", ["shape1", "shape3"])
+def test_table1_convergence_outcomes(shape):
+    for k, converges in TABLE1[shape]:
+        if shape == "shape1":
+            p = W.annulus_shape1(k=k, n=31, M=8192, h=1e-4, precision=32, seed=51)
+            fine, step = W.annulus_shape1(k=k, n=121), 4
+        else:
+            p = W.annulus_shape3(k=k, nx=21, ny=33, M=8192, h=1e-4, precision=32, seed=53)
+            fine, step = W.annulus_shape3(k=k, nx=161, ny=257), 8
+        ref = FM.direct(shrunk(fine, p.h))[::step, ::step]
+        ids = fkmc.interior_ids(p)
+        s = fkh.Solver(p)
+        acc = np.zeros(len(ids), complex)
+        errs = []
+        for it in range(30):
+            s.iterate(1)
+            u = s.get()[0].ravel()[ids]
+            errs.append(float(np.max(np.abs(u.real - ref.ravel()[ids].real))))
+            if it >= 22:
+                acc += u
+        s.close()
+        avg_err = float(np.max(np.abs((acc / 8.0).real - ref.ravel()[ids].real)))
+        say(shape, "k=%.2f sup|Re(U_30) - Re(u_FD)| %.4f (mean of last 8: %.4f), err at 10/20/30: %.3f %.3f %.3f"
+            % (k, errs[-1], avg_err, errs[9], errs[19], errs[29]))
+        if converges:
+            assert avg_err < 0.1
+        else:
+            assert errs[-1] > 0.5 and errs[-1] > errs[19] > errs[9]
