@@ -73,6 +73,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP32, batched and serving figures")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--annulus-only", action="store_true",
+                    help="only time the reflecting-edge kernels on the shape-3 annulus and print that line")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run three device-to-device copies of MIB MiB (the reference kernel for "
                          "scaling HBM byte counters) and exit")
@@ -143,6 +145,36 @@ def fp32_same_config(k, steps):
     return dict(value=steps_total / wall, unit="path-steps/s", ms_per_step=wall / steps * 1e3,
                 kernel_ms_avg=ms / max(n, 1),
                 roofline_frac=FLOPS_PER_STEP[32] * steps_total / (ms / 1e3) / 1e12 / PEAK_TFLOPS[32])
+
+
+def annulus_shape3(steps=3):
+    """The annular problem of Sec. 2.3 on the paper's shape 3 (rectangle
+    [-0.5, 0.5] x [-0.8, 0.8] with the box hole [-0.05, 0.05] x [-0.4, 0.4],
+    reflecting Robin edge) at the grid step 0.01 of its FE mesh (101 x 161
+    nodes), k = 0.5, M = 4096, h = 1e-4: path-steps/s of the reflecting
+    kernels in both precisions, one iteration per step after two warm-up
+    iterations."""
+    import torch
+    from paper_2308_11469_amd import fkh
+    from paper_2308_11469_amd import workloads as W
+    out = {"workload": "annulus shape 3, 101x161, k=0.5, M=4096, h=1e-4, reflecting edge"}
+    for prec in (64, 32):
+        s = fkh.Solver(W.annulus_shape3(k=0.5, nx=101, ny=161, M=4096, h=1e-4, precision=prec))
+        s.iterate(2)
+        s.timing(reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = [s.iterate(1) for _ in range(steps)]
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms, n = s.timing()
+        s.close()
+        total = sum(r["path_steps"] for r in reps)
+        out["fp%d" % prec] = dict(value=total / wall, unit="path-steps/s", ms_per_step=wall / steps * 1e3,
+                                  kernel_ms_avg=ms / max(n, 1), path_steps_per_iteration=total / steps,
+                                  roofline_frac=FLOPS_PER_STEP[prec] * total / (ms / 1e3) / 1e12
+                                  / PEAK_TFLOPS[prec])
+    return out
 
 
 def batched_vs_plain(n_sub=16, ticks=2):
@@ -233,6 +265,9 @@ def main():
     if a.calibrate_copy:
         calibrate_copy(a.calibrate_copy)
         return
+    if a.annulus_only:
+        print(json.dumps(annulus_shape3(a.steps)), flush=True)
+        return
     import numpy as np
     import torch
     from paper_2308_11469_amd import build, fkh
@@ -304,6 +339,7 @@ def main():
         out["extra"]["fp32_same_config"] = fp32_same_config(a.k, 5)
         out["extra"]["batched_fp32_vs_plain_fp64"] = batched_vs_plain()
         out["extra"]["serving_scatter_window"] = serving_window()
+        out["extra"]["annulus_shape3_reflecting"] = annulus_shape3()
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p, a.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -361,6 +361,38 @@ __device__ __forceinline__ bool advance(const Inst &D, const Consts<R> &K, PathS
     if (refl) m1 = reflect(K, x1, y1);
     R x2 = x1 + K.sigma * z1x, y2 = y1 + K.sigma * z1y;
     if (refl) m2 = reflect(K, x2, y2);
+    const bool general = (F & kFeatGeneral) && K.general;
+    bool out1, out2, second;
+    if constexpr ((F & kFeatReflect) != 0) {
+        // with a reflecting edge the exit tests and the local-time terms come
+        // before the left-point gathers, so that the mirror state is dead
+        // while those are in flight
+        out1 = is_out<F>(D, K, x1, y1);
+        out2 = is_out<F>(D, K, x2, y2);
+        second = !out1 && P.t + 1 < K.jmax;
+        // local time of the step(s) taken: up to one mirror move per face and
+        // step (bits 0-3: step 1 x, step 1 y, step 2 x, step 2 y), each at
+        // the end-of-step discount.  Each lane works through its own moves,
+        // so the wave runs the term as often as its busiest lane needs (one
+        // move per trip, nearly always), not once per kind of move.
+        uint32_t todo = (uint32_t)(m1.fx >= 0) | ((uint32_t)(m1.fy >= 0) << 1);
+        if (second) todo |= ((uint32_t)(m2.fx >= 0) << 2) | ((uint32_t)(m2.fy >= 0) << 3);
+        if (todo) {
+            const double w1 = general ? P.w * K.q : 1.0;
+            const double w2 = general ? w1 * K.q : 1.0;
+            do {
+                const int c = __builtin_ctz(todo);
+                todo &= todo - 1u;
+                const bool s2 = c >= 2, ym = (c & 1) != 0;
+                const int face = ym ? (s2 ? m2.fy : m1.fy) : (s2 ? m2.fx : m1.fx);
+                const R px = s2 ? x2 : x1, py = s2 ? y2 : y1;
+                const R fx = face == 0 ? K.rx0 : (face == 1 ? K.rx1 : px);
+                const R fy = face == 2 ? K.ry0 : (face == 3 ? K.ry1 : py);
+                const R dxi = ym ? (s2 ? m2.ly : m1.ly) : (s2 ? m2.lx : m1.lx);
+                local_time_term<R, F>(D, K, face, fx, fy, dxi, s2 ? w2 : w1, cu.ik, P);
+            } while (todo);
+        }
+    }
     g0.c = locate(K, P.x, P.y);
     g1.c = locate(K, x1, y1);
     issue_reads(K, g0.c.off, g0);
@@ -371,7 +403,6 @@ __device__ __forceinline__ bool advance(const Inst &D, const Consts<R> &K, PathS
     value(g0, v0r, v0i);
     value(g1, v1r, v1i);
     R fr, fi, gr, gi;
-    const bool general = (F & kFeatGeneral) && K.general;
     if (general) {
         fr = -(cu.re * v0r - cu.im * v0i);
         fi = -(cu.re * v0i + cu.im * v0r);
@@ -392,25 +423,10 @@ __device__ __forceinline__ bool advance(const Inst &D, const Consts<R> &K, PathS
         gr += sr;
         gi += si;
     }
-    const bool out1 = is_out<F>(D, K, x1, y1);
-    const bool out2 = is_out<F>(D, K, x2, y2);
-    const bool second = !out1 && P.t + 1 < K.jmax;
-    if ((F & kFeatReflect) && refl && (m1.fx >= 0 || m1.fy >= 0 || (second && (m2.fx >= 0 || m2.fy >= 0)))) {
-        // local time of the step(s) taken: up to one mirror move per face
-        // and step, each at the end-of-step discount
-        const double w1 = general ? P.w * K.q : 1.0;
-        const double w2 = general ? w1 * K.q : 1.0;
-#pragma unroll 1
-        for (int c = 0; c < 4; ++c) {
-            const bool s2 = c >= 2;
-            const Mirror<R> &m = s2 ? m2 : m1;
-            const int face = (c & 1) ? m.fy : m.fx;
-            if (face < 0 || (s2 && !second)) continue;
-            const R px = s2 ? x2 : x1, py = s2 ? y2 : y1;
-            const R fx = face == 0 ? K.rx0 : (face == 1 ? K.rx1 : px);
-            const R fy = face == 2 ? K.ry0 : (face == 3 ? K.ry1 : py);
-            local_time_term<R, F>(D, K, face, fx, fy, (c & 1) ? m.ly : m.lx, s2 ? w2 : w1, cu.ik, P);
-        }
+    if constexpr ((F & kFeatReflect) == 0) {
+        out1 = is_out<F>(D, K, x1, y1);
+        out2 = is_out<F>(D, K, x2, y2);
+        second = !out1 && P.t + 1 < K.jmax;
     }
     if (general) {
         // each value with its own discount, summed in FP64
