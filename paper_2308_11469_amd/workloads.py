@@ -20,7 +20,7 @@ plane-wave scattering by a sound-soft obstacle of Sec. 1):
 * ``scatter_stream`` sound-soft disc r = 0.25 in [-1, 1]^2 with exact outer
                      Dirichlet data from the Hankel series, Poisson arrivals.
 * ``annulus_shape1`` / ``annulus_shape3`` / ``annulus_fig2``  the annular
-                     problems of Sec. 2.3 and Sec. 3: a rectangle whose edge
+                     problems of Sec. 2.3 and Sec. 2.5: a rectangle whose edge
                      carries the Robin condition d_n u - i k u = 0 (reflected
                      paths with local time) around an absorbing hole with
                      u = -exp(-i k x); the geometries of the paper's shapes 1
