@@ -238,6 +238,23 @@ fk_status fk_helmholtz_node_stats(fk_solver *s, int64_t *sum_j, int64_t *capped)
  * checkpoint and to feed the same u_n to another implementation. */
 fk_status fk_helmholtz_set_iterate(fk_solver *s, const double *u_reim, int32_t n, int32_t on_device);
 
+/* Probabilistic domain decomposition (the two-stage procedure of Sec. 3,
+ * motivated in Sec. 1): from the next iteration on, Feynman-Kac paths run
+ * only from the unknown nodes on the listed grid lines (x index in cuts_x,
+ * y index in cuts_y: the subdomain interfaces), and every block of unknown
+ * nodes between consecutive lines (or the edge) is then solved on the
+ * device as its own Dirichlet problem of the same Poisson step,
+ *   (Delta_h - (alpha - k^2)) u_{n+1} = f - (alpha + i p) u_n,
+ * 5-point Laplacian, boundary values = the new interface values and g, by
+ * fast diagonalisation (DST-I in x and y).  The iteration report's
+ * statistics (max_du, sup, max_se, noise_ratio, path_steps) cover the
+ * interface nodes.  Host arrays, copied.  FK_EINVAL: not a plain rectangle
+ * with an absorbing edge, called after the first iteration or twice, no cut,
+ * cuts not strictly increasing within [1, nx-2] / [1, ny-2], or a block
+ * wider than 64 nodes.  Allocates its device tables (freed at destroy). */
+fk_status fk_helmholtz_set_pdd(fk_solver *s, const int32_t *cuts_x, int32_t n_cuts_x, const int32_t *cuts_y,
+                               int32_t n_cuts_y);
+
 /* Accumulated device time of the path kernel since creation or the last
  * reset (HIP events recorded on the solver's stream around each launch). */
 fk_status fk_helmholtz_timing(fk_solver *s, double *step_ms_total, int64_t *launches, int32_t reset);

@@ -919,6 +919,135 @@ __global__ void fk_advance_kernel(const Inst *__restrict__ insts, const int32_t 
     st->use_u = 1;
 }
 
+// ------------------------------------------- probabilistic domain decomposition
+// Sec. 3's two-stage procedure: the path kernel has estimated u_{n+1} at the
+// interface nodes only (the instance's node list is the interface); the
+// update kernel has written them.  Every block of unknown nodes between the
+// interface lines is then the Dirichlet problem
+//   (Delta_h - (alpha - k^2)) u_{n+1} = f - (alpha + i p) u_n
+// with the 5-point Laplacian, the interface values and the edge data g as
+// boundary values.  The 5-point Laplacian of an mx x my block is
+// S_x L_x S_x (x) + S_y L_y S_y (y) with the orthonormal DST-I matrices
+// S_m[a][b] = sqrt(2/(m+1)) sin(pi (a+1)(b+1)/(m+1)) (symmetric, S_m^2 = I)
+// and L_m = -(4/h^2) sin^2(pi (p+1)/(2(m+1))), so
+//   u = S_x ((S_x r S_y) / (L_x[p] + L_y[q] - (alpha - k^2))) S_y.
+// Tables per block size m (host-built): 2(m+1) values sqrt(2/(m+1))
+// sin(pi t/(m+1)) (entry S[a][b] is t = (a+1)(b+1) mod 2(m+1)), then m
+// values 4 sin^2(pi (p+1)/(2(m+1))).
+
+__device__ __forceinline__ double comp_of(double2 v, int c) { return c ? v.y : v.x; }
+
+// Right-hand side of every block node (both components): one block per
+// workgroup.  Kept apart from the solve, which overwrites u_n.
+__global__ void __launch_bounds__(256) fk_pdd_rhs_kernel(const Inst *__restrict__ inst,
+                                                         const PddBlock *__restrict__ blocks,
+                                                         double2 *__restrict__ rhs)
+{
+    const Inst &D = *inst;
+    const PddBlock B = blocks[blockIdx.x];
+    const int mx = B.i1 - B.i0, my = B.j1 - B.j0, n = mx * my;
+    const double idx2 = D.idx * D.idx, idy2 = D.idy * D.idy;
+    const bool use_u = D.state->use_u != 0;
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const int a = e / my, b = e - (e / my) * my;
+        const int gi = B.i0 + a, gj = B.j0 + b;
+        const int node = gi + D.nx * gj;
+        double rr = 0.0, ri = 0.0;
+        if (D.src_kind == SRC_CONST) {
+            rr = D.src_re;
+            ri = D.src_im;
+        } else if (D.src_kind == SRC_GAUSSIAN) {
+            const double ex = D.x0 + (double)gi * D.dx - D.src_cx, ey = D.y0 + (double)gj * D.dy - D.src_cy;
+            const double g = exp(-D.src_c * (ex * ex + ey * ey));
+            rr = D.src_re * g;
+            ri = D.src_im * g;
+        }
+        if (use_u) {
+            const double2 u = D.u64[node];
+            rr -= D.alpha * u.x - D.damp * u.y;
+            ri -= D.alpha * u.y + D.damp * u.x;
+        }
+        // Dirichlet neighbours outside the block: interface values of u_{n+1}
+        // (already written) or the edge data
+        if (a == 0) { const double2 v = D.u64[node - 1]; rr -= idx2 * v.x; ri -= idx2 * v.y; }
+        if (a == mx - 1) { const double2 v = D.u64[node + 1]; rr -= idx2 * v.x; ri -= idx2 * v.y; }
+        if (b == 0) { const double2 v = D.u64[node - D.nx]; rr -= idy2 * v.x; ri -= idy2 * v.y; }
+        if (b == my - 1) { const double2 v = D.u64[node + D.nx]; rr -= idy2 * v.x; ri -= idy2 * v.y; }
+        rhs[node] = make_double2(rr, ri);
+    }
+}
+
+// One (block, component) per workgroup: r and a work array of mx * my
+// doubles in LDS (at most 64 x 64: 64 KiB), four dense products with the
+// DST tables.  Writes the component into the FP64 iterate and the gather copy.
+__global__ void __launch_bounds__(256) fk_pdd_solve_kernel(const Inst *__restrict__ inst,
+                                                           const PddBlock *__restrict__ blocks,
+                                                           const double *__restrict__ tab,
+                                                           const double2 *__restrict__ rhs)
+{
+    extern __shared__ double lds_pdd[];
+    const Inst &D = *inst;
+    const PddBlock B = blocks[blockIdx.x];
+    const int comp = blockIdx.y;
+    const int mx = B.i1 - B.i0, my = B.j1 - B.j0, n = mx * my;
+    const int px = 2 * (mx + 1), py = 2 * (my + 1);
+    const double *sx = tab + B.tx, *sy = tab + B.ty;          // sines
+    const double *ex = sx + px, *ey = sy + py;                // eigenvalue factors
+    double *R = lds_pdd, *T = lds_pdd + n;
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const int a = e / my, b = e - (e / my) * my;
+        R[e] = comp_of(rhs[(B.i0 + a) + D.nx * (B.j0 + b)], comp);
+    }
+    __syncthreads();
+    // T = R S_y
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const int a = e / my, q = e - (e / my) * my;
+        double acc = 0.0;
+        for (int b = 0; b < my; ++b) acc = fma(R[a * my + b], sy[((b + 1) * (q + 1)) % py], acc);
+        T[e] = acc;
+    }
+    __syncthreads();
+    // R = S_x T, divided by the eigenvalue of (Delta_h - c)
+    const double idx2 = D.idx * D.idx, idy2 = D.idy * D.idy, c = D.alpha - D.k2;
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const int p = e / my, q = e - (e / my) * my;
+        double acc = 0.0;
+        for (int a = 0; a < mx; ++a) acc = fma(sx[((p + 1) * (a + 1)) % px], T[a * my + q], acc);
+        R[e] = acc / (-(idx2 * ex[p] + idy2 * ey[q]) - c);
+    }
+    __syncthreads();
+    // T = S_x R
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const int a = e / my, q = e - (e / my) * my;
+        double acc = 0.0;
+        for (int p = 0; p < mx; ++p) acc = fma(sx[((a + 1) * (p + 1)) % px], R[p * my + q], acc);
+        T[e] = acc;
+    }
+    __syncthreads();
+    // u = T S_y, into the iterate and its gather copy
+    const int cw = D.nx - 1;
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const int a = e / my, b = e - (e / my) * my;
+        double v = 0.0;
+        for (int q = 0; q < my; ++q) v = fma(T[a * my + q], sy[((q + 1) * (b + 1)) % py], v);
+        const int gi = B.i0 + a, gj = B.j0 + b;
+        const int node = gi + D.nx * gj;
+        ((double *)D.u64)[2 * node + comp] = v;
+        if (D.prec == 32 && !D.cells) {
+            ((float *)D.gather)[2 * node + comp] = (float)v;
+        } else if (D.cells) {
+            for (int cq = 1; cq >= 0; --cq)
+                for (int cp = 1; cp >= 0; --cp) {
+                    const int p = gi - cp, q = gj - cq;
+                    if (p < 0 || p > D.nx - 2 || q < 0 || q > D.ny - 2) continue;
+                    const int at = 4 * (p + cw * q) + cp + 2 * cq;
+                    if (D.prec == 32) ((float *)D.gather)[2 * at + comp] = (float)v;
+                    else ((double *)D.gather)[2 * at + comp] = v;
+                }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ debug
 
 __global__ void fk_debug_philox_kernel(uint32_t k0, uint32_t k1, const uint4 *__restrict__ ctr, int64_t n,
@@ -1036,6 +1165,16 @@ hipError_t launch_advance(const Inst *d_insts, const int32_t *which, int32_t n, 
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(fk_advance_kernel, dim3(blocks_for(n, 64)), dim3(64), 0, s, d_insts, which, n, n_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_pdd_blocks(const Inst *d_inst, const PddBlock *blocks, int32_t n_blocks, int32_t max_nodes,
+                             const double *tables, double2 *rhs, hipStream_t s)
+{
+    if (n_blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fk_pdd_rhs_kernel, dim3(n_blocks), dim3(256), 0, s, d_inst, blocks, rhs);
+    hipLaunchKernelGGL(fk_pdd_solve_kernel, dim3(n_blocks, 2), dim3(256), (size_t)2 * max_nodes * sizeof(double), s,
+                       d_inst, blocks, tables, (const double2 *)rhs);
     return hipGetLastError();
 }
 

@@ -7,6 +7,7 @@
 // status) and the iteration-index advance; then one 64-byte status copy to
 // pinned host memory.  The host applies the
 // sup-norm stopping rule (Sec. 3) and the divergence rule.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -38,6 +39,11 @@ struct fk_solver {
     int32_t iter = 0;
     std::vector<double> hist_sup, hist_du;
     fk_iter_report last{};
+    // probabilistic domain decomposition (library-owned device memory)
+    int32_t pdd_blocks = 0, pdd_max_nodes = 0;
+    fkd::PddBlock *d_pdd_blocks = nullptr;
+    double *d_pdd_tables = nullptr;
+    double2 *d_pdd_rhs = nullptr;
 };
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -140,6 +146,9 @@ static fk_status run_one(fk_solver *s, fk_iter_report *rep)
     FK_HIP(fkk::launch_stream(prec, s->P.features(), s->d_inst, s->d_queue, s->d_head, s->n_blocks, s->stream));
     FK_HIP(hipEventRecord(s->ev1, s->stream));
     FK_HIP(fkk::launch_update(s->d_inst, nullptr, 1, nullptr, (int32_t)s->P.interior.size(), s->stream));
+    if (s->pdd_blocks > 0)
+        FK_HIP(fkk::launch_pdd_blocks(s->d_inst, s->d_pdd_blocks, s->pdd_blocks, s->pdd_max_nodes, s->d_pdd_tables,
+                                      s->d_pdd_rhs, s->stream));
     FK_HIP(fkk::launch_advance(s->d_inst, nullptr, 1, nullptr, s->stream));
     FK_HIP(hipMemcpyAsync(s->h_status, s->B.state, sizeof(fkd::DevState), hipMemcpyDeviceToHost, s->stream));
     FK_HIP(hipStreamSynchronize(s->stream));
@@ -174,6 +183,94 @@ static fk_status run_one(fk_solver *s, fk_iter_report *rep)
     s->last = r;
     if (rep) *rep = r;
     return div ? fail(FK_EDIVERGED, "divergence rule fired at iteration " + std::to_string(r.n)) : FK_OK;
+}
+
+fk_status fk_helmholtz_set_pdd(fk_solver *s, const int32_t *cuts_x, int32_t n_cuts_x, const int32_t *cuts_y,
+                               int32_t n_cuts_y)
+{
+    if (!s) return fail(FK_EINVAL, "solver is NULL");
+    const HostProblem &P0 = s->P;
+    const fk_domain &d = P0.dom;
+    if (s->iter != 0 || s->pdd_blocks != 0) return fail(FK_EINVAL, "set PDD once, before the first iteration");
+    if (d.kind != FK_DOMAIN_RECT || P0.reflect())
+        return fail(FK_EINVAL, "PDD needs a plain rectangle with an absorbing edge");
+    if (n_cuts_x < 0 || n_cuts_y < 0 || n_cuts_x + n_cuts_y == 0 || (n_cuts_x > 0 && !cuts_x) ||
+        (n_cuts_y > 0 && !cuts_y))
+        return fail(FK_EINVAL, "at least one cut line");
+    std::vector<int32_t> xs{0}, ys{0};
+    for (int32_t i = 0; i < n_cuts_x; ++i) xs.push_back(cuts_x[i]);
+    for (int32_t i = 0; i < n_cuts_y; ++i) ys.push_back(cuts_y[i]);
+    xs.push_back(d.nx - 1);
+    ys.push_back(d.ny - 1);
+    for (auto *v : {&xs, &ys})
+        for (size_t i = 1; i < v->size(); ++i)
+            if ((*v)[i] <= (*v)[i - 1]) return fail(FK_EINVAL, "cuts must increase strictly within [1, n - 2]");
+    // blocks, their DST tables (one per distinct side length)
+    std::vector<fkd::PddBlock> blocks;
+    std::vector<double> tables;
+    std::vector<int32_t> offset(fkd::kPddMaxSide + 1, -1);
+    auto table_of = [&](int m) {
+        if (offset[m] < 0) {
+            offset[m] = (int32_t)tables.size();
+            const double sc = std::sqrt(2.0 / (double)(m + 1));
+            for (int t = 0; t < 2 * (m + 1); ++t) tables.push_back(sc * std::sin(M_PI * (double)t / (double)(m + 1)));
+            for (int q = 0; q < m; ++q) {
+                const double sn = std::sin(M_PI * (double)(q + 1) / (2.0 * (double)(m + 1)));
+                tables.push_back(4.0 * sn * sn);
+            }
+        }
+        return offset[m];
+    };
+    int32_t max_nodes = 0;
+    for (size_t b = 0; b + 1 < ys.size(); ++b)
+        for (size_t a = 0; a + 1 < xs.size(); ++a) {
+            fkd::PddBlock B;
+            B.i0 = xs[a] + 1;
+            B.i1 = xs[a + 1];
+            B.j0 = ys[b] + 1;
+            B.j1 = ys[b + 1];
+            if (B.i1 <= B.i0 || B.j1 <= B.j0) continue;   // adjacent cut lines: no block between
+            const int mx = B.i1 - B.i0, my = B.j1 - B.j0;
+            if (mx > fkd::kPddMaxSide || my > fkd::kPddMaxSide)
+                return fail(FK_EINVAL, "a block between cut lines is wider than 64 nodes; cut finer");
+            B.tx = table_of(mx);
+            B.ty = table_of(my);
+            max_nodes = std::max(max_nodes, mx * my);
+            blocks.push_back(B);
+        }
+    // the node list becomes the interface (in the same longest-first order)
+    std::vector<uint8_t> on_x(d.nx, 0), on_y(d.ny, 0);
+    for (int32_t i = 0; i < n_cuts_x; ++i) on_x[cuts_x[i]] = 1;
+    for (int32_t i = 0; i < n_cuts_y; ++i) on_y[cuts_y[i]] = 1;
+    std::vector<int32_t> iface;
+    for (int32_t id : P0.interior)
+        if (on_x[id % d.nx] || on_y[id / d.nx]) iface.push_back(id);
+    hipError_t e;
+    if (!blocks.empty()) {
+        if ((e = hipMalloc((void **)&s->d_pdd_blocks, blocks.size() * sizeof(fkd::PddBlock))) != hipSuccess ||
+            (e = hipMalloc((void **)&s->d_pdd_tables, tables.size() * sizeof(double))) != hipSuccess ||
+            (e = hipMalloc((void **)&s->d_pdd_rhs, P0.n_nodes() * sizeof(double2))) != hipSuccess)
+            return hip_fail(e, "hipMalloc(pdd)");
+        FK_HIP(hipMemcpyAsync(s->d_pdd_blocks, blocks.data(), blocks.size() * sizeof(fkd::PddBlock),
+                              hipMemcpyHostToDevice, s->stream));
+        FK_HIP(hipMemcpyAsync(s->d_pdd_tables, tables.data(), tables.size() * sizeof(double), hipMemcpyHostToDevice,
+                              s->stream));
+    }
+    s->P.interior = iface;
+    s->P.n_items = (int64_t)iface.size() * s->P.items_per_node;
+    FK_HIP(hipMemcpyAsync(s->B.nodes, iface.data(), iface.size() * sizeof(int32_t), hipMemcpyHostToDevice, s->stream));
+    fkd::Inst D = make_inst(s->P, s->B);
+    FK_HIP(hipMemcpyAsync(s->d_inst, &D, sizeof(D), hipMemcpyHostToDevice, s->stream));
+    fkd::EngineQueue q;
+    std::memset(&q, 0, sizeof(q));
+    q.n_seg = 1;
+    q.seg_end[0] = s->P.n_items;
+    q.seg_inst[0] = 0;
+    FK_HIP(hipMemcpyAsync(s->d_queue, &q, sizeof(q), hipMemcpyHostToDevice, s->stream));
+    FK_HIP(hipStreamSynchronize(s->stream));
+    s->pdd_blocks = (int32_t)blocks.size();
+    s->pdd_max_nodes = max_nodes;
+    return FK_OK;
 }
 
 fk_status fk_helmholtz_iterate(fk_solver *s, int32_t n_iters, fk_iter_report *last)
@@ -278,6 +375,9 @@ fk_status fk_helmholtz_destroy(fk_solver *s)
     if (s->ev0) (void)hipEventDestroy(s->ev0);
     if (s->ev1) (void)hipEventDestroy(s->ev1);
     if (s->h_status) (void)hipHostFree(s->h_status);
+    if (s->d_pdd_blocks) (void)hipFree(s->d_pdd_blocks);
+    if (s->d_pdd_tables) (void)hipFree(s->d_pdd_tables);
+    if (s->d_pdd_rhs) (void)hipFree(s->d_pdd_rhs);
     if (s->own_arena && s->arena) (void)hipFree(s->arena);
     delete s;
     return FK_OK;

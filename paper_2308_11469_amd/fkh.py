@@ -80,7 +80,8 @@ class fk_engine_config(C.Structure):
 
 # every entry point of include/fk_helmholtz.h
 EXPORTS = ["fk_helmholtz_arena_bytes", "fk_helmholtz_create", "fk_helmholtz_iterate", "fk_helmholtz_solve",
-           "fk_helmholtz_get", "fk_helmholtz_node_stats", "fk_helmholtz_set_iterate", "fk_helmholtz_timing",
+           "fk_helmholtz_get", "fk_helmholtz_node_stats", "fk_helmholtz_set_iterate", "fk_helmholtz_set_pdd",
+           "fk_helmholtz_timing",
            "fk_helmholtz_destroy", "fk_helmholtz_last_error", "fk_debug_philox", "fk_debug_normals",
            "fk_helmholtz_debug_paths", "fk_engine_create", "fk_engine_add", "fk_engine_tick", "fk_engine_get",
            "fk_engine_remove", "fk_engine_timing", "fk_engine_destroy"]
@@ -112,6 +113,7 @@ def lib():
             "fk_helmholtz_get": [vp, vp, vp, C.c_int32],
             "fk_helmholtz_node_stats": [vp, i64p, i64p],
             "fk_helmholtz_set_iterate": [vp, vp, C.c_int32, C.c_int32],
+            "fk_helmholtz_set_pdd": [vp, i32p, C.c_int32, i32p, C.c_int32],
             "fk_helmholtz_timing": [vp, dp, i64p, C.c_int32],
             "fk_helmholtz_destroy": [vp],
             "fk_debug_philox": [C.c_uint64, u32p, C.c_int64, u32p],
@@ -289,6 +291,15 @@ class Solver:
     def set_iterate(self, u, n):
         ub = np.ascontiguousarray(np.asarray(u, dtype=np.complex128))
         _check(lib().fk_helmholtz_set_iterate(self.h, ub.ctypes.data_as(C.c_void_p), int(n), 0))
+
+    def set_pdd(self, cuts_x, cuts_y):
+        """Probabilistic domain decomposition from the next iteration on:
+        paths only from the nodes on the grid lines x index in cuts_x,
+        y index in cuts_y; the blocks between them solved on the device."""
+        cx = np.ascontiguousarray(np.asarray(cuts_x, dtype=np.int32))
+        cy = np.ascontiguousarray(np.asarray(cuts_y, dtype=np.int32))
+        i32p = C.POINTER(C.c_int32)
+        _check(lib().fk_helmholtz_set_pdd(self.h, cx.ctypes.data_as(i32p), len(cx), cy.ctypes.data_as(i32p), len(cy)))
 
     def timing(self, reset=False):
         ms = C.c_double()

@@ -1,0 +1,144 @@
+"""GPU parity of the probabilistic domain decomposition (Sec. 3's two-stage
+procedure): Feynman-Kac at the interface nodes only, against the oracle's
+estimator at those nodes; the device's fast-diagonalisation block solves,
+against the oracle's sparse LU of each block from the same interface values;
+both gather layouts; the PDD iteration on the cavity settling on the plane
+wave; argument checks."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import closed_forms as CF
+from oracle import fkmc, pdd
+from paper_2308_11469_amd import fkh
+from paper_2308_11469_amd import workloads as W
+
+from gpu_util import assert_fp64_node_parity, require_lib, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    require_lib()
+
+
+def _cases():
+    plain = (W.cavity_small().replace(nx=33, ny=33, M=128, seed=5), [8, 16, 24], [11, 20])
+    general = (W.cavity_source(precision=64).replace(nx=29, ny=21, x1=1.4, M=96, h=1e-3, alpha=20.0, damping=1.5),
+               [5, 17], [11])
+    wide = (W.cavity_65(k=3.0).replace(M=64, h=1e-3), [32], [])    # two 31 x 63 blocks, one interface line
+    return {"plain_33": plain, "source_general_aniso": general, "wide_blocks_65": wide}
+
+
+def frame_of(p, g, ids):
+    f = fkmc.boundary_grid(p)
+    f.ravel()[ids] = g.ravel()[ids]
+    return f
+
+
+@pytest.mark.parametrize("name", list(_cases().keys()))
+def test_pdd_interfaces_and_blocks_match_oracle(name):
+    p, cx, cy = _cases()[name]
+    say("pdd", name)
+    s = fkh.Solver(p)
+    s.set_pdd(cx, cy)
+    ids = pdd.interface_ids(p, cx, cy)
+    u = None
+    for it in range(3):
+        s.iterate(1)
+        g, se = s.get()
+        sj, _ = s.node_stats()
+        orc = fkmc.fk_nodes(p, u, it, ids)
+        assert_fp64_node_parity(g.ravel()[ids], sj[ids], orc, p.M, label="%s it %d" % (name, it))
+        # blocks: the oracle's LU from the same interface values and u_n
+        ref = pdd.fill_blocks(p, u, frame_of(p, g, ids), cx, cy)
+        scale = max(1.0, np.abs(ref).max())
+        assert np.max(np.abs(g - ref)) <= 1e-11 * scale, np.max(np.abs(g - ref))
+        # Monte Carlo ran at the interface only
+        mask = np.zeros(p.nx * p.ny, bool)
+        mask[ids] = True
+        assert np.all(se.ravel()[~mask] == 0) and np.all(sj[~mask] == 0)
+        u = g
+    s.close()
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_pdd_gather_layouts_identical(precision):
+    # the block solve writes the gather copy the next iteration's paths read
+    p = W.cavity_source(precision=precision).replace(M=64, h=1e-3)
+    cuts = [32, 64, 96]
+    out = []
+    for layout in ("nodes", "cells"):
+        s = fkh.Solver(p, gather_layout=layout)
+        s.set_pdd(cuts, cuts)
+        s.iterate(3)
+        out.append(s.get()[0])
+        s.close()
+    assert np.array_equal(out[0], out[1])
+
+
+def test_pdd_fp32_blocks_from_own_interfaces():
+    p = W.cavity_source(precision=32).replace(M=256, h=1e-3)
+    cuts = [32, 64, 96]
+    s = fkh.Solver(p)
+    s.set_pdd(cuts, cuts)
+    ids = pdd.interface_ids(p, cuts, cuts)
+    s.iterate(1)
+    u1 = s.get()[0]
+    s.iterate(1)
+    g = s.get()[0]
+    s.close()
+    ref = pdd.fill_blocks(p, u1, frame_of(p, g, ids), cuts, cuts)
+    assert np.max(np.abs(g - ref)) <= 1e-11 * max(1.0, np.abs(ref).max())
+
+
+def test_pdd_iteration_settles_on_the_plane_wave():
+    # the bench cavity with interfaces every 16 nodes: paths from 369 of the
+    # 3969 unknown nodes; the blocks carry the interface noise inwards
+    # harmonically, so the error is no larger than on the interfaces
+    p = W.cavity_65(k=2.0, precision=32).replace(seed=9)
+    cuts = [16, 32, 48]
+    s = fkh.Solver(p)
+    s.set_pdd(cuts, cuts)
+    for _ in range(8):
+        rep = s.iterate(1)
+    g, se = s.get()
+    s.close()
+    ex = W.exact_solution(p)
+    ids = fkmc.interior_ids(p)
+    iface = pdd.interface_ids(p, cuts, cuts)
+    err = np.abs(g.ravel()[ids] - ex.ravel()[ids])
+    err_if = np.abs(g.ravel()[iface] - ex.ravel()[iface])
+    max_se = np.abs(se.ravel()[iface]).max()
+    # exit-bias scale of the once-per-step test: beta sqrt(2h) |grad u|
+    bias = CF.bgk_beta() * math.sqrt(2.0 * p.h) * p.k
+    say("pdd cavity65: max err %.4f (interfaces %.4f), rms %.4f, max SE %.4f, %d path-steps per iteration"
+        % (err.max(), err_if.max(), np.sqrt(np.mean(err ** 2)), max_se, rep["path_steps"]))
+    assert err.max() < 4.5 * max_se + bias
+    assert np.sqrt(np.mean(err ** 2)) < max_se + bias
+    assert err.max() <= err_if.max() + 1e-3
+
+
+@pytest.mark.parametrize("bad", ["after_iterate", "twice", "disc", "too_wide", "no_cut", "unsorted"])
+def test_pdd_argument_checks(bad):
+    p = W.cavity_small().replace(nx=33, ny=33, M=64)
+    cx, cy = [16], [16]
+    if bad == "disc":
+        p = W.scatter_problem(k=2.0, theta=0.0, N=33, M=64, seed=1, precision=64, table_len=256)
+    if bad == "too_wide":
+        p = W.cavity_65().replace(nx=129, ny=129, M=64)
+        cx, cy = [100], [64]
+    if bad == "no_cut":
+        cx, cy = [], []
+    if bad == "unsorted":
+        cx = [20, 10]
+    s = fkh.Solver(p)
+    if bad == "after_iterate":
+        s.iterate(1)
+    if bad == "twice":
+        s.set_pdd(cx, cy)
+    with pytest.raises(ValueError):
+        s.set_pdd(cx, cy)
+    s.close()
