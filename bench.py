@@ -177,6 +177,39 @@ def annulus_shape3(steps=3):
     return out
 
 
+def pdd_cavity65(k, n_iters=12):
+    """The bench cavity (FP64, M = 4096, h = 1e-4) by probabilistic domain
+    decomposition: paths from the nodes on the grid lines 16, 32, 48 in x
+    and y only (369 of 3969 unknowns), the 16 blocks of 15 x 15 nodes solved
+    on the device.  Wall time per iteration, path-steps per iteration,
+    iterations to the first settled iteration, RMS error against the plane
+    wave after n_iters iterations."""
+    import numpy as np
+    import torch
+    from paper_2308_11469_amd import fkh, serving
+    from paper_2308_11469_amd import workloads as W
+    p = W.cavity_65(k=k, precision=64)
+    s = fkh.Solver(p)
+    s.set_pdd([16, 32, 48], [16, 32, 48])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = [s.iterate(1) for _ in range(n_iters)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    u, _ = s.get()
+    s.close()
+    ex = W.exact_solution(p)
+    ids = np.nonzero((np.arange(p.nx * p.ny) % p.nx > 0) & (np.arange(p.nx * p.ny) % p.nx < p.nx - 1)
+                     & (np.arange(p.nx * p.ny) // p.nx > 0) & (np.arange(p.nx * p.ny) // p.nx < p.ny - 1))[0]
+    settle = next((r["n"] for r in reps if serving.settled(r)), None)
+    ms = wall / n_iters * 1e3
+    return {"workload": "cavity 65x65, k=%g, M=4096, h=1e-4, FP64, interfaces x,y in {16,32,48}" % k,
+            "ms_per_iteration": ms, "path_steps_per_iteration": sum(r["path_steps"] for r in reps) / n_iters,
+            "iterations_per_solve": settle,
+            "solves_per_s": (1e3 / (ms * settle)) if settle else None,
+            "rms_error_vs_exact": float(np.sqrt(np.mean(np.abs(u.ravel()[ids] - ex.ravel()[ids]) ** 2)))}
+
+
 def batched_vs_plain(n_sub=16, ticks=2):
     """Solves/s of the batched FP32 engine (one persistent launch per tick for
     all instances) against the plain FP64 single-instance path (instances one
@@ -340,6 +373,7 @@ def main():
         out["extra"]["batched_fp32_vs_plain_fp64"] = batched_vs_plain()
         out["extra"]["serving_scatter_window"] = serving_window()
         out["extra"]["annulus_shape3_reflecting"] = annulus_shape3()
+        out["extra"]["pdd_same_cavity"] = pdd_cavity65(a.k)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p, a.cpu_seconds)
     print(json.dumps(out), flush=True)
