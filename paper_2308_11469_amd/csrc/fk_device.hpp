@@ -87,6 +87,7 @@ struct Inst {
     double bx0, bx1, by0, by1;                       // box hole
     float x0_rd, x1_ru, y0_rd, y1_ru;                // edges rounded outward to binary32
     float bx0_ru, bx1_rd, by0_ru, by1_rd;            // box edges rounded inward to binary32
+    float x0_ri, x1_ri, y0_ri, y1_ri;                // edges rounded inward (reflection tests)
     int32_t nx, ny, hole, n_interior;                // hole: HOLE_NONE / _DISC / _BOX
     int32_t reflect, pad0;                           // 1: the rectangle's edge reflects
     int32_t src_kind, g_unproj;

@@ -36,7 +36,9 @@ template <class R> struct Consts {
     R ex0, ex1, ey0, ey1;   // rectangle edges for the exit test (FP32: rounded outward)
     R cxf, cyf, r2f, band;
     R hx0, hx1, hy0, hy1;   // box hole for the exit test (FP32: rounded inward)
-    R rx0, rx1, ry0, ry1;   // reflecting faces
+    R rx0, rx1, ry0, ry1;   // reflection thresholds (FP32: faces rounded inward)
+    R lx0, lx1, ly0, ly1;   // faces as R (the feet of mirror moves)
+    double fx0, fx1, fy0, fy1;  // faces (FP64)
     R kk;                   // k (the Robin coupling i k u_n on a reflecting edge)
     double ih;              // 1 / h
     R src_re, src_im, src_cx, src_cy, src_c;
@@ -62,7 +64,8 @@ template <class R> struct Consts {
     __device__ Consts(const Inst &D, const typename TablesOf<R>::type *T)
         : x0((R)D.x0), y0((R)D.y0), idx((R)D.idx), idy((R)D.idy), sigma((R)D.sigma), k2((R)D.k2),
           cxf((R)D.cx), cyf((R)D.cy), r2f((R)D.r2), band((R)(1e-5 * (D.r + 1.0))),
-          rx0((R)D.x0), rx1((R)D.x1), ry0((R)D.y0), ry1((R)D.y1), kk((R)D.k), ih(D.ih),
+          lx0((R)D.x0), lx1((R)D.x1), ly0((R)D.y0), ly1((R)D.y1), fx0(D.x0), fx1(D.x1), fy0(D.y0), fy1(D.y1),
+          kk((R)D.k), ih(D.ih),
           src_re((R)D.src_re), src_im((R)D.src_im), src_cx((R)D.src_cx), src_cy((R)D.src_cy),
           src_c((R)D.src_c), pmax((R)(D.nx - 2)), qmax((R)(D.ny - 2)), jmax((int)D.jmax),
           hole(D.hole), src_kind(D.src_kind), reflect(D.reflect), robin_g2(D.outer.kind != BC_ZERO),
@@ -74,9 +77,12 @@ template <class R> struct Consts {
         if (sizeof(R) == 4) {
             ex0 = (R)D.x0_rd; ex1 = (R)D.x1_ru; ey0 = (R)D.y0_rd; ey1 = (R)D.y1_ru;
             hx0 = (R)D.bx0_ru; hx1 = (R)D.bx1_rd; hy0 = (R)D.by0_ru; hy1 = (R)D.by1_rd;
+            // x < x0 exactly iff x < RU(x0) for a binary32 x; x > x1 iff x > RD(x1)
+            rx0 = (R)D.x0_ri; rx1 = (R)D.x1_ri; ry0 = (R)D.y0_ri; ry1 = (R)D.y1_ri;
         } else {
             ex0 = (R)D.x0; ex1 = (R)D.x1; ey0 = (R)D.y0; ey1 = (R)D.y1;
             hx0 = (R)D.bx0; hx1 = (R)D.bx1; hy0 = (R)D.by0; hy1 = (R)D.by1;
+            rx0 = (R)D.x0; rx1 = (R)D.x1; ry0 = (R)D.y0; ry1 = (R)D.y1;
         }
         const uint32_t node_bytes = (uint32_t)(2 * sizeof(R));
         uint32_t bytes;
@@ -150,6 +156,9 @@ __device__ __forceinline__ bool is_out(const Inst &D, const Consts<float> &K, fl
 // length of the mirror move, twice the overshoot.  The rectangle is wider
 // than any single step (checked at set-up), so one mirror per coordinate
 // lands inside.  face: 0 x = x0, 1 x = x1, 2 y = y0, 3 y = y1, -1 none.
+// The test and the mirror are exact against the FP64 faces in both
+// precisions: FP32 compares with the inward-rounded faces and forms the
+// mirrored point and the increment in FP64 (mirror moves are rare).
 template <class R> struct Mirror {
     R lx, ly;     // local-time increments of the x and y faces
     int fx, fy;   // the faces crossed
@@ -160,21 +169,25 @@ __device__ __forceinline__ Mirror<R> reflect(const Consts<R> &K, R &x, R &y)
 {
     Mirror<R> m{(R)0, (R)0, -1, -1};
     if (x < K.rx0) {
-        m.lx = (R)2 * (K.rx0 - x);
-        x = (R)2 * K.rx0 - x;
+        const double xd = (double)x;
+        m.lx = (R)(2.0 * (K.fx0 - xd));
+        x = (R)(2.0 * K.fx0 - xd);
         m.fx = 0;
     } else if (x > K.rx1) {
-        m.lx = (R)2 * (x - K.rx1);
-        x = (R)2 * K.rx1 - x;
+        const double xd = (double)x;
+        m.lx = (R)(2.0 * (xd - K.fx1));
+        x = (R)(2.0 * K.fx1 - xd);
         m.fx = 1;
     }
     if (y < K.ry0) {
-        m.ly = (R)2 * (K.ry0 - y);
-        y = (R)2 * K.ry0 - y;
+        const double yd = (double)y;
+        m.ly = (R)(2.0 * (K.fy0 - yd));
+        y = (R)(2.0 * K.fy0 - yd);
         m.fy = 2;
     } else if (y > K.ry1) {
-        m.ly = (R)2 * (y - K.ry1);
-        y = (R)2 * K.ry1 - y;
+        const double yd = (double)y;
+        m.ly = (R)(2.0 * (yd - K.fy1));
+        y = (R)(2.0 * K.fy1 - yd);
         m.fy = 3;
     }
     return m;
@@ -386,8 +399,8 @@ __device__ __forceinline__ bool advance(const Inst &D, const Consts<R> &K, PathS
                 const bool s2 = c >= 2, ym = (c & 1) != 0;
                 const int face = ym ? (s2 ? m2.fy : m1.fy) : (s2 ? m2.fx : m1.fx);
                 const R px = s2 ? x2 : x1, py = s2 ? y2 : y1;
-                const R fx = face == 0 ? K.rx0 : (face == 1 ? K.rx1 : px);
-                const R fy = face == 2 ? K.ry0 : (face == 3 ? K.ry1 : py);
+                const R fx = face == 0 ? K.lx0 : (face == 1 ? K.lx1 : px);
+                const R fy = face == 2 ? K.ly0 : (face == 3 ? K.ly1 : py);
                 const R dxi = ym ? (s2 ? m2.ly : m1.ly) : (s2 ? m2.lx : m1.lx);
                 local_time_term<R, F>(D, K, face, fx, fy, dxi, s2 ? w2 : w1, cu.ik, P);
             } while (todo);

@@ -371,6 +371,8 @@ fkd::Inst make_inst(const HostProblem &P, const InstanceBuffers &B)
     D.x0_rd = rd(d.x0); D.x1_ru = ru(d.x1); D.y0_rd = rd(d.y0); D.y1_ru = ru(d.y1);
     // box: x >= bx0 exactly iff x >= RU(bx0) for a binary32 x, x <= bx1 iff x <= RD(bx1)
     D.bx0_ru = ru(D.bx0); D.bx1_rd = rd(D.bx1); D.by0_ru = ru(D.by0); D.by1_rd = rd(D.by1);
+    // reflection: x < x0 exactly iff x < RU(x0), x > x1 iff x > RD(x1)
+    D.x0_ri = ru(d.x0); D.x1_ri = rd(d.x1); D.y0_ri = ru(d.y0); D.y1_ri = rd(d.y1);
     D.nx = d.nx; D.ny = d.ny;
     D.hole = d.kind == FK_DOMAIN_RECT_MINUS_DISC ? fkd::HOLE_DISC
            : (d.kind == FK_DOMAIN_RECT_MINUS_BOX ? fkd::HOLE_BOX : fkd::HOLE_NONE);

@@ -118,3 +118,60 @@ def test_scattering_257_fp32_against_fp64_and_oracle():
     oracle_sampled(p, s64, g64, 1, 8, "scatter257")
     s64.close()
     s32.close()
+
+
+def test_annulus_shape3_bench_configuration_fp64_and_fp32():
+    # the reflecting-edge bench line: shape 3 at 101 x 161, k = 0.5,
+    # M = 4096, h = 1e-4; sampled nodes include edge and corner nodes
+    p = W.annulus_shape3(k=0.5, nx=101, ny=161, M=4096, h=1e-4, precision=64)
+    s = fkh.Solver(p)
+    s.iterate(1)
+    u1, _ = s.get()
+    s.iterate(1)
+    g, se = s.get()
+    sj, _ = s.node_stats()
+    ids = np.array([0, p.nx - 1, p.nx * (p.ny - 1), p.nx * p.ny - 1, 50, 80 * p.nx, 40 + 30 * p.nx,
+                    70 + 120 * p.nx, 44 + 80 * p.nx], dtype=np.int32)
+    assert (fkmc.node_classes(p).ravel()[ids] == 0).all()
+    orc = fkmc.fk_nodes(p, u1, 1, ids)
+    say("annulus shape 3 101x161: oracle nodes", len(ids))
+    assert_fp64_node_parity(g.ravel()[ids], sj[ids], orc, p.M, label="annulus3 full size")
+    s32 = fkh.Solver(p.replace(precision=32))
+    s32.set_iterate(u1, 1)
+    s32.iterate(1)
+    g32, _ = s32.get()
+    s.close()
+    s32.close()
+    # Reflected paths here run 2000 steps on average (up to ~2e4): FP32
+    # rounding of the position flips the exit decision of a few paths per
+    # node near the hole, and a path that escapes in one precision and is
+    # absorbed in the other differs by O(0.1) in score.  So the bar is per
+    # node fraction: 99.9% within 0.1 SE, none beyond 0.5 SE, RMS 0.01 SE.
+    r = np.abs(interior_values(p, g32) - interior_values(p, g)) / np.abs(interior_values(p, se))
+    say("annulus3 FP32 vs FP64: max %.4f SE, rms %.4f SE, %d of %d nodes above 0.1 SE"
+        % (r.max(), np.sqrt(np.mean(r ** 2)), int((r > 0.1).sum()), r.size))
+    assert (r > 0.1).mean() <= 1e-3 and r.max() <= 0.5 and np.sqrt(np.mean(r ** 2)) <= 0.01
+
+
+def test_pdd_cavity65_bench_configuration():
+    # the PDD bench line: interfaces on the lines 16, 32, 48; sampled
+    # interface nodes against the oracle, every block against its LU
+    from oracle import pdd
+    p = W.cavity_65(k=2.0, precision=64)
+    cuts = [16, 32, 48]
+    s = fkh.Solver(p)
+    s.set_pdd(cuts, cuts)
+    s.iterate(1)
+    u1, _ = s.get()
+    s.iterate(1)
+    g, _ = s.get()
+    sj, _ = s.node_stats()
+    s.close()
+    iface = pdd.interface_ids(p, cuts, cuts)
+    ids = np.sort(np.random.default_rng(5).choice(iface, size=24, replace=False)).astype(np.int32)
+    orc = fkmc.fk_nodes(p, u1, 1, ids)
+    assert_fp64_node_parity(g.ravel()[ids], sj[ids], orc, p.M, label="pdd cavity65")
+    frame = fkmc.boundary_grid(p)
+    frame.ravel()[iface] = g.ravel()[iface]
+    ref = pdd.fill_blocks(p, u1, frame, cuts, cuts)
+    assert np.max(np.abs(g - ref)) <= 1e-11 * max(1.0, np.abs(ref).max())
