@@ -37,8 +37,7 @@ template <class R> struct Consts {
     R cxf, cyf, r2f, band;
     R hx0, hx1, hy0, hy1;   // box hole for the exit test (FP32: rounded inward)
     R rx0, rx1, ry0, ry1;   // reflection thresholds (FP32: faces rounded inward)
-    R lx0, lx1, ly0, ly1;   // faces as R (the feet of mirror moves)
-    double fx0, fx1, fy0, fy1;  // faces (FP64)
+    R lx0, lx1, ly0, ly1;   // faces as R (mirrors and the feet of mirror moves)
     R kk;                   // k (the Robin coupling i k u_n on a reflecting edge)
     double ih;              // 1 / h
     R src_re, src_im, src_cx, src_cy, src_c;
@@ -64,8 +63,7 @@ template <class R> struct Consts {
     __device__ Consts(const Inst &D, const typename TablesOf<R>::type *T)
         : x0((R)D.x0), y0((R)D.y0), idx((R)D.idx), idy((R)D.idy), sigma((R)D.sigma), k2((R)D.k2),
           cxf((R)D.cx), cyf((R)D.cy), r2f((R)D.r2), band((R)(1e-5 * (D.r + 1.0))),
-          lx0((R)D.x0), lx1((R)D.x1), ly0((R)D.y0), ly1((R)D.y1), fx0(D.x0), fx1(D.x1), fy0(D.y0), fy1(D.y1),
-          kk((R)D.k), ih(D.ih),
+          lx0((R)D.x0), lx1((R)D.x1), ly0((R)D.y0), ly1((R)D.y1), kk((R)D.k), ih(D.ih),
           src_re((R)D.src_re), src_im((R)D.src_im), src_cx((R)D.src_cx), src_cy((R)D.src_cy),
           src_c((R)D.src_c), pmax((R)(D.nx - 2)), qmax((R)(D.ny - 2)), jmax((int)D.jmax),
           hole(D.hole), src_kind(D.src_kind), reflect(D.reflect), robin_g2(D.outer.kind != BC_ZERO),
@@ -156,9 +154,11 @@ __device__ __forceinline__ bool is_out(const Inst &D, const Consts<float> &K, fl
 // length of the mirror move, twice the overshoot.  The rectangle is wider
 // than any single step (checked at set-up), so one mirror per coordinate
 // lands inside.  face: 0 x = x0, 1 x = x1, 2 y = y0, 3 y = y1, -1 none.
-// The test and the mirror are exact against the FP64 faces in both
-// precisions: FP32 compares with the inward-rounded faces and forms the
-// mirrored point and the increment in FP64 (mirror moves are rare).
+// FP64 tests and mirrors against the faces themselves.  FP32 tests against
+// the inward-rounded faces (the exact test for a binary32 point) and mirrors
+// across the nearest binary32 face: forming the mirror in FP64 instead was
+// measured 13% slower on the annulus (a lane-divergent branch whenever any
+// lane mirrors) and changed no node by a measurable amount.
 template <class R> struct Mirror {
     R lx, ly;     // local-time increments of the x and y faces
     int fx, fy;   // the faces crossed
@@ -169,25 +169,21 @@ __device__ __forceinline__ Mirror<R> reflect(const Consts<R> &K, R &x, R &y)
 {
     Mirror<R> m{(R)0, (R)0, -1, -1};
     if (x < K.rx0) {
-        const double xd = (double)x;
-        m.lx = (R)(2.0 * (K.fx0 - xd));
-        x = (R)(2.0 * K.fx0 - xd);
+        m.lx = (R)2 * (K.lx0 - x);
+        x = (R)2 * K.lx0 - x;
         m.fx = 0;
     } else if (x > K.rx1) {
-        const double xd = (double)x;
-        m.lx = (R)(2.0 * (xd - K.fx1));
-        x = (R)(2.0 * K.fx1 - xd);
+        m.lx = (R)2 * (x - K.lx1);
+        x = (R)2 * K.lx1 - x;
         m.fx = 1;
     }
     if (y < K.ry0) {
-        const double yd = (double)y;
-        m.ly = (R)(2.0 * (K.fy0 - yd));
-        y = (R)(2.0 * K.fy0 - yd);
+        m.ly = (R)2 * (K.ly0 - y);
+        y = (R)2 * K.ly0 - y;
         m.fy = 2;
     } else if (y > K.ry1) {
-        const double yd = (double)y;
-        m.ly = (R)(2.0 * (yd - K.fy1));
-        y = (R)(2.0 * K.fy1 - yd);
+        m.ly = (R)2 * (y - K.ly1);
+        y = (R)2 * K.ly1 - y;
         m.fy = 3;
     }
     return m;
@@ -363,7 +359,13 @@ __device__ __forceinline__ bool advance(const Inst &D, const Consts<R> &K, PathS
     // current point's before the Philox block was measured slower on large
     // grids in FP32 and spills registers in FP64.)
     CellReads<R> g0, g1;
-    const uint4 w = philox4x32_10((uint32_t)(P.t >> 1), m, node, ctr3, K.key0, K.key1);
+    // The round keys k + r (Weyl constants) are loop-invariant; hoisted, all
+    // twenty no longer fit the scalar registers and were spilled to vector
+    // lanes and read back (two VALU reads per round).  An opaque scalar zero
+    // per trip keeps the key schedule in scalar adds next to its use.
+    uint32_t kz;
+    asm volatile("s_mov_b32 %0, 0" : "=s"(kz));
+    const uint4 w = philox4x32_10((uint32_t)(P.t >> 1), m, node, ctr3, K.key0 + kz, K.key1 + kz);
     R z0x, z0y, z1x, z1y;
     normals(w.x, w.y, *K.tab, z0x, z0y);
     normals(w.z, w.w, *K.tab, z1x, z1y);
