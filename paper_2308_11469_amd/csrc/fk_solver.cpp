@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "fk_internal.hpp"
@@ -256,18 +257,22 @@ fk_status fk_helmholtz_set_pdd(fk_solver *s, const int32_t *cuts_x, int32_t n_cu
         FK_HIP(hipMemcpyAsync(s->d_pdd_tables, tables.data(), tables.size() * sizeof(double), hipMemcpyHostToDevice,
                               s->stream));
     }
-    s->P.interior = iface;
-    s->P.n_items = (int64_t)iface.size() * s->P.items_per_node;
-    FK_HIP(hipMemcpyAsync(s->B.nodes, iface.data(), iface.size() * sizeof(int32_t), hipMemcpyHostToDevice, s->stream));
-    fkd::Inst D = make_inst(s->P, s->B);
-    FK_HIP(hipMemcpyAsync(s->d_inst, &D, sizeof(D), hipMemcpyHostToDevice, s->stream));
+    // the host record changes only once the device has the new node list,
+    // instance record and queue (a failed copy leaves the solver as it was)
+    HostProblem P2 = s->P;
+    P2.interior = iface;
+    P2.n_items = (int64_t)iface.size() * P2.items_per_node;
+    fkd::Inst D = make_inst(P2, s->B);
     fkd::EngineQueue q;
     std::memset(&q, 0, sizeof(q));
     q.n_seg = 1;
-    q.seg_end[0] = s->P.n_items;
+    q.seg_end[0] = P2.n_items;
     q.seg_inst[0] = 0;
+    FK_HIP(hipMemcpyAsync(s->B.nodes, iface.data(), iface.size() * sizeof(int32_t), hipMemcpyHostToDevice, s->stream));
+    FK_HIP(hipMemcpyAsync(s->d_inst, &D, sizeof(D), hipMemcpyHostToDevice, s->stream));
     FK_HIP(hipMemcpyAsync(s->d_queue, &q, sizeof(q), hipMemcpyHostToDevice, s->stream));
     FK_HIP(hipStreamSynchronize(s->stream));
+    s->P = std::move(P2);
     s->pdd_blocks = (int32_t)blocks.size();
     s->pdd_max_nodes = max_nodes;
     return FK_OK;
