@@ -215,9 +215,28 @@ __device__ __forceinline__ void sincospi_uniform(uint32_t j, const F64Tables &T,
     cs = fma(-t.x, s1, fma(t.y, c1, t.y));
 }
 
+// sqrt(a) for a positive normal a (here a = -2 ln U in [2^-23, 33.3]):
+// the hardware reciprocal square root y0, one coupled Newton step on
+// g ~ sqrt(a) and h ~ 1/(2 sqrt(a)), then two residual corrections
+// g += (a - g^2) h (Markstein's scheme), correctly rounded in practice.  The
+// general sqrt adds range scaling for denormals and checks for 0, inf and
+// NaN, which cannot occur here.
+__device__ __forceinline__ double sqrt_pos(double a)
+{
+    const double y = __builtin_amdgcn_rsq(a);
+    double g = a * y, h = 0.5 * y;
+    const double r = fma(-h, g, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    double d = fma(-g, g, a);
+    g = fma(d, h, g);
+    d = fma(-g, g, a);
+    return fma(d, h, g);
+}
+
 __device__ __forceinline__ void normals(uint32_t ra, uint32_t rb, const F64Tables &T, double &zx, double &zy)
 {
-    const double rho = sqrt(-2.0 * ln_uniform((ra >> 8) | 1u, T));
+    const double rho = sqrt_pos(-2.0 * ln_uniform((ra >> 8) | 1u, T));
     double sn, cs;
     sincospi_uniform((rb >> 8) | 1u, T, sn, cs);
     zx = rho * cs;
