@@ -29,7 +29,11 @@ def _cases():
     general = (W.cavity_source(precision=64).replace(nx=29, ny=21, x1=1.4, M=96, h=1e-3, alpha=20.0, damping=1.5),
                [5, 17], [11])
     wide = (W.cavity_65(k=3.0).replace(M=64, h=1e-3), [32], [])    # two 31 x 63 blocks, one interface line
-    return {"plain_33": plain, "source_general_aniso": general, "wide_blocks_65": wide}
+    # degenerate cuts: at 1 and n - 2 (nothing outside them), adjacent lines
+    # 7 and 8 (no block between), one-node-wide blocks (the DST of size 1)
+    degenerate = (W.cavity_small().replace(nx=23, ny=17, M=96, seed=13), [1, 7, 8, 19, 21], [2, 8, 15])
+    return {"plain_33": plain, "source_general_aniso": general, "wide_blocks_65": wide,
+            "degenerate_cuts": degenerate}
 
 
 def frame_of(p, g, ids):
