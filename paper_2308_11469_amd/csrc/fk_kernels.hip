@@ -468,6 +468,157 @@ __device__ __forceinline__ bool advance(const Inst &D, const Consts<R> &K, PathS
     return exited || P.t >= K.jmax;
 }
 
+// ------------------------------------------------------------ tail mode
+// At the end of an iteration the last paths run on a nearly idle GPU, each at
+// the latency of one lonely wave; the longest of ~10^7 paths takes ~20 mean
+// path lengths, and this tail was a sixth of an iteration.  But a path's
+// positions depend only on its normals (counter-based, one Philox block per
+// trip), not on u_n, so its future can be computed in parallel in time: with
+// all 64 lanes of the wave on one path, lane i draws the normals of trip i of
+// the next 64, one serial chain of the same multiply-adds (in the same order,
+// on uniform values) gives every trip's points, the exit tests and the
+// gathers of all trips run at once, and a serial pass adds the trips'
+// integrands in path order.  Every value is the one the step-by-step loop
+// forms, so the results are identical.  Not used with a reflecting edge.
+// A wave enters it once the queue has nothing left for it and at most
+// FK_TAIL_LANES of its lanes still run a path (measured on the 65 x 65
+// cavity: 8 and 4 best, 16 slower, 32 and 64 slower than no tail mode; one
+// path at a time beats 64 lanes on 64 paths only when few paths are left).
+
+#ifndef FK_TAIL_LANES
+#define FK_TAIL_LANES 8
+#endif
+constexpr int kTailLanes = FK_TAIL_LANES;   // a wave with no work left and at most this many active lanes
+
+template <class R> struct TailPath {
+    R x, y;
+    double ar, ai, w;
+    int t;
+    uint32_t m, node;
+};
+
+__device__ __forceinline__ float lane_value(float v, int i) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), i)); }
+__device__ __forceinline__ double lane_value(double v, int i)
+{
+    const long long b = __double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, i);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), i);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+__device__ __forceinline__ int lane_value(int v, int i) { return __builtin_amdgcn_readlane(v, i); }
+__device__ __forceinline__ uint32_t lane_value(uint32_t v, int i) { return (uint32_t)__builtin_amdgcn_readlane((int)v, i); }
+
+// Up to 64 trips (128 steps) of path S, by the whole wave (S uniform).
+// Returns true when the path finished (exited or capped); S is advanced.
+template <class R, int F>
+__device__ __forceinline__ bool tail_pass(const Inst &D, const Consts<R> &K, TailPath<R> &S, uint32_t ctr3, Coef<R> cu,
+                                       bool &exited)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    uint32_t kz;
+    asm volatile("s_mov_b32 %0, 0" : "=s"(kz));
+    const uint4 wd = philox4x32_10((uint32_t)(S.t >> 1) + (uint32_t)lane, S.m, S.node, ctr3, K.key0 + kz,
+                                   K.key1 + kz);
+    R z0x, z0y, z1x, z1y;
+    normals(wd.x, wd.y, *K.tab, z0x, z0y);
+    normals(wd.z, wd.w, *K.tab, z1x, z1y);
+    // the points of every trip, in the order and form of the step loop
+    R px = S.x, py = S.y, x1 = S.x, y1 = S.y, x2 = S.x, y2 = S.y;
+    {
+        R cx = S.x, cy = S.y;
+#pragma unroll 1
+        for (int i = 0; i < kWave; ++i) {
+            const R a0 = lane_value(z0x, i), b0 = lane_value(z0y, i);
+            const R a1 = lane_value(z1x, i), b1 = lane_value(z1y, i);
+            const R nx1 = cx + K.sigma * a0, ny1 = cy + K.sigma * b0;
+            const R nx2 = nx1 + K.sigma * a1, ny2 = ny1 + K.sigma * b1;
+            if (lane == i) {
+                px = cx; py = cy; x1 = nx1; y1 = ny1; x2 = nx2; y2 = ny2;
+            }
+            cx = nx2;
+            cy = ny2;
+        }
+    }
+    const int ts = S.t + 2 * lane;                      // steps taken before this lane's trip
+    const bool out1 = is_out<F>(D, K, x1, y1);
+    const bool out2 = is_out<F>(D, K, x2, y2);
+    const bool second = !out1 && ts + 1 < K.jmax;
+    const bool ends = (second ? out2 : out1) || ts + (second ? 2 : 1) >= K.jmax;
+    const unsigned long long em = __ballot(ends);
+    const int n = em ? __ffsll((long long)em) : kWave;   // trips that count
+    // integrands at the two left points of each counted trip (as in advance)
+    R fr = (R)0, fi = (R)0, gr = (R)0, gi = (R)0;
+    const bool general = (F & kFeatGeneral) && K.general;
+    if (lane < n) {
+        CellReads<R> g0, g1;
+        g0.c = locate(K, px, py);
+        g1.c = locate(K, x1, y1);
+        issue_reads(K, g0.c.off, g0);
+        uint32_t o1 = g1.c.off;
+        if (K.cells) after_reads(o1, g0);
+        issue_reads(K, o1, g1);
+        R v0r, v0i, v1r, v1i;
+        value(g0, v0r, v0i);
+        value(g1, v1r, v1i);
+        if (general) {
+            fr = -(cu.re * v0r - cu.im * v0i);
+            fi = -(cu.re * v0i + cu.im * v0r);
+            gr = -(cu.re * v1r - cu.im * v1i);
+            gi = -(cu.re * v1i + cu.im * v1r);
+        } else {
+            fr = -(cu.re * v0r);
+            fi = -(cu.re * v0i);
+            gr = -(cu.re * v1r);
+            gi = -(cu.re * v1i);
+        }
+        if ((F & kFeatSource) && K.src_kind != SRC_ZERO) {
+            R sr, si;
+            source<R>(K, px, py, sr, si);
+            fr += sr;
+            fi += si;
+            source<R>(K, x1, y1, sr, si);
+            gr += sr;
+            gi += si;
+        }
+        if (!general && second) {
+            fr += gr;
+            fi += gi;
+        }
+    }
+    // the trips' sums in path order
+    const unsigned long long sm = __ballot(second);
+    double ar = S.ar, ai = S.ai, w = S.w;
+#pragma unroll 1
+    for (int i = 0; i < n; ++i) {
+        const bool sec = (sm >> i) & 1ull;
+        const R a = lane_value(fr, i), b = lane_value(fi, i);
+        if (general) {
+            const R c = lane_value(gr, i), d = lane_value(gi, i);
+            const double w1 = w * K.q;
+            ar += w * (double)a;
+            ai += w * (double)b;
+            if (sec) {
+                ar += w1 * (double)c;
+                ai += w1 * (double)d;
+            }
+            w = sec ? w1 * K.q : w1;
+        } else {
+            ar += (double)a;
+            ai += (double)b;
+        }
+    }
+    const int l = n - 1;                                  // the last counted trip
+    const bool sec_l = (sm >> l) & 1ull;
+    S.x = lane_value(sec_l ? x2 : x1, l);
+    S.y = lane_value(sec_l ? y2 : y1, l);
+    S.ar = ar;
+    S.ai = ai;
+    S.w = w;
+    S.t = S.t + 2 * l + (sec_l ? 2 : 1);
+    exited = lane_value((int)(sec_l ? out2 : out1), l) != 0;
+    return n < kWave || (em >> (kWave - 1)) != 0ull;
+}
+
 // A finished path waiting for its score: the last point and the left-point
 // sum (FP64), its exit-step index and the node it belongs to.
 struct Pending {
@@ -743,7 +894,40 @@ __device__ __forceinline__ void stream_paths(const Inst *__restrict__ insts, con
             }
             if (__ballot(active) == 0ull) break;
             bool fin = false, exited = false;
-            if (active) fin = advance<R, F>(D, K, P, m, (uint32_t)node, ctr3, cu, exited);
+            const unsigned long long act = __ballot(active);
+            if (!(F & kFeatReflect) && !more && pool_m >= pool_end && __popcll(act) <= kTailLanes) {
+                // tail mode: no work left for this wave and few paths still
+                // running; the whole wave takes them one at a time
+                const int lane = threadIdx.x & (kWave - 1);
+                unsigned long long todo = act;
+                while (todo) {
+                    const int L = __ffsll((long long)todo) - 1;
+                    todo &= todo - 1ull;
+                    TailPath<R> S;
+                    S.x = lane_value(P.x, L);
+                    S.y = lane_value(P.y, L);
+                    S.ar = lane_value(P.ar, L);
+                    S.ai = lane_value(P.ai, L);
+                    S.w = lane_value(P.w, L);
+                    S.t = lane_value(P.t, L);
+                    S.m = lane_value(m, L);
+                    S.node = lane_value((uint32_t)node, L);
+                    bool ex = false;
+                    const bool f = tail_pass<R, F>(D, K, S, ctr3, cu, ex);
+                    if (lane == L) {
+                        P.x = S.x;
+                        P.y = S.y;
+                        P.ar = S.ar;
+                        P.ai = S.ai;
+                        P.w = S.w;
+                        P.t = S.t;
+                        fin = f;
+                        exited = ex;
+                    }
+                }
+            } else if (active) {
+                fin = advance<R, F>(D, K, P, m, (uint32_t)node, ctr3, cu, exited);
+            }
             const unsigned long long done = __ballot(fin);
             if (done) {
                 // score the parked paths first when a finishing lane still
