@@ -858,6 +858,19 @@ __device__ __forceinline__ void stream_paths(const Inst *__restrict__ insts, con
         int32_t node = 0, node_idx = 0;
         uint32_t m = 0;
         auto flush = [&]() { deposit_parked<F>(D, Qp, A); };
+        // a lane whose path finished parks it; parked paths are scored first
+        // when a finishing lane still holds one, or when enough have gathered
+        auto on_done = [&](bool fin, bool exited) {
+            const unsigned long long done = __ballot(fin);
+            if (done) {
+                const unsigned long long pend = __ballot(Qp.live);
+                if ((done & pend) || __popcll(done | pend) > kScoreBatch) flush();
+                if (fin) {
+                    park<R>(Qp, P, exited, node_idx);
+                    active = false;
+                }
+            }
+        };
 
         for (;;) {
             // give every idle lane the next path index, opening items as needed
@@ -892,13 +905,22 @@ __device__ __forceinline__ void stream_paths(const Inst *__restrict__ insts, con
                 const int64_t taken = (int64_t)__popcll(need);
                 pool_m += taken < avail ? taken : avail;
             }
-            if (__ballot(active) == 0ull) break;
-            bool fin = false, exited = false;
             const unsigned long long act = __ballot(active);
-            if (!(F & kFeatReflect) && !more && pool_m >= pool_end && __popcll(act) <= kTailLanes) {
-                // tail mode: no work left for this wave and few paths still
-                // running; the whole wave takes them one at a time
-                const int lane = threadIdx.x & (kWave - 1);
+            if (act == 0ull) break;
+            // no work left for this wave and few paths running: tail phase
+            if (!(F & kFeatReflect) && !more && pool_m >= pool_end && __popcll(act) <= kTailLanes) break;
+            bool fin = false, exited = false;
+            if (active) fin = advance<R, F>(D, K, P, m, (uint32_t)node, ctr3, cu, exited);
+            on_done(fin, exited);
+        }
+        if constexpr (!(F & kFeatReflect)) {
+            // tail mode: the whole wave takes the remaining paths one at a
+            // time (the main loop leaves only when no refill is possible)
+            const int lane = threadIdx.x & (kWave - 1);
+            for (;;) {
+                const unsigned long long act = __ballot(active);
+                if (act == 0ull) break;
+                bool fin = false, exited = false;
                 unsigned long long todo = act;
                 while (todo) {
                     const int L = __ffsll((long long)todo) - 1;
@@ -925,19 +947,7 @@ __device__ __forceinline__ void stream_paths(const Inst *__restrict__ insts, con
                         exited = ex;
                     }
                 }
-            } else if (active) {
-                fin = advance<R, F>(D, K, P, m, (uint32_t)node, ctr3, cu, exited);
-            }
-            const unsigned long long done = __ballot(fin);
-            if (done) {
-                // score the parked paths first when a finishing lane still
-                // holds one, or when enough have gathered
-                const unsigned long long pend = __ballot(Qp.live);
-                if ((done & pend) || __popcll(done | pend) > kScoreBatch) flush();
-                if (fin) {
-                    park<R>(Qp, P, exited, node_idx);
-                    active = false;
-                }
+                on_done(fin, exited);
             }
         }
         flush();
