@@ -619,6 +619,124 @@ __device__ __forceinline__ bool tail_pass(const Inst &D, const Consts<R> &K, Tai
     return n < kWave || (em >> (kWave - 1)) != 0ull;
 }
 
+// The same for several paths at once: the wave is split into groups of G
+// lanes (G = 64 / 2^ceil(log2 k) for k paths), group g takes the g-th path
+// and G trips of it per pass; values move between lanes by shuffles.
+// S holds the group's path on every lane of the group.
+__device__ __forceinline__ float lane_from(float v, int src) { return __shfl(v, src, kWave); }
+__device__ __forceinline__ double lane_from(double v, int src) { return __shfl(v, src, kWave); }
+__device__ __forceinline__ int lane_from(int v, int src) { return __shfl(v, src, kWave); }
+
+template <class R, int F>
+__device__ __forceinline__ bool tail_pass_grouped(const Inst &D, const Consts<R> &K, TailPath<R> &S, int G,
+                                                  uint32_t ctr3, Coef<R> cu, bool &exited)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int base = lane & ~(G - 1), j = lane - base;
+    uint32_t kz;
+    asm volatile("s_mov_b32 %0, 0" : "=s"(kz));
+    const uint4 wd = philox4x32_10((uint32_t)(S.t >> 1) + (uint32_t)j, S.m, S.node, ctr3, K.key0 + kz,
+                                   K.key1 + kz);
+    R z0x, z0y, z1x, z1y;
+    normals(wd.x, wd.y, *K.tab, z0x, z0y);
+    normals(wd.z, wd.w, *K.tab, z1x, z1y);
+    R px = S.x, py = S.y, x1 = S.x, y1 = S.y, x2 = S.x, y2 = S.y;
+    {
+        R cx = S.x, cy = S.y;
+#pragma unroll 1
+        for (int i = 0; i < G; ++i) {
+            const R a0 = lane_from(z0x, base + i), b0 = lane_from(z0y, base + i);
+            const R a1 = lane_from(z1x, base + i), b1 = lane_from(z1y, base + i);
+            const R nx1 = cx + K.sigma * a0, ny1 = cy + K.sigma * b0;
+            const R nx2 = nx1 + K.sigma * a1, ny2 = ny1 + K.sigma * b1;
+            if (j == i) {
+                px = cx; py = cy; x1 = nx1; y1 = ny1; x2 = nx2; y2 = ny2;
+            }
+            cx = nx2;
+            cy = ny2;
+        }
+    }
+    const int ts = S.t + 2 * j;
+    const bool out1 = is_out<F>(D, K, x1, y1);
+    const bool out2 = is_out<F>(D, K, x2, y2);
+    const bool second = !out1 && ts + 1 < K.jmax;
+    const bool ends = (second ? out2 : out1) || ts + (second ? 2 : 1) >= K.jmax;
+    const unsigned long long gmask = (G == kWave) ? ~0ull : ((1ull << G) - 1ull);
+    const unsigned long long em = (__ballot(ends) >> base) & gmask;
+    const unsigned long long sm = (__ballot(second) >> base) & gmask;
+    const int n = em ? __ffsll((long long)em) : G;
+    R fr = (R)0, fi = (R)0, gr = (R)0, gi = (R)0;
+    const bool general = (F & kFeatGeneral) && K.general;
+    if (j < n) {
+        CellReads<R> g0, g1;
+        g0.c = locate(K, px, py);
+        g1.c = locate(K, x1, y1);
+        issue_reads(K, g0.c.off, g0);
+        uint32_t o1 = g1.c.off;
+        if (K.cells) after_reads(o1, g0);
+        issue_reads(K, o1, g1);
+        R v0r, v0i, v1r, v1i;
+        value(g0, v0r, v0i);
+        value(g1, v1r, v1i);
+        if (general) {
+            fr = -(cu.re * v0r - cu.im * v0i);
+            fi = -(cu.re * v0i + cu.im * v0r);
+            gr = -(cu.re * v1r - cu.im * v1i);
+            gi = -(cu.re * v1i + cu.im * v1r);
+        } else {
+            fr = -(cu.re * v0r);
+            fi = -(cu.re * v0i);
+            gr = -(cu.re * v1r);
+            gi = -(cu.re * v1i);
+        }
+        if ((F & kFeatSource) && K.src_kind != SRC_ZERO) {
+            R sr, si;
+            source<R>(K, px, py, sr, si);
+            fr += sr;
+            fi += si;
+            source<R>(K, x1, y1, sr, si);
+            gr += sr;
+            gi += si;
+        }
+        if (!general && second) {
+            fr += gr;
+            fi += gi;
+        }
+    }
+    double ar = S.ar, ai = S.ai, w = S.w;
+#pragma unroll 1
+    for (int i = 0; i < G; ++i) {
+        const R a = lane_from(fr, base + i), b = lane_from(fi, base + i);
+        const R c = lane_from(gr, base + i), d = lane_from(gi, base + i);
+        if (i < n) {
+            const bool sec = (sm >> i) & 1ull;
+            if (general) {
+                const double w1 = w * K.q;
+                ar += w * (double)a;
+                ai += w * (double)b;
+                if (sec) {
+                    ar += w1 * (double)c;
+                    ai += w1 * (double)d;
+                }
+                w = sec ? w1 * K.q : w1;
+            } else {
+                ar += (double)a;
+                ai += (double)b;
+            }
+        }
+    }
+    const int l = base + n - 1;
+    const bool sec_l = (sm >> (n - 1)) & 1ull;
+    S.x = lane_from(sec_l ? x2 : x1, l);
+    S.y = lane_from(sec_l ? y2 : y1, l);
+    S.ar = ar;
+    S.ai = ai;
+    S.w = w;
+    S.t = S.t + 2 * (n - 1) + (sec_l ? 2 : 1);
+    exited = lane_from((int)(sec_l ? out2 : out1), l) != 0;
+    return em != 0ull;
+}
+
 // A finished path waiting for its score: the last point and the left-point
 // sum (FP64), its exit-step index and the node it belongs to.
 struct Pending {
@@ -921,6 +1039,46 @@ __device__ __forceinline__ void stream_paths(const Inst *__restrict__ insts, con
                 const unsigned long long act = __ballot(active);
                 if (act == 0ull) break;
                 bool fin = false, exited = false;
+                const int k = __popcll(act);
+                if (k >= 2) {
+                    // k paths at once: group g (G lanes) takes the g-th
+                    int P2 = 2;
+                    while (P2 < k) P2 <<= 1;
+                    const int G = kWave / P2, g = lane / G;
+                    // the owner of path g: the g-th set bit of act
+                    unsigned long long b = act;
+                    for (int r = 0; r < g && b; ++r) b &= b - 1ull;
+                    const int owner = b ? __ffsll((long long)b) - 1 : 0;
+                    TailPath<R> S;
+                    S.x = lane_from(P.x, owner);
+                    S.y = lane_from(P.y, owner);
+                    S.ar = lane_from(P.ar, owner);
+                    S.ai = lane_from(P.ai, owner);
+                    S.w = lane_from(P.w, owner);
+                    S.t = lane_from(P.t, owner);
+                    S.m = (uint32_t)lane_from((int)m, owner);
+                    S.node = (uint32_t)lane_from((int)node, owner);
+                    bool ex = false;
+                    const bool f = tail_pass_grouped<R, F>(D, K, S, G, ctr3, cu, ex) && g < k;
+                    // every active lane takes its path's results from its group's first lane
+                    const int mine = __builtin_amdgcn_mbcnt_hi((uint32_t)(act >> 32),
+                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)act, 0u)) * G;
+                    const R nx = lane_from(S.x, mine), ny = lane_from(S.y, mine);
+                    const double nar = lane_from(S.ar, mine), nai = lane_from(S.ai, mine), nw = lane_from(S.w, mine);
+                    const int nt = lane_from(S.t, mine), nf = lane_from((int)f, mine), ne = lane_from((int)ex, mine);
+                    if (active) {
+                        P.x = nx;
+                        P.y = ny;
+                        P.ar = nar;
+                        P.ai = nai;
+                        P.w = nw;
+                        P.t = nt;
+                        fin = nf != 0;
+                        exited = ne != 0;
+                    }
+                    on_done(fin, exited);
+                    continue;
+                }
                 unsigned long long todo = act;
                 while (todo) {
                     const int L = __ffsll((long long)todo) - 1;
