@@ -481,12 +481,12 @@ __device__ __forceinline__ bool advance(const Inst &D, const Consts<R> &K, PathS
 // integrands in path order.  Every value is the one the step-by-step loop
 // forms, so the results are identical.  Not used with a reflecting edge.
 // A wave enters it once the queue has nothing left for it and at most
-// FK_TAIL_LANES of its lanes still run a path (measured on the 65 x 65
-// cavity: 8 and 4 best, 16 slower, 32 and 64 slower than no tail mode; one
-// path at a time beats 64 lanes on 64 paths only when few paths are left).
+// FK_TAIL_LANES of its lanes still run a path; several paths share a pass in
+// lane groups (measured on the 65 x 65 cavity: 16 best, 8 and 32 within 1%;
+// with one path per pass 8 was best and 32 or more lost to no tail mode).
 
 #ifndef FK_TAIL_LANES
-#define FK_TAIL_LANES 8
+#define FK_TAIL_LANES 16
 #endif
 constexpr int kTailLanes = FK_TAIL_LANES;   // a wave with no work left and at most this many active lanes
 
