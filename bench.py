@@ -32,7 +32,7 @@ PEAK_TFLOPS = {64: 78.6, 32: 157.3}
 # 18, integrand 2, left-point sum 1 (FP64) or 1.5 (FP32: half an FP32 add for
 # the trip's two values, then half a conversion and half an FP64 add).
 FLOPS_PER_STEP = {64: 50.0, 32: 48.5}
-KERNEL = {64: "fk_stream_f64", 32: "fk_stream_f32"}
+KERNEL = {64: "fk_stream_f64_l1", 32: "fk_stream_f32"}
 # HBM bytes per launch of the path kernels from FETCH_SIZE / WRITE_SIZE
 # counters (scaled by a plain copy of known size), valid only for the kernel
 # sources they were taken on

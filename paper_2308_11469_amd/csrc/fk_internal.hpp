@@ -33,8 +33,10 @@ struct PddBlock {
 namespace fkk {
 // features: bit 0 some instance has a hole, bit 1 a source term, bit 2 a
 // shift alpha != k^2 or a damping, bit 3 a reflecting edge
+// l1_grid: every instance reads a row-major copy (picks the four-wave build
+// of the plain FP64 kernel)
 hipError_t launch_stream(int precision, int features, const fkd::Inst *d_insts, const fkd::EngineQueue *Q,
-                         unsigned long long *head, int n_blocks, hipStream_t s);
+                         unsigned long long *head, int n_blocks, hipStream_t s, bool l1_grid = false);
 hipError_t launch_reset(const fkd::Inst *d_insts, const int32_t *which, int32_t n, const int32_t *n_dev,
                         unsigned long long *head, hipStream_t s);
 hipError_t launch_update(const fkd::Inst *d_insts, const int32_t *which, int32_t n_inst, const int32_t *n_dev,

@@ -1115,22 +1115,20 @@ __device__ __forceinline__ void stream_paths(const Inst *__restrict__ insts, con
 }
 
 // Occupancy targets (waves per SIMD) of the path kernels; they bound the
-// registers the compiler may use.  The plain FP64 kernel fits four waves in
-// 128 VGPRs with a 20-byte spill and runs 3% faster than with three (same
-// box, alternating runs); every FP64 variant with a feature spills 88-184
-// bytes at 128 and keeps three.
+// registers the compiler may use.  FP64 runs three waves.  A second build of
+// the plain FP64 kernel runs four (128 VGPRs, a small spill): 2% faster on
+// the 65 x 65 cavity, whose row-major copy sits in the vector L1, but 37%
+// slower on 257 x 257 with the cell-major copy, where the loop is bound by
+// L2 requests; the solver takes it for row-major instances only.
 #ifndef FK_WAVES_F32
 #define FK_WAVES_F32 4
 #endif
 #ifndef FK_WAVES_F64
 #define FK_WAVES_F64 3
 #endif
-#ifndef FK_WAVES_F64_PLAIN
-#define FK_WAVES_F64_PLAIN 4
+#ifndef FK_WAVES_F64_L1
+#define FK_WAVES_F64_L1 4
 #endif
-template <int F> struct WavesF64 {
-    static constexpr int value = F == 0 ? FK_WAVES_F64_PLAIN : FK_WAVES_F64;
-};
 
 template <int F>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FK_WAVES_F32)))
@@ -1140,10 +1138,17 @@ fk_stream_f32(const Inst *__restrict__ insts, const EngineQueue *__restrict__ Q,
 }
 
 template <int F>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WavesF64<F>::value)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FK_WAVES_F64)))
 fk_stream_f64(const Inst *__restrict__ insts, const EngineQueue *__restrict__ Q, unsigned long long *head)
 {
     stream_paths<double, F>(insts, Q, head);
+}
+
+// the plain FP64 kernel at four waves, for a row-major copy in the vector L1
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FK_WAVES_F64_L1)))
+fk_stream_f64_l1(const Inst *__restrict__ insts, const EngineQueue *__restrict__ Q, unsigned long long *head)
+{
+    stream_paths<double, 0>(insts, Q, head);
 }
 
 // Instance lists: `which` (device, optional) names the instances by index
@@ -1499,9 +1504,13 @@ static void launch_stream_f(int precision, dim3 grid, dim3 block, const Inst *d_
 }
 
 hipError_t launch_stream(int precision, int features, const Inst *d_insts, const EngineQueue *Q,
-                         unsigned long long *head, int n_blocks, hipStream_t s)
+                         unsigned long long *head, int n_blocks, hipStream_t s, bool l1_grid)
 {
     dim3 grid(n_blocks), block(256);
+    if (precision == 64 && (features & kFeatAll) == 0 && l1_grid) {
+        hipLaunchKernelGGL(fk_stream_f64_l1, grid, block, 0, s, d_insts, Q, head);
+        return hipGetLastError();
+    }
     // a reflecting edge comes with a hole: the sets with bit 3 all have bit 0
     switch (features & kFeatAll) {
     case 0: launch_stream_f<0>(precision, grid, block, d_insts, Q, head, s); break;

@@ -144,7 +144,8 @@ static fk_status run_one(fk_solver *s, fk_iter_report *rep)
     const int prec = s->P.par.precision;
     FK_HIP(fkk::launch_reset(s->d_inst, nullptr, 1, nullptr, s->d_head, s->stream));
     FK_HIP(hipEventRecord(s->ev0, s->stream));
-    FK_HIP(fkk::launch_stream(prec, s->P.features(), s->d_inst, s->d_queue, s->d_head, s->n_blocks, s->stream));
+    FK_HIP(fkk::launch_stream(prec, s->P.features(), s->d_inst, s->d_queue, s->d_head, s->n_blocks, s->stream,
+                              s->P.cells == 0));
     FK_HIP(hipEventRecord(s->ev1, s->stream));
     FK_HIP(fkk::launch_update(s->d_inst, nullptr, 1, nullptr, (int32_t)s->P.interior.size(), s->stream));
     if (s->pdd_blocks > 0)
