@@ -35,6 +35,9 @@ constexpr int kFeatGeneral = 4;  // a shift alpha != k^2 or a damping p (discoun
 constexpr int kFeatReflect = 8;  // the rectangle's edge reflects (Robin condition, local time); always
                                  // with a hole
 constexpr int kFeatAll = kFeatDisc | kFeatSource | kFeatGeneral | kFeatReflect;
+// Not a feature: a build of the plain kernel for instances whose gather copy
+// is row-major (held in the vector L1), with its own instruction order.
+constexpr int kRowMajor = 16;
 
 enum : int32_t { BC_ZERO = 0, BC_PLANE_WAVE = 1, BC_BILINEAR = 2, BC_TABLE = 3, BC_PLANE_WAVE_ROBIN = 4 };
 enum : int32_t { HOLE_NONE = 0, HOLE_DISC = 1, HOLE_BOX = 2 };
@@ -172,20 +175,21 @@ __device__ __forceinline__ void init_f64_tables(F64Tables &T)
     }
 }
 
-// ln(j 2^-24).  j 2^-24 = 2^n y with y in [2/3, 4/3); y = c (1 + r) with
+// ln(j 2^-24).  j = 2^e y with y in [0x3FE55555 00000000, 0x3FF55555 00000000)
+// as binary64 bit patterns (about [2/3, 4/3)): the exponent e comes from the
+// high word of (double) j, offset so that the split falls at 2/3, and y is
+// j with e taken out of its exponent field (exact).  y = c (1 + r) with
 // c = k/256 the table point nearest y, so |r| < 2^-9 / c < 0.003 and y - c is
 // exact; ln(1 + r) by its Taylor series to r^7 (the next term is below 1e-21).
-// Near U = 1 the table point is c = 1 (ln c = 0, n = 0) and ln U is ln(1 + r)
-// alone, without cancellation.  n ln 2 in two parts (Cody-Waite split: the
-// high part has trailing zero bits, so n * ln2_hi is exact).
+// Near U = 1 the table point is c = 1 (ln c = 0, n = e - 24 = 0) and ln U is
+// ln(1 + r) alone, without cancellation.  n ln 2 in two parts (Cody-Waite
+// split: the high part has trailing zero bits, so n * ln2_hi is exact).
 __device__ __forceinline__ double ln_uniform(uint32_t j, const F64Tables &T)
 {
-    int e = 31 - __clz((int)j);
-    double y = ldexp((double)j, -e);
-    if (y >= 4.0 / 3.0) {
-        y *= 0.5;
-        e += 1;
-    }
+    const double dj = (double)j;
+    const int hi = __double2hiint(dj);
+    const int e = (hi - 0x3FE55555) >> 20;
+    const double y = __hiloint2double(hi - (e << 20), __double2loint(dj));
     const int k = (int)(y * 256.0 + 0.5);
     const double2 t = T.lg[k - 128];
     const double r = (y - (double)k * 0x1p-8) * t.y;

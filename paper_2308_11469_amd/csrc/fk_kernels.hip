@@ -351,6 +351,10 @@ __device__ __forceinline__ void local_time_term(const Inst &D, const Consts<R> &
     P.ai -= c * gi;
 }
 
+#ifndef FK_EARLY
+#define FK_EARLY 1
+#endif
+
 template <class R, int F>
 __device__ __forceinline__ bool advance(const Inst &D, const Consts<R> &K, PathState<R> &P, uint32_t m,
                                         uint32_t node, uint32_t ctr3, Coef<R> cu, bool &exited)
@@ -368,8 +372,29 @@ __device__ __forceinline__ bool advance(const Inst &D, const Consts<R> &K, PathS
     const uint4 w = philox4x32_10((uint32_t)(P.t >> 1), m, node, ctr3, K.key0 + kz, K.key1 + kz);
     R z0x, z0y, z1x, z1y;
     normals(w.x, w.y, *K.tab, z0x, z0y);
-    normals(w.z, w.w, *K.tab, z1x, z1y);
+    constexpr bool early = (F & kRowMajor) != 0;
+    if constexpr (!early) normals(w.z, w.w, *K.tab, z1x, z1y);
     R x1 = P.x + K.sigma * z0x, y1 = P.y + K.sigma * z0y;
+    if constexpr (early) {
+#if FK_EARLY
+        // Row-major copy (L1 hits): both cells' reads go out first and the
+        // second pair of normals runs while they are in flight.  Left to
+        // itself the compiler moves that pair into the branch of the second
+        // step, after the first cell's values are needed, and the wave waits
+        // for both reads with little to do; the empty asm statements pin
+        // the pair between the reads and their use.
+        g0.c = locate(K, P.x, P.y);
+        g1.c = locate(K, x1, y1);
+        issue_reads(K, g0.c.off, g0);
+        issue_reads(K, g1.c.off, g1);
+        uint32_t wz = w.z, ww = w.w;
+        asm volatile("" : "+v"(wz), "+v"(ww));
+        normals(wz, ww, *K.tab, z1x, z1y);
+        asm volatile("" : : "v"(z1x), "v"(z1y));
+#else
+        normals(w.z, w.w, *K.tab, z1x, z1y);
+#endif
+    }
     // a reflecting edge mirrors each step back into the rectangle
     const bool refl = (F & kFeatReflect) && K.reflect;
     Mirror<R> m1{(R)0, (R)0, -1, -1}, m2{(R)0, (R)0, -1, -1};
@@ -408,12 +433,14 @@ __device__ __forceinline__ bool advance(const Inst &D, const Consts<R> &K, PathS
             } while (todo);
         }
     }
-    g0.c = locate(K, P.x, P.y);
-    g1.c = locate(K, x1, y1);
-    issue_reads(K, g0.c.off, g0);
-    uint32_t o1 = g1.c.off;
-    if (K.cells) after_reads(o1, g0);
-    issue_reads(K, o1, g1);
+    if constexpr (!early || !FK_EARLY) {
+        g0.c = locate(K, P.x, P.y);
+        g1.c = locate(K, x1, y1);
+        issue_reads(K, g0.c.off, g0);
+        uint32_t o1 = g1.c.off;
+        if (!early && K.cells) after_reads(o1, g0);
+        issue_reads(K, o1, g1);
+    }
     R v0r, v0i, v1r, v1i;
     value(g0, v0r, v0i);
     value(g1, v1r, v1i);
@@ -1148,7 +1175,7 @@ fk_stream_f64(const Inst *__restrict__ insts, const EngineQueue *__restrict__ Q,
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FK_WAVES_F64_L1)))
 fk_stream_f64_l1(const Inst *__restrict__ insts, const EngineQueue *__restrict__ Q, unsigned long long *head)
 {
-    stream_paths<double, 0>(insts, Q, head);
+    stream_paths<double, kRowMajor>(insts, Q, head);
 }
 
 // Instance lists: `which` (device, optional) names the instances by index

@@ -46,6 +46,10 @@ def test_normals_fp64_and_fp32():
     w[0] = (0, 0)
     w[1] = (2 ** 32 - 1, 2 ** 32 - 1)
     w[2] = (0, 2 ** 31)
+    # U = j 2^-24 on both sides of the FP64 log's argument split just below
+    # 4/3 (2^e y with y either near 4/3 or near 2/3)
+    for i, j in enumerate((1398101, 5592405, 11184809, 1398099, 11184811, 2 ** 24 - 1)):
+        w[3 + i] = (j << 8, (977 * i + 5) << 8)
     ref = np.array([fkmc.box_muller(a, b) for a, b in w])
     z64 = fkh.debug_normals(64, w)
     z32 = fkh.debug_normals(32, w)
