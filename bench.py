@@ -75,6 +75,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--annulus-only", action="store_true",
                     help="only time the reflecting-edge kernels on the shape-3 annulus and print that line")
+    ap.add_argument("--pdd-only", action="store_true",
+                    help="only run the domain-decomposed bench cavity and print that line")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run three device-to-device copies of MIB MiB (the reference kernel for "
                          "scaling HBM byte counters) and exit")
@@ -300,6 +302,9 @@ def main():
         return
     if a.annulus_only:
         print(json.dumps(annulus_shape3(a.steps)), flush=True)
+        return
+    if a.pdd_only:
+        print(json.dumps(pdd_cavity65(a.k)), flush=True)
         return
     import numpy as np
     import torch

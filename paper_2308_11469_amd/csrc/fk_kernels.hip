@@ -33,6 +33,7 @@ template <class R> __device__ __forceinline__ void setup_tables(typename TablesO
 // loop touches no instance memory.
 template <class R> struct Consts {
     R x0, y0, idx, idy, sigma, k2;
+    R ox, oy;               // -x0 / dx, -y0 / dy: grid coordinates as x / dx + ox
     R ex0, ex1, ey0, ey1;   // rectangle edges for the exit test (FP32: rounded outward)
     R cxf, cyf, r2f, band;
     R hx0, hx1, hy0, hy1;   // box hole for the exit test (FP32: rounded inward)
@@ -62,6 +63,7 @@ template <class R> struct Consts {
     __amdgpu_buffer_rsrc_t grid;   // buffer resource of the iterate grid
     __device__ Consts(const Inst &D, const typename TablesOf<R>::type *T)
         : x0((R)D.x0), y0((R)D.y0), idx((R)D.idx), idy((R)D.idy), sigma((R)D.sigma), k2((R)D.k2),
+          ox((R)(-D.x0 * D.idx)), oy((R)(-D.y0 * D.idy)),
           cxf((R)D.cx), cyf((R)D.cy), r2f((R)D.r2), band((R)(1e-5 * (D.r + 1.0))),
           lx0((R)D.x0), lx1((R)D.x1), ly0((R)D.y0), ly1((R)D.y1), kk((R)D.k), ih(D.ih),
           src_re((R)D.src_re), src_im((R)D.src_im), src_cx((R)D.src_cx), src_cy((R)D.src_cy),
@@ -205,7 +207,10 @@ template <class R> struct Cell {
 template <class R>
 __device__ __forceinline__ Cell<R> locate(const Consts<R> &K, R x, R y)
 {
-    const R fx = (x - K.x0) * K.idx, fy = (y - K.y0) * K.idy;
+    // one multiply-add per coordinate; just inside the lower edge the
+    // rounding may give a fraction a few ulp below 0, which the clamp keeps
+    // in the first cell (the interpolant is continuous there)
+    const R fx = fma(x, K.idx, K.ox), fy = fma(y, K.idy, K.oy);
     const R pf = clamp_cell(floor(fx), K.pmax);
     const R qf = clamp_cell(floor(fy), K.qmax);
     // p, q < 2^24 and the strides < 2^24 (checked at set-up): full-rate

@@ -109,6 +109,28 @@ def test_single_paths_bit_exact_exit_steps(name):
 
 # --------------------------------------------------- node estimates (FP64)
 
+def test_step_cap_inside_long_paths_fp64():
+    # a cap longer than one tail pass (128 steps) and odd, so that paths are
+    # capped mid-trip both in the main loop and at any offset of the tail
+    # passes of the iteration's end; the capped counts per node are exact
+    p = W.cavity_small().replace(h=2e-4, jmax=301, M=400, seed=21)
+    say("step cap 301")
+    s = fkh.Solver(p)
+    ids = fkmc.interior_ids(p)
+    u = None
+    for it in range(2):
+        s.iterate(1)
+        g, _ = s.get()
+        sj, cp = s.node_stats()
+        orc = fkmc.fk_nodes(p, u, it)
+        assert_fp64_node_parity(interior_values(p, g), sj[ids], orc, p.M, label="cap301 it %d" % it)
+        assert np.array_equal(cp[ids], orc["capped"])
+        assert 0 < orc["capped"].sum() < p.M * len(ids)
+        u = g
+    s.close()
+
+
+
 @pytest.mark.parametrize("name", ["cavity_9x9", "gaussian_17", "disc_33", "aniso_23x7", "crn", "general_9x9",
                                   "general_src_disc_33"])
 def test_node_estimates_fp64_per_iteration(name):
