@@ -119,8 +119,12 @@ def exit_time_problem(p, M=1024):
                      inner=BC("zero"), M=M, crn=False, max_iters=1, tol=0.0)
 
 
-def kstar_cavity(exit_times: np.ndarray) -> float:
-    return 1.0 / math.sqrt(float(np.max(exit_times)))
+def kstar_cavity(exit_times: np.ndarray, damping: float = 0.0) -> float:
+    """k_*^C = sqrt(1 / max E[tau] - p) from an exit-time map (eq. (2.9)): the
+    largest k for which the sufficient condition (alpha + p) E[tau] < 1 of
+    Theorem 2.2 can hold with alpha >= k^2; 0 when even k = 0 fails it."""
+    v = 1.0 / float(np.max(exit_times)) - damping
+    return math.sqrt(v) if v > 0 else 0.0
 
 
 def local_time_problem(p, M=1024):

@@ -130,6 +130,38 @@ def test_torsion_series_vs_fd_and_kstar():
                         rel_tol=1e-12)
 
 
+@pytest.mark.parametrize("damping", [0.0, 2.0, 6.0])
+def test_cavity_kstar_with_damping_is_a_sufficient_bound(damping):
+    # Theorem 2.2 asks (alpha + p) E[tau] < 1 with alpha >= k^2; at alpha = k^2
+    # that is k < k_*^C = sqrt(1 / max E[tau] - p) (eq. (2.9)).  On the FD
+    # model the increments of the iteration shrink by |k^2 + i p| / lambda_1^h
+    # per step, and max E >= 1 / lambda_1^h, so at k_*^C the iteration must
+    # contract, with room to spare; it diverges only past
+    # k_max = (lambda_1^h^2 - p^2)^(1/4), which lies above k_*^C.  (Without
+    # damping the contraction at k_*^C is exactly 1 / (max E lambda_1^h).)
+    n = 33
+    base = cavity(n, k=1.0).replace(damping=damping)
+    emax = float(fd.torsion(base).max())
+    lam = cf.lambda1h_rect(n, n, 1, 1)
+    kc = cf.kstar_cavity(emax, damping)
+    assert emax * lam > 1.0
+    assert abs((kc * kc + damping) * emax - 1.0) < 1e-12
+    kmax = (lam * lam - damping * damping) ** 0.25
+    assert kc < kmax
+
+    def growth(k):
+        its = fd.neumann(base.replace(k=k), 24)   # increments still far above rounding
+        d = [np.max(np.abs(its[i + 1] - its[i])) for i in range(len(its) - 1)]
+        return d[-1] / d[-2]
+
+    r = growth(kc)
+    assert abs(r - abs(complex(kc * kc, damping)) / lam) < 1e-6
+    assert r <= 1.0 / (emax * lam) + 1e-6 < 1.0
+    assert growth(1.03 * kmax) > 1.0
+    # the bound falls as the damping grows
+    assert cf.kstar_cavity(emax, damping + 1.0) < kc
+
+
 def test_bgk_constant():
     assert abs(cf.bgk_beta() - 0.5825971579) < 1e-9
 
