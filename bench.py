@@ -49,9 +49,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, workload):
-    """Counter-derived HBM bytes per launch, or None when no measurement
-    exists for these kernel sources and this workload."""
+def measured_counters(kernel, workload):
+    """The counter record of the kernel on this workload (HBM bytes per
+    launch, VALU issue figures), or None when no measurement exists for these
+    kernel sources and this workload."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -60,7 +61,20 @@ def measured_traffic(kernel, workload):
     k = t.get("kernels", {}).get(kernel)
     if t.get("source_sha") != kernel_source_hash() or not k or k.get("workload") != workload:
         return None
-    return k["bytes_per_launch"]
+    return k
+
+
+def measured_traffic(kernel, workload):
+    """Counter-derived HBM bytes per launch, or None (see measured_counters)."""
+    k = measured_counters(kernel, workload)
+    return None if k is None else k["bytes_per_launch"]
+
+
+def _issue(k):
+    if k is None or "valu_busy" not in k:
+        return None
+    return {"busy": k["valu_busy"], "lane_utilisation": k["valu_lane_utilisation"],
+            "instructions_per_path_step": k["valu_instructions_per_path_step"]}
 
 
 def parse():
@@ -367,7 +381,13 @@ def main():
                      "frac": achieved / peak,
                      "traffic": measured_traffic(KERNEL[a.precision], workload),
                      "kernel": KERNEL[a.precision],
-                     "kernel_ms_avg": avg_kernel_s * 1e3, "flops_per_path_step": FLOPS_PER_STEP[a.precision]},
+                     "kernel_ms_avg": avg_kernel_s * 1e3, "flops_per_path_step": FLOPS_PER_STEP[a.precision],
+                     # the ALU bound in issue terms, from the committed counter
+                     # profile of these kernel sources (None once they change):
+                     # VALU-active cycles at four per instruction over the
+                     # dispatch, lanes active per instruction, instructions
+                     # per path-step
+                     "valu_issue": _issue(measured_counters(KERNEL[a.precision], workload))},
         "extra": {"solves_per_s": 1.0 / (ms_per_step / 1e3 * solve_iters),
                   "iterations_per_solve": solve_iters,
                   "rms_error_vs_exact": rms,
