@@ -8,9 +8,12 @@ seeded sample of nodes one by one from the same u_n: FP64 node means within
 at every interior node against the FP64 path on the same streams and the
 same u_n: within 0.1 standard errors.
 """
+import math
+
 import numpy as np
 import pytest
 
+from oracle import closed_forms as CF
 from oracle import fkmc
 from paper_2308_11469_amd import fkh
 from paper_2308_11469_amd import workloads as W
@@ -59,6 +62,45 @@ def test_cavity65_fp64_bench_configuration(k):
     s.iterate(1)
     oracle_sampled(p, s, u1, 1, 24, "cavity65 k=%g" % k)
     s.close()
+
+
+@pytest.mark.parametrize("k", [1.0, 2.0, 3.0, 4.0, 4.6])
+def test_cavity65_solve_outcomes_with_common_random_numbers(k):
+    # the 65 x 65 configuration's solves: M = 4096, h = 1e-4, FP64, up to 40
+    # iterations to a change of 1e-6, with common random numbers (with fresh
+    # paths the change floors at ~4 SE, far above 1e-6).  The changes shrink
+    # by the contraction k^2 / lambda_1 of the square enlarged by the
+    # continuity shift beta sqrt(2h) of the once-per-step exit test: 1e-6 is
+    # reached within 40 iterations for k <= 3, not at k = 4 (ratio 0.84), and
+    # k = 4.6 > pi sqrt(2) diverges.  (Measured: the ratios match that model
+    # to 0.2-2%.)
+    p = W.cavity_65(k=k, precision=64).replace(crn=True, max_iters=40, tol=1e-6)
+    d = CF.bgk_beta() * math.sqrt(2.0 * p.h)
+    rho = k * k / CF.lambda1_rect(1 + 2 * d, 1 + 2 * d)
+    s = fkh.Solver(p)
+    rep = s.solve()
+    s.close()
+    s = fkh.Solver(p)
+    du = [s.iterate(1)["max_du"] for _ in range(rep["n"])]
+    u, _ = s.get()
+    s.close()
+    ratios = [du[i + 1] / du[i] for i in range(3, len(du) - 1)]
+    say("cavity65 CRN k=%g: %s after %d iterations, last change %.3g, ratios %s (rho %.3f)"
+        % (k, rep["status"], rep["n"], rep["max_du"], " ".join("%.3f" % r for r in ratios[-4:]), rho))
+    assert rep["max_du"] == du[-1]
+    if k <= 3.0:
+        assert rep["status"] == "FK_OK" and rep["n"] <= 40 and du[-1] < 1e-6 <= du[-2]
+        assert ratios and all(abs(r / rho - 1.0) < 0.05 for r in ratios)
+        ex = W.exact_solution(p)
+        ids = fkmc.interior_ids(p)
+        # Monte Carlo noise plus the O(sqrt h) exit bias (0.0133 RMS at k = 2)
+        assert np.sqrt(np.mean(np.abs(u.ravel()[ids] - ex.ravel()[ids]) ** 2)) < 0.02 * k + 0.01
+    elif k == 4.0:
+        assert rep["status"] == "FK_ENOTCONVERGED" and rep["n"] == 40
+        assert all(abs(r / rho - 1.0) < 0.05 for r in ratios[-10:])
+    else:
+        assert rep["status"] == "FK_EDIVERGED" and rep["n"] < 40
+        assert all(abs(r / rho - 1.0) < 0.05 for r in ratios[-4:])
 
 
 def test_gaussian_source_129_fp32_against_fp64_and_oracle():
