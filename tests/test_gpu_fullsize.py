@@ -124,6 +124,62 @@ def test_gaussian_source_129_fp32_against_fp64_and_oracle():
     s32.close()
 
 
+def shifted_square_fd(p, N=513):
+    """The estimator's continuous-monitoring model on a rectangle: the FD
+    direct solve on the rectangle enlarged by the continuity shift
+    beta sqrt(2h) per side (the once-per-step exit test), with the datum g
+    taken at the clamped point (the estimator's projection), sampled at the
+    interior nodes of p by spline interpolation."""
+    import scipy.interpolate as si
+    from oracle import fd
+    d = CF.bgk_beta() * math.sqrt(2.0 * p.h)
+    q = p.replace(x0=p.x0 - d, x1=p.x1 + d, y0=p.y0 - d, y1=p.y1 + d, nx=N, ny=N, outer=W.BC("table"))
+    px, py = W.perimeter_points(q.x0, q.x1, q.y0, q.y1, 4 * 8192)
+    q.outer.table = CF.plane_wave(p.k, p.outer.theta, np.clip(px, p.x0, p.x1), np.clip(py, p.y0, p.y1))
+    u = fd.direct(q)
+    xs = np.linspace(q.x0, q.x1, N)
+    ys = np.linspace(q.y0, q.y1, N)
+    fr = si.RectBivariateSpline(ys, xs, u.real)
+    fi = si.RectBivariateSpline(ys, xs, u.imag)
+    ids = fkmc.interior_ids(p)
+    x = p.x0 + (ids % p.nx) * (p.x1 - p.x0) / (p.nx - 1)
+    y = p.y0 + (ids // p.nx) * (p.y1 - p.y0) / (p.ny - 1)
+    return fr(y, x, grid=False) + 1j * fi(y, x, grid=False)
+
+
+def test_gaussian_source_129_fp32_solve_against_fd_513():
+    # the 129 x 129 configuration solved with FP32 stepping (k = 3.5, complex
+    # Gaussian source, M = 16384, h = 5e-5): the mean of iterates 21-30
+    # against (a) the estimator's model, the FD solve on the square enlarged
+    # by beta sqrt(2h) (node by node within 4.5 stationary standard errors
+    # plus the bilinear-interpolation bias of u_n), and (b) the 5-point FD
+    # direct solve on 513 x 513, from which it differs by that model's O(sqrt h)
+    # exit bias
+    from oracle import fd
+    p = W.cavity_source(precision=32)
+    s = fkh.Solver(p)
+    acc = np.zeros((p.ny, p.nx), complex)
+    for it in range(30):
+        s.iterate(1)
+        if it >= 20:
+            g, se = s.get()
+            acc += g
+    s.close()
+    ids = fkmc.interior_ids(p)
+    u = (acc / 10.0).ravel()[ids]
+    model = shifted_square_fd(p)
+    plain = fd.direct(p.replace(nx=513, ny=513))[::4, ::4].ravel()[ids]
+    rho = p.k ** 2 / CF.lambda1h_rect(p.nx, p.ny, 1.0, 1.0)
+    se_eff = np.abs(se.ravel()[ids]) / math.sqrt(1.0 - rho ** 2)
+    b_x = p.k ** 4 * 0.0737 * (1.0 / (p.nx - 1)) ** 2 / 8.0 / (1.0 - rho)
+    err_model = np.abs(u - model)
+    rms = lambda v: float(np.sqrt(np.mean(np.abs(v) ** 2)))
+    say("source129 solve: |u - model| max %.4f (%.2f SE_eff), rms %.4f; rms vs FD 513: %.4f (model %.4f)"
+        % (err_model.max(), (err_model / se_eff).max(), rms(err_model), rms(u - plain), rms(model - plain)))
+    assert np.all(err_model <= 4.5 * se_eff + b_x)
+    assert abs(rms(u - plain) - rms(model - plain)) < 0.25 * rms(model - plain)
+
+
 def test_largest_batch_rectangle_engine_fp32():
     # the largest-grid instance of the 256-rectangle batch (244 x 252) through
     # the FP32 engine, against the FP64 solver and the oracle
