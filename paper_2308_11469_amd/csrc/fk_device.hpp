@@ -153,24 +153,23 @@ __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
 // Box-Muller: z = sqrt(-2 ln U(ra)) (cos 2 pi U(rb), sin 2 pi U(rb)).
 
 // FP64.  U = j 2^-24 with j = (r >> 8) | 1 odd, 1 <= j < 2^24, so ln U and
-// sincos(2 pi U) only ever see 2^23 arguments; two small tables in LDS (built
-// once per block by init_f64_tables) and short polynomials give them in far
-// fewer operations than the general library functions, to about 1 ulp.
+// sincos(2 pi U) only ever see 2^23 arguments; two tables of 1024 points in
+// LDS (16 KB each, built once per block by init_f64_tables) and short
+// polynomials give them in far fewer operations than the general library
+// functions, to about 1 ulp.
 struct F64Tables {
-    double2 sc[512];   // (sin, cos)(pi i / 256)
-    double2 lg[256];   // (ln c, 1 / c) for c = (i + 128) / 256
+    double2 sc[1024];   // (sin, cos)(pi i / 512)
+    double2 lg[1024];   // (ln c, 1 / c) for c = (i + 512) / 1024
 };
 
 // Every thread of the block calls this; the caller synchronises the block.
 __device__ __forceinline__ void init_f64_tables(F64Tables &T)
 {
-    for (int i = threadIdx.x; i < 512; i += blockDim.x) {
+    for (int i = threadIdx.x; i < 1024; i += blockDim.x) {
         double sn, cs;
-        sincospi((double)i * 0x1p-8, &sn, &cs);
+        sincospi((double)i * 0x1p-9, &sn, &cs);
         T.sc[i] = make_double2(sn, cs);
-    }
-    for (int i = threadIdx.x; i < 256; i += blockDim.x) {
-        const double c = (double)(i + 128) * 0x1p-8;
+        const double c = (double)(i + 512) * 0x1p-10;
         T.lg[i] = make_double2(log(c), 1.0 / c);
     }
 }
@@ -179,10 +178,12 @@ __device__ __forceinline__ void init_f64_tables(F64Tables &T)
 // as binary64 bit patterns (about [2/3, 4/3)): the exponent e comes from the
 // high word of (double) j, offset so that the split falls at 2/3, and y is
 // j with e taken out of its exponent field (exact).  y = c (1 + r) with
-// c = k/256 the table point nearest y, so |r| < 2^-9 / c < 0.003 and y - c is
-// exact; ln(1 + r) by its Taylor series to r^7 (the next term is below 1e-21).
-// Near U = 1 the table point is c = 1 (ln c = 0, n = e - 24 = 0) and ln U is
-// ln(1 + r) alone, without cancellation.  n ln 2 in two parts (Cody-Waite
+// c = k/1024 the table point nearest y, so |r| < 2^-11 / c < 7.4e-4 and y - c
+// is exact; ln(1 + r) by its Taylor series to r^5.  The next term is below
+// 3e-20, and below 2.4e-21 where |ln U| is smallest without c = 1 (c = 1023/1024,
+// |ln U| > 4.8e-4): under 0.02 ulp.  Near U = 1 the table point is c = 1
+// (ln c = 0, n = e - 24 = 0) and ln U is ln(1 + r) alone, without
+// cancellation.  n ln 2 in two parts (Cody-Waite
 // split: the high part has trailing zero bits, so n * ln2_hi is exact).
 __device__ __forceinline__ double ln_uniform(uint32_t j, const F64Tables &T)
 {
@@ -190,12 +191,10 @@ __device__ __forceinline__ double ln_uniform(uint32_t j, const F64Tables &T)
     const int hi = __double2hiint(dj);
     const int e = (hi - 0x3FE55555) >> 20;
     const double y = __hiloint2double(hi - (e << 20), __double2loint(dj));
-    const int k = (int)(y * 256.0 + 0.5);
-    const double2 t = T.lg[k - 128];
-    const double r = (y - (double)k * 0x1p-8) * t.y;
-    double q = 1.0 / 7.0;
-    q = fma(r, q, -1.0 / 6.0);
-    q = fma(r, q, 1.0 / 5.0);
+    const int k = (int)(y * 1024.0 + 0.5);
+    const double2 t = T.lg[k - 512];
+    const double r = (y - (double)k * 0x1p-10) * t.y;
+    double q = 1.0 / 5.0;
     q = fma(r, q, -0.25);
     q = fma(r, q, 1.0 / 3.0);
     q = fma(r, q, -0.5);
@@ -205,15 +204,16 @@ __device__ __forceinline__ double ln_uniform(uint32_t j, const F64Tables &T)
     return fma(n, ln2_hi, fma(n, ln2_lo, t.x + l1p));
 }
 
-// (sin, cos)(pi j 2^-23) = (sin, cos)(pi (jh 2^-8 + x/pi)) with jh = j >> 15
-// from the table and x = pi (j mod 2^15) 2^-23 in [0, 0.0123): sin x to x^7
-// and cos x - 1 to x^6 (next terms below 2e-20), then the addition formulas.
+// (sin, cos)(pi j 2^-23) = (sin, cos)(pi (jh 2^-9 + x/pi)) with jh = j >> 14
+// from the table and x = pi (j mod 2^14) 2^-23 in [0, 0.0062): sin x to x^5
+// and cos x - 1 to x^6 (next terms below 7e-20 and 6e-23), then the addition
+// formulas.
 __device__ __forceinline__ void sincospi_uniform(uint32_t j, const F64Tables &T, double &sn, double &cs)
 {
-    const double2 t = T.sc[j >> 15];
-    const double x = (double)(j & 0x7FFFu) * 3.7450702829239286e-07;   // pi 2^-23
+    const double2 t = T.sc[j >> 14];
+    const double x = (double)(j & 0x3FFFu) * 3.7450702829239286e-07;   // pi 2^-23
     const double x2 = x * x;
-    const double s1 = fma(x * x2, fma(x2, fma(x2, -1.0 / 5040.0, 1.0 / 120.0), -1.0 / 6.0), x);
+    const double s1 = fma(x * x2, fma(x2, 1.0 / 120.0, -1.0 / 6.0), x);
     const double c1 = x2 * fma(x2, fma(x2, -1.0 / 720.0, 1.0 / 24.0), -0.5);
     sn = fma(t.y, s1, fma(t.x, c1, t.x));
     cs = fma(-t.x, s1, fma(t.y, c1, t.y));
