@@ -43,6 +43,7 @@ template <class R> struct Consts {
     double ih;              // 1 / h
     R src_re, src_im, src_cx, src_cy, src_c;
     R pmax, qmax;       // largest cell index as R (nx - 2, ny - 2)
+    int pmaxi, qmaxi;   // the same as integers
     int jmax;
     int hole, src_kind;
     int reflect;        // the rectangle's edge reflects
@@ -67,7 +68,7 @@ template <class R> struct Consts {
           cxf((R)D.cx), cyf((R)D.cy), r2f((R)D.r2), band((R)(1e-5 * (D.r + 1.0))),
           lx0((R)D.x0), lx1((R)D.x1), ly0((R)D.y0), ly1((R)D.y1), kk((R)D.k), ih(D.ih),
           src_re((R)D.src_re), src_im((R)D.src_im), src_cx((R)D.src_cx), src_cy((R)D.src_cy),
-          src_c((R)D.src_c), pmax((R)(D.nx - 2)), qmax((R)(D.ny - 2)), jmax((int)D.jmax),
+          src_c((R)D.src_c), pmax((R)(D.nx - 2)), qmax((R)(D.ny - 2)), pmaxi(D.nx - 2), qmaxi(D.ny - 2), jmax((int)D.jmax),
           hole(D.hole), src_kind(D.src_kind), reflect(D.reflect), robin_g2(D.outer.kind != BC_ZERO),
           cells(D.cells), q(D.q), alpha((R)D.alpha), damp((R)D.damp),
           general(D.alpha != D.k2 || D.damp != 0.0),
@@ -211,12 +212,24 @@ __device__ __forceinline__ Cell<R> locate(const Consts<R> &K, R x, R y)
     // rounding may give a fraction a few ulp below 0, which the clamp keeps
     // in the first cell (the interpolant is continuous there)
     const R fx = fma(x, K.idx, K.ox), fy = fma(y, K.idy, K.oy);
-    const R pf = clamp_cell(floor(fx), K.pmax);
-    const R qf = clamp_cell(floor(fy), K.qmax);
-    // p, q < 2^24 and the strides < 2^24 (checked at set-up): full-rate
-    // 24-bit products
-    const uint32_t off = (uint32_t)__umul24((uint32_t)pf, K.sx) + (uint32_t)__umul24((uint32_t)qf, K.sy);
-    return Cell<R>{fx - pf, fy - qf, off};
+    if constexpr (sizeof(R) == 8) {
+        // FP64: truncate, then clamp as integers (half the issue cost of
+        // FP64 floor / max / min); for fx > -1 truncation is the floor, and
+        // below it both clamp to cell 0, so cell and fraction are those of
+        // the clamped floor.  Points lie within a few cells of the grid
+        // (|z| < 6), well inside the int range.
+        const int p = min(max((int)fx, 0), K.pmaxi);
+        const int q = min(max((int)fy, 0), K.qmaxi);
+        const uint32_t off = (uint32_t)__umul24((uint32_t)p, K.sx) + (uint32_t)__umul24((uint32_t)q, K.sy);
+        return Cell<R>{fx - (R)p, fy - (R)q, off};
+    } else {
+        const R pf = clamp_cell(floor(fx), K.pmax);
+        const R qf = clamp_cell(floor(fy), K.qmax);
+        // p, q < 2^24 and the strides < 2^24 (checked at set-up): full-rate
+        // 24-bit products
+        const uint32_t off = (uint32_t)__umul24((uint32_t)pf, K.sx) + (uint32_t)__umul24((uint32_t)qf, K.sy);
+        return Cell<R>{fx - pf, fy - qf, off};
+    }
 }
 
 template <class R>
