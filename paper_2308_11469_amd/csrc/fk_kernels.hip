@@ -42,8 +42,8 @@ template <class R> struct Consts {
     R kk;                   // k (the Robin coupling i k u_n on a reflecting edge)
     double ih;              // 1 / h
     R src_re, src_im, src_cx, src_cy, src_c;
-    R pmax, qmax;       // largest cell index as R (nx - 2, ny - 2)
-    int pmaxi, qmaxi;   // the same as integers
+    R pmax, qmax;       // largest cell index as R (nx - 2, ny - 2): FP32 cell location
+    int pmaxi, qmaxi;   // the same as integers: FP64 cell location
     int jmax;
     int hole, src_kind;
     int reflect;        // the rectangle's edge reflects
@@ -198,7 +198,6 @@ __device__ __forceinline__ Mirror<R> reflect(const Consts<R> &K, R &x, R &y)
 // registers, the offset is 32-bit, and an offset outside the grid returns
 // zero instead of touching other memory.
 __device__ __forceinline__ float clamp_cell(float v, float hi) { return __builtin_amdgcn_fmed3f(v, 0.0f, hi); }
-__device__ __forceinline__ double clamp_cell(double v, double hi) { return fmin(fmax(v, 0.0), hi); }
 
 template <class R> struct Cell {
     R a, b;          // fractions within the cell
