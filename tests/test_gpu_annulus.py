@@ -20,6 +20,7 @@ from oracle import fkmc
 from paper_2308_11469_amd import fkh, serving
 from paper_2308_11469_amd import workloads as W
 
+import paper_values as PV
 from gpu_util import require_lib, say
 
 pytestmark = pytest.mark.gpu
@@ -67,8 +68,8 @@ def corner_mean(u, p):
     return float(np.mean([u[0, 0], u[0, -1], u[-1, 0], u[-1, -1]]))
 
 
-@pytest.mark.parametrize("shape,table", [("shape1", (0.03, 0.46, 1.93)), ("shape3", (0.20, 1.24, 0.72))])
-def test_table1_suprema_and_kstar_from_gpu(shape, table):
+@pytest.mark.parametrize("shape", ["shape1", "shape3"])
+def test_table1_suprema_and_kstar_from_gpu(shape):
     # the suprema sit at the rectangle's four corners (farthest from the
     # hole, by symmetry equal); E(h) = E_0 + c sqrt(h) + O(h): from h and h/4,
     # E_0 ~ 2 E(h/4) - E(h)
@@ -86,15 +87,16 @@ def test_table1_suprema_and_kstar_from_gpu(shape, table):
         est[which] = 2.0 * vals[1] - vals[0]
         say(shape, which, "E(4e-5) %.5f E(1e-5) %.5f -> %.5f" % (vals[0], vals[1], est[which]))
     ks = float(serving.khat_annulus(est["exit_time"], est["local_time"]))
-    say(shape, "k_*^A %.4f (Table 1: %s)" % (ks, table))
-    assert round(est["exit_time"], 2) == table[0]
-    assert round(est["local_time"], 2) == table[1]
-    assert round(ks, 2) == table[2]
+    t = PV.table1()[int(shape[-1])]
+    say(shape, "k_*^A %.4f (Table 1: %s %s %s)" % (ks, t["sup_tau"], t["sup_xi"], t["kstar_A"]))
+    assert round(est["exit_time"], 2) == t["sup_tau"]
+    assert round(est["local_time"], 2) == t["sup_xi"]
+    assert round(ks, 2) == t["kstar_A"]
 
 
-# Table 1: tested k, and whether the sum of 30 iterates converged
-TABLE1 = {"shape1": [(1.50, True), (1.93, True), (1.94, True), (2.90, False)],
-          "shape3": [(0.50, True), (0.72, True), (0.73, True), (1.07, False)]}
+# Table 1 (tests/golden/table1_annulus.txt): tested k, and whether the sum
+# of 30 iterates converged
+TABLE1 = {"shape%d" % sh: PV.table1()[sh]["tested"] for sh in (1, 3)}
 
 
 @pytest.mark.parametrize("shape", ["shape1", "shape3"])
