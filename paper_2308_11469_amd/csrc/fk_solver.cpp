@@ -41,6 +41,7 @@ struct fk_solver {
     std::vector<double> hist_sup, hist_du;
     fk_iter_report last{};
     // probabilistic domain decomposition (library-owned device memory)
+    bool pdd = false;   // set_pdd succeeded (the blocks may be none: every line a cut)
     int32_t pdd_blocks = 0, pdd_max_nodes = 0;
     fkd::PddBlock *d_pdd_blocks = nullptr;
     double *d_pdd_tables = nullptr;
@@ -193,7 +194,7 @@ fk_status fk_helmholtz_set_pdd(fk_solver *s, const int32_t *cuts_x, int32_t n_cu
     if (!s) return fail(FK_EINVAL, "solver is NULL");
     const HostProblem &P0 = s->P;
     const fk_domain &d = P0.dom;
-    if (s->iter != 0 || s->pdd_blocks != 0) return fail(FK_EINVAL, "set PDD once, before the first iteration");
+    if (s->iter != 0 || s->pdd) return fail(FK_EINVAL, "set PDD once, before the first iteration");
     if (d.kind != FK_DOMAIN_RECT || P0.reflect())
         return fail(FK_EINVAL, "PDD needs a plain rectangle with an absorbing edge");
     if (n_cuts_x < 0 || n_cuts_y < 0 || n_cuts_x + n_cuts_y == 0 || (n_cuts_x > 0 && !cuts_x) ||
@@ -247,19 +248,30 @@ fk_status fk_helmholtz_set_pdd(fk_solver *s, const int32_t *cuts_x, int32_t n_cu
     std::vector<int32_t> iface;
     for (int32_t id : P0.interior)
         if (on_x[id % d.nx] || on_y[id / d.nx]) iface.push_back(id);
-    hipError_t e;
+    // on any failure below the solver is left as it was: no partial buffers
+    // behind a retry, the host record unchanged
+    auto drop = [s]() {
+        for (void **b : {(void **)&s->d_pdd_blocks, (void **)&s->d_pdd_tables, (void **)&s->d_pdd_rhs})
+            if (*b) {
+                (void)hipFree(*b);
+                *b = nullptr;
+            }
+    };
+    hipError_t e = hipSuccess;
+    const char *what = nullptr;
     if (!blocks.empty()) {
         if ((e = hipMalloc((void **)&s->d_pdd_blocks, blocks.size() * sizeof(fkd::PddBlock))) != hipSuccess ||
             (e = hipMalloc((void **)&s->d_pdd_tables, tables.size() * sizeof(double))) != hipSuccess ||
             (e = hipMalloc((void **)&s->d_pdd_rhs, P0.n_nodes() * sizeof(double2))) != hipSuccess)
-            return hip_fail(e, "hipMalloc(pdd)");
-        FK_HIP(hipMemcpyAsync(s->d_pdd_blocks, blocks.data(), blocks.size() * sizeof(fkd::PddBlock),
-                              hipMemcpyHostToDevice, s->stream));
-        FK_HIP(hipMemcpyAsync(s->d_pdd_tables, tables.data(), tables.size() * sizeof(double), hipMemcpyHostToDevice,
-                              s->stream));
+            what = "hipMalloc(pdd)";
+        else if ((e = hipMemcpyAsync(s->d_pdd_blocks, blocks.data(), blocks.size() * sizeof(fkd::PddBlock),
+                                     hipMemcpyHostToDevice, s->stream)) != hipSuccess ||
+                 (e = hipMemcpyAsync(s->d_pdd_tables, tables.data(), tables.size() * sizeof(double),
+                                     hipMemcpyHostToDevice, s->stream)) != hipSuccess)
+            what = "hipMemcpyAsync(pdd tables)";
     }
     // the host record changes only once the device has the new node list,
-    // instance record and queue (a failed copy leaves the solver as it was)
+    // instance record and queue
     HostProblem P2 = s->P;
     P2.interior = iface;
     P2.n_items = (int64_t)iface.size() * P2.items_per_node;
@@ -269,11 +281,33 @@ fk_status fk_helmholtz_set_pdd(fk_solver *s, const int32_t *cuts_x, int32_t n_cu
     q.n_seg = 1;
     q.seg_end[0] = P2.n_items;
     q.seg_inst[0] = 0;
-    FK_HIP(hipMemcpyAsync(s->B.nodes, iface.data(), iface.size() * sizeof(int32_t), hipMemcpyHostToDevice, s->stream));
-    FK_HIP(hipMemcpyAsync(s->d_inst, &D, sizeof(D), hipMemcpyHostToDevice, s->stream));
-    FK_HIP(hipMemcpyAsync(s->d_queue, &q, sizeof(q), hipMemcpyHostToDevice, s->stream));
-    FK_HIP(hipStreamSynchronize(s->stream));
+    const bool touched = !what;   // the device node list is being rewritten
+    if (!what &&
+        ((e = hipMemcpyAsync(s->B.nodes, iface.data(), iface.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                             s->stream)) != hipSuccess ||
+         (e = hipMemcpyAsync(s->d_inst, &D, sizeof(D), hipMemcpyHostToDevice, s->stream)) != hipSuccess ||
+         (e = hipMemcpyAsync(s->d_queue, &q, sizeof(q), hipMemcpyHostToDevice, s->stream)) != hipSuccess ||
+         (e = hipStreamSynchronize(s->stream)) != hipSuccess))
+        what = "hipMemcpyAsync(pdd node list)";
+    if (what) {
+        (void)hipStreamSynchronize(s->stream);
+        drop();
+        if (touched) {
+            // best effort: the device node list, record and queue back to the
+            // host record's (unchanged)
+            const fkd::Inst D0 = make_inst(s->P, s->B);
+            fkd::EngineQueue q0 = q;
+            q0.seg_end[0] = s->P.n_items;
+            (void)hipMemcpyAsync(s->B.nodes, s->P.interior.data(), s->P.interior.size() * sizeof(int32_t),
+                                 hipMemcpyHostToDevice, s->stream);
+            (void)hipMemcpyAsync(s->d_inst, &D0, sizeof(D0), hipMemcpyHostToDevice, s->stream);
+            (void)hipMemcpyAsync(s->d_queue, &q0, sizeof(q0), hipMemcpyHostToDevice, s->stream);
+            (void)hipStreamSynchronize(s->stream);
+        }
+        return hip_fail(e, what);
+    }
     s->P = std::move(P2);
+    s->pdd = true;
     s->pdd_blocks = (int32_t)blocks.size();
     s->pdd_max_nodes = max_nodes;
     return FK_OK;

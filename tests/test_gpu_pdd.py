@@ -125,7 +125,8 @@ def test_pdd_iteration_settles_on_the_plane_wave():
     assert err.max() <= err_if.max() + 1e-3
 
 
-@pytest.mark.parametrize("bad", ["after_iterate", "twice", "disc", "too_wide", "no_cut", "unsorted"])
+@pytest.mark.parametrize("bad", ["after_iterate", "twice", "twice_no_blocks", "disc", "too_wide", "no_cut",
+                                 "unsorted"])
 def test_pdd_argument_checks(bad):
     p = W.cavity_small().replace(nx=33, ny=33, M=64)
     cx, cy = [16], [16]
@@ -138,10 +139,14 @@ def test_pdd_argument_checks(bad):
         cx, cy = [], []
     if bad == "unsorted":
         cx = [20, 10]
+    if bad == "twice_no_blocks":
+        # every interior column a cut line: no block between them, and still
+        # only one call
+        cx, cy = list(range(1, p.nx - 1)), []
     s = fkh.Solver(p)
     if bad == "after_iterate":
         s.iterate(1)
-    if bad == "twice":
+    if bad in ("twice", "twice_no_blocks"):
         s.set_pdd(cx, cy)
     with pytest.raises(ValueError):
         s.set_pdd(cx, cy)
