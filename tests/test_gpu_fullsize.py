@@ -180,6 +180,33 @@ def test_gaussian_source_129_fp32_solve_against_fd_513():
     assert abs(rms(u - plain) - rms(model - plain)) < 0.25 * rms(model - plain)
 
 
+def test_scattering_error_against_disc_series_decays_like_sqrt_h():
+    # the served problem (sound-soft disc r = 0.25 in [-1, 1]^2, outer data
+    # from the exact series) on a 65 x 65 grid, k = 2.5, M = 8192, FP32: the
+    # error of the mean of iterates 15-24 against the exact disc series is the
+    # O(sqrt h) bias of the once-per-step exit test at the square and at the
+    # circle, so it halves when h falls by four; Monte Carlo noise and the
+    # bilinear interpolation error stay well below it
+    errs = {}
+    for h in (4e-4, 1e-4):
+        p = W.scatter_problem(k=2.5, theta=0.7, N=65, M=8192, seed=61, precision=32, h=h, table_len=4096)
+        s = fkh.Solver(p)
+        acc = np.zeros((p.ny, p.nx), complex)
+        for it in range(24):
+            s.iterate(1)
+            if it >= 14:
+                acc += s.get()[0]
+        s.close()
+        ids = fkmc.interior_ids(p)
+        ex = W.exact_solution(p).ravel()[ids]
+        errs[h] = float(np.sqrt(np.mean(np.abs((acc / 10.0).ravel()[ids] - ex) ** 2)))
+    ratio = errs[4e-4] / errs[1e-4]
+    say("scattering 65: rms error vs disc series %.4f (h = 4e-4), %.4f (h = 1e-4), ratio %.2f"
+        % (errs[4e-4], errs[1e-4], ratio))
+    assert 1.6 < ratio < 2.5
+    assert errs[1e-4] < 0.05
+
+
 def test_largest_batch_rectangle_engine_fp32():
     # the largest-grid instance of the 256-rectangle batch (244 x 252) through
     # the FP32 engine, against the FP64 solver and the oracle
