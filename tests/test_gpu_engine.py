@@ -101,6 +101,23 @@ def test_engine_fp64_matches_oracle():
     e.close()
 
 
+def test_engine_fp64_second_iteration_matches_oracle():
+    # iteration 1 reads u_1 through the gather, in the kernel for the union
+    # of the launch's features (here all four: the mix plus a reflecting
+    # edge), against the oracle on the same u_1
+    probs = mix(64) + [W.annulus_shape1(k=1.5, n=13, M=64, h=1e-4, seed=31)]
+    e = engine(64)
+    slots = [e.add(p) for p in probs]
+    e.tick()
+    u1 = [e.get(sl)[0] for sl in slots]
+    e.tick()
+    for p, sl, u in zip(probs, slots, u1):
+        g, _ = e.get(sl)
+        orc = fkmc.fk_nodes(p, u, 1)
+        assert_fp64_node_parity(interior_values(p, g), orc["sumJ"], orc, p.M, label="engine it 1 " + p.name)
+    e.close()
+
+
 def test_engine_memory_admission():
     # a pool too small for two large instances admits one, then the next after removal
     p = W.cavity_65().replace(M=256)
