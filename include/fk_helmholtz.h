@@ -252,9 +252,9 @@ fk_status fk_helmholtz_set_iterate(fk_solver *s, const double *u_reim, int32_t n
  * with an absorbing edge, called after the first iteration or twice, no cut,
  * cuts not strictly increasing within [1, nx-2] / [1, ny-2], or a block
  * wider than 64 nodes (a second call is rejected even when the cuts left no
- * block).  Allocates its device tables (freed at destroy).  FK_EDEVICE
- * (allocation or copy failed): the solver is left as it was, with no
- * buffers of the call kept, and the call may be repeated. */
+ * block).  Allocates its device tables (freed at destroy).  FK_ENOMEM (the
+ * allocation failed) or FK_EDEVICE (a copy failed): the solver is left as it
+ * was, with no buffers of the call kept, and the call may be repeated. */
 fk_status fk_helmholtz_set_pdd(fk_solver *s, const int32_t *cuts_x, int32_t n_cuts_x, const int32_t *cuts_y,
                                int32_t n_cuts_y);
 
