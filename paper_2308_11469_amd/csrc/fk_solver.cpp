@@ -274,6 +274,16 @@ fk_status fk_helmholtz_set_pdd(fk_solver *s, const int32_t *cuts_x, int32_t n_cu
     // instance record and queue
     HostProblem P2 = s->P;
     P2.interior = iface;
+    if (P2.par.paths_per_item == 0) {
+        // far fewer nodes than the grid: smaller items, at least two per
+        // persistent wave of the default launch (the bench cavity with lines
+        // 16, 32, 48: 128 paths per item 4.5% faster than 256; results do not
+        // depend on the item size)
+        int64_t ppi = P2.ppi;
+        while (ppi > 64 && (int64_t)iface.size() * ((P2.par.M + ppi - 1) / ppi) < 8192) ppi /= 2;
+        P2.ppi = (int32_t)ppi;
+        P2.items_per_node = (int32_t)((P2.par.M + ppi - 1) / ppi);
+    }
     P2.n_items = (int64_t)iface.size() * P2.items_per_node;
     fkd::Inst D = make_inst(P2, s->B);
     fkd::EngineQueue q;
