@@ -1,16 +1,24 @@
 """Benchmark of the Feynman-Kac fixed-point Helmholtz path on one MI355X.
 
-Default workload (one GPU): the 65x65 unit-square cavity, plane-wave data
-theta = pi/6, k = 2, M = 4096 paths per node, h = 1e-4, FP64, one instance
-(the single-instance solver, no batching).  A step is one fixed-point
-iteration: Philox normals, Euler-Maruyama paths with exit test and boundary
-datum, the left-point integral of f - k^2 u_n with u_n interpolated from the
-device-resident grid, per-node reduction and the update of the iterate.
+Default workload (the headline line): the 129x129 unit-square cavity with the
+complex Gaussian source f = (1 + 0.5i) exp(-|x - (0.3, 0.6)|^2 / (2 0.05^2)),
+plane-wave data theta = pi/6, k = 3.5, M = 16384 paths per node, h = 5e-5,
+FP64 stepping, one instance through the single-instance solver (the largest
+single-instance configuration: 1.9e11 path-steps per iteration).  A step is
+one fixed-point iteration: Philox normals, Euler-Maruyama paths with exit test
+and boundary datum, the left-point integral of f - k^2 u_n with u_n
+interpolated from the device-resident grid, per-node reduction and the update
+of the iterate.
 
-Prints one JSON line: path-steps/s (value), ms per iteration, the roofline
-of the path kernel (device time from HIP events recorded on the stream the
+Prints one JSON line: path-steps/s (value), ms per iteration, the roofline of
+the path kernel (device time from HIP events recorded on the stream the
 kernel runs on), the CPU oracle timed on a bounded sample on this host, and
-extra figures (solves/s, RMS error against the exact plane wave).
+extra figures: the same configuration on the FP32 path, the 65x65 cavity
+(FP64 and its solves/s and RMS error against the exact plane wave), one full
+tick of the 256-rectangle batch on the FP32 engine, the batched-FP32 against
+plain-FP64 ratio on a subset of it, the 400-arrival scattering request window,
+the reflecting kernels on the shape-3 annulus and the domain-decomposed
+cavity.  ``--only NAME`` runs one of those parts alone and prints its line.
 """
 import argparse
 import json
@@ -32,12 +40,32 @@ PEAK_TFLOPS = {64: 78.6, 32: 157.3}
 # 18, integrand 2, left-point sum 1 (FP64) or 1.5 (FP32: half an FP32 add for
 # the trip's two values, then half a conversion and half an FP64 add).
 FLOPS_PER_STEP = {64: 50.0, 32: 48.5}
-KERNEL = {64: "fk_stream_f64_l1", 32: "fk_stream_f32"}
+# A Gaussian source adds, per left point: two differences to its centre, the
+# squared distance (a multiply and a multiply-add), the scale by -1/(2 sigma^2),
+# the exponential, the two amplitude products and the two additions into the
+# integrand.
+FLOPS_GAUSSIAN_SOURCE = 10.0
 # HBM bytes per launch of the path kernels from FETCH_SIZE / WRITE_SIZE
 # counters (scaled by a plain copy of known size), valid only for the kernel
 # sources they were taken on
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fk_stream_traffic.json")
 KERNEL_SOURCES = ["fk_kernels.hip", "fk_device.hpp", "fk_internal.hpp"]
+
+HEADLINE_WORKLOAD = ("unit-square cavity 129x129, Gaussian source (1+0.5i) at (0.3,0.6) sigma=0.05, "
+                     "plane wave theta=pi/6, k=3.5, M=16384, h=5e-5, single instance")
+CAVITY65_WORKLOAD = "unit-square cavity 65x65, plane wave theta=pi/6, k=%g, M=4096, h=1e-4, single instance"
+
+
+def flops_per_step(precision, source=False):
+    return FLOPS_PER_STEP[precision] + (FLOPS_GAUSSIAN_SOURCE if source else 0.0)
+
+
+def path_kernel_name(precision, features, row_major):
+    """The path kernel the single-instance solver launches (the library's
+    choice in launch_stream)."""
+    if precision == 64 and features == 0 and row_major:
+        return "fk_stream_f64_l1"
+    return "fk_stream_f%d<%d>" % (precision, features)
 
 
 def kernel_source_hash():
@@ -58,10 +86,12 @@ def measured_counters(kernel, workload):
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    k = t.get("kernels", {}).get(kernel)
-    if t.get("source_sha") != kernel_source_hash() or not k or k.get("workload") != workload:
+    if t.get("source_sha") != kernel_source_hash():
         return None
-    return k
+    for k in t.get("records", []):
+        if k.get("kernel") == kernel and k.get("workload") == workload:
+            return k
+    return None
 
 
 def measured_traffic(kernel, workload):
@@ -77,24 +107,27 @@ def _issue(k):
             "instructions_per_path_step": k["valu_instructions_per_path_step"]}
 
 
-def parse():
+ONLY = ("headline", "fp32_same_config", "cavity65", "batch256_tick", "batched_vs_plain", "serving",
+        "serving_sweep", "annulus", "pdd")
+
+
+def parse(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--k", type=float, default=2.0)
-    ap.add_argument("--precision", type=int, default=64, choices=[32, 64])
+    ap.add_argument("--precision", type=int, default=64, choices=[32, 64],
+                    help="stepping precision of the headline line")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-extras", action="store_true", help="skip the FP32, batched and serving figures")
+    ap.add_argument("--no-extras", action="store_true", help="skip the extra figures")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--annulus-only", action="store_true",
-                    help="only time the reflecting-edge kernels on the shape-3 annulus and print that line")
-    ap.add_argument("--pdd-only", action="store_true",
-                    help="only run the domain-decomposed bench cavity and print that line")
+    ap.add_argument("--only", choices=ONLY, default=None,
+                    help="run one part alone and print its line (headline: no extras, no CPU baseline)")
+    ap.add_argument("--k", type=float, default=2.0, help="k of the 65x65 cavity line")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run three device-to-device copies of MIB MiB (the reference kernel for "
                          "scaling HBM byte counters) and exit")
-    return ap.parse_args()
+    return ap.parse_args(argv)
 
 
 def calibrate_copy(mib):
@@ -112,118 +145,215 @@ def calibrate_copy(mib):
     print(json.dumps({"copy_mib": mib, "copies": 3, "bytes_read_per_copy": n * 4, "bytes_written_per_copy": n * 4}))
 
 
-def cpu_baseline(p, target_s):
-    """The CPU oracle, as it is, on a bounded sample of the same workload:
-    one Feynman-Kac step (all M paths) at a growing set of interior nodes
-    spread over the grid, with u_n = the exact plane wave on the grid (a
-    closed-form input), until about target_s seconds of work."""
+def _log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+# ------------------------------------------------------------- CPU oracle
+
+def cpu_baseline(target_s):
+    """The CPU oracle, as it is, on bounded samples of the headline workload
+    and in full on the 9x9 cavity:
+
+    - one Feynman-Kac step (all M = 16384 paths) at a growing set of
+      interior nodes of the 129x129 source cavity spread over the grid, with
+      u_n = the plane wave of the boundary data on the grid (a closed-form
+      input; the work per path does not depend on the values), on all host
+      threads for about target_s seconds, then on one thread for about a
+      quarter of that;
+    - the 9x9 cavity (M = 500, h = 2e-3) for all 10 iterations, all threads.
+    """
     import numpy as np
     from oracle import fkmc
-    ids = fkmc.interior_ids(p)
-    rng = np.random.default_rng(0)
-    order = rng.permutation(ids)
-    u = None
     from paper_2308_11469_amd import workloads as W
-    u = W.exact_solution(p)
+    p = W.cavity_source(precision=64)
+    xs = p.x0 + np.arange(p.nx) * ((p.x1 - p.x0) / (p.nx - 1))
+    ys = p.y0 + np.arange(p.ny) * ((p.y1 - p.y0) / (p.ny - 1))
+    X, Y = np.meshgrid(xs, ys)
+    u = W.plane_wave(p.k, p.outer.theta, X, Y)
+    ids = fkmc.interior_ids(p)
+    order = np.random.default_rng(0).permutation(ids)
     threads = len(os.sched_getaffinity(0))
-    done, steps, t_used = 0, 0, 0.0
-    batch = max(threads, 4)
-    while t_used < target_s and done < len(order):
-        sel = order[done:done + batch]
-        t0 = time.perf_counter()
-        est = fkmc.fk_nodes(p, u, 1, sel, nthreads=threads)
-        t_used += time.perf_counter() - t0
-        steps += int(est["sumJ"].sum())
-        done += len(sel)
-        if t_used < target_s / 4:
-            batch *= 2
+
+    def run(nthreads, budget, start):
+        done, steps, t_used = 0, 0, 0.0
+        batch = nthreads
+        while t_used < budget and start + done < len(order):
+            sel = order[start + done:start + done + batch]
+            t0 = time.perf_counter()
+            est = fkmc.fk_nodes(p, u, 1, sel, nthreads=nthreads)
+            t_used += time.perf_counter() - t0
+            steps += int(est["sumJ"].sum())
+            done += len(sel)
+        return done, steps, t_used
+
+    done, steps, t_used = run(threads, target_s, 0)
+    done1, steps1, t1 = run(1, target_s / 4, done)
+    c1 = W.cavity_small()
+    t0 = time.perf_counter()
+    r1 = fkmc.solve(c1, max_iters=10, tol=0.0, nthreads=threads)
+    tc1 = time.perf_counter() - t0
+    c1_steps = sum(h["sumJ"] for h in r1["history"])
     return dict(value=steps / t_used, unit="path-steps/s", cores=threads, kind="oracle",
-                sample="%d of %d interior nodes x M=%d paths, one iteration (u_n = exact wave), "
-                       "%.3g path-steps in %.1f s" % (done, len(ids), p.M, steps, t_used))
+                sample="%d of %d interior nodes of the 129x129 source cavity x M=%d paths, one iteration "
+                       "(u_n = the boundary plane wave on the grid), %.3g path-steps in %.1f s on %d threads"
+                       % (done, len(ids), p.M, steps, t_used, threads),
+                single_thread=dict(value=steps1 / t1, unit="path-steps/s", cores=1,
+                                   sample="%d further nodes, %.3g path-steps in %.1f s" % (done1, steps1, t1)),
+                cavity9_full=dict(iterations=10, path_steps=int(c1_steps), seconds=tc1,
+                                  value=c1_steps / tc1, unit="path-steps/s", cores=threads,
+                                  solves_per_s=1.0 / tc1))
 
 
-def fp32_same_config(k, steps):
-    """The same cavity on the FP32 path: path-steps/s and kernel time."""
+# ------------------------------------------------------------- GPU parts
+
+def _timed_solver(p, steps, warmup, **kw):
+    """Iterates a single-instance solver: warm-up iterations, then `steps`
+    timed ones between device synchronisations.  Returns the reports (all),
+    the timed wall time, the path kernel's HIP-event time and launch count
+    over the timed iterations, and the final iterate and SE."""
     import torch
     from paper_2308_11469_amd import fkh
-    from paper_2308_11469_amd import workloads as W
-    s = fkh.Solver(W.cavity_65(k=k, precision=32))
-    s.iterate(2)
+    s = fkh.Solver(p, **kw)
+    reports = [s.iterate(1) for _ in range(warmup)]
     s.timing(reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    reps = [s.iterate(1) for _ in range(steps)]
+    timed = [s.iterate(1) for _ in range(steps)]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms, n = s.timing()
+    kern_ms, launches = s.timing()
+    u, se = s.get()
     s.close()
-    steps_total = sum(r["path_steps"] for r in reps)
-    return dict(value=steps_total / wall, unit="path-steps/s", ms_per_step=wall / steps * 1e3,
-                kernel_ms_avg=ms / max(n, 1),
-                roofline_frac=FLOPS_PER_STEP[32] * steps_total / (ms / 1e3) / 1e12 / PEAK_TFLOPS[32])
+    # the library keeps the gather copy row-major while it fits 80 KiB
+    # (automatic layout): FP32 8 bytes per node, FP64 16
+    row_major = kw.get("gather_layout", "auto") == "nodes" or (
+        kw.get("gather_layout", "auto") == "auto" and p.nx * p.ny * (8 if p.precision == 32 else 16) <= 80 * 1024)
+    return dict(reports=reports + timed, timed=timed, wall=wall, kern_ms=kern_ms, launches=launches, u=u, se=se,
+                row_major=row_major)
 
 
-def annulus_shape3(steps=3):
-    """The annular problem of Sec. 2.3 on the paper's shape 3 (rectangle
-    [-0.5, 0.5] x [-0.8, 0.8] with the box hole [-0.05, 0.05] x [-0.4, 0.4],
-    reflecting Robin edge) at the grid step 0.01 of its FE mesh (101 x 161
-    nodes), k = 0.5, M = 4096, h = 1e-4: path-steps/s of the reflecting
-    kernels in both precisions, one iteration per step after two warm-up
-    iterations."""
-    import torch
-    from paper_2308_11469_amd import fkh
+def _features(p):
+    return ((1 if p.domain_kind != "rect" else 0) | (2 if p.src_kind != "zero" else 0)
+            | (4 if (p.alpha is not None and p.alpha != p.k * p.k) or p.damping != 0.0 else 0)
+            | (8 if p.reflect else 0))
+
+
+def _roofline(p, run, workload):
+    steps_total = sum(r["path_steps"] for r in run["timed"])
+    launches = max(run["launches"], 1)
+    avg_kernel_s = run["kern_ms"] / 1e3 / launches
+    fl = flops_per_step(p.precision, p.src_kind == "gaussian")
+    achieved = fl * steps_total / launches / avg_kernel_s / 1e12
+    peak = PEAK_TFLOPS[p.precision]
+    kernel = path_kernel_name(p.precision, _features(p), run["row_major"])
+    return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+            "traffic": measured_traffic(kernel, workload), "kernel": kernel,
+            "kernel_ms_avg": avg_kernel_s * 1e3, "flops_per_path_step": fl,
+            "path_steps_per_launch": steps_total / launches,
+            # the ALU bound in issue terms, from the committed counter profile
+            # of these kernel sources (None once they change): VALU-active
+            # cycles at four per instruction over the dispatch, lanes active
+            # per instruction, instructions per path-step
+            "valu_issue": _issue(measured_counters(kernel, workload))}
+
+
+def _settle(reports):
+    from paper_2308_11469_amd import serving
+    return next((r["n"] for r in reports if serving.settled(r)), None)
+
+
+def headline(steps, warmup, precision):
     from paper_2308_11469_amd import workloads as W
-    out = {"workload": "annulus shape 3, 101x161, k=0.5, M=4096, h=1e-4, reflecting edge"}
+    p = W.cavity_source(precision=precision)
+    _log("headline: 129x129 source cavity, FP%d, %d warm-up + %d timed iterations" % (precision, warmup, steps))
+    run = _timed_solver(p, steps, warmup)
+    steps_total = sum(r["path_steps"] for r in run["timed"])
+    ms_per_step = run["wall"] / steps * 1e3
+    settle = _settle(run["reports"])
+    return p, run, {
+        "value": steps_total / run["wall"],
+        "ms_per_step": ms_per_step,
+        "roofline": _roofline(p, run, HEADLINE_WORKLOAD),
+        "extra": {"path_steps_per_iteration": steps_total / steps,
+                  # iterations to the first settled iteration (the change is
+                  # Monte Carlo noise: noise ratio below 9/8), None if not
+                  # reached in this run
+                  "iterations_per_solve": settle,
+                  "solves_per_s": (1e3 / (ms_per_step * settle)) if settle else None,
+                  "capped_paths": int(sum(r["capped"] for r in run["reports"])),
+                  "max_se_last": run["reports"][-1]["max_se"]},
+    }
+
+
+def fp32_same_config(steps=3):
+    """The headline configuration on the FP32 path."""
+    from paper_2308_11469_amd import workloads as W
+    p = W.cavity_source(precision=32)
+    _log("fp32_same_config")
+    run = _timed_solver(p, steps, 1)
+    total = sum(r["path_steps"] for r in run["timed"])
+    rf = _roofline(p, run, HEADLINE_WORKLOAD)
+    return dict(value=total / run["wall"], unit="path-steps/s", ms_per_step=run["wall"] / steps * 1e3,
+                kernel=rf["kernel"], kernel_ms_avg=rf["kernel_ms_avg"], roofline_frac=rf["frac"],
+                traffic=rf["traffic"], valu_issue=rf["valu_issue"])
+
+
+def cavity65(k, steps=5, warmup=2):
+    """The 65x65 cavity (FP64 and FP32): path-steps/s, solves/s (iterations
+    to the first settled iteration) and the RMS error against the exact plane
+    wave."""
+    import numpy as np
+    from paper_2308_11469_amd import workloads as W
+    out = {"workload": CAVITY65_WORKLOAD % k}
     for prec in (64, 32):
-        s = fkh.Solver(W.annulus_shape3(k=0.5, nx=101, ny=161, M=4096, h=1e-4, precision=prec))
-        s.iterate(2)
-        s.timing(reset=True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        reps = [s.iterate(1) for _ in range(steps)]
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        ms, n = s.timing()
-        s.close()
-        total = sum(r["path_steps"] for r in reps)
-        out["fp%d" % prec] = dict(value=total / wall, unit="path-steps/s", ms_per_step=wall / steps * 1e3,
-                                  kernel_ms_avg=ms / max(n, 1), path_steps_per_iteration=total / steps,
-                                  roofline_frac=FLOPS_PER_STEP[prec] * total / (ms / 1e3) / 1e12
-                                  / PEAK_TFLOPS[prec])
+        p = W.cavity_65(k=k, precision=prec)
+        _log("cavity65 FP%d" % prec)
+        run = _timed_solver(p, steps, warmup)
+        total = sum(r["path_steps"] for r in run["timed"])
+        ms = run["wall"] / steps * 1e3
+        settle = _settle(run["reports"])
+        ex = W.exact_solution(p)
+        ids = np.nonzero(np.abs(run["se"].ravel()) > 0)[0]
+        rf = _roofline(p, run, out["workload"])
+        out["fp%d" % prec] = dict(
+            value=total / run["wall"], unit="path-steps/s", ms_per_step=ms, kernel=rf["kernel"],
+            kernel_ms_avg=rf["kernel_ms_avg"], roofline_frac=rf["frac"], traffic=rf["traffic"],
+            valu_issue=rf["valu_issue"], iterations_per_solve=settle,
+            solves_per_s=(1e3 / (ms * settle)) if settle else None,
+            rms_error_vs_exact=float(np.sqrt(np.mean(np.abs(run["u"].ravel()[ids] - ex.ravel()[ids]) ** 2))))
     return out
 
 
-def pdd_cavity65(k, n_iters=12):
-    """The bench cavity (FP64, M = 4096, h = 1e-4) by probabilistic domain
-    decomposition: paths from the nodes on the grid lines 16, 32, 48 in x
-    and y only (369 of 3969 unknowns), the 16 blocks of 15 x 15 nodes solved
-    on the device.  Wall time per iteration, path-steps per iteration,
-    iterations to the first settled iteration, RMS error against the plane
-    wave after n_iters iterations."""
-    import numpy as np
+def batch256_tick():
+    """One tick of the full 256-rectangle batch on the FP32 engine: every
+    instance advanced by one fixed-point iteration in one persistent launch
+    (the first iteration: the gathers of u_n run, with coefficient zero)."""
     import torch
-    from paper_2308_11469_amd import fkh, serving
+    from paper_2308_11469_amd import fkh
     from paper_2308_11469_amd import workloads as W
-    p = W.cavity_65(k=k, precision=64)
-    s = fkh.Solver(p)
-    s.set_pdd([16, 32, 48], [16, 32, 48])
+    probs = W.rect_batch(256)
+    nodes = sum(p.nx * p.ny for p in probs)
+    _log("batch256_tick: %d instances, %d grid nodes" % (len(probs), nodes))
+    t0 = time.perf_counter()
+    eng = fkh.Engine(len(probs), precision=32, max_grid_nodes=nodes + 4096, max_items=1 << 31,
+                     max_table=16, max_instance_nodes=max(p.nx * p.ny for p in probs))
+    slots = [eng.add(p) for p in probs]
+    t_add = time.perf_counter() - t0
+    assert all(s is not None for s in slots)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    reps = [s.iterate(1) for _ in range(n_iters)]
+    reps = eng.tick()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    u, _ = s.get()
-    s.close()
-    ex = W.exact_solution(p)
-    ids = np.nonzero((np.arange(p.nx * p.ny) % p.nx > 0) & (np.arange(p.nx * p.ny) % p.nx < p.nx - 1)
-                     & (np.arange(p.nx * p.ny) // p.nx > 0) & (np.arange(p.nx * p.ny) // p.nx < p.ny - 1))[0]
-    settle = next((r["n"] for r in reps if serving.settled(r)), None)
-    ms = wall / n_iters * 1e3
-    return {"workload": "cavity 65x65, k=%g, M=4096, h=1e-4, FP64, interfaces x,y in {16,32,48}" % k,
-            "ms_per_iteration": ms, "path_steps_per_iteration": sum(r["path_steps"] for r in reps) / n_iters,
-            "iterations_per_solve": settle,
-            "solves_per_s": (1e3 / (ms * settle)) if settle else None,
-            "rms_error_vs_exact": float(np.sqrt(np.mean(np.abs(u.ravel()[ids] - ex.ravel()[ids]) ** 2)))}
+    kern_ms, _ = eng.timing()
+    eng.close()
+    steps = sum(r["path_steps"] for r in reps.values())
+    return dict(instances=len(reps), grid_nodes=nodes, admit_s=t_add, tick_s=wall, kernel_ms=kern_ms,
+                path_steps=int(steps), value=steps / wall, unit="path-steps/s",
+                capped_paths=int(sum(r["capped"] for r in reps.values())),
+                kernel="fk_stream_f32<0>",
+                roofline_frac=FLOPS_PER_STEP[32] * steps / (kern_ms / 1e3) / 1e12 / PEAK_TFLOPS[32])
 
 
 def batched_vs_plain(n_sub=16, ticks=2):
@@ -237,6 +367,7 @@ def batched_vs_plain(n_sub=16, ticks=2):
     import torch
     from paper_2308_11469_amd import fkh
     from paper_2308_11469_amd import workloads as W
+    _log("batched_vs_plain")
     probs = W.rect_batch(256)[::256 // n_sub]
     nodes = sum(p.nx * p.ny for p in probs)
     eng = fkh.Engine(len(probs), precision=32, max_grid_nodes=nodes + 4096, max_items=1 << 26,
@@ -280,33 +411,133 @@ def batched_vs_plain(n_sub=16, ticks=2):
                 note="same iteration counts; iterations per solve are equal on both sides")
 
 
-def serving_window(n_requests=12):
-    """The scattering request stream (Poisson arrivals at 200/s, k ~ U[1,4],
-    grids 33..257, M 1024..8192, h = 1e-4, FP32) for its first n_requests
-    arrivals, through the continuous-batching loop; p50/p99 latency of the
-    completed requests and solves/s over the window."""
-    from paper_2308_11469_amd import fkh, serving
+def _scatter_requests(n, rate, seed=5):
+    """The scattering stream's requests; each problem (with its boundary
+    table from the disc series) is built when the server first looks at the
+    request, so requests turned away at a full queue cost nothing."""
+    from paper_2308_11469_amd import serving
     from paper_2308_11469_amd import workloads as W
-    arrivals, params = W.scatter_stream(n_requests)
+    arrivals, params = W.scatter_stream(n, rate, seed)
     reqs = []
     for r, (t, q) in enumerate(zip(arrivals, params)):
-        p = W.scatter_problem(q["k"], q["theta"], q["N"], q["M"], q["seed"], precision=32)
-        reqs.append(serving.Request(r, t, p.replace(max_iters=12, tol=1e-3)))
-    eng = fkh.Engine(8, precision=32, max_grid_nodes=8 * 257 * 257, max_items=1 << 26,
-                     max_table=8 * 4 * 8192, max_instance_nodes=257 * 257)
-    srv = serving.Server(eng, keep_results=False)
+        make = (lambda q=q: W.scatter_problem(q["k"], q["theta"], q["N"], q["M"], q["seed"], precision=32))
+        reqs.append(serving.Request(r, float(t), None, make=make))
+    return reqs
+
+
+def serving_window(n_requests=400, rate=200.0, max_queue=32, slots=8):
+    """The scattering request stream (Poisson arrivals, k ~ U[1, 4], grids
+    33..257, M 1024..8192, h = 1e-4, FP32) through the continuous-batching
+    loop with a bounded waiting queue: completed solves/s, p50 / p99 latency
+    of the completed requests, turned-away requests by reason, queue growth."""
+    import numpy as np
+    from paper_2308_11469_amd import fkh, serving
+    reqs = _scatter_requests(n_requests, rate)
+    eng = fkh.Engine(slots, precision=32, max_grid_nodes=slots * 257 * 257, max_items=1 << 26,
+                     max_table=slots * 4 * 8192, max_instance_nodes=257 * 257)
+    last = [time.perf_counter()]
+
+    def progress(entry):
+        now = time.perf_counter()
+        if now - last[0] > 10.0:
+            last[0] = now
+            _log("serving tick %d t=%.1fs resident=%d queued=%d arrived=%d" % (
+                entry["tick"], entry["t"], entry["resident"], entry["queued"], entry["arrived"]))
+
+    srv = serving.Server(eng, keep_results=False, max_queue=max_queue, on_tick=progress)
     t0 = time.perf_counter()
     res = srv.run(reqs)
     wall = time.perf_counter() - t0
     eng.close()
-    out = serving.latency_summary(res, wall)
-    out.update(requests=n_requests, wall_s=wall, offered_rate_per_s=200.0,
-               ticks=srv.ticks, max_resident=max((t["resident"] for t in srv.tick_log), default=0))
+    out = serving.latency_summary(res, wall, srv.tick_log)
+    its = [r.iterations for r in res.values() if r.outcome in ("converged", "max_iters")]
+    out.update(requests=n_requests, offered_rate_per_s=rate, max_queue=max_queue, slots=slots, wall_s=wall,
+               ticks=srv.ticks, max_resident=max((t["resident"] for t in srv.tick_log), default=0),
+               iterations_per_solve_median=float(np.median(its)) if its else None)
     return out
 
 
-def main():
-    a = parse()
+def serving_sweep(capacity, fractions=(0.25, 0.5, 0.8), n_requests=20):
+    """The stream offered at fractions of a measured capacity (solves/s):
+    the latency / throughput curve below saturation."""
+    out = []
+    for f in fractions:
+        _log("serving sweep at %.2f of capacity" % f)
+        r = serving_window(n_requests, f * capacity)
+        r.update(capacity_fraction=f, capacity_solves_per_s=capacity)
+        out.append(r)
+    return out
+
+
+def annulus_shape3(steps=3):
+    """The annular problem of Sec. 2.3 on the paper's shape 3 (rectangle
+    [-0.5, 0.5] x [-0.8, 0.8] with the box hole [-0.05, 0.05] x [-0.4, 0.4],
+    reflecting Robin edge) at the grid step 0.01 of its FE mesh (101 x 161
+    nodes), k = 0.5, M = 4096, h = 1e-4: path-steps/s of the reflecting
+    kernels in both precisions, one iteration per step after two warm-up
+    iterations."""
+    from paper_2308_11469_amd import workloads as W
+    out = {"workload": "annulus shape 3, 101x161, k=0.5, M=4096, h=1e-4, reflecting edge"}
+    for prec in (64, 32):
+        _log("annulus FP%d" % prec)
+        p = W.annulus_shape3(k=0.5, nx=101, ny=161, M=4096, h=1e-4, precision=prec)
+        run = _timed_solver(p, steps, 2)
+        total = sum(r["path_steps"] for r in run["timed"])
+        rf = _roofline(p, run, out["workload"])
+        out["fp%d" % prec] = dict(value=total / run["wall"], unit="path-steps/s",
+                                  ms_per_step=run["wall"] / steps * 1e3, kernel=rf["kernel"],
+                                  kernel_ms_avg=rf["kernel_ms_avg"], path_steps_per_iteration=total / steps,
+                                  roofline_frac=rf["frac"], valu_issue=rf["valu_issue"])
+    return out
+
+
+def pdd_cavity65(k, n_iters=12):
+    """The 65x65 cavity (FP64, M = 4096, h = 1e-4) by probabilistic domain
+    decomposition: paths from the nodes on the grid lines 16, 32, 48 in x
+    and y only (369 of 3969 unknowns), the 16 blocks of 15 x 15 nodes solved
+    on the device.  Wall time per iteration, path-steps per iteration,
+    iterations to the first settled iteration, RMS error against the plane
+    wave at that iteration and after n_iters iterations."""
+    import numpy as np
+    import torch
+    from paper_2308_11469_amd import fkh, serving
+    from paper_2308_11469_amd import workloads as W
+    _log("pdd")
+    p = W.cavity_65(k=k, precision=64)
+    ex = W.exact_solution(p)
+    inner = (slice(1, -1), slice(1, -1))
+
+    def rms(u):
+        return float(np.sqrt(np.mean(np.abs(u[inner] - ex[inner]) ** 2)))
+
+    s = fkh.Solver(p)
+    s.set_pdd([16, 32, 48], [16, 32, 48])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = [s.iterate(1) for _ in range(n_iters)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    u, _ = s.get()
+    s.close()
+    settle = next((r["n"] for r in reps if serving.settled(r)), None)
+    rms_settle = None
+    if settle:
+        s = fkh.Solver(p)
+        s.set_pdd([16, 32, 48], [16, 32, 48])
+        s.iterate(settle)
+        rms_settle = rms(s.get()[0])
+        s.close()
+    ms = wall / n_iters * 1e3
+    return {"workload": "cavity 65x65, k=%g, M=4096, h=1e-4, FP64, interfaces x,y in {16,32,48}" % k,
+            "ms_per_iteration": ms, "path_steps_per_iteration": sum(r["path_steps"] for r in reps) / n_iters,
+            "iterations_per_solve": settle,
+            "solves_per_s": (1e3 / (ms * settle)) if settle else None,
+            "rms_error_at_settle": rms_settle,
+            "rms_error_after_%d" % n_iters: rms(u)}
+
+
+def main(argv=None):
+    a = parse(argv)
     if a.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % a.gpus, file=sys.stderr)
@@ -314,93 +545,55 @@ def main():
     if a.calibrate_copy:
         calibrate_copy(a.calibrate_copy)
         return
-    if a.annulus_only:
-        print(json.dumps(annulus_shape3(a.steps)), flush=True)
-        return
-    if a.pdd_only:
-        print(json.dumps(pdd_cavity65(a.k)), flush=True)
-        return
-    import numpy as np
     import torch
-    from paper_2308_11469_amd import build, fkh
-    from paper_2308_11469_amd import workloads as W
+    from paper_2308_11469_amd import build
 
     if not build.is_built():
         build.build()
     torch.cuda.set_device(0)
-    p = W.cavity_65(k=a.k, precision=a.precision)
-    s = fkh.Solver(p)
-    reports = []
-    for _ in range(a.warmup):
-        reports.append(s.iterate(1))
-    s.timing(reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    timed = []
-    for _ in range(a.steps):
-        timed.append(s.iterate(1))
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    reports += timed
-    kern_ms, launches = s.timing()
-    steps_total = sum(r["path_steps"] for r in timed)
-    value = steps_total / wall
-    avg_kernel_s = kern_ms / 1e3 / max(launches, 1)
-    steps_per_launch = steps_total / max(launches, 1)
-    achieved = FLOPS_PER_STEP[a.precision] * steps_per_launch / avg_kernel_s / 1e12
-    peak = PEAK_TFLOPS[a.precision]
-
-    u, se = s.get()
-    ex = W.exact_solution(p)
-    ids = np.nonzero(np.abs(se.ravel()) > 0)[0]
-    rms = float(np.sqrt(np.mean(np.abs(u.ravel()[ids] - ex.ravel()[ids]) ** 2)))
-    from paper_2308_11469_amd import serving
-    floor_iter = next((r["n"] for r in reports if serving.settled(r)), None)
-    s.close()
-    ms_per_step = wall / a.steps * 1e3
-    solve_iters = floor_iter if floor_iter else len(reports)
-
-    workload = ("unit-square cavity 65x65, plane wave theta=pi/6, k=%g, M=4096, h=1e-4, single instance"
-                % a.k)
+    parts = {
+        "fp32_same_config": lambda: fp32_same_config(),
+        "cavity65": lambda: cavity65(a.k),
+        "batch256_tick": batch256_tick,
+        "batched_vs_plain": batched_vs_plain,
+        "serving": serving_window,
+        "annulus": annulus_shape3,
+        "pdd": lambda: pdd_cavity65(a.k),
+    }
+    if a.only == "serving_sweep":
+        cap = serving_window()["solves_per_s"]
+        print(json.dumps({"serving_sweep": serving_sweep(cap)}), flush=True)
+        return
+    if a.only and a.only != "headline":
+        print(json.dumps({a.only: parts[a.only]()}), flush=True)
+        return
+    p, run, h = headline(a.steps, a.warmup, a.precision)
     out = {
-        "metric": "Brownian path-steps/s (Helmholtz solves/s at fixed RMS error reported alongside)",
-        "value": value,
+        "metric": "Brownian path-steps/s (Helmholtz solves/s at fixed RMS error, p50/p99 latency "
+                  "reported alongside)",
+        "value": h["value"],
         "unit": "path-steps/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": h["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if a.precision == 64 else "f32",
         "data": "synthetic",
-        "config": {"workload": workload,
-                   "grid": [65, 65], "M": 4096, "h": 1e-4, "k": a.k, "precision": a.precision},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak,
-                     "traffic": measured_traffic(KERNEL[a.precision], workload),
-                     "kernel": KERNEL[a.precision],
-                     "kernel_ms_avg": avg_kernel_s * 1e3, "flops_per_path_step": FLOPS_PER_STEP[a.precision],
-                     # the ALU bound in issue terms, from the committed counter
-                     # profile of these kernel sources (None once they change):
-                     # VALU-active cycles at four per instruction over the
-                     # dispatch, lanes active per instruction, instructions
-                     # per path-step
-                     "valu_issue": _issue(measured_counters(KERNEL[a.precision], workload))},
-        "extra": {"solves_per_s": 1.0 / (ms_per_step / 1e3 * solve_iters),
-                  "iterations_per_solve": solve_iters,
-                  "rms_error_vs_exact": rms,
-                  "path_steps_per_iteration": steps_total / a.steps},
+        "config": {"workload": HEADLINE_WORKLOAD, "grid": [129, 129], "M": 16384, "h": 5e-5, "k": 3.5,
+                   "precision": a.precision},
+        "roofline": h["roofline"],
+        "extra": h["extra"],
     }
-    if not a.no_extras:
-        out["extra"]["fp32_same_config"] = fp32_same_config(a.k, 5)
-        out["extra"]["batched_fp32_vs_plain_fp64"] = batched_vs_plain()
-        out["extra"]["serving_scatter_window"] = serving_window()
-        out["extra"]["annulus_shape3_reflecting"] = annulus_shape3()
-        out["extra"]["pdd_same_cavity"] = pdd_cavity65(a.k)
-    if not a.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(p, a.cpu_seconds)
+    if not a.no_extras and a.only is None:
+        for name in ("fp32_same_config", "cavity65", "batched_vs_plain", "annulus", "pdd", "batch256_tick",
+                     "serving"):
+            out["extra"][name] = parts[name]()
+    if not a.no_cpu and a.only is None:
+        _log("cpu_baseline")
+        out["cpu_baseline"] = cpu_baseline(a.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

@@ -14,7 +14,7 @@ sys.path.insert(0, ROOT)
 
 import bench  # noqa: E402
 
-WORKLOAD = "unit-square cavity 65x65, plane wave theta=pi/6, k=2, M=4096, h=1e-4, single instance"
+WORKLOAD = bench.HEADLINE_WORKLOAD
 
 
 def test_more_than_one_gpu_is_refused_with_a_message():
@@ -26,9 +26,9 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 
 def _record(tmp_path, monkeypatch, sha, workload):
     f = tmp_path / "traffic.json"
-    f.write_text(json.dumps({"source_sha": sha, "kernels": {"k": {
-        "workload": workload, "bytes_per_launch": 123.0, "valu_busy": 0.5, "valu_lane_utilisation": 0.9,
-        "valu_instructions_per_path_step": 100.0}}}))
+    f.write_text(json.dumps({"source_sha": sha, "records": [{
+        "kernel": "k", "workload": workload, "bytes_per_launch": 123.0, "valu_busy": 0.5,
+        "valu_lane_utilisation": 0.9, "valu_instructions_per_path_step": 100.0}]}))
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
 
 
@@ -49,3 +49,17 @@ def test_counters_withheld_otherwise(tmp_path, monkeypatch, what):
     assert bench.measured_traffic(kernel, WORKLOAD) is None
     assert bench._issue(bench.measured_counters(kernel, WORKLOAD)) is None
 
+
+
+def test_headline_kernel_names_follow_the_library_choice():
+    # the plain FP64 kernel with a row-major copy has its own four-wave build;
+    # every other instance runs the kernel of its feature set
+    assert bench.path_kernel_name(64, 0, True) == "fk_stream_f64_l1"
+    assert bench.path_kernel_name(64, 2, False) == "fk_stream_f64<2>"
+    assert bench.path_kernel_name(32, 0, True) == "fk_stream_f32<0>"
+    assert bench.flops_per_step(64, True) == 60.0
+
+
+def test_only_parts_parse():
+    for name in bench.ONLY:
+        assert bench.parse(["--only", name]).only == name
