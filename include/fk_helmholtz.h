@@ -258,6 +258,32 @@ fk_status fk_helmholtz_set_iterate(fk_solver *s, const double *u_reim, int32_t n
 fk_status fk_helmholtz_set_pdd(fk_solver *s, const int32_t *cuts_x, int32_t n_cuts_x, const int32_t *cuts_y,
                                int32_t n_cuts_y);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one
+ * fixed-point iteration u_n -> u_{n+1} of the problem given by value, the same
+ * computation as fk_helmholtz_create + fk_helmholtz_set_iterate(u_n, n) +
+ * fk_helmholtz_iterate(1) + fk_helmholtz_get (bit-identical results), with
+ * every working buffer of the library in one static device array of
+ * FK_STATIC_SCRATCH_BYTES per GPU (held until the process ends): no device
+ * allocation, no pinned host memory, no events.
+ *   u_n     device, nx*ny complex (unknown nodes read; edge and hole nodes
+ *           take the problem's data), or NULL for u_0 = 0 (then n must be 0)
+ *   n       index of u_n (the Philox counter word of the iteration)
+ *   u_next  device, nx*ny complex: receives u_{n+1}; se: device or NULL,
+ *           nx*ny complex standard errors; report (host, may be NULL):
+ *           report->n = n + 1, step_ms = 0 (not timed).
+ * Ordered on hip_stream and synchronised before returning (host staging
+ * copies are made from pageable memory).  Every call on a GPU reuses that
+ * GPU's array, so calls that overlap on one GPU (other threads, other
+ * streams) race and must be serialised by the caller.  FK_EINVAL: as
+ * fk_helmholtz_create, or the problem needs more working memory than the
+ * array holds (about 212 bytes per grid node: every grid up to 257 x 257
+ * fits); FK_EDIVERGED: u_{n+1} is not finite (still written). */
+#define FK_STATIC_SCRATCH_BYTES (16u * 1024u * 1024u)
+fk_status fk_helmholtz_step_static(const fk_domain *domain, const fk_source *f, const fk_bc *g_outer,
+                                   const fk_bc *g_inner, const fk_params *params, const double *u_n, int32_t n,
+                                   double *u_next, double *se, void *hip_stream, fk_iter_report *report);
+
 /* Accumulated device time of the path kernel since creation or the last
  * reset (HIP events recorded on the solver's stream around each launch). */
 fk_status fk_helmholtz_timing(fk_solver *s, double *step_ms_total, int64_t *launches, int32_t reset);

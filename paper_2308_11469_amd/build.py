@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfk_helmholtz.so")
-SOURCES = ["fk_kernels.hip", "fk_problem.cpp", "fk_solver.cpp", "fk_engine.cpp"]
+SOURCES = ["fk_kernels.hip", "fk_problem.cpp", "fk_solver.cpp", "fk_engine.cpp", "fk_static.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("FK_OFFLOAD_ARCH", "gfx950")

@@ -473,4 +473,34 @@ fk_status upload_instance(const HostProblem &P, const InstanceBuffers &B, hipStr
     return FK_OK;
 }
 
+fk_status load_iterate(const HostProblem &P, const InstanceBuffers &B, const double *u_reim, int32_t n,
+                       bool on_device, hipStream_t s)
+{
+    const size_t nn = P.n_nodes();
+    std::vector<double> full(2 * nn);
+    if (on_device) {
+        FK_HIP(hipMemcpyAsync(full.data(), u_reim, nn * sizeof(double2), hipMemcpyDeviceToHost, s));
+        FK_HIP(hipStreamSynchronize(s));
+    } else {
+        std::memcpy(full.data(), u_reim, nn * sizeof(double2));
+    }
+    // boundary and hole nodes keep their data
+    for (size_t i = 0; i < nn; ++i)
+        if (P.cls[i] != 0) {
+            full[2 * i] = P.grid0[2 * i];
+            full[2 * i + 1] = P.grid0[2 * i + 1];
+        }
+    std::vector<uint8_t> gc;
+    gather_copy(P, full.data(), gc);
+    fkd::DevState st;
+    std::memset(&st, 0, sizeof(st));
+    st.iter = n;
+    st.use_u = 1;
+    FK_HIP(hipMemcpyAsync(B.u64, full.data(), nn * sizeof(double2), hipMemcpyHostToDevice, s));
+    if (!gc.empty()) FK_HIP(hipMemcpyAsync(B.gather, gc.data(), gc.size(), hipMemcpyHostToDevice, s));
+    FK_HIP(hipMemcpyAsync(B.state, &st, sizeof(st), hipMemcpyHostToDevice, s));
+    FK_HIP(hipStreamSynchronize(s));
+    return FK_OK;
+}
+
 }  // namespace fkh

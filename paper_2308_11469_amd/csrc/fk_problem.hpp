@@ -96,6 +96,13 @@ fk_status upload_instance(const HostProblem &P, const InstanceBuffers &B, hipStr
 // and layout.
 void gather_copy(const HostProblem &P, const double *grid, std::vector<uint8_t> &out);
 
+// Replaces the iterate on the unknown nodes by u_reim (nx*ny complex, host, or
+// device when on_device) and sets the iteration index to n (use_u = 1):
+// absorbing-edge and hole nodes keep the problem's data, the gather copy is
+// rebuilt from the FP64 values, the status record is cleared.  Synchronises s.
+fk_status load_iterate(const HostProblem &P, const InstanceBuffers &B, const double *u_reim, int32_t n,
+                       bool on_device, hipStream_t s);
+
 // Paths per work item when the caller leaves it to the library.
 int32_t auto_paths_per_item(int64_t n_interior, int64_t M);
 

@@ -376,30 +376,8 @@ fk_status fk_helmholtz_set_iterate(fk_solver *s, const double *u_reim, int32_t n
 {
     if (!s || !u_reim) return fail(FK_EINVAL, "solver and u_reim are required");
     if (n < 0) return fail(FK_EINVAL, "n must be >= 0");
-    const size_t nn = s->P.n_nodes();
-    std::vector<double> full(2 * nn);
-    if (on_device) {
-        FK_HIP(hipMemcpyAsync(full.data(), u_reim, nn * sizeof(double2), hipMemcpyDeviceToHost, s->stream));
-        FK_HIP(hipStreamSynchronize(s->stream));
-    } else {
-        std::memcpy(full.data(), u_reim, nn * sizeof(double2));
-    }
-    // boundary and hole nodes keep their data
-    for (size_t i = 0; i < nn; ++i)
-        if (s->P.cls[i] != 0) {
-            full[2 * i] = s->P.grid0[2 * i];
-            full[2 * i + 1] = s->P.grid0[2 * i + 1];
-        }
-    std::vector<uint8_t> gc;
-    gather_copy(s->P, full.data(), gc);
-    fkd::DevState st;
-    std::memset(&st, 0, sizeof(st));
-    st.iter = n;
-    st.use_u = 1;
-    FK_HIP(hipMemcpyAsync(s->B.u64, full.data(), nn * sizeof(double2), hipMemcpyHostToDevice, s->stream));
-    if (!gc.empty()) FK_HIP(hipMemcpyAsync(s->B.gather, gc.data(), gc.size(), hipMemcpyHostToDevice, s->stream));
-    FK_HIP(hipMemcpyAsync(s->B.state, &st, sizeof(st), hipMemcpyHostToDevice, s->stream));
-    FK_HIP(hipStreamSynchronize(s->stream));
+    const fk_status st = load_iterate(s->P, s->B, u_reim, n, on_device != 0, s->stream);
+    if (st != FK_OK) return st;
     s->iter = n;
     s->hist_du.clear();
     s->hist_sup.clear();

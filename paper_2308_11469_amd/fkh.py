@@ -81,7 +81,7 @@ class fk_engine_config(C.Structure):
 # every entry point of include/fk_helmholtz.h
 EXPORTS = ["fk_helmholtz_arena_bytes", "fk_helmholtz_create", "fk_helmholtz_iterate", "fk_helmholtz_solve",
            "fk_helmholtz_get", "fk_helmholtz_node_stats", "fk_helmholtz_set_iterate", "fk_helmholtz_set_pdd",
-           "fk_helmholtz_timing",
+           "fk_helmholtz_timing", "fk_helmholtz_step_static",
            "fk_helmholtz_destroy", "fk_helmholtz_last_error", "fk_debug_philox", "fk_debug_normals",
            "fk_helmholtz_debug_paths", "fk_engine_create", "fk_engine_add", "fk_engine_tick", "fk_engine_get",
            "fk_engine_remove", "fk_engine_timing", "fk_engine_destroy"]
@@ -115,6 +115,8 @@ def lib():
             "fk_helmholtz_set_iterate": [vp, vp, C.c_int32, C.c_int32],
             "fk_helmholtz_set_pdd": [vp, i32p, C.c_int32, i32p, C.c_int32],
             "fk_helmholtz_timing": [vp, dp, i64p, C.c_int32],
+            "fk_helmholtz_step_static": [P(fk_domain), P(fk_source), P(fk_bc), P(fk_bc), P(fk_params), vp,
+                                         C.c_int32, vp, vp, vp, P(fk_iter_report)],
             "fk_helmholtz_destroy": [vp],
             "fk_debug_philox": [C.c_uint64, u32p, C.c_int64, u32p],
             "fk_debug_normals": [C.c_int32, u32p, C.c_int64, dp],
@@ -318,6 +320,25 @@ class Solver:
                                               ms.ctypes.data_as(C.POINTER(C.c_int64)), n,
                                               J.ctypes.data_as(C.POINTER(C.c_int64)), _dptr(s), _dptr(x)))
         return J, s[0::2] + 1j * s[1::2], x.reshape(-1, 2)
+
+
+STATIC_SCRATCH_BYTES = 16 * 1024 * 1024   # FK_STATIC_SCRATCH_BYTES
+
+
+def step_static(problem, u_n, n, u_next, se=None, stream=None, paths_per_item=0, gather_layout="auto"):
+    """One fixed-point iteration without any device allocation in the library
+    (fk_helmholtz_step_static): u_n and u_next (and se) are device tensors of
+    nx * ny complex128 (or 2 nx ny float64) that the caller owns; u_n None
+    means u_0 = 0.  Returns the report; a non-finite iterate is reported as
+    ``diverging`` (not raised)."""
+    m = Marshalled(problem, paths_per_item, gather_layout)
+    r = fk_iter_report()
+    st = lib().fk_helmholtz_step_static(
+        *m.args(), C.c_void_p(u_n.data_ptr()) if u_n is not None else None, int(n),
+        C.c_void_p(u_next.data_ptr()), C.c_void_p(se.data_ptr()) if se is not None else None,
+        C.c_void_p(stream if stream is not None else current_stream_handle()), C.byref(r))
+    _check(st, allow=(FK_EDIVERGED,))
+    return r.as_dict()
 
 
 def debug_philox(seed, ctrs):
