@@ -15,8 +15,9 @@ the path kernel (device time from HIP events recorded on the stream the
 kernel runs on), the CPU oracle timed on a bounded sample on this host, and
 extra figures: the same configuration on the FP32 path, the 65x65 cavity
 (FP64 and its solves/s and RMS error against the exact plane wave), one full
-tick of the 256-rectangle batch on the FP32 engine, the batched-FP32 against
-plain-FP64 ratio on a subset of it, the 400-arrival scattering request window,
+tick of the 256-rectangle batch on the FP32 engine, served batched FP32
+solves/s (with and without the domain decomposition) against the plain FP64
+path on a subset of it, the 400-arrival scattering request window,
 the reflecting kernels on the shape-3 annulus and the domain-decomposed
 cavity.  ``--only NAME`` runs one of those parts alone and prints its line.
 """
@@ -107,7 +108,7 @@ def _issue(k):
             "instructions_per_path_step": k["valu_instructions_per_path_step"]}
 
 
-ONLY = ("headline", "fp32_same_config", "cavity65", "batch256_tick", "batched_vs_plain", "serving",
+ONLY = ("headline", "fp32_same_config", "cavity65", "batch256_tick", "served_vs_plain", "serving",
         "serving_sweep", "annulus", "pdd")
 
 
@@ -356,59 +357,72 @@ def batch256_tick():
                 roofline_frac=FLOPS_PER_STEP[32] * steps / (kern_ms / 1e3) / 1e12 / PEAK_TFLOPS[32])
 
 
-def batched_vs_plain(n_sub=16, ticks=2):
-    """Solves/s of the batched FP32 engine (one persistent launch per tick for
-    all instances) against the plain FP64 single-instance path (instances one
-    after another), on every 16th instance of the 256-rectangle workload, at
-    the same iterations (so the same estimator and RMS error up to FP32
-    rounding, which stays below 0.1 SE).  Timed: iterations 1..ticks after
-    the first (iteration 0 has no interpolation)."""
+def served_vs_plain(n_sub=16, spacing=32):
+    """Solves/s at the stopping rule (settled, max |du| < tol or max_iters) on
+    every 16th instance of the 256-rectangle workload:
+
+    - plain: the FP64 single-instance solver with paths from every unknown
+      node, the instances one after another;
+    - served: the same requests all arriving at once at the continuous-
+      batching loop over the FP32 engine (one persistent launch per tick),
+      with paths from every node, and with the probabilistic domain
+      decomposition (interface lines every `spacing` nodes, the blocks between
+      them solved on the device in the same tick; Sec. 3's two-stage
+      procedure).
+
+    RMS error of each result against the exact plane wave (mean over the
+    instances) beside each rate."""
     import numpy as np
     import torch
-    from paper_2308_11469_amd import fkh
+    from paper_2308_11469_amd import fkh, serving
     from paper_2308_11469_amd import workloads as W
-    _log("batched_vs_plain")
     probs = W.rect_batch(256)[::256 // n_sub]
     nodes = sum(p.nx * p.ny for p in probs)
-    eng = fkh.Engine(len(probs), precision=32, max_grid_nodes=nodes + 4096, max_items=1 << 26,
-                     max_table=16, max_instance_nodes=max(p.nx * p.ny for p in probs))
-    slots = [eng.add(p) for p in probs]
-    eng.tick()
+
+    def rms(p, u):
+        return float(np.sqrt(np.mean(np.abs(u - W.exact_solution(p))[1:-1, 1:-1] ** 2)))
+
+    _log("served_vs_plain: plain FP64")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    steps_b = 0
-    for _ in range(ticks):
-        reps = eng.tick()
-        steps_b += sum(r["path_steps"] for r in reps.values())
-    torch.cuda.synchronize()
-    t_batched = (time.perf_counter() - t0) / ticks
-    err_b = []
-    for p, sl in zip(probs, slots):
-        u, _ = eng.get(sl)
-        err_b.append(np.sqrt(np.mean(np.abs(u - W.exact_solution(p))[1:-1, 1:-1] ** 2)))
-    eng.close()
-    t_plain = 0.0
-    steps_p = 0
-    err_p = []
+    err_p, its_p = [], []
     for p in probs:
-        s = fkh.Solver(p.replace(precision=64))
-        s.iterate(1)
+        q = p.replace(precision=64)
+        s = fkh.Solver(q)
+        while True:
+            rep = s.iterate(1)
+            if rep["diverging"] or rep["max_du"] < q.tol or serving.settled(rep) or rep["n"] >= q.max_iters:
+                break
+        err_p.append(rms(q, s.get()[0]))
+        its_p.append(rep["n"])
+        s.close()
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    out = {"instances": len(probs), "pdd_spacing": spacing,
+           "plain_fp64": dict(wall_s=t_plain, solves_per_s=len(probs) / t_plain,
+                              rms_error=float(np.mean(err_p)), iterations_mean=float(np.mean(its_p)))}
+    for name, pdd in (("served_fp32", False), ("served_fp32_pdd", True)):
+        _log("served_vs_plain: %s" % name)
+        eng = fkh.Engine(len(probs), precision=32, max_grid_nodes=nodes + 4096, max_items=1 << 28,
+                         max_table=16, max_instance_nodes=max(p.nx * p.ny for p in probs))
+        reqs = [serving.Request(i, 0.0, p, pdd=(serving.grid_cuts(p.nx, spacing), serving.grid_cuts(p.ny, spacing))
+                                if pdd else None) for i, p in enumerate(probs)]
+        srv = serving.Server(eng, keep_results=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(ticks):
-            steps_p += s.iterate(1)["path_steps"]
-        torch.cuda.synchronize()
-        t_plain += (time.perf_counter() - t0) / ticks
-        u, _ = s.get()
-        err_p.append(np.sqrt(np.mean(np.abs(u - W.exact_solution(p))[1:-1, 1:-1] ** 2)))
-        s.close()
-    return dict(instances=len(probs), ticks_timed=ticks,
-                batched_fp32_s_per_iteration=t_batched, plain_fp64_s_per_iteration=t_plain,
-                solves_per_s_ratio=t_plain / t_batched,
-                batched_path_steps_per_s=steps_b / ticks / t_batched,
-                plain_path_steps_per_s=steps_p / ticks / t_plain,
-                rms_error_batched=float(np.mean(err_b)), rms_error_plain=float(np.mean(err_p)),
-                note="same iteration counts; iterations per solve are equal on both sides")
+        res = srv.run(reqs)
+        wall = time.perf_counter() - t0
+        eng.close()
+        done = [r for r in res.values() if r.outcome in ("converged", "max_iters", "diverged")]
+        out[name] = dict(wall_s=wall, solves_per_s=len(done) / wall, completed=len(done),
+                         rms_error=float(np.mean([rms(probs[r.rid], r.u) for r in done])),
+                         iterations_mean=float(np.mean([r.iterations for r in done])),
+                         path_steps=int(sum(r.path_steps for r in done)), ticks=srv.ticks)
+    out["ratio_served_fp32_vs_plain_fp64"] = out["served_fp32"]["solves_per_s"] / out["plain_fp64"]["solves_per_s"]
+    out["ratio_served_fp32_pdd_vs_plain_fp64"] = (out["served_fp32_pdd"]["solves_per_s"]
+                                                  / out["plain_fp64"]["solves_per_s"])
+    out["rms_ratio_pdd_vs_plain"] = out["served_fp32_pdd"]["rms_error"] / out["plain_fp64"]["rms_error"]
+    return out
 
 
 def _scatter_requests(n, rate, seed=5):
@@ -555,7 +569,7 @@ def main(argv=None):
         "fp32_same_config": lambda: fp32_same_config(),
         "cavity65": lambda: cavity65(a.k),
         "batch256_tick": batch256_tick,
-        "batched_vs_plain": batched_vs_plain,
+        "served_vs_plain": served_vs_plain,
         "serving": serving_window,
         "annulus": annulus_shape3,
         "pdd": lambda: pdd_cavity65(a.k),
@@ -588,7 +602,7 @@ def main(argv=None):
         "extra": h["extra"],
     }
     if not a.no_extras and a.only is None:
-        for name in ("fp32_same_config", "cavity65", "batched_vs_plain", "annulus", "pdd", "batch256_tick",
+        for name in ("fp32_same_config", "cavity65", "served_vs_plain", "annulus", "pdd", "batch256_tick",
                      "serving"):
             out["extra"][name] = parts[name]()
     if not a.no_cpu and a.only is None:

@@ -66,7 +66,9 @@ typedef enum {
     FK_EDEVICE = 3,        /* a HIP runtime call failed                       */
     FK_EDIVERGED = 4,      /* divergence rule fired (result still readable)   */
     FK_ENOTCONVERGED = 5,  /* max_iters reached above tol (result readable)   */
-    FK_EBUSY = 6           /* engine: no free slot                            */
+    FK_EBUSY = 6,          /* engine: no free slot                            */
+    FK_ECANCELLED = 7      /* fk_helmholtz_cancel stopped the call (result
+                              readable: the last completed iterate)       */
 } fk_status;
 
 /* Omega: the open rectangle (x0,x1) x (y0,y1); for RECT_MINUS_DISC also
@@ -223,6 +225,16 @@ fk_status fk_helmholtz_iterate(fk_solver *s, int32_t n_iters, fk_iter_report *la
  * sup-norm control).  FK_ENOTCONVERGED if tol > 0 was not reached. */
 fk_status fk_helmholtz_solve(fk_solver *s, fk_iter_report *final_report);
 
+/* Asks the fk_helmholtz_iterate or fk_helmholtz_solve call running on s (in
+ * another thread), or else the next such call, to stop before its next
+ * iteration: that call returns FK_ECANCELLED with the report of the last
+ * completed iteration, the iterate stays readable and a later call resumes
+ * the run (the same results as without the stop: the random numbers depend
+ * only on the iteration index).  The request is taken by that one call.  The
+ * only entry point that may be called concurrently with others on the same
+ * handle (not with or after fk_helmholtz_destroy). */
+fk_status fk_helmholtz_cancel(fk_solver *s);
+
 /* Copies the current iterate u_n (nx*ny complex) and, if se_reim is not NULL,
  * the per-node standard errors (SE_re, SE_im; 0 on nodes that are not
  * unknowns) of the last iteration.  on_device != 0: the pointers are device pointers. */
@@ -348,6 +360,25 @@ fk_status fk_engine_tick(fk_engine *e, fk_iter_report *reports, uint8_t *active_
 
 /* Copies the iterate and SE of a slot (host pointers, nx*ny complex each). */
 fk_status fk_engine_get(fk_engine *e, int32_t slot, double *u_reim, double *se_reim);
+
+/* Per-node sum of exit-step indices and capped-path counts of the slot's last
+ * iteration (nx*ny each, host pointers; 0 on nodes that are not unknowns). */
+fk_status fk_engine_node_stats(fk_engine *e, int32_t slot, int64_t *sum_j, int64_t *capped);
+
+/* Replaces the slot's iterate as fk_helmholtz_set_iterate does (resume from a
+ * checkpoint; also used to inject a fault in tests).  Between ticks. */
+fk_status fk_engine_set_iterate(fk_engine *e, int32_t slot, const double *u_reim, int32_t n, int32_t on_device);
+
+/* Probabilistic domain decomposition of a resident instance (the two-stage
+ * procedure of Sec. 3), as fk_helmholtz_set_pdd: from its next tick on, paths
+ * run only from the unknown nodes on the cut lines, and its blocks are solved
+ * on the device in the same tick (one launch for the blocks of all
+ * instances, inside the tick's graph).  Before the instance's first tick,
+ * once.  Takes its DST tables and right-hand sides from the engine pool.
+ * FK_EINVAL as fk_helmholtz_set_pdd; FK_ENOMEM: the pool cannot hold them
+ * now, or more than 16384 blocks would be resident. */
+fk_status fk_engine_set_pdd(fk_engine *e, int32_t slot, const int32_t *cuts_x, int32_t n_cuts_x,
+                            const int32_t *cuts_y, int32_t n_cuts_y);
 
 /* Frees a slot and its memory for new instances. */
 fk_status fk_engine_remove(fk_engine *e, int32_t slot);

@@ -160,6 +160,7 @@ __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
 struct F64Tables {
     double2 sc[1024];   // (sin, cos)(pi i / 512)
     double2 lg[1024];   // (ln c, 1 / c) for c = (i + 512) / 1024
+    double ex[64];      // 2^(i / 64): the exponential of the source term
 };
 
 // Every thread of the block calls this; the caller synchronises the block.
@@ -171,7 +172,30 @@ __device__ __forceinline__ void init_f64_tables(F64Tables &T)
         T.sc[i] = make_double2(sn, cs);
         const double c = (double)(i + 512) * 0x1p-10;
         T.lg[i] = make_double2(log(c), 1.0 / c);
+        if (i < 64) T.ex[i] = exp2((double)i * 0x1p-6);
     }
+}
+
+// e^a for a <= 0 (the Gaussian source, a = -|x - c|^2 / (2 sigma^2)) by the
+// table-driven reduction of Tang (ACM TOMS 15, 1989): a = (64 m + j) ln2/64
+// + r with j in [0, 64) and |r| <= ln2/128 (ln2/64 in two parts, the first
+// with 35 significant bits so that n times it is exact for |n| < 2^18), then
+// e^a = 2^m 2^(j/64) e^r with e^r - 1 by its Taylor series to r^5 (the next
+// term is below 4e-17 relative, about a third of an ulp).  Far below the
+// underflow threshold the integer conversion saturates and the scaling
+// still gives 0.  Replaces the library exponential, whose wider reduction
+// needs a degree-11 polynomial.
+__device__ __forceinline__ double exp_nonpos(double a, const F64Tables &T)
+{
+    const double n = rint(a * 92.332482616893656877);     // 64 / ln 2
+    const int i = (int)n;
+    const double r = fma(n, 2.0164562921995537e-13, fma(n, -0.010830424696450791, a));
+    double q = fma(r, 1.0 / 120.0, 1.0 / 24.0);
+    q = fma(r, q, 1.0 / 6.0);
+    q = fma(r, q, 0.5);
+    q = fma(r, q, 1.0);
+    const double t = T.ex[i & 63];
+    return ldexp(fma(t, r * q, t), i >> 6);
 }
 
 // ln(j 2^-24).  j = 2^e y with y in [0x3FE55555 00000000, 0x3FF55555 00000000)

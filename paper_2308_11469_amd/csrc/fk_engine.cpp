@@ -84,7 +84,16 @@ struct SlotInfo {
     int32_t iter = 0;
     double est_cost = 0.0;           // expected path steps per item (ordering)
     std::vector<double> hist_sup, hist_du;
+    // probabilistic domain decomposition: the block solves of the instance
+    // (pointers into its own pool region: DST tables, right-hand sides)
+    bool pdd = false;
+    Region pdd_region{};
+    std::vector<fkd::PddTask> tasks;
 };
+
+// Block solves of the probabilistic domain decomposition per tick, over all
+// instances (the graph's launch loops over the listed tasks).
+constexpr int32_t kMaxPddTasks = 16384;
 
 }  // namespace
 
@@ -107,6 +116,11 @@ struct fk_engine {
     fkd::DevState *h_states = nullptr;  // pinned [max_instances]
     fkd::EngineQueue *h_queue = nullptr;  // pinned
     int32_t *h_active = nullptr;        // pinned [max_instances + 1]
+    fkd::PddTask *d_tasks = nullptr;    // [kMaxPddTasks] + count
+    int32_t *d_n_tasks = nullptr;
+    fkd::PddTask *h_tasks = nullptr;    // pinned [kMaxPddTasks]
+    int32_t *h_n_tasks = nullptr;       // pinned
+    int32_t pdd_grid = 0;               // workgroups of the block-solve launch
     std::vector<SlotInfo> slots;
     std::vector<fkd::Inst> h_insts;
     PoolAllocator pool;
@@ -135,6 +149,11 @@ static fk_status capture_graph(fk_engine *e, int features)
         err = fkk::launch_stream(prec, features, e->d_insts, e->d_queue, e->d_head, e->n_blocks, e->cap_stream);
     if (err == hipSuccess)
         err = fkk::launch_update(e->d_insts, e->d_active, cap, e->d_n_active, e->max_interior_cap, e->cap_stream);
+    // block solves of the instances with a domain decomposition (none: the
+    // launch finds no task and ends at once)
+    if (err == hipSuccess)
+        err = fkk::launch_pdd(e->d_insts, e->d_tasks, 0, e->d_n_tasks, e->pdd_grid,
+                              fkd::kPddMaxSide * fkd::kPddMaxSide, e->cap_stream);
     if (err == hipSuccess) err = fkk::launch_advance(e->d_insts, e->d_active, cap, e->d_n_active, e->cap_stream);
     if (err == hipSuccess)
         err = hipMemcpyAsync(e->h_states, e->d_states, cap * sizeof(fkd::DevState), hipMemcpyDeviceToHost,
@@ -170,7 +189,19 @@ static void rebuild_tables(fk_engine *e)
         e->h_active[s] = act[s];
     }
     e->h_active[e->cfg.max_instances] = e->n_active;
+    int32_t nt = 0;
+    for (int32_t s = 0; s < e->n_active; ++s)
+        for (const fkd::PddTask &t : e->slots[act[s]].tasks) e->h_tasks[nt++] = t;
+    *e->h_n_tasks = nt;
     e->tables_dirty = true;
+}
+
+static int32_t pdd_task_count(const fk_engine *e)
+{
+    int32_t n = 0;
+    for (const SlotInfo &o : e->slots)
+        if (o.used) n += (int32_t)o.tasks.size();
+    return n;
 }
 
 extern "C" {
@@ -204,10 +235,11 @@ fk_status fk_engine_create(const fk_engine_config *cfg, void *hip_stream, fk_eng
     e->max_interior_cap = cfg->max_instance_nodes > 0 ? cfg->max_instance_nodes : 257 * 257;
     const int32_t cap = cfg->max_instances;
     // pool: per-node arrays (u64 16, gather copy up to 64 when FP64
-    // cell-major, nodes 4, se 16, sum_j 8, capped 8, slot), tables, and 9
-    // alignment paddings per instance
-    e->pool_bytes = (size_t)cfg->max_grid_nodes * (116 + sizeof(fkd::Slot)) + (size_t)cfg->max_table * 16 +
-                    (size_t)cap * 9 * 256;
+    // cell-major, nodes 4, se 16, sum_j 8, capped 8, slot, and the block
+    // right-hand sides 16 of a domain decomposition), tables, and per
+    // instance 11 alignment paddings and the decomposition's DST tables
+    e->pool_bytes = (size_t)cfg->max_grid_nodes * (132 + sizeof(fkd::Slot)) + (size_t)cfg->max_table * 16 +
+                    (size_t)cap * (11 * 256 + 8192);
     if ((err = hipStreamCreateWithFlags(&e->cap_stream, hipStreamNonBlocking)) != hipSuccess)
         return bail(hip_fail(err, "hipStreamCreateWithFlags"));
     if ((err = hipMalloc((void **)&e->d_insts, cap * sizeof(fkd::Inst))) != hipSuccess ||
@@ -215,13 +247,19 @@ fk_status fk_engine_create(const fk_engine_config *cfg, void *hip_stream, fk_eng
         (err = hipMalloc((void **)&e->d_active, (cap + 1) * sizeof(int32_t))) != hipSuccess ||
         (err = hipMalloc((void **)&e->d_queue, sizeof(fkd::EngineQueue))) != hipSuccess ||
         (err = hipMalloc((void **)&e->d_head, 256)) != hipSuccess ||
-        (err = hipMalloc((void **)&e->d_pool, e->pool_bytes)) != hipSuccess)
+        (err = hipMalloc((void **)&e->d_pool, e->pool_bytes)) != hipSuccess ||
+        (err = hipMalloc((void **)&e->d_tasks, kMaxPddTasks * sizeof(fkd::PddTask) + 256)) != hipSuccess)
         return bail(hip_fail(err, "hipMalloc(engine)"));
+    e->d_n_tasks = (int32_t *)((char *)e->d_tasks + kMaxPddTasks * sizeof(fkd::PddTask));
     e->d_n_active = e->d_active + cap;
     if ((err = hipHostMalloc((void **)&e->h_states, cap * sizeof(fkd::DevState), hipHostMallocDefault)) != hipSuccess ||
         (err = hipHostMalloc((void **)&e->h_queue, sizeof(fkd::EngineQueue), hipHostMallocDefault)) != hipSuccess ||
-        (err = hipHostMalloc((void **)&e->h_active, (cap + 1) * sizeof(int32_t), hipHostMallocDefault)) != hipSuccess)
+        (err = hipHostMalloc((void **)&e->h_active, (cap + 1) * sizeof(int32_t), hipHostMallocDefault)) != hipSuccess ||
+        (err = hipHostMalloc((void **)&e->h_tasks, kMaxPddTasks * sizeof(fkd::PddTask), hipHostMallocDefault)) !=
+            hipSuccess ||
+        (err = hipHostMalloc((void **)&e->h_n_tasks, sizeof(int32_t), hipHostMallocDefault)) != hipSuccess)
         return bail(hip_fail(err, "hipHostMalloc(engine)"));
+    *e->h_n_tasks = 0;
     std::memset(e->h_states, 0, cap * sizeof(fkd::DevState));
     std::memset(e->h_queue, 0, sizeof(fkd::EngineQueue));
     std::memset(e->h_active, 0, (cap + 1) * sizeof(int32_t));
@@ -229,8 +267,16 @@ fk_status fk_engine_create(const fk_engine_config *cfg, void *hip_stream, fk_eng
     if ((err = hipMemcpy(e->d_insts, e->h_insts.data(), cap * sizeof(fkd::Inst), hipMemcpyHostToDevice)) != hipSuccess ||
         (err = hipMemcpy(e->d_states, e->h_states, cap * sizeof(fkd::DevState), hipMemcpyHostToDevice)) != hipSuccess ||
         (err = hipMemcpy(e->d_active, e->h_active, (cap + 1) * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess ||
-        (err = hipMemcpy(e->d_queue, e->h_queue, sizeof(fkd::EngineQueue), hipMemcpyHostToDevice)) != hipSuccess)
+        (err = hipMemcpy(e->d_queue, e->h_queue, sizeof(fkd::EngineQueue), hipMemcpyHostToDevice)) != hipSuccess ||
+        (err = hipMemcpy(e->d_n_tasks, e->h_n_tasks, sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess)
         return bail(hip_fail(err, "hipMemcpy(engine tables)"));
+    {
+        int dev = 0, n_cu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n_cu <= 0)
+            n_cu = 256;
+        e->pdd_grid = n_cu;
+    }
     if ((err = hipEventCreate(&e->ev0)) != hipSuccess || (err = hipEventCreate(&e->ev1)) != hipSuccess)
         return bail(hip_fail(err, "hipEventCreate"));
     e->pool.reset(e->pool_bytes);
@@ -276,6 +322,8 @@ fk_status fk_engine_add(fk_engine *e, const fk_domain *domain, const fk_source *
     S.iter = 0;
     S.hist_du.clear();
     S.hist_sup.clear();
+    S.pdd = false;
+    S.tasks.clear();
     const double a = S.P.dom.x1 - S.P.dom.x0, b = S.P.dom.y1 - S.P.dom.y0;
     // mean exit time of a rectangle ~ 0.0351 * 2 a^2 b^2 / (a^2 + b^2) (unit square: 0.0351)
     S.est_cost = 0.0351 * 2.0 * a * a * b * b / (a * a + b * b) / S.P.par.h * (double)S.P.ppi;
@@ -305,7 +353,10 @@ fk_status fk_engine_remove(fk_engine *e, int32_t slot)
     SlotInfo &S = e->slots[slot];
     // the slot's memory may be reused right away: no tick is in flight here
     e->pool.release(S.region.off, S.region.size);
+    if (S.pdd) e->pool.release(S.pdd_region.off, S.pdd_region.size);
     S.used = false;
+    S.pdd = false;
+    S.tasks.clear();
     S.P = HostProblem();
     rebuild_tables(e);
     return FK_OK;
@@ -321,6 +372,10 @@ fk_status fk_engine_tick(fk_engine *e, fk_iter_report *reports, uint8_t *active_
     if (e->tables_dirty) {
         FK_HIP(hipMemcpyAsync(e->d_active, e->h_active, (cap + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
         FK_HIP(hipMemcpyAsync(e->d_queue, e->h_queue, sizeof(fkd::EngineQueue), hipMemcpyHostToDevice, s));
+        if (*e->h_n_tasks > 0)
+            FK_HIP(hipMemcpyAsync(e->d_tasks, e->h_tasks, *e->h_n_tasks * sizeof(fkd::PddTask), hipMemcpyHostToDevice,
+                                  s));
+        FK_HIP(hipMemcpyAsync(e->d_n_tasks, e->h_n_tasks, sizeof(int32_t), hipMemcpyHostToDevice, s));
         e->tables_dirty = false;
     }
     int features = 0;
@@ -382,6 +437,86 @@ fk_status fk_engine_get(fk_engine *e, int32_t slot, double *u_reim, double *se_r
     return FK_OK;
 }
 
+fk_status fk_engine_set_pdd(fk_engine *e, int32_t slot, const int32_t *cuts_x, int32_t n_cuts_x,
+                            const int32_t *cuts_y, int32_t n_cuts_y)
+{
+    if (!e || slot < 0 || slot >= e->cfg.max_instances || !e->slots[slot].used)
+        return fail(FK_EINVAL, "no instance in that slot");
+    SlotInfo &S = e->slots[slot];
+    if (S.iter != 0 || S.pdd) return fail(FK_EINVAL, "set PDD once, before the instance's first tick");
+    PddPlan plan;
+    fk_status st = plan_pdd(S.P, cuts_x, n_cuts_x, cuts_y, n_cuts_y, plan);
+    if (st != FK_OK) return st;
+    if (pdd_task_count(e) + (int64_t)plan.blocks.size() > kMaxPddTasks)
+        return fail(FK_ENOMEM, "engine block-solve capacity reached");
+    // tables, then the right-hand sides (one complex value per grid node)
+    const size_t tab_bytes = align256(plan.tables.size() * sizeof(double));
+    const size_t bytes = tab_bytes + S.P.n_nodes() * sizeof(double2);
+    size_t off = 0;
+    if (!e->pool.alloc(bytes, off)) return fail(FK_ENOMEM, "engine pool cannot hold the decomposition now");
+    double *tables = (double *)(e->d_pool + off);
+    double2 *rhs = (double2 *)(e->d_pool + off + tab_bytes);
+    HostProblem P2 = S.P;
+    apply_pdd(P2, plan, 2 * (int64_t)e->n_blocks * 4);
+    const fkd::Inst D = make_inst(P2, S.B);
+    const hipStream_t s = e->cap_stream;
+    hipError_t err = hipSuccess;
+    if (!plan.tables.empty())
+        err = hipMemcpyAsync(tables, plan.tables.data(), plan.tables.size() * sizeof(double), hipMemcpyHostToDevice, s);
+    if (err == hipSuccess && !P2.interior.empty())
+        err = hipMemcpyAsync(S.B.nodes, P2.interior.data(), P2.interior.size() * sizeof(int32_t),
+                             hipMemcpyHostToDevice, s);
+    if (err == hipSuccess) err = hipMemcpyAsync(e->d_insts + slot, &D, sizeof(D), hipMemcpyHostToDevice, s);
+    if (err == hipSuccess) err = hipStreamSynchronize(s);
+    if (err != hipSuccess) {
+        // best effort: the device node list and record back to the host's
+        const fkd::Inst D0 = make_inst(S.P, S.B);
+        (void)hipMemcpyAsync(S.B.nodes, S.P.interior.data(), S.P.interior.size() * sizeof(int32_t),
+                             hipMemcpyHostToDevice, s);
+        (void)hipMemcpyAsync(e->d_insts + slot, &D0, sizeof(D0), hipMemcpyHostToDevice, s);
+        (void)hipStreamSynchronize(s);
+        e->pool.release(off, bytes);
+        return hip_fail(err, "engine set_pdd");
+    }
+    S.tasks.clear();
+    for (const PddPlan::Block &B : plan.blocks)
+        S.tasks.push_back(fkd::PddTask{slot, B.i0, B.i1, B.j0, B.j1, 0, tables + B.tx, tables + B.ty, rhs});
+    S.P = std::move(P2);
+    S.pdd = true;
+    S.pdd_region = {off, bytes};
+    e->h_insts[slot] = D;
+    rebuild_tables(e);
+    return FK_OK;
+}
+
+fk_status fk_engine_node_stats(fk_engine *e, int32_t slot, int64_t *sum_j, int64_t *capped)
+{
+    if (!e || slot < 0 || slot >= e->cfg.max_instances || !e->slots[slot].used)
+        return fail(FK_EINVAL, "no instance in that slot");
+    const SlotInfo &S = e->slots[slot];
+    const size_t nn = S.P.n_nodes();
+    const hipStream_t s = e->user_stream ? e->user_stream : e->cap_stream;
+    if (sum_j) FK_HIP(hipMemcpyAsync(sum_j, S.B.sum_j, nn * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    if (capped) FK_HIP(hipMemcpyAsync(capped, S.B.capped, nn * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    FK_HIP(hipStreamSynchronize(s));
+    return FK_OK;
+}
+
+fk_status fk_engine_set_iterate(fk_engine *e, int32_t slot, const double *u_reim, int32_t n, int32_t on_device)
+{
+    if (!e || slot < 0 || slot >= e->cfg.max_instances || !e->slots[slot].used)
+        return fail(FK_EINVAL, "no instance in that slot");
+    if (!u_reim || n < 0) return fail(FK_EINVAL, "u_reim is required and n must be >= 0");
+    SlotInfo &S = e->slots[slot];
+    const hipStream_t s = e->user_stream ? e->user_stream : e->cap_stream;
+    const fk_status st = load_iterate(S.P, S.B, u_reim, n, on_device != 0, s);
+    if (st != FK_OK) return st;
+    S.iter = n;
+    S.hist_du.clear();
+    S.hist_sup.clear();
+    return FK_OK;
+}
+
 fk_status fk_engine_timing(fk_engine *e, double *kernel_ms_total, int64_t *launches, int32_t reset)
 {
     if (!e) return fail(FK_EINVAL, "engine is NULL");
@@ -411,9 +546,12 @@ fk_status fk_engine_destroy(fk_engine *e)
     (void)hipFree(e->d_queue);
     (void)hipFree(e->d_head);
     (void)hipFree(e->d_pool);
+    (void)hipFree(e->d_tasks);
     if (e->h_states) (void)hipHostFree(e->h_states);
     if (e->h_queue) (void)hipHostFree(e->h_queue);
     if (e->h_active) (void)hipHostFree(e->h_active);
+    if (e->h_tasks) (void)hipHostFree(e->h_tasks);
+    if (e->h_n_tasks) (void)hipHostFree(e->h_n_tasks);
     if (e->cap_stream) (void)hipStreamDestroy(e->cap_stream);
     delete e;
     return FK_OK;

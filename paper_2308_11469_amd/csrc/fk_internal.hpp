@@ -21,12 +21,15 @@ struct EngineQueue {
 };
 
 // One subdomain of the probabilistic domain decomposition: the unknown nodes
-// [i0, i1) x [j0, j1) between two interface lines (or the edge), and the
-// offsets of its DST tables for the sizes i1 - i0 and j1 - j0.
+// [i0, i1) x [j0, j1) of instance `inst` (an index into the instance array)
+// between two interface lines (or the edge), the DST tables of its sides
+// i1 - i0 and j1 - j0 (2 (m + 1) sines, then m eigenvalue factors), and the
+// right-hand-side buffer of its instance (one complex value per grid node).
 constexpr int kPddMaxSide = 64;
-struct PddBlock {
-    int32_t i0, i1, j0, j1;
-    int32_t tx, ty;
+struct PddTask {
+    int32_t inst, i0, i1, j0, j1, pad;
+    const double *tx, *ty;
+    double2 *rhs;
 };
 }  // namespace fkd
 
@@ -43,11 +46,13 @@ hipError_t launch_update(const fkd::Inst *d_insts, const int32_t *which, int32_t
                          int32_t max_interior, hipStream_t s);
 hipError_t launch_advance(const fkd::Inst *d_insts, const int32_t *which, int32_t n, const int32_t *n_dev,
                           hipStream_t s);
-// The blocks of one PDD step: right-hand sides into rhs (per grid node),
+// The blocks of one PDD step: right-hand sides into each task's rhs buffer,
 // then the fast-diagonalisation solve of every block and component, written
-// into the iterate and its gather copy.  max_nodes: the largest block.
-hipError_t launch_pdd_blocks(const fkd::Inst *d_inst, const fkd::PddBlock *blocks, int32_t n_blocks,
-                             int32_t max_nodes, const double *tables, double2 *rhs, hipStream_t s);
+// into the iterate and its gather copy.  The task count is *n_dev when given
+// (graph replays read it from the device), else n; `grid` workgroups (per
+// component) loop over the tasks; max_nodes bounds the largest block.
+hipError_t launch_pdd(const fkd::Inst *d_insts, const fkd::PddTask *tasks, int32_t n, const int32_t *n_dev,
+                      int32_t grid, int32_t max_nodes, hipStream_t s);
 hipError_t launch_debug_philox(uint32_t k0, uint32_t k1, const uint4 *ctr, int64_t n, uint4 *out, hipStream_t s);
 hipError_t launch_debug_normals(int precision, const uint2 *words, int64_t n, double2 *z, hipStream_t s);
 hipError_t launch_debug_paths(int precision, const fkd::Inst *d_inst, const int32_t *nodes, const int64_t *ms,

@@ -113,8 +113,13 @@ template <class R> struct PathState {
     int t;        // steps taken
 };
 
-__device__ __forceinline__ double exp_src(double a) { return exp(a); }
-__device__ __forceinline__ float exp_src(float a) { return __builtin_amdgcn_exp2f(a * 1.44269504088896341f); }
+// exponential of the source term (argument <= 0): FP64 by the table-driven
+// reduction, FP32 by the hardware base-2 exponential
+__device__ __forceinline__ double exp_src(double a, const F64Tables &T) { return exp_nonpos(a, T); }
+__device__ __forceinline__ float exp_src(float a, const NoTables &)
+{
+    return __builtin_amdgcn_exp2f(a * 1.44269504088896341f);
+}
 
 // Exit test: outside the open rectangle (unless its edge reflects), or in
 // the closed hole.  FP64: the same comparisons as the problem statement.
@@ -319,7 +324,7 @@ __device__ __forceinline__ void source(const Consts<R> &K, R x, R y, R &fr, R &f
         fi = K.src_im;
     } else {
         const R ex = x - K.src_cx, ey = y - K.src_cy;
-        const R e = exp_src(-K.src_c * (ex * ex + ey * ey));
+        const R e = exp_src(-K.src_c * (ex * ex + ey * ey), *K.tab);
         fr = K.src_re * e;
         fi = K.src_im * e;
     }
@@ -1358,113 +1363,120 @@ __global__ void fk_advance_kernel(const Inst *__restrict__ insts, const int32_t 
 
 __device__ __forceinline__ double comp_of(double2 v, int c) { return c ? v.y : v.x; }
 
-// Right-hand side of every block node (both components): one block per
-// workgroup.  Kept apart from the solve, which overwrites u_n.
-__global__ void __launch_bounds__(256) fk_pdd_rhs_kernel(const Inst *__restrict__ inst,
-                                                         const PddBlock *__restrict__ blocks,
-                                                         double2 *__restrict__ rhs)
+// Right-hand side of every block node (both components); workgroups loop
+// over the tasks.  Kept apart from the solve, which overwrites u_n.
+__global__ void __launch_bounds__(256) fk_pdd_rhs_kernel(const Inst *__restrict__ insts,
+                                                         const PddTask *__restrict__ tasks, int32_t n_tasks,
+                                                         const int32_t *__restrict__ n_dev)
 {
-    const Inst &D = *inst;
-    const PddBlock B = blocks[blockIdx.x];
-    const int mx = B.i1 - B.i0, my = B.j1 - B.j0, n = mx * my;
-    const double idx2 = D.idx * D.idx, idy2 = D.idy * D.idy;
-    const bool use_u = D.state->use_u != 0;
-    for (int e = threadIdx.x; e < n; e += blockDim.x) {
-        const int a = e / my, b = e - (e / my) * my;
-        const int gi = B.i0 + a, gj = B.j0 + b;
-        const int node = gi + D.nx * gj;
-        double rr = 0.0, ri = 0.0;
-        if (D.src_kind == SRC_CONST) {
-            rr = D.src_re;
-            ri = D.src_im;
-        } else if (D.src_kind == SRC_GAUSSIAN) {
-            const double ex = D.x0 + (double)gi * D.dx - D.src_cx, ey = D.y0 + (double)gj * D.dy - D.src_cy;
-            const double g = exp(-D.src_c * (ex * ex + ey * ey));
-            rr = D.src_re * g;
-            ri = D.src_im * g;
+    const int32_t count = list_count(n_tasks, n_dev);
+    for (int32_t t = blockIdx.x; t < count; t += gridDim.x) {
+        const PddTask B = tasks[t];
+        const Inst &D = insts[B.inst];
+        const int mx = B.i1 - B.i0, my = B.j1 - B.j0, n = mx * my;
+        const double idx2 = D.idx * D.idx, idy2 = D.idy * D.idy;
+        const bool use_u = D.state->use_u != 0;
+        for (int e = threadIdx.x; e < n; e += blockDim.x) {
+            const int a = e / my, b = e - (e / my) * my;
+            const int gi = B.i0 + a, gj = B.j0 + b;
+            const int node = gi + D.nx * gj;
+            double rr = 0.0, ri = 0.0;
+            if (D.src_kind == SRC_CONST) {
+                rr = D.src_re;
+                ri = D.src_im;
+            } else if (D.src_kind == SRC_GAUSSIAN) {
+                const double ex = D.x0 + (double)gi * D.dx - D.src_cx, ey = D.y0 + (double)gj * D.dy - D.src_cy;
+                const double g = exp(-D.src_c * (ex * ex + ey * ey));
+                rr = D.src_re * g;
+                ri = D.src_im * g;
+            }
+            if (use_u) {
+                const double2 u = D.u64[node];
+                rr -= D.alpha * u.x - D.damp * u.y;
+                ri -= D.alpha * u.y + D.damp * u.x;
+            }
+            // Dirichlet neighbours outside the block: interface values of
+            // u_{n+1} (already written) or the edge data
+            if (a == 0) { const double2 v = D.u64[node - 1]; rr -= idx2 * v.x; ri -= idx2 * v.y; }
+            if (a == mx - 1) { const double2 v = D.u64[node + 1]; rr -= idx2 * v.x; ri -= idx2 * v.y; }
+            if (b == 0) { const double2 v = D.u64[node - D.nx]; rr -= idy2 * v.x; ri -= idy2 * v.y; }
+            if (b == my - 1) { const double2 v = D.u64[node + D.nx]; rr -= idy2 * v.x; ri -= idy2 * v.y; }
+            B.rhs[node] = make_double2(rr, ri);
         }
-        if (use_u) {
-            const double2 u = D.u64[node];
-            rr -= D.alpha * u.x - D.damp * u.y;
-            ri -= D.alpha * u.y + D.damp * u.x;
-        }
-        // Dirichlet neighbours outside the block: interface values of u_{n+1}
-        // (already written) or the edge data
-        if (a == 0) { const double2 v = D.u64[node - 1]; rr -= idx2 * v.x; ri -= idx2 * v.y; }
-        if (a == mx - 1) { const double2 v = D.u64[node + 1]; rr -= idx2 * v.x; ri -= idx2 * v.y; }
-        if (b == 0) { const double2 v = D.u64[node - D.nx]; rr -= idy2 * v.x; ri -= idy2 * v.y; }
-        if (b == my - 1) { const double2 v = D.u64[node + D.nx]; rr -= idy2 * v.x; ri -= idy2 * v.y; }
-        rhs[node] = make_double2(rr, ri);
     }
 }
 
-// One (block, component) per workgroup: r and a work array of mx * my
-// doubles in LDS (at most 64 x 64: 64 KiB), four dense products with the
-// DST tables.  Writes the component into the FP64 iterate and the gather copy.
-__global__ void __launch_bounds__(256) fk_pdd_solve_kernel(const Inst *__restrict__ inst,
-                                                           const PddBlock *__restrict__ blocks,
-                                                           const double *__restrict__ tab,
-                                                           const double2 *__restrict__ rhs)
+// One (task, component) at a time per workgroup (component blockIdx.y): r
+// and a work array of mx * my doubles in LDS (at most 64 x 64: 64 KiB), four
+// dense products with the DST tables.  Writes the component into the FP64
+// iterate and the gather copy.
+__global__ void __launch_bounds__(256) fk_pdd_solve_kernel(const Inst *__restrict__ insts,
+                                                           const PddTask *__restrict__ tasks, int32_t n_tasks,
+                                                           const int32_t *__restrict__ n_dev)
 {
     extern __shared__ double lds_pdd[];
-    const Inst &D = *inst;
-    const PddBlock B = blocks[blockIdx.x];
     const int comp = blockIdx.y;
-    const int mx = B.i1 - B.i0, my = B.j1 - B.j0, n = mx * my;
-    const int px = 2 * (mx + 1), py = 2 * (my + 1);
-    const double *sx = tab + B.tx, *sy = tab + B.ty;          // sines
-    const double *ex = sx + px, *ey = sy + py;                // eigenvalue factors
-    double *R = lds_pdd, *T = lds_pdd + n;
-    for (int e = threadIdx.x; e < n; e += blockDim.x) {
-        const int a = e / my, b = e - (e / my) * my;
-        R[e] = comp_of(rhs[(B.i0 + a) + D.nx * (B.j0 + b)], comp);
-    }
-    __syncthreads();
-    // T = R S_y
-    for (int e = threadIdx.x; e < n; e += blockDim.x) {
-        const int a = e / my, q = e - (e / my) * my;
-        double acc = 0.0;
-        for (int b = 0; b < my; ++b) acc = fma(R[a * my + b], sy[((b + 1) * (q + 1)) % py], acc);
-        T[e] = acc;
-    }
-    __syncthreads();
-    // R = S_x T, divided by the eigenvalue of (Delta_h - c)
-    const double idx2 = D.idx * D.idx, idy2 = D.idy * D.idy, c = D.alpha - D.k2;
-    for (int e = threadIdx.x; e < n; e += blockDim.x) {
-        const int p = e / my, q = e - (e / my) * my;
-        double acc = 0.0;
-        for (int a = 0; a < mx; ++a) acc = fma(sx[((p + 1) * (a + 1)) % px], T[a * my + q], acc);
-        R[e] = acc / (-(idx2 * ex[p] + idy2 * ey[q]) - c);
-    }
-    __syncthreads();
-    // T = S_x R
-    for (int e = threadIdx.x; e < n; e += blockDim.x) {
-        const int a = e / my, q = e - (e / my) * my;
-        double acc = 0.0;
-        for (int p = 0; p < mx; ++p) acc = fma(sx[((a + 1) * (p + 1)) % px], R[p * my + q], acc);
-        T[e] = acc;
-    }
-    __syncthreads();
-    // u = T S_y, into the iterate and its gather copy
-    const int cw = D.nx - 1;
-    for (int e = threadIdx.x; e < n; e += blockDim.x) {
-        const int a = e / my, b = e - (e / my) * my;
-        double v = 0.0;
-        for (int q = 0; q < my; ++q) v = fma(T[a * my + q], sy[((q + 1) * (b + 1)) % py], v);
-        const int gi = B.i0 + a, gj = B.j0 + b;
-        const int node = gi + D.nx * gj;
-        ((double *)D.u64)[2 * node + comp] = v;
-        if (D.prec == 32 && !D.cells) {
-            ((float *)D.gather)[2 * node + comp] = (float)v;
-        } else if (D.cells) {
-            for (int cq = 1; cq >= 0; --cq)
-                for (int cp = 1; cp >= 0; --cp) {
-                    const int p = gi - cp, q = gj - cq;
-                    if (p < 0 || p > D.nx - 2 || q < 0 || q > D.ny - 2) continue;
-                    const int at = 4 * (p + cw * q) + cp + 2 * cq;
-                    if (D.prec == 32) ((float *)D.gather)[2 * at + comp] = (float)v;
-                    else ((double *)D.gather)[2 * at + comp] = v;
-                }
+    const int32_t count = list_count(n_tasks, n_dev);
+    for (int32_t t = blockIdx.x; t < count; t += gridDim.x) {
+        const PddTask B = tasks[t];
+        const Inst &D = insts[B.inst];
+        const int mx = B.i1 - B.i0, my = B.j1 - B.j0, n = mx * my;
+        const int px = 2 * (mx + 1), py = 2 * (my + 1);
+        const double *sx = B.tx, *sy = B.ty;                  // sines
+        const double *ex = sx + px, *ey = sy + py;            // eigenvalue factors
+        double *R = lds_pdd, *T = lds_pdd + n;
+        __syncthreads();   // the previous task's last reads of T are done
+        for (int e = threadIdx.x; e < n; e += blockDim.x) {
+            const int a = e / my, b = e - (e / my) * my;
+            R[e] = comp_of(B.rhs[(B.i0 + a) + D.nx * (B.j0 + b)], comp);
+        }
+        __syncthreads();
+        // T = R S_y
+        for (int e = threadIdx.x; e < n; e += blockDim.x) {
+            const int a = e / my, q = e - (e / my) * my;
+            double acc = 0.0;
+            for (int b = 0; b < my; ++b) acc = fma(R[a * my + b], sy[((b + 1) * (q + 1)) % py], acc);
+            T[e] = acc;
+        }
+        __syncthreads();
+        // R = S_x T, divided by the eigenvalue of (Delta_h - c)
+        const double idx2 = D.idx * D.idx, idy2 = D.idy * D.idy, c = D.alpha - D.k2;
+        for (int e = threadIdx.x; e < n; e += blockDim.x) {
+            const int p = e / my, q = e - (e / my) * my;
+            double acc = 0.0;
+            for (int a = 0; a < mx; ++a) acc = fma(sx[((p + 1) * (a + 1)) % px], T[a * my + q], acc);
+            R[e] = acc / (-(idx2 * ex[p] + idy2 * ey[q]) - c);
+        }
+        __syncthreads();
+        // T = S_x R
+        for (int e = threadIdx.x; e < n; e += blockDim.x) {
+            const int a = e / my, q = e - (e / my) * my;
+            double acc = 0.0;
+            for (int p = 0; p < mx; ++p) acc = fma(sx[((a + 1) * (p + 1)) % px], R[p * my + q], acc);
+            T[e] = acc;
+        }
+        __syncthreads();
+        // u = T S_y, into the iterate and its gather copy
+        const int cw = D.nx - 1;
+        for (int e = threadIdx.x; e < n; e += blockDim.x) {
+            const int a = e / my, b = e - (e / my) * my;
+            double v = 0.0;
+            for (int q = 0; q < my; ++q) v = fma(T[a * my + q], sy[((q + 1) * (b + 1)) % py], v);
+            const int gi = B.i0 + a, gj = B.j0 + b;
+            const int node = gi + D.nx * gj;
+            ((double *)D.u64)[2 * node + comp] = v;
+            if (D.prec == 32 && !D.cells) {
+                ((float *)D.gather)[2 * node + comp] = (float)v;
+            } else if (D.cells) {
+                for (int cq = 1; cq >= 0; --cq)
+                    for (int cp = 1; cp >= 0; --cp) {
+                        const int p = gi - cp, q = gj - cq;
+                        if (p < 0 || p > D.nx - 2 || q < 0 || q > D.ny - 2) continue;
+                        const int at = 4 * (p + cw * q) + cp + 2 * cq;
+                        if (D.prec == 32) ((float *)D.gather)[2 * at + comp] = (float)v;
+                        else ((double *)D.gather)[2 * at + comp] = v;
+                    }
+            }
         }
     }
 }
@@ -1593,13 +1605,13 @@ hipError_t launch_advance(const Inst *d_insts, const int32_t *which, int32_t n, 
     return hipGetLastError();
 }
 
-hipError_t launch_pdd_blocks(const Inst *d_inst, const PddBlock *blocks, int32_t n_blocks, int32_t max_nodes,
-                             const double *tables, double2 *rhs, hipStream_t s)
+hipError_t launch_pdd(const Inst *d_insts, const PddTask *tasks, int32_t n, const int32_t *n_dev, int32_t grid,
+                      int32_t max_nodes, hipStream_t s)
 {
-    if (n_blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(fk_pdd_rhs_kernel, dim3(n_blocks), dim3(256), 0, s, d_inst, blocks, rhs);
-    hipLaunchKernelGGL(fk_pdd_solve_kernel, dim3(n_blocks, 2), dim3(256), (size_t)2 * max_nodes * sizeof(double), s,
-                       d_inst, blocks, tables, (const double2 *)rhs);
+    if ((n <= 0 && !n_dev) || grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fk_pdd_rhs_kernel, dim3(grid), dim3(256), 0, s, d_insts, tasks, n, n_dev);
+    hipLaunchKernelGGL(fk_pdd_solve_kernel, dim3(grid, 2), dim3(256), (size_t)2 * max_nodes * sizeof(double), s,
+                       d_insts, tasks, n, n_dev);
     return hipGetLastError();
 }
 

@@ -1,6 +1,8 @@
 // fk_problem.cpp -- host-side problem setup (see fk_problem.hpp).
 #include "fk_problem.hpp"
 
+#include "fk_internal.hpp"
+
 #include <cmath>
 #include <algorithm>
 #include <cstring>
@@ -471,6 +473,79 @@ fk_status upload_instance(const HostProblem &P, const InstanceBuffers &B, hipStr
     // the staging vectors go out of scope: wait for the copies
     FK_HIP(hipStreamSynchronize(s));
     return FK_OK;
+}
+
+fk_status plan_pdd(const HostProblem &P, const int32_t *cuts_x, int32_t n_cuts_x, const int32_t *cuts_y,
+                   int32_t n_cuts_y, PddPlan &out)
+{
+    const fk_domain &d = P.dom;
+    if (d.kind != FK_DOMAIN_RECT || P.reflect())
+        return fail(FK_EINVAL, "PDD needs a plain rectangle with an absorbing edge");
+    if (n_cuts_x < 0 || n_cuts_y < 0 || n_cuts_x + n_cuts_y == 0 || (n_cuts_x > 0 && !cuts_x) ||
+        (n_cuts_y > 0 && !cuts_y))
+        return fail(FK_EINVAL, "at least one cut line");
+    std::vector<int32_t> xs{0}, ys{0};
+    for (int32_t i = 0; i < n_cuts_x; ++i) xs.push_back(cuts_x[i]);
+    for (int32_t i = 0; i < n_cuts_y; ++i) ys.push_back(cuts_y[i]);
+    xs.push_back(d.nx - 1);
+    ys.push_back(d.ny - 1);
+    for (auto *v : {&xs, &ys})
+        for (size_t i = 1; i < v->size(); ++i)
+            if ((*v)[i] <= (*v)[i - 1]) return fail(FK_EINVAL, "cuts must increase strictly within [1, n - 2]");
+    PddPlan plan;
+    std::vector<int32_t> offset(fkd::kPddMaxSide + 1, -1);
+    auto table_of = [&](int m) {
+        if (offset[m] < 0) {
+            offset[m] = (int32_t)plan.tables.size();
+            const double sc = std::sqrt(2.0 / (double)(m + 1));
+            for (int t = 0; t < 2 * (m + 1); ++t)
+                plan.tables.push_back(sc * std::sin(M_PI * (double)t / (double)(m + 1)));
+            for (int q = 0; q < m; ++q) {
+                const double sn = std::sin(M_PI * (double)(q + 1) / (2.0 * (double)(m + 1)));
+                plan.tables.push_back(4.0 * sn * sn);
+            }
+        }
+        return offset[m];
+    };
+    for (size_t b = 0; b + 1 < ys.size(); ++b)
+        for (size_t a = 0; a + 1 < xs.size(); ++a) {
+            PddPlan::Block B;
+            B.i0 = xs[a] + 1;
+            B.i1 = xs[a + 1];
+            B.j0 = ys[b] + 1;
+            B.j1 = ys[b + 1];
+            if (B.i1 <= B.i0 || B.j1 <= B.j0) continue;   // adjacent cut lines: no block between
+            const int mx = B.i1 - B.i0, my = B.j1 - B.j0;
+            if (mx > fkd::kPddMaxSide || my > fkd::kPddMaxSide)
+                return fail(FK_EINVAL, "a block between cut lines is wider than 64 nodes; cut finer");
+            B.tx = table_of(mx);
+            B.ty = table_of(my);
+            plan.max_nodes = std::max(plan.max_nodes, mx * my);
+            plan.blocks.push_back(B);
+        }
+    // the node list becomes the interface (in the same longest-first order)
+    std::vector<uint8_t> on_x(d.nx, 0), on_y(d.ny, 0);
+    for (int32_t i = 0; i < n_cuts_x; ++i) on_x[cuts_x[i]] = 1;
+    for (int32_t i = 0; i < n_cuts_y; ++i) on_y[cuts_y[i]] = 1;
+    for (int32_t id : P.interior)
+        if (on_x[id % d.nx] || on_y[id / d.nx]) plan.iface.push_back(id);
+    out = std::move(plan);
+    return FK_OK;
+}
+
+void apply_pdd(HostProblem &P, const PddPlan &plan, int64_t target_items)
+{
+    P.interior = plan.iface;
+    if (P.par.paths_per_item == 0) {
+        // far fewer nodes than the grid: smaller items, so that the launch's
+        // waves still find work
+        int64_t ppi = 64;
+        while (ppi * 2 <= P.ppi) ppi *= 2;
+        while (ppi > 64 && (int64_t)plan.iface.size() * ((P.par.M + ppi - 1) / ppi) < target_items) ppi /= 2;
+        P.ppi = (int32_t)ppi;
+        P.items_per_node = (int32_t)((P.par.M + ppi - 1) / ppi);
+    }
+    P.n_items = (int64_t)plan.iface.size() * P.items_per_node;
 }
 
 fk_status load_iterate(const HostProblem &P, const InstanceBuffers &B, const double *u_reim, int32_t n,

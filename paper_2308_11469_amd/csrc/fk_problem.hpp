@@ -103,6 +103,32 @@ void gather_copy(const HostProblem &P, const double *grid, std::vector<uint8_t> 
 fk_status load_iterate(const HostProblem &P, const InstanceBuffers &B, const double *u_reim, int32_t n,
                        bool on_device, hipStream_t s);
 
+// Probabilistic domain decomposition of a problem (Sec. 3's two-stage
+// procedure): the interface is the unknown nodes on the grid lines x index in
+// cuts_x, y index in cuts_y; the blocks are the unknown nodes between
+// consecutive lines (or the edge), each with the DST tables of its two sides
+// (offsets into `tables`: 2 (m + 1) sines sqrt(2/(m+1)) sin(pi t/(m+1)),
+// then m factors 4 sin^2(pi (q+1) / (2 (m+1)))).
+struct PddPlan {
+    struct Block {
+        int32_t i0, i1, j0, j1;   // unknown nodes [i0, i1) x [j0, j1)
+        int32_t tx, ty;           // table offsets of the sides i1 - i0, j1 - j0
+    };
+    std::vector<Block> blocks;
+    std::vector<double> tables;
+    std::vector<int32_t> iface;   // interface node ids, in the problem's work order
+    int32_t max_nodes = 0;        // largest block
+};
+// FK_EINVAL: not a plain rectangle with an absorbing edge, no cut, cuts not
+// strictly increasing within [1, n - 2], or a block wider than 64 nodes.
+fk_status plan_pdd(const HostProblem &P, const int32_t *cuts_x, int32_t n_cuts_x, const int32_t *cuts_y,
+                   int32_t n_cuts_y, PddPlan &out);
+// Makes the PDD node list the problem's work list.  With the automatic item
+// size, items are re-sized for the shorter list: the item size is rounded
+// down to 64 times a power of two and halved (not below 64) while the
+// instance has fewer than target_items items.
+void apply_pdd(HostProblem &P, const PddPlan &plan, int64_t target_items);
+
 // Paths per work item when the caller leaves it to the library.
 int32_t auto_paths_per_item(int64_t n_interior, int64_t M);
 

@@ -8,6 +8,7 @@
 // pinned host memory.  The host applies the
 // sup-norm stopping rule (Sec. 3) and the divergence rule.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -43,9 +44,11 @@ struct fk_solver {
     // probabilistic domain decomposition (library-owned device memory)
     bool pdd = false;   // set_pdd succeeded (the blocks may be none: every line a cut)
     int32_t pdd_blocks = 0, pdd_max_nodes = 0;
-    fkd::PddBlock *d_pdd_blocks = nullptr;
+    fkd::PddTask *d_pdd_tasks = nullptr;
     double *d_pdd_tables = nullptr;
     double2 *d_pdd_rhs = nullptr;
+    // set by fk_helmholtz_cancel (any thread), taken by the next iteration
+    std::atomic<int> cancel{0};
 };
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -150,8 +153,8 @@ static fk_status run_one(fk_solver *s, fk_iter_report *rep)
     FK_HIP(hipEventRecord(s->ev1, s->stream));
     FK_HIP(fkk::launch_update(s->d_inst, nullptr, 1, nullptr, (int32_t)s->P.interior.size(), s->stream));
     if (s->pdd_blocks > 0)
-        FK_HIP(fkk::launch_pdd_blocks(s->d_inst, s->d_pdd_blocks, s->pdd_blocks, s->pdd_max_nodes, s->d_pdd_tables,
-                                      s->d_pdd_rhs, s->stream));
+        FK_HIP(fkk::launch_pdd(s->d_inst, s->d_pdd_tasks, s->pdd_blocks, nullptr, s->pdd_blocks, s->pdd_max_nodes,
+                               s->stream));
     FK_HIP(fkk::launch_advance(s->d_inst, nullptr, 1, nullptr, s->stream));
     FK_HIP(hipMemcpyAsync(s->h_status, s->B.state, sizeof(fkd::DevState), hipMemcpyDeviceToHost, s->stream));
     FK_HIP(hipStreamSynchronize(s->stream));
@@ -192,99 +195,47 @@ fk_status fk_helmholtz_set_pdd(fk_solver *s, const int32_t *cuts_x, int32_t n_cu
                                int32_t n_cuts_y)
 {
     if (!s) return fail(FK_EINVAL, "solver is NULL");
-    const HostProblem &P0 = s->P;
-    const fk_domain &d = P0.dom;
     if (s->iter != 0 || s->pdd) return fail(FK_EINVAL, "set PDD once, before the first iteration");
-    if (d.kind != FK_DOMAIN_RECT || P0.reflect())
-        return fail(FK_EINVAL, "PDD needs a plain rectangle with an absorbing edge");
-    if (n_cuts_x < 0 || n_cuts_y < 0 || n_cuts_x + n_cuts_y == 0 || (n_cuts_x > 0 && !cuts_x) ||
-        (n_cuts_y > 0 && !cuts_y))
-        return fail(FK_EINVAL, "at least one cut line");
-    std::vector<int32_t> xs{0}, ys{0};
-    for (int32_t i = 0; i < n_cuts_x; ++i) xs.push_back(cuts_x[i]);
-    for (int32_t i = 0; i < n_cuts_y; ++i) ys.push_back(cuts_y[i]);
-    xs.push_back(d.nx - 1);
-    ys.push_back(d.ny - 1);
-    for (auto *v : {&xs, &ys})
-        for (size_t i = 1; i < v->size(); ++i)
-            if ((*v)[i] <= (*v)[i - 1]) return fail(FK_EINVAL, "cuts must increase strictly within [1, n - 2]");
-    // blocks, their DST tables (one per distinct side length)
-    std::vector<fkd::PddBlock> blocks;
-    std::vector<double> tables;
-    std::vector<int32_t> offset(fkd::kPddMaxSide + 1, -1);
-    auto table_of = [&](int m) {
-        if (offset[m] < 0) {
-            offset[m] = (int32_t)tables.size();
-            const double sc = std::sqrt(2.0 / (double)(m + 1));
-            for (int t = 0; t < 2 * (m + 1); ++t) tables.push_back(sc * std::sin(M_PI * (double)t / (double)(m + 1)));
-            for (int q = 0; q < m; ++q) {
-                const double sn = std::sin(M_PI * (double)(q + 1) / (2.0 * (double)(m + 1)));
-                tables.push_back(4.0 * sn * sn);
-            }
-        }
-        return offset[m];
-    };
-    int32_t max_nodes = 0;
-    for (size_t b = 0; b + 1 < ys.size(); ++b)
-        for (size_t a = 0; a + 1 < xs.size(); ++a) {
-            fkd::PddBlock B;
-            B.i0 = xs[a] + 1;
-            B.i1 = xs[a + 1];
-            B.j0 = ys[b] + 1;
-            B.j1 = ys[b + 1];
-            if (B.i1 <= B.i0 || B.j1 <= B.j0) continue;   // adjacent cut lines: no block between
-            const int mx = B.i1 - B.i0, my = B.j1 - B.j0;
-            if (mx > fkd::kPddMaxSide || my > fkd::kPddMaxSide)
-                return fail(FK_EINVAL, "a block between cut lines is wider than 64 nodes; cut finer");
-            B.tx = table_of(mx);
-            B.ty = table_of(my);
-            max_nodes = std::max(max_nodes, mx * my);
-            blocks.push_back(B);
-        }
-    // the node list becomes the interface (in the same longest-first order)
-    std::vector<uint8_t> on_x(d.nx, 0), on_y(d.ny, 0);
-    for (int32_t i = 0; i < n_cuts_x; ++i) on_x[cuts_x[i]] = 1;
-    for (int32_t i = 0; i < n_cuts_y; ++i) on_y[cuts_y[i]] = 1;
-    std::vector<int32_t> iface;
-    for (int32_t id : P0.interior)
-        if (on_x[id % d.nx] || on_y[id / d.nx]) iface.push_back(id);
+    PddPlan plan;
+    fk_status st = plan_pdd(s->P, cuts_x, n_cuts_x, cuts_y, n_cuts_y, plan);
+    if (st != FK_OK) return st;
     // on any failure below the solver is left as it was: no partial buffers
     // behind a retry, the host record unchanged
     auto drop = [s]() {
-        for (void **b : {(void **)&s->d_pdd_blocks, (void **)&s->d_pdd_tables, (void **)&s->d_pdd_rhs})
+        for (void **b : {(void **)&s->d_pdd_tasks, (void **)&s->d_pdd_tables, (void **)&s->d_pdd_rhs})
             if (*b) {
                 (void)hipFree(*b);
                 *b = nullptr;
             }
     };
+    const size_t nb = plan.blocks.size();
     hipError_t e = hipSuccess;
     const char *what = nullptr;
-    if (!blocks.empty()) {
-        if ((e = hipMalloc((void **)&s->d_pdd_blocks, blocks.size() * sizeof(fkd::PddBlock))) != hipSuccess ||
-            (e = hipMalloc((void **)&s->d_pdd_tables, tables.size() * sizeof(double))) != hipSuccess ||
-            (e = hipMalloc((void **)&s->d_pdd_rhs, P0.n_nodes() * sizeof(double2))) != hipSuccess)
+    if (nb > 0) {
+        if ((e = hipMalloc((void **)&s->d_pdd_tasks, nb * sizeof(fkd::PddTask))) != hipSuccess ||
+            (e = hipMalloc((void **)&s->d_pdd_tables, plan.tables.size() * sizeof(double))) != hipSuccess ||
+            (e = hipMalloc((void **)&s->d_pdd_rhs, s->P.n_nodes() * sizeof(double2))) != hipSuccess) {
             what = "hipMalloc(pdd)";
-        else if ((e = hipMemcpyAsync(s->d_pdd_blocks, blocks.data(), blocks.size() * sizeof(fkd::PddBlock),
-                                     hipMemcpyHostToDevice, s->stream)) != hipSuccess ||
-                 (e = hipMemcpyAsync(s->d_pdd_tables, tables.data(), tables.size() * sizeof(double),
-                                     hipMemcpyHostToDevice, s->stream)) != hipSuccess)
-            what = "hipMemcpyAsync(pdd tables)";
+        } else {
+            std::vector<fkd::PddTask> tasks(nb);
+            for (size_t i = 0; i < nb; ++i) {
+                const PddPlan::Block &B = plan.blocks[i];
+                tasks[i] = fkd::PddTask{0, B.i0, B.i1, B.j0, B.j1, 0, s->d_pdd_tables + B.tx,
+                                        s->d_pdd_tables + B.ty, s->d_pdd_rhs};
+            }
+            if ((e = hipMemcpyAsync(s->d_pdd_tasks, tasks.data(), nb * sizeof(fkd::PddTask), hipMemcpyHostToDevice,
+                                    s->stream)) != hipSuccess ||
+                (e = hipMemcpyAsync(s->d_pdd_tables, plan.tables.data(), plan.tables.size() * sizeof(double),
+                                    hipMemcpyHostToDevice, s->stream)) != hipSuccess ||
+                (e = hipStreamSynchronize(s->stream)) != hipSuccess)
+                what = "hipMemcpyAsync(pdd tables)";
+        }
     }
     // the host record changes only once the device has the new node list,
-    // instance record and queue
+    // instance record and queue; items sized for at least two per wave of
+    // the launch
     HostProblem P2 = s->P;
-    P2.interior = iface;
-    if (P2.par.paths_per_item == 0) {
-        // far fewer nodes than the grid: smaller items, at least two per
-        // persistent wave of the default launch (the bench cavity with lines
-        // 16, 32, 48: 128 paths per item 4.5% faster than 256; results do not
-        // depend on the item size)
-        int64_t ppi = P2.ppi;
-        while (ppi > 64 && (int64_t)iface.size() * ((P2.par.M + ppi - 1) / ppi) < 8192) ppi /= 2;
-        P2.ppi = (int32_t)ppi;
-        P2.items_per_node = (int32_t)((P2.par.M + ppi - 1) / ppi);
-    }
-    P2.n_items = (int64_t)iface.size() * P2.items_per_node;
+    apply_pdd(P2, plan, 2 * (int64_t)s->n_blocks * 4);
     fkd::Inst D = make_inst(P2, s->B);
     fkd::EngineQueue q;
     std::memset(&q, 0, sizeof(q));
@@ -293,8 +244,8 @@ fk_status fk_helmholtz_set_pdd(fk_solver *s, const int32_t *cuts_x, int32_t n_cu
     q.seg_inst[0] = 0;
     const bool touched = !what;   // the device node list is being rewritten
     if (!what &&
-        ((e = hipMemcpyAsync(s->B.nodes, iface.data(), iface.size() * sizeof(int32_t), hipMemcpyHostToDevice,
-                             s->stream)) != hipSuccess ||
+        ((e = hipMemcpyAsync(s->B.nodes, P2.interior.data(), P2.interior.size() * sizeof(int32_t),
+                             hipMemcpyHostToDevice, s->stream)) != hipSuccess ||
          (e = hipMemcpyAsync(s->d_inst, &D, sizeof(D), hipMemcpyHostToDevice, s->stream)) != hipSuccess ||
          (e = hipMemcpyAsync(s->d_queue, &q, sizeof(q), hipMemcpyHostToDevice, s->stream)) != hipSuccess ||
          (e = hipStreamSynchronize(s->stream)) != hipSuccess))
@@ -318,16 +269,30 @@ fk_status fk_helmholtz_set_pdd(fk_solver *s, const int32_t *cuts_x, int32_t n_cu
     }
     s->P = std::move(P2);
     s->pdd = true;
-    s->pdd_blocks = (int32_t)blocks.size();
-    s->pdd_max_nodes = max_nodes;
+    s->pdd_blocks = (int32_t)nb;
+    s->pdd_max_nodes = plan.max_nodes;
     return FK_OK;
 }
+
+fk_status fk_helmholtz_cancel(fk_solver *s)
+{
+    if (!s) return fail(FK_EINVAL, "solver is NULL");
+    s->cancel.store(1);
+    return FK_OK;
+}
+
+// Takes a pending cancel request (true: the caller stops with FK_ECANCELLED).
+static bool take_cancel(fk_solver *s) { return s->cancel.exchange(0) != 0; }
 
 fk_status fk_helmholtz_iterate(fk_solver *s, int32_t n_iters, fk_iter_report *last)
 {
     if (!s) return fail(FK_EINVAL, "solver is NULL");
     if (n_iters < 0) return fail(FK_EINVAL, "n_iters must be >= 0");
     for (int32_t i = 0; i < n_iters; ++i) {
+        if (take_cancel(s)) {
+            if (last) *last = s->last;
+            return fail(FK_ECANCELLED, "cancelled after iteration " + std::to_string(s->iter));
+        }
         fk_status st = run_one(s, last);
         if (st != FK_OK) return st;
     }
@@ -340,6 +305,10 @@ fk_status fk_helmholtz_solve(fk_solver *s, fk_iter_report *final_report)
     if (!s) return fail(FK_EINVAL, "solver is NULL");
     const double tol = s->P.par.tol;
     while (s->iter < s->P.par.max_iters) {
+        if (take_cancel(s)) {
+            if (final_report) *final_report = s->last;
+            return fail(FK_ECANCELLED, "cancelled after iteration " + std::to_string(s->iter));
+        }
         fk_iter_report r;
         fk_status st = run_one(s, &r);
         if (final_report) *final_report = r;
@@ -403,7 +372,7 @@ fk_status fk_helmholtz_destroy(fk_solver *s)
     if (s->ev0) (void)hipEventDestroy(s->ev0);
     if (s->ev1) (void)hipEventDestroy(s->ev1);
     if (s->h_status) (void)hipHostFree(s->h_status);
-    if (s->d_pdd_blocks) (void)hipFree(s->d_pdd_blocks);
+    if (s->d_pdd_tasks) (void)hipFree(s->d_pdd_tasks);
     if (s->d_pdd_tables) (void)hipFree(s->d_pdd_tables);
     if (s->d_pdd_rhs) (void)hipFree(s->d_pdd_rhs);
     if (s->own_arena && s->arena) (void)hipFree(s->arena);

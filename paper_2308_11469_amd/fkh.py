@@ -18,9 +18,9 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfk_helmholtz.so")
 
-FK_OK, FK_EINVAL, FK_ENOMEM, FK_EDEVICE, FK_EDIVERGED, FK_ENOTCONVERGED, FK_EBUSY = range(7)
+FK_OK, FK_EINVAL, FK_ENOMEM, FK_EDEVICE, FK_EDIVERGED, FK_ENOTCONVERGED, FK_EBUSY, FK_ECANCELLED = range(8)
 STATUS_NAMES = {0: "FK_OK", 1: "FK_EINVAL", 2: "FK_ENOMEM", 3: "FK_EDEVICE", 4: "FK_EDIVERGED",
-                5: "FK_ENOTCONVERGED", 6: "FK_EBUSY"}
+                5: "FK_ENOTCONVERGED", 6: "FK_EBUSY", 7: "FK_ECANCELLED"}
 
 _DOMAIN = {"rect": 0, "rect_minus_disc": 1, "rect_minus_box": 2}
 _SRC = {"zero": 0, "const": 1, "gaussian": 2}
@@ -81,6 +81,7 @@ class fk_engine_config(C.Structure):
 # every entry point of include/fk_helmholtz.h
 EXPORTS = ["fk_helmholtz_arena_bytes", "fk_helmholtz_create", "fk_helmholtz_iterate", "fk_helmholtz_solve",
            "fk_helmholtz_get", "fk_helmholtz_node_stats", "fk_helmholtz_set_iterate", "fk_helmholtz_set_pdd",
+           "fk_helmholtz_cancel", "fk_engine_node_stats", "fk_engine_set_iterate", "fk_engine_set_pdd",
            "fk_helmholtz_timing", "fk_helmholtz_step_static",
            "fk_helmholtz_destroy", "fk_helmholtz_last_error", "fk_debug_philox", "fk_debug_normals",
            "fk_helmholtz_debug_paths", "fk_engine_create", "fk_engine_add", "fk_engine_tick", "fk_engine_get",
@@ -118,6 +119,10 @@ def lib():
             "fk_helmholtz_step_static": [P(fk_domain), P(fk_source), P(fk_bc), P(fk_bc), P(fk_params), vp,
                                          C.c_int32, vp, vp, vp, P(fk_iter_report)],
             "fk_helmholtz_destroy": [vp],
+            "fk_helmholtz_cancel": [vp],
+            "fk_engine_node_stats": [vp, C.c_int32, i64p, i64p],
+            "fk_engine_set_iterate": [vp, C.c_int32, vp, C.c_int32, C.c_int32],
+            "fk_engine_set_pdd": [vp, C.c_int32, i32p, C.c_int32, i32p, C.c_int32],
             "fk_debug_philox": [C.c_uint64, u32p, C.c_int64, u32p],
             "fk_debug_normals": [C.c_int32, u32p, C.c_int64, dp],
             "fk_helmholtz_debug_paths": [vp, i32p, i64p, C.c_int64, i64p, dp, dp],
@@ -257,17 +262,26 @@ class Solver:
 
     def iterate(self, n=1):
         """Runs n iterations; returns the last report (dict).  A fired
-        divergence rule is reported as ``diverging`` (not raised)."""
+        divergence rule is reported as ``diverging`` (not raised); a cancelled
+        call raises FkError with status FK_ECANCELLED."""
         r = fk_iter_report()
         _check(lib().fk_helmholtz_iterate(self.h, int(n), C.byref(r)), allow=(FK_EDIVERGED,))
         return r.as_dict()
 
     def solve(self):
+        """Iterates to the stopping rule; the report carries ``status``
+        (FK_OK, FK_ENOTCONVERGED, FK_EDIVERGED or FK_ECANCELLED)."""
         r = fk_iter_report()
-        st = _check(lib().fk_helmholtz_solve(self.h, C.byref(r)), allow=(FK_EDIVERGED, FK_ENOTCONVERGED))
+        st = _check(lib().fk_helmholtz_solve(self.h, C.byref(r)),
+                    allow=(FK_EDIVERGED, FK_ENOTCONVERGED, FK_ECANCELLED))
         d = r.as_dict()
         d["status"] = STATUS_NAMES[st]
         return d
+
+    def cancel(self):
+        """Stops the iterate / solve call running on this solver in another
+        thread (or the next one) before its next iteration."""
+        _check(lib().fk_helmholtz_cancel(self.h))
 
     def get(self):
         p = self.problem
@@ -418,6 +432,29 @@ class Engine:
         se = np.zeros((p.ny, p.nx), dtype=np.complex128)
         _check(lib().fk_engine_get(self.h, int(slot), _dptr(u.view(np.float64)), _dptr(se.view(np.float64))))
         return u, se
+
+    def node_stats(self, slot):
+        p = self.problems[slot]
+        sj = np.zeros(p.nx * p.ny, dtype=np.int64)
+        cp = np.zeros(p.nx * p.ny, dtype=np.int64)
+        _check(lib().fk_engine_node_stats(self.h, int(slot), sj.ctypes.data_as(C.POINTER(C.c_int64)),
+                                          cp.ctypes.data_as(C.POINTER(C.c_int64))))
+        return sj, cp
+
+    def set_iterate(self, slot, u, n):
+        ub = np.ascontiguousarray(np.asarray(u, dtype=np.complex128))
+        _check(lib().fk_engine_set_iterate(self.h, int(slot), ub.ctypes.data_as(C.c_void_p), int(n), 0))
+
+    def set_pdd(self, slot, cuts_x, cuts_y):
+        """Probabilistic domain decomposition of a resident instance before
+        its first tick (as Solver.set_pdd).  Returns False when the engine
+        cannot hold it now (FK_ENOMEM)."""
+        cx = np.ascontiguousarray(np.asarray(cuts_x, dtype=np.int32))
+        cy = np.ascontiguousarray(np.asarray(cuts_y, dtype=np.int32))
+        i32p = C.POINTER(C.c_int32)
+        st = _check(lib().fk_engine_set_pdd(self.h, int(slot), cx.ctypes.data_as(i32p), len(cx),
+                                            cy.ctypes.data_as(i32p), len(cy)), allow=(FK_ENOMEM,))
+        return st == FK_OK
 
     def remove(self, slot):
         _check(lib().fk_engine_remove(self.h, int(slot)))

@@ -27,7 +27,9 @@ instance, so each result is bit-identical to the same request solved alone.
 """
 from __future__ import annotations
 
+import json
 import math
+import os
 import time
 from dataclasses import dataclass
 from typing import Callable, Dict, List, Optional
@@ -155,6 +157,15 @@ def theorem23_bound(p, sup_exit_time, sup_local_time) -> float:
 
 # ----------------------------------------------------------------- server
 
+def grid_cuts(n: int, spacing: int = 32) -> list:
+    """Interface lines every ``spacing`` nodes of an n-node grid side for the
+    probabilistic domain decomposition (blocks of spacing - 1 nodes, at most
+    64: the device block solver's limit)."""
+    if not 2 <= spacing <= 65:
+        raise ValueError("spacing must be in [2, 65]")
+    return list(range(spacing, n - 1, spacing))
+
+
 @dataclass
 class Request:
     rid: int
@@ -162,6 +173,9 @@ class Request:
     problem: object             # or None with ``make`` given
     seed_note: str = ""
     make: Optional[Callable[[], object]] = None   # builds the problem when first needed
+    # probabilistic domain decomposition (cuts_x, cuts_y), or None: paths
+    # from every unknown node
+    pdd: Optional[tuple] = None
 
     def get_problem(self):
         if self.problem is None and self.make is not None:
@@ -194,7 +208,8 @@ class Server:
 
     def __init__(self, engine, rho_max: float = 0.98, keep_results: bool = True,
                  clock: Callable[[], float] = time.perf_counter, sleep: Callable[[float], None] = time.sleep,
-                 max_queue: Optional[int] = None, on_tick: Optional[Callable[[dict], None]] = None):
+                 max_queue: Optional[int] = None, on_tick: Optional[Callable[[dict], None]] = None,
+                 log_path: Optional[str] = None):
         self.engine = engine
         self.rho_max = rho_max
         self.keep = keep_results
@@ -204,6 +219,16 @@ class Server:
         self.on_tick = on_tick
         self.ticks = 0
         self.tick_log: List[dict] = []
+        # JSON lines of ticks and finished requests (FKH_LOG names the file)
+        self.log_path = log_path if log_path is not None else os.environ.get("FKH_LOG")
+        self._log = None
+
+    def _emit(self, rec: dict):
+        if self.log_path:
+            if self._log is None:
+                self._log = open(self.log_path, "a")
+            self._log.write(json.dumps(rec) + "\n")
+            self._log.flush()
 
     def run(self, requests: List[Request], horizon: Optional[float] = None) -> Dict[int, Result]:
         pending = sorted(requests, key=lambda r: r.arrival)
@@ -236,6 +261,9 @@ class Server:
                     continue
                 try:
                     slot = self.engine.add(req.get_problem())
+                    if slot is not None and req.pdd is not None and not self.engine.set_pdd(slot, *req.pdd):
+                        self.engine.remove(slot)      # its block data do not fit now
+                        slot = None
                 except ValueError as ex:       # invalid problem description
                     res.outcome = "invalid: %s" % ex
                     res.completed = self.clock() - t0
@@ -269,6 +297,10 @@ class Server:
             now = self.clock() - t0
             self.tick_log.append(dict(tick=self.ticks, t=now, resident=len(resident), queued=len(queue),
                                       arrived=i))
+            if self.log_path:
+                self._emit(dict(event="tick", **self.tick_log[-1],
+                                path_steps=int(sum(r.get("path_steps", 0) for r in reps.values())),
+                                step_ms=max((r.get("step_ms", 0.0) for r in reps.values()), default=0.0)))
             if self.on_tick is not None:
                 self.on_tick(self.tick_log[-1])
             for slot, rep in reps.items():
@@ -293,6 +325,15 @@ class Server:
                     del resident[slot]
                     res.outcome = done
                     res.completed = now
+                    self._emit(dict(event="done", rid=res.rid, outcome=done, iterations=res.iterations,
+                                    arrival=res.arrival, admitted=res.admitted, completed=res.completed,
+                                    latency=res.latency, path_steps=res.path_steps))
+        for r in results.values():
+            if r.outcome in ("rejected", "queue_full", "too_large") or r.outcome.startswith("invalid"):
+                self._emit(dict(event="turned_away", rid=r.rid, outcome=r.outcome, arrival=r.arrival))
+        if self._log is not None:
+            self._log.close()
+            self._log = None
         return results
 
 

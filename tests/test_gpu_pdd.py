@@ -151,3 +151,91 @@ def test_pdd_argument_checks(bad):
     with pytest.raises(ValueError):
         s.set_pdd(cx, cy)
     s.close()
+
+
+def test_pdd_item_size_with_m_not_a_power_of_two():
+    # the item size re-derived for the interface list stays a multiple of 64
+    # and never changes the result: automatic against a fixed 64 paths
+    p = W.cavity_65(k=2.0).replace(nx=49, ny=49, M=150, h=1e-3)
+    cuts = [12, 24, 36]
+    out = []
+    for ppi in (0, 64, 192):
+        s = fkh.Solver(p, paths_per_item=ppi)
+        s.set_pdd(cuts, cuts)
+        s.iterate(2)
+        out.append(s.get()[0])
+        s.close()
+    assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
+
+
+def _pdd_engine(precision, n=8):
+    return fkh.Engine(n, precision=precision, max_grid_nodes=1 << 16, max_items=1 << 18, max_table=1 << 14,
+                      max_instance_nodes=1 << 14)
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_engine_pdd_alone_mix_and_solver_bit_identical(precision):
+    # two decomposed instances (different grids and cuts) batched with two
+    # full Monte Carlo instances: each result equals the single-instance
+    # solver's, whatever shares the launch and its block-solve pass
+    a = (W.cavity_small().replace(nx=33, ny=33, M=128, seed=5, precision=precision), [8, 16, 24], [11, 20])
+    b = (W.cavity_source(precision=precision).replace(nx=29, ny=21, x1=1.4, M=96, h=1e-3, alpha=20.0,
+                                                      damping=1.5), [5, 17], [11])
+    plain = [W.cavity_small().replace(precision=precision, M=256, seed=21),
+             W.scatter_problem(k=2.0, theta=1.0, N=21, M=128, seed=5007, precision=precision, h=2e-3,
+                               table_len=2048)]
+    ticks = 3
+    ref = []
+    for p, cx, cy in (a, b):
+        s = fkh.Solver(p, paths_per_item=64)
+        s.set_pdd(cx, cy)
+        s.iterate(ticks)
+        ref.append(s.get()[0])
+        s.close()
+        e = _pdd_engine(precision)
+        sl = e.add(p, paths_per_item=64)
+        assert e.set_pdd(sl, cx, cy)
+        for _ in range(ticks):
+            e.tick()
+        alone = e.get(sl)[0]
+        e.close()
+        assert np.array_equal(alone, ref[-1])
+    e = _pdd_engine(precision)
+    slots = [e.add(p, paths_per_item=64) for p in plain]
+    sa = e.add(a[0], paths_per_item=64)
+    assert e.set_pdd(sa, a[1], a[2])
+    sb = e.add(b[0], paths_per_item=64)
+    assert e.set_pdd(sb, b[1], b[2])
+    for _ in range(ticks):
+        e.tick()
+    say("engine pdd mix", precision)
+    assert np.array_equal(e.get(sa)[0], ref[0]) and np.array_equal(e.get(sb)[0], ref[1])
+    mixed_plain = [e.get(s)[0] for s in slots]
+    # a decomposition may only be set before the instance's first tick
+    with pytest.raises(ValueError):
+        e.set_pdd(sa, a[1], a[2])
+    e.close()
+    for p, g in zip(plain, mixed_plain):
+        s = fkh.Solver(p, paths_per_item=64)
+        s.iterate(ticks)
+        assert np.array_equal(s.get()[0], g)
+        s.close()
+
+
+def test_engine_pdd_matches_oracle():
+    p, cx, cy = _cases()["plain_33"]
+    e = _pdd_engine(64)
+    sl = e.add(p)
+    assert e.set_pdd(sl, cx, cy)
+    ids = pdd.interface_ids(p, cx, cy)
+    u = None
+    for it in range(2):
+        e.tick()
+        g, _ = e.get(sl)
+        sj, _ = e.node_stats(sl)
+        orc = fkmc.fk_nodes(p, u, it, ids)
+        assert_fp64_node_parity(g.ravel()[ids], sj[ids], orc, p.M, label="engine pdd it %d" % it)
+        ref = pdd.fill_blocks(p, u, frame_of(p, g, ids), cx, cy)
+        assert np.max(np.abs(g - ref)) <= 1e-11 * max(1.0, np.abs(ref).max())
+        u = g
+    e.close()

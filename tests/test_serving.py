@@ -63,6 +63,14 @@ class ScriptedEngine:
         del self.res[slot]
         self.log.append(("remove", slot))
 
+    def set_pdd(self, slot, cx, cy):
+        # block data of a decomposition: fits while the pool has room for it
+        p, n = self.res[slot]
+        used = sum(self.footprint(q) for q, _ in self.res.values())
+        ok = used + len(cx) + len(cy) <= self.pool
+        self.log.append(("set_pdd", slot, tuple(cx), tuple(cy), ok))
+        return ok
+
 
 def req(rid, t, N=40, k=1.0, max_iters=40):
     p = W.Problem(name="r%d" % rid, nx=N, ny=N, k=k, h=1e-4, M=64, max_iters=max_iters, tol=0.0)
@@ -174,3 +182,46 @@ def test_predicted_rho_rectangle_and_disc():
     lam = serving.lambda1(q)
     assert 12.5 < lam < 13.5                  # [-1,1]^2 minus the r = 0.25 disc
     assert serving.predicted_rho(q.replace(k=3.7)) > 0.98
+
+
+def test_pdd_requests_get_their_cuts_and_wait_when_they_do_not_fit():
+    a = req(0, 0.0)
+    a.pdd = ([10, 20], [15])
+    b = req(1, 0.0)
+    srv, eng, res = run([a, b])
+    assert ("set_pdd", 0, (10, 20), (15,), True) in eng.log
+    assert all(e[0] != "set_pdd" or e[1] == 0 for e in eng.log)
+    assert res[0].outcome == res[1].outcome == "converged"
+    # a decomposition that does not fit: the instance is taken out again and
+    # the request keeps waiting (here until nothing else is resident)
+    c = req(2, 0.0, N=70)
+    c.pdd = (list(range(1, 3000)), [])
+    d = req(3, 0.0, N=40)
+    srv, eng, res = run([d, c], pool=8000)
+    assert ("set_pdd", 1, tuple(range(1, 3000)), (), False) in eng.log and ("remove", 1) in eng.log
+    assert res[2].admitted_tick == 7 and res[2].outcome == "converged"
+
+
+def test_grid_cuts():
+    assert serving.grid_cuts(129, 32) == [32, 64, 96]
+    assert serving.grid_cuts(33, 32) == []
+    assert serving.grid_cuts(34, 32) == [32]
+    with pytest.raises(ValueError):
+        serving.grid_cuts(129, 80)
+
+
+def test_jsonl_log_of_ticks_and_requests(tmp_path):
+    import json
+    path = tmp_path / "serve.jsonl"
+    clk = VirtualClock()
+    eng = ScriptedEngine(clk, slots=2)
+    srv = serving.Server(eng, clock=clk, sleep=clk.sleep, log_path=str(path))
+    res = srv.run([req(i, 0.0) for i in range(3)] + [req(9, 0.0, k=4.6)])
+    recs = [json.loads(ln) for ln in path.read_text().splitlines()]
+    ticks = [r for r in recs if r["event"] == "tick"]
+    done = [r for r in recs if r["event"] == "done"]
+    away = [r for r in recs if r["event"] == "turned_away"]
+    assert len(ticks) == srv.ticks and ticks[0]["resident"] == 2 and ticks[0]["path_steps"] == 2000
+    assert sorted(r["rid"] for r in done) == [0, 1, 2] and all(r["iterations"] == 7 for r in done)
+    assert [r["rid"] for r in away] == [9] and away[0]["outcome"] == "rejected"
+    assert all(math.isclose(r["latency"], res[r["rid"]].latency) for r in done)
