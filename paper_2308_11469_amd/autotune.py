@@ -85,7 +85,11 @@ class Tuner:
         os.replace(tmp, self.cache_path)
 
     def best(self, problem):
-        """Best launch parameters for the problem's shape (cached)."""
+        """Best launch parameters for the problem's shape (cached).  When the
+        proxy has fewer paths than the problem, the proxy's winner is timed
+        once more at the full M against the library's own choice, and the
+        faster of the two is kept (the item count, and so the balance of the
+        launch, depends on M)."""
         key = shape_key(problem)
         hit = self.cache.get(key)
         if hit is not None:
@@ -100,7 +104,24 @@ class Tuner:
         # the library's own choice, for comparison
         default = float(self.measure(proxy, AUTO))
         self.timed += 1
-        self.cache[key] = {"config": cfg, "path_steps_per_s": rate, "auto_path_steps_per_s": default,
-                           "proxy_paths": int(proxy.M), "candidates": len(results)}
+        rec = {"config": cfg, "path_steps_per_s": rate, "auto_path_steps_per_s": default,
+               "proxy_paths": int(proxy.M), "candidates": len(results)}
+        if int(proxy.M) < int(problem.M):
+            full_best = float(self.measure(problem, cfg))
+            full_auto = float(self.measure(problem, AUTO))
+            self.timed += 2
+            rec.update(full_paths=int(problem.M), full_path_steps_per_s=full_best,
+                       full_auto_path_steps_per_s=full_auto)
+            if full_auto > full_best:
+                rec["config"] = dict(AUTO)
+                rec["kept"] = "auto at full M"
+            cfg = rec["config"]
+        self.cache[key] = rec
         self._save()
         return dict(cfg)
+
+    def instance_config(self, problem):
+        """The per-instance part of best() (item size and gather layout),
+        for admission into the batched engine, whose launch width is its own."""
+        cfg = self.best(problem)
+        return {"paths_per_item": cfg["paths_per_item"], "gather_layout": cfg["gather_layout"]}

@@ -12,6 +12,8 @@
 // No MFMA: nothing on this path is a dense contraction.  The stepping loop is
 // bound by VALU issue (Philox integer products, transcendentals, the bilinear
 // gather of u_n and the FP arithmetic of the step).
+#include <type_traits>
+
 #include "fk_device.hpp"
 #include "fk_internal.hpp"
 
@@ -39,6 +41,7 @@ template <class R> struct Consts {
     R hx0, hx1, hy0, hy1;   // box hole for the exit test (FP32: rounded inward)
     R rx0, rx1, ry0, ry1;   // reflection thresholds (FP32: faces rounded inward)
     R lx0, lx1, ly0, ly1;   // faces as R (mirrors and the feet of mirror moves)
+    R lx0l, lx1l, ly0l, ly1l;   // FP32: the faces minus their binary32 values (FP64: 0)
     R kk;                   // k (the Robin coupling i k u_n on a reflecting edge)
     double ih;              // 1 / h
     R src_re, src_im, src_cx, src_cy, src_c;
@@ -75,6 +78,10 @@ template <class R> struct Consts {
           key0(D.key0), key1(D.key1),
           tab(T)
     {
+        lx0l = (R)(D.x0 - (double)lx0);
+        lx1l = (R)(D.x1 - (double)lx1);
+        ly0l = (R)(D.y0 - (double)ly0);
+        ly1l = (R)(D.y1 - (double)ly1);
         if (sizeof(R) == 4) {
             ex0 = (R)D.x0_rd; ex1 = (R)D.x1_ru; ey0 = (R)D.y0_rd; ey1 = (R)D.y1_ru;
             hx0 = (R)D.bx0_ru; hx1 = (R)D.bx1_rd; hy0 = (R)D.by0_ru; hy1 = (R)D.by1_rd;
@@ -108,7 +115,12 @@ template <class R> struct Consts {
 // so its rounding error does not grow with the path length.
 template <class R> struct PathState {
     R x, y;       // position
+    R xl, yl;     // FP32: the rounding error of the position, carried by a
+                  // compensated addition at every step (x + xl is the position
+                  // to far below an ulp of x); FP64: unused, 0
     double ar, ai;  // sum of the integrand over the left points
+    double lr, li;  // reflecting edge: sum of the deferred local-time terms (batched
+                    // evaluation), kept apart so that its value depends on the path alone
     double w;     // discount e^{-(alpha - k^2) t h} at the current point (1 without a shift)
     int t;        // steps taken
 };
@@ -195,6 +207,68 @@ __device__ __forceinline__ Mirror<R> reflect(const Consts<R> &K, R &x, R &y)
         m.fy = 3;
     }
     return m;
+}
+
+// The Euler step x + sigma z.  FP64: one multiply-add.  FP32, compensated:
+// d = sigma z + xl (the step and the carried rounding error, one multiply-add)
+// is added to x, and the exact rounding error of that sum (Fast2Sum: exact
+// for |x| >= |d|; within one step of the origin its error stays below an ulp
+// of d) becomes the new xl.  The position's drift over a path is then set by
+// the rounding of d (an ulp of the step, not of the position): on the
+// reflected paths of about 2000 steps, ~1e-8 against ~1e-6 uncompensated.
+__device__ __forceinline__ void move(const Consts<double> &K, double x, double, double z, double &nx, double &nl)
+{
+    nx = x + K.sigma * z;
+    nl = 0.0;
+}
+__device__ __forceinline__ void move(const Consts<float> &K, float x, float xl, float z, float &nx, float &nl)
+{
+    const float d = fmaf(K.sigma, z, xl);
+    nx = x + d;
+    nl = d - (nx - x);
+}
+
+// FP32 reflection with the compensated position: the overshoot past the
+// face (x0 = lx0 + lx0l, its binary32 value and the rest) is
+// o = (lx0 - x) + (lx0l - xl), exact in its leading part; the mirrored point
+// is the face plus o, again as a compensated pair, and the local time grows
+// by 2 o.  Same tests against the inward-rounded faces as the FP64 reflect.
+__device__ __forceinline__ void mirror_lo(float face, float face_l, float o, float &x, float &xl)
+{
+    x = face + o;
+    xl = face_l + (o - (x - face));
+}
+__device__ __forceinline__ Mirror<float> reflect_c(const Consts<float> &K, float &x, float &y, float &xl, float &yl)
+{
+    Mirror<float> m{0.0f, 0.0f, -1, -1};
+    if (x < K.rx0) {
+        const float o = (K.lx0 - x) + (K.lx0l - xl);
+        m.lx = 2.0f * o;
+        mirror_lo(K.lx0, K.lx0l, o, x, xl);
+        m.fx = 0;
+    } else if (x > K.rx1) {
+        const float o = (x - K.lx1) + (xl - K.lx1l);
+        m.lx = 2.0f * o;
+        mirror_lo(K.lx1, K.lx1l, -o, x, xl);
+        m.fx = 1;
+    }
+    if (y < K.ry0) {
+        const float o = (K.ly0 - y) + (K.ly0l - yl);
+        m.ly = 2.0f * o;
+        mirror_lo(K.ly0, K.ly0l, o, y, yl);
+        m.fy = 2;
+    } else if (y > K.ry1) {
+        const float o = (y - K.ly1) + (yl - K.ly1l);
+        m.ly = 2.0f * o;
+        mirror_lo(K.ly1, K.ly1l, -o, y, yl);
+        m.fy = 3;
+    }
+    return m;
+}
+// FP64 keeps its reflect (no compensation term)
+__device__ __forceinline__ Mirror<double> reflect_c(const Consts<double> &K, double &x, double &y, double &, double &)
+{
+    return reflect(K, x, y);
 }
 
 // Bilinear interpolation of u_n at (x, y): cell p = floor((x - x0)/dx)
@@ -373,9 +447,155 @@ __device__ __forceinline__ void local_time_term(const Inst &D, const Consts<R> &
     P.ai -= c * gi;
 }
 
+// The local-time moves of one trip, handed to the wave's batched evaluation
+// instead of being evaluated at once (reflecting edge, path kernels): up to
+// four per lane (bits of todo: step 1 x face, step 1 y face, step 2 x face,
+// step 2 y face, the chronological order), each with w dxi, the foot's
+// coordinate along its face and the face.
+template <class R> struct LtEvents {
+    uint32_t bits;     // todo (bits 0-3) | the four faces (2 bits each, from bit 4)
+    R dxi[4];          // increments of the local time
+    R coord[4];
+    double w1, w2;     // end-of-step discounts (1 without a shift)
+};
+
+// Batched local-time terms (reflecting edge).  Evaluated one move at a time,
+// the term runs for the whole wave whenever any lane mirrors (nearly every
+// trip, with one lane in ten active).  Instead the wave appends its moves to
+// a queue in LDS, in chronological order, and evaluates 64 of them at once,
+// one per lane; each owner then adds the results of its own moves, in queue
+// order, to its path's local-time sum.  That sum is kept apart from the
+// left-point sum, so a path's score depends on its own moves only, not on
+// when its wave happened to evaluate them.  A path's queued moves are
+// evaluated before its score (the wave drains the queue whenever a finishing
+// lane still owns a move).
+constexpr int kLtCap = 2 * kWave;   // queued moves per wave
+
+template <class R> struct LtStore {
+    double cw[kLtCap];      // w dxi
+    R coord[kLtCap];        // the foot's coordinate along its face
+    int32_t fo[kLtCap];     // face | owner lane << 2
+    double res_r[kWave], res_i[kWave];
+};
+struct LtNone {};
+
+template <class R> struct LtQueue {
+    LtStore<R> *s;
+    int count;                  // moves held (wave-uniform)
+    unsigned long long own0, own1;   // this lane's moves at queue positions 0..63 and 64..127
+};
+
+// Evaluates the first min(count, 64) queued moves, one per lane, and adds
+// each owner's results in order to its local-time sum; moves the rest down.
+// Every lane of the wave calls it.
 template <class R, int F>
+__device__ __forceinline__ void lt_eval(const Inst &D, const Consts<R> &K, LtQueue<R> &Q, R ik, PathState<R> &P)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int n = Q.count < kWave ? Q.count : kWave;
+    LtStore<R> &S = *Q.s;
+    if (lane < n) {
+        const int fo = S.fo[lane];
+        const int face = fo & 3;
+        const R c = S.coord[lane];
+        const R fx = face == 0 ? K.lx0 : (face == 1 ? K.lx1 : c);
+        const R fy = face == 2 ? K.ly0 : (face == 3 ? K.ly1 : c);
+        CellReads<R> g;
+        g.c = locate(K, fx, fy);
+        issue_reads(K, g.c.off, g);
+        R vr, vi;
+        value(g, vr, vi);
+        double gr = -(double)(ik * vi), gi = (double)(ik * vr);
+        if (K.robin_g2) {
+            const double xf = face == 0 ? D.x0 : (face == 1 ? D.x1 : (double)fx);
+            const double yf = face == 2 ? D.y0 : (face == 3 ? D.y1 : (double)fy);
+            const double2 g2 = robin_datum<F>(D, face, xf, yf);
+            gr += g2.x;
+            gi += g2.y;
+        }
+        const double cc = S.cw[lane] * K.ih;
+        S.res_r[lane] = cc * gr;
+        S.res_i[lane] = cc * gi;
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    unsigned long long mine = Q.own0;
+    while (mine) {
+        const int q = __ffsll((long long)mine) - 1;
+        mine &= mine - 1ull;
+        P.lr -= S.res_r[q];
+        P.li -= S.res_i[q];
+    }
+    const int rest = Q.count - n;
+    if (rest > 0) {
+        // positions 64.. move down to 0..
+        double cw = 0.0;
+        R co = (R)0;
+        int32_t fo = 0;
+        if (lane < rest) {
+            cw = S.cw[kWave + lane];
+            co = S.coord[kWave + lane];
+            fo = S.fo[kWave + lane];
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (lane < rest) {
+            S.cw[lane] = cw;
+            S.coord[lane] = co;
+            S.fo[lane] = fo;
+        }
+    }
+    Q.own0 = rest > 0 ? Q.own1 : 0ull;
+    Q.own1 = 0ull;
+    Q.count = rest;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Appends one kind of move of the trip (the lanes where `has`) to the queue,
+// evaluating a batch first when 64 are waiting (the queue then has room for
+// 64 more).  Every lane of the wave calls it.
+template <class R, int F>
+__device__ __forceinline__ void lt_push(const Inst &D, const Consts<R> &K, LtQueue<R> &Q, R ik, PathState<R> &P,
+                                        bool has, double cw, R coord, int face)
+{
+    const unsigned long long b = __ballot(has);
+    if (b == 0ull) return;
+    if (Q.count >= kWave) lt_eval<R, F>(D, K, Q, ik, P);
+    const int lane = threadIdx.x & (kWave - 1);
+    if (has) {
+        const int q = Q.count + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32),
+                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+        Q.s->cw[q] = cw;
+        Q.s->coord[q] = coord;
+        Q.s->fo[q] = face | (lane << 2);
+        if (q < kWave) Q.own0 |= 1ull << q;
+        else Q.own1 |= 1ull << (q - kWave);
+    }
+    Q.count += __popcll(b);
+}
+
+// The trip's moves (in the order of LtEvents) into the queue, then every
+// queued move if a finishing path (fin) owns one.
+template <class R, int F>
+__device__ __forceinline__ void lt_trip(const Inst &D, const Consts<R> &K, LtQueue<R> &Q, R ik, PathState<R> &P,
+                                        const LtEvents<R> &ev, bool fin)
+{
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+        lt_push<R, F>(D, K, Q, ik, P, ((ev.bits >> kk) & 1u) != 0u, (kk < 2 ? ev.w1 : ev.w2) * (double)ev.dxi[kk],
+                      ev.coord[kk], (int)((ev.bits >> (4 + 2 * kk)) & 3u));
+    if (__ballot(fin && (Q.own0 | Q.own1) != 0ull))
+        while (Q.count > 0) lt_eval<R, F>(D, K, Q, ik, P);
+}
+
+template <class R, int F, bool kDefer = false>
 __device__ __forceinline__ bool advance(const Inst &D, const Consts<R> &K, PathState<R> &P, uint32_t m,
-                                        uint32_t node, uint32_t ctr3, Coef<R> cu, bool &exited)
+                                        uint32_t node, uint32_t ctr3, Coef<R> cu, bool &exited,
+                                        LtEvents<R> *ev = nullptr)
 {
     // Both points' reads are issued after the normals, except in the build
     // for row-major copies.  (Issuing the current point's before the Philox
@@ -405,7 +625,9 @@ __device__ __forceinline__ bool advance(const Inst &D, const Consts<R> &K, PathS
     R z0x, z0y, z1x, z1y;
     normals(w.x, w.y, *K.tab, z0x, z0y);
     normals(w.z, w.w, *K.tab, z1x, z1y);
-    R x1 = P.x + K.sigma * z0x, y1 = P.y + K.sigma * z0y;
+    R x1, y1, x1l, y1l;
+    move(K, P.x, P.xl, z0x, x1, x1l);
+    move(K, P.y, P.yl, z0y, y1, y1l);
     if constexpr (early) {
         // the second pair stays ahead of the branch of the second step (the
         // compiler would move it there), and the second cell's reads follow
@@ -416,9 +638,11 @@ __device__ __forceinline__ bool advance(const Inst &D, const Consts<R> &K, PathS
     // a reflecting edge mirrors each step back into the rectangle
     const bool refl = (F & kFeatReflect) && K.reflect;
     Mirror<R> m1{(R)0, (R)0, -1, -1}, m2{(R)0, (R)0, -1, -1};
-    if (refl) m1 = reflect(K, x1, y1);
-    R x2 = x1 + K.sigma * z1x, y2 = y1 + K.sigma * z1y;
-    if (refl) m2 = reflect(K, x2, y2);
+    if (refl) m1 = reflect_c(K, x1, y1, x1l, y1l);
+    R x2, y2, x2l, y2l;
+    move(K, x1, x1l, z1x, x2, x2l);
+    move(K, y1, y1l, z1y, y2, y2l);
+    if (refl) m2 = reflect_c(K, x2, y2, x2l, y2l);
     const bool general = (F & kFeatGeneral) && K.general;
     bool out1, out2, second;
     if constexpr ((F & kFeatReflect) != 0) {
@@ -430,12 +654,28 @@ __device__ __forceinline__ bool advance(const Inst &D, const Consts<R> &K, PathS
         second = !out1 && P.t + 1 < K.jmax;
         // local time of the step(s) taken: up to one mirror move per face and
         // step (bits 0-3: step 1 x, step 1 y, step 2 x, step 2 y), each at
-        // the end-of-step discount.  Each lane works through its own moves,
-        // so the wave runs the term as often as its busiest lane needs (one
-        // move per trip, nearly always), not once per kind of move.
+        // the end-of-step discount.  The path kernels hand the moves to the
+        // wave's batched evaluation (a trip has a move in about one lane in
+        // ten); evaluated at once (single paths), each lane works through its
+        // own moves.
         uint32_t todo = (uint32_t)(m1.fx >= 0) | ((uint32_t)(m1.fy >= 0) << 1);
         if (second) todo |= ((uint32_t)(m2.fx >= 0) << 2) | ((uint32_t)(m2.fy >= 0) << 3);
-        if (todo) {
+        if constexpr (kDefer) {
+            // the moves in chronological order; the foot of an x-face move is
+            // (face, y of the mirrored point), of a y-face move (x, face)
+            ev->w1 = general ? P.w * K.q : 1.0;
+            ev->w2 = general ? ev->w1 * K.q : 1.0;
+            ev->bits = todo | ((uint32_t)(m1.fx & 3) << 4) | ((uint32_t)(m1.fy & 3) << 6) |
+                       ((uint32_t)(m2.fx & 3) << 8) | ((uint32_t)(m2.fy & 3) << 10);
+            ev->dxi[0] = m1.lx;
+            ev->coord[0] = y1;
+            ev->dxi[1] = m1.ly;
+            ev->coord[1] = x1;
+            ev->dxi[2] = m2.lx;
+            ev->coord[2] = y2;
+            ev->dxi[3] = m2.ly;
+            ev->coord[3] = x2;
+        } else if (todo) {
             const double w1 = general ? P.w * K.q : 1.0;
             const double w2 = general ? w1 * K.q : 1.0;
             do {
@@ -508,6 +748,10 @@ __device__ __forceinline__ bool advance(const Inst &D, const Consts<R> &K, PathS
     }
     P.x = second ? x2 : x1;
     P.y = second ? y2 : y1;
+    if constexpr (sizeof(R) == 4) {
+        P.xl = second ? x2l : x1l;
+        P.yl = second ? y2l : y1l;
+    }
     P.t += second ? 2 : 1;
     exited = second ? out2 : out1;
     return exited || P.t >= K.jmax;
@@ -536,7 +780,7 @@ __device__ __forceinline__ bool advance(const Inst &D, const Consts<R> &K, PathS
 constexpr int kTailLanes = FK_TAIL_LANES;   // a wave with no work left and at most this many active lanes
 
 template <class R> struct TailPath {
-    R x, y;
+    R x, y, xl, yl;
     double ar, ai, w;
     int t;
     uint32_t m, node;
@@ -569,19 +813,26 @@ __device__ __forceinline__ bool tail_pass(const Inst &D, const Consts<R> &K, Tai
     normals(wd.z, wd.w, *K.tab, z1x, z1y);
     // the points of every trip, in the order and form of the step loop
     R px = S.x, py = S.y, x1 = S.x, y1 = S.y, x2 = S.x, y2 = S.y;
+    R x1l = S.xl, y1l = S.yl, x2l = S.xl, y2l = S.yl;
     {
-        R cx = S.x, cy = S.y;
+        R cx = S.x, cy = S.y, cxl = S.xl, cyl = S.yl;
 #pragma unroll 1
         for (int i = 0; i < kWave; ++i) {
             const R a0 = lane_value(z0x, i), b0 = lane_value(z0y, i);
             const R a1 = lane_value(z1x, i), b1 = lane_value(z1y, i);
-            const R nx1 = cx + K.sigma * a0, ny1 = cy + K.sigma * b0;
-            const R nx2 = nx1 + K.sigma * a1, ny2 = ny1 + K.sigma * b1;
+            R nx1, ny1, nx2, ny2, nx1l, ny1l, nx2l, ny2l;
+            move(K, cx, cxl, a0, nx1, nx1l);
+            move(K, cy, cyl, b0, ny1, ny1l);
+            move(K, nx1, nx1l, a1, nx2, nx2l);
+            move(K, ny1, ny1l, b1, ny2, ny2l);
             if (lane == i) {
                 px = cx; py = cy; x1 = nx1; y1 = ny1; x2 = nx2; y2 = ny2;
+                x1l = nx1l; y1l = ny1l; x2l = nx2l; y2l = ny2l;
             }
             cx = nx2;
             cy = ny2;
+            cxl = nx2l;
+            cyl = ny2l;
         }
     }
     const int ts = S.t + 2 * lane;                      // steps taken before this lane's trip
@@ -656,6 +907,10 @@ __device__ __forceinline__ bool tail_pass(const Inst &D, const Consts<R> &K, Tai
     const bool sec_l = (sm >> l) & 1ull;
     S.x = lane_value(sec_l ? x2 : x1, l);
     S.y = lane_value(sec_l ? y2 : y1, l);
+    if constexpr (sizeof(R) == 4) {
+        S.xl = lane_value(sec_l ? x2l : x1l, l);
+        S.yl = lane_value(sec_l ? y2l : y1l, l);
+    }
     S.ar = ar;
     S.ai = ai;
     S.w = w;
@@ -686,19 +941,26 @@ __device__ __forceinline__ bool tail_pass_grouped(const Inst &D, const Consts<R>
     normals(wd.x, wd.y, *K.tab, z0x, z0y);
     normals(wd.z, wd.w, *K.tab, z1x, z1y);
     R px = S.x, py = S.y, x1 = S.x, y1 = S.y, x2 = S.x, y2 = S.y;
+    R x1l = S.xl, y1l = S.yl, x2l = S.xl, y2l = S.yl;
     {
-        R cx = S.x, cy = S.y;
+        R cx = S.x, cy = S.y, cxl = S.xl, cyl = S.yl;
 #pragma unroll 1
         for (int i = 0; i < G; ++i) {
             const R a0 = lane_from(z0x, base + i), b0 = lane_from(z0y, base + i);
             const R a1 = lane_from(z1x, base + i), b1 = lane_from(z1y, base + i);
-            const R nx1 = cx + K.sigma * a0, ny1 = cy + K.sigma * b0;
-            const R nx2 = nx1 + K.sigma * a1, ny2 = ny1 + K.sigma * b1;
+            R nx1, ny1, nx2, ny2, nx1l, ny1l, nx2l, ny2l;
+            move(K, cx, cxl, a0, nx1, nx1l);
+            move(K, cy, cyl, b0, ny1, ny1l);
+            move(K, nx1, nx1l, a1, nx2, nx2l);
+            move(K, ny1, ny1l, b1, ny2, ny2l);
             if (j == i) {
                 px = cx; py = cy; x1 = nx1; y1 = ny1; x2 = nx2; y2 = ny2;
+                x1l = nx1l; y1l = ny1l; x2l = nx2l; y2l = ny2l;
             }
             cx = nx2;
             cy = ny2;
+            cxl = nx2l;
+            cyl = ny2l;
         }
     }
     const int ts = S.t + 2 * j;
@@ -774,6 +1036,10 @@ __device__ __forceinline__ bool tail_pass_grouped(const Inst &D, const Consts<R>
     const bool sec_l = (sm >> (n - 1)) & 1ull;
     S.x = lane_from(sec_l ? x2 : x1, l);
     S.y = lane_from(sec_l ? y2 : y1, l);
+    if constexpr (sizeof(R) == 4) {
+        S.xl = lane_from(sec_l ? x2l : x1l, l);
+        S.yl = lane_from(sec_l ? y2l : y1l, l);
+    }
     S.ar = ar;
     S.ai = ai;
     S.w = w;
@@ -791,13 +1057,19 @@ struct Pending {
     bool exited, live;
 };
 
-template <class R>
+template <class R, bool kLt = false>
 __device__ __forceinline__ void park(Pending &Q, const PathState<R> &P, bool exited, int32_t node_idx)
 {
-    Q.x = (double)P.x;
-    Q.y = (double)P.y;
-    Q.ar = P.ar;
-    Q.ai = P.ai;
+    if constexpr (sizeof(R) == 4) {
+        Q.x = (double)P.x + (double)P.xl;   // the compensated position
+        Q.y = (double)P.y + (double)P.yl;
+    } else {
+        Q.x = (double)P.x;
+        Q.y = (double)P.y;
+    }
+    // with batched local-time terms, their sum joins the left-point sum here
+    Q.ar = kLt ? P.ar + P.lr : P.ar;
+    Q.ai = kLt ? P.ai + P.li : P.ai;
     Q.wj = P.w;
     Q.t = P.t;
     Q.node_idx = node_idx;
@@ -904,11 +1176,14 @@ __device__ __forceinline__ void flush_acc(const Inst &D, unsigned long long *acc
 constexpr int kScoreBatch = 40;
 
 template <class R>
-__device__ __forceinline__ void start(PathState<R> &P, R sx, R sy)
+__device__ __forceinline__ void start(PathState<R> &P, R sx, R sy, R sxl = (R)0, R syl = (R)0)
 {
     P.x = sx;
     P.y = sy;
+    P.xl = sxl;
+    P.yl = syl;
     P.ar = P.ai = 0.0;
+    P.lr = P.li = 0.0;
     P.w = 1.0;
     P.t = 0;
 }
@@ -960,6 +1235,14 @@ __device__ __forceinline__ void stream_paths(const Inst *__restrict__ insts, con
     __shared__ typename TablesOf<R>::type tables;
     setup_tables<R>(tables);
     __shared__ unsigned long long lds_acc[4][2][12];   // two node accumulators per wave
+    // the queue of local-time moves of each wave (reflecting edge only)
+    constexpr bool kLt = (F & kFeatReflect) != 0;
+    using LtS = typename std::conditional<kLt, LtStore<R>, LtNone>::type;
+    __shared__ LtS lt_store[4];
+    LtQueue<R> ltq;
+    if constexpr (kLt) ltq.s = (LtStore<R> *)&lt_store[threadIdx.x / kWave];
+    ltq.count = 0;
+    ltq.own0 = ltq.own1 = 0ull;
     NodeAcc A;
     A.buf0 = lds_acc[threadIdx.x / kWave][0];
     A.buf1 = lds_acc[threadIdx.x / kWave][1];
@@ -988,7 +1271,7 @@ __device__ __forceinline__ void stream_paths(const Inst *__restrict__ insts, con
         int32_t pool_node_idx = 0, pool_node = 0;
         A.node0 = A.node1 = -1;
         A.cur = 0;
-        R pool_sx = (R)0, pool_sy = (R)0;
+        R pool_sx = (R)0, pool_sy = (R)0, pool_sxl = (R)0, pool_syl = (R)0;
         bool more = true;       // the queue may hold further items of this instance
         auto open_item = [&](int64_t gg) {
             const int64_t item = gg - (seg > 0 ? Q->seg_end[seg - 1] : 0);
@@ -998,8 +1281,13 @@ __device__ __forceinline__ void stream_paths(const Inst *__restrict__ insts, con
             pool_end = pool_m + D.ppi < D.M ? pool_m + D.ppi : D.M;
             pool_node = D.nodes[pool_node_idx];
             const int32_t gi = pool_node % D.nx, gj = pool_node / D.nx;
-            pool_sx = (R)(D.x0 + (double)gi * D.dx);
-            pool_sy = (R)(D.y0 + (double)gj * D.dy);
+            // the start node, and in FP32 its rounding remainder (the
+            // compensated position starts at the node itself)
+            const double sx = D.x0 + (double)gi * D.dx, sy = D.y0 + (double)gj * D.dy;
+            pool_sx = (R)sx;
+            pool_sy = (R)sy;
+            pool_sxl = (R)(sx - (double)pool_sx);
+            pool_syl = (R)(sy - (double)pool_sy);
             // a new node takes the older accumulator (wave-uniform branch)
             if (A.cur == 0 && pool_node_idx != A.node0) {
                 flush_acc(D, A.buf1, A.node1);
@@ -1029,7 +1317,7 @@ __device__ __forceinline__ void stream_paths(const Inst *__restrict__ insts, con
                 const unsigned long long pend = __ballot(Qp.live);
                 if ((done & pend) || __popcll(done | pend) > kScoreBatch) flush();
                 if (fin) {
-                    park<R>(Qp, P, exited, node_idx);
+                    park<R, kLt>(Qp, P, exited, node_idx);
                     active = false;
                 }
             }
@@ -1062,7 +1350,7 @@ __device__ __forceinline__ void stream_paths(const Inst *__restrict__ insts, con
                     m = (uint32_t)(pool_m + rank);
                     node = pool_node;
                     node_idx = pool_node_idx;
-                    start(P, pool_sx, pool_sy);
+                    start(P, pool_sx, pool_sy, pool_sxl, pool_syl);
                     active = true;
                 }
                 const int64_t taken = (int64_t)__popcll(need);
@@ -1073,7 +1361,12 @@ __device__ __forceinline__ void stream_paths(const Inst *__restrict__ insts, con
             // no work left for this wave and few paths running: tail phase
             if (!(F & kFeatReflect) && !more && pool_m >= pool_end && __popcll(act) <= kTailLanes) break;
             bool fin = false, exited = false;
-            if (active) fin = advance<R, F>(D, K, P, m, (uint32_t)node, ctr3, cu, exited);
+            LtEvents<R> ev;
+            ev.bits = 0u;
+            if (active) fin = advance<R, F, kLt>(D, K, P, m, (uint32_t)node, ctr3, cu, exited, &ev);
+            // the trip's local-time moves join the wave's queue, in order; a
+            // finishing path's moves are evaluated before its score
+            if constexpr (kLt) lt_trip<R, F>(D, K, ltq, cu.ik, P, ev, fin);
             on_done(fin, exited);
         }
         if constexpr (!(F & kFeatReflect)) {
@@ -1097,6 +1390,12 @@ __device__ __forceinline__ void stream_paths(const Inst *__restrict__ insts, con
                     TailPath<R> S;
                     S.x = lane_from(P.x, owner);
                     S.y = lane_from(P.y, owner);
+                    S.xl = (R)0;
+                    S.yl = (R)0;
+                    if constexpr (sizeof(R) == 4) {
+                        S.xl = lane_from(P.xl, owner);
+                        S.yl = lane_from(P.yl, owner);
+                    }
                     S.ar = lane_from(P.ar, owner);
                     S.ai = lane_from(P.ai, owner);
                     S.w = lane_from(P.w, owner);
@@ -1109,11 +1408,18 @@ __device__ __forceinline__ void stream_paths(const Inst *__restrict__ insts, con
                     const int mine = __builtin_amdgcn_mbcnt_hi((uint32_t)(act >> 32),
                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)act, 0u)) * G;
                     const R nx = lane_from(S.x, mine), ny = lane_from(S.y, mine);
+                    R nxl = (R)0, nyl = (R)0;
+                    if constexpr (sizeof(R) == 4) {
+                        nxl = lane_from(S.xl, mine);
+                        nyl = lane_from(S.yl, mine);
+                    }
                     const double nar = lane_from(S.ar, mine), nai = lane_from(S.ai, mine), nw = lane_from(S.w, mine);
                     const int nt = lane_from(S.t, mine), nf = lane_from((int)f, mine), ne = lane_from((int)ex, mine);
                     if (active) {
                         P.x = nx;
                         P.y = ny;
+                        P.xl = nxl;
+                        P.yl = nyl;
                         P.ar = nar;
                         P.ai = nai;
                         P.w = nw;
@@ -1131,6 +1437,12 @@ __device__ __forceinline__ void stream_paths(const Inst *__restrict__ insts, con
                     TailPath<R> S;
                     S.x = lane_value(P.x, L);
                     S.y = lane_value(P.y, L);
+                    S.xl = (R)0;
+                    S.yl = (R)0;
+                    if constexpr (sizeof(R) == 4) {
+                        S.xl = lane_value(P.xl, L);
+                        S.yl = lane_value(P.yl, L);
+                    }
                     S.ar = lane_value(P.ar, L);
                     S.ai = lane_value(P.ai, L);
                     S.w = lane_value(P.w, L);
@@ -1142,6 +1454,8 @@ __device__ __forceinline__ void stream_paths(const Inst *__restrict__ insts, con
                     if (lane == L) {
                         P.x = S.x;
                         P.y = S.y;
+                        P.xl = S.xl;
+                        P.yl = S.yl;
                         P.ar = S.ar;
                         P.ai = S.ai;
                         P.w = S.w;
@@ -1525,7 +1839,8 @@ __global__ void fk_debug_paths_kernel(const Inst *__restrict__ inst, const int32
     const int32_t node = nodes[i];
     const int32_t gi = node % D.nx, gj = node / D.nx;
     PathState<R> P;
-    start(P, (R)(D.x0 + (double)gi * D.dx), (R)(D.y0 + (double)gj * D.dy));
+    const double sx = D.x0 + (double)gi * D.dx, sy = D.y0 + (double)gj * D.dy;
+    start(P, (R)sx, (R)sy, (R)(sx - (double)(R)sx), (R)(sy - (double)(R)sy));
     bool exited = false;
     while (!advance<R, kFeatAll>(D, K, P, (uint32_t)ms[i], (uint32_t)node, ctr3, cu, exited)) {
     }
@@ -1533,7 +1848,10 @@ __global__ void fk_debug_paths_kernel(const Inst *__restrict__ inst, const int32
     Pending Q;
     park<R>(Q, P, exited, 0);
     score_out[i] = score<kFeatAll>(D, Q);
-    xj[i] = make_double2((double)P.x, (double)P.y);
+    if constexpr (sizeof(R) == 4)
+        xj[i] = make_double2((double)P.x + (double)P.xl, (double)P.y + (double)P.yl);
+    else
+        xj[i] = make_double2((double)P.x, (double)P.y);
 }
 
 }  // namespace fkd

@@ -50,13 +50,17 @@ double lambda1_bounding_rect(const fk_domain &d)
 int32_t auto_paths_per_item(int64_t n_interior, int64_t M)
 {
     // Lanes stream across items, so items can be small; 256 paths (four per
-    // lane) keep the queue fine-grained without many fetches.  Fewer when an
-    // instance has too few paths in total to fill a few thousand items.
+    // lane) keep the queue fine-grained without many fetches.  Each item ends
+    // with a flush of its node sums (device-scope 64-bit atomics, performed
+    // beyond the per-XCD L2), so an instance with many paths takes items of up
+    // to 1024 paths while it keeps at least 65536 items (16 per resident wave
+    // of the default launch).  Fewer than 256 when an instance has too few
+    // paths in total to fill a few thousand items.
     int64_t p = 256;
+    while (p < 1024 && n_interior * ((M + 2 * p - 1) / (2 * p)) >= 65536) p *= 2;
     while (p > 64 && n_interior * ((M + p - 1) / p) < 4096) p /= 2;
     const int64_t mcap = ((M + 63) / 64) * 64;
     if (p > mcap) p = mcap;
-    (void)n_interior;
     return (int32_t)p;
 }
 

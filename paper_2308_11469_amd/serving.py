@@ -209,8 +209,11 @@ class Server:
     def __init__(self, engine, rho_max: float = 0.98, keep_results: bool = True,
                  clock: Callable[[], float] = time.perf_counter, sleep: Callable[[float], None] = time.sleep,
                  max_queue: Optional[int] = None, on_tick: Optional[Callable[[dict], None]] = None,
-                 log_path: Optional[str] = None):
+                 log_path: Optional[str] = None, tuner=None):
         self.engine = engine
+        # launch parameters per request shape (item size, gather layout) from
+        # the autotuner, or the library's own choice; results never depend on them
+        self.tuner = tuner
         self.rho_max = rho_max
         self.keep = keep_results
         self.clock = clock
@@ -260,7 +263,8 @@ class Server:
                     res.completed = self.clock() - t0
                     continue
                 try:
-                    slot = self.engine.add(req.get_problem())
+                    cfg = self.tuner.instance_config(req.get_problem()) if self.tuner is not None else {}
+                    slot = self.engine.add(req.get_problem(), **cfg)
                     if slot is not None and req.pdd is not None and not self.engine.set_pdd(slot, *req.pdd):
                         self.engine.remove(slot)      # its block data do not fit now
                         slot = None

@@ -25,12 +25,30 @@ def test_shape_key_ignores_k_seed_and_data_but_not_grid():
     assert autotune.shape_key(a) != autotune.shape_key(a.replace(precision=32))
 
 
+def test_proxy_choice_checked_at_full_m(tmp_path):
+    # the proxy prefers 1024-path items, the full problem does not: the
+    # library's own choice is kept
+    seen = []
+
+    def fake(problem, cfg):
+        seen.append((int(problem.M), cfg))
+        if cfg == autotune.AUTO:
+            return 10.0 if problem.M > 512 else 1.0
+        return cfg["paths_per_item"] / (100.0 if problem.M > 512 else 1.0)
+
+    t = autotune.Tuner(cache_path=str(tmp_path / "t.json"), proxy_paths=512, measure=fake)
+    p = W.cavity_65(precision=32)
+    assert t.best(p) == autotune.AUTO
+    assert (p.M, dict(paths_per_item=512, gather_layout="nodes", waves_per_cu=8)) in seen
+    assert t.cache[autotune.shape_key(p)]["kept"] == "auto at full M"
+    assert t.instance_config(p) == {"paths_per_item": 0, "gather_layout": "auto"}
+
+
 def test_best_picks_fastest_and_caches(tmp_path):
     calls = []
 
     def fake(problem, cfg):
         calls.append(cfg)
-        assert problem.M <= 512            # timed on the proxy
         if cfg == autotune.AUTO:
             return 1.0
         return cfg["paths_per_item"] * (2 if cfg["gather_layout"] == "cells" else 1) + cfg["waves_per_cu"]
@@ -41,7 +59,8 @@ def test_best_picks_fastest_and_caches(tmp_path):
     best = t.best(p)
     assert best == dict(paths_per_item=512, gather_layout="cells", waves_per_cu=16)
     n = len(calls)
-    assert n == len(autotune.candidates(p.replace(M=512))) + 1
+    # the proxy's candidates and the library's choice, then both at full M
+    assert n == len(autotune.candidates(p.replace(M=512))) + 3
     # second call: cache hit, nothing timed
     assert t.best(p.replace(k=3.5)) == best and len(calls) == n
     # a fresh tuner reads the file

@@ -225,3 +225,21 @@ def test_jsonl_log_of_ticks_and_requests(tmp_path):
     assert sorted(r["rid"] for r in done) == [0, 1, 2] and all(r["iterations"] == 7 for r in done)
     assert [r["rid"] for r in away] == [9] and away[0]["outcome"] == "rejected"
     assert all(math.isclose(r["latency"], res[r["rid"]].latency) for r in done)
+
+
+def test_tuner_sets_the_launch_parameters_of_admitted_instances():
+    class Tuner:
+        def instance_config(self, p):
+            return {"paths_per_item": 128, "gather_layout": "cells"}
+
+    class Eng(ScriptedEngine):
+        def add(self, p, **cfg):
+            self.log.append(("cfg", cfg))
+            return super().add(p)
+
+    clk = VirtualClock()
+    eng = Eng(clk)
+    srv = serving.Server(eng, clock=clk, sleep=clk.sleep, tuner=Tuner())
+    res = srv.run([req(0, 0.0), req(1, 0.0)])
+    assert [e for e in eng.log if e[0] == "cfg"] == [("cfg", {"paths_per_item": 128, "gather_layout": "cells"})] * 2
+    assert all(r.outcome == "converged" for r in res.values())
