@@ -61,11 +61,13 @@ def flops_per_step(precision, source=False):
     return FLOPS_PER_STEP[precision] + (FLOPS_GAUSSIAN_SOURCE if source else 0.0)
 
 
-def path_kernel_name(precision, features, row_major):
+def path_kernel_name(precision, features, row_major, lds=False):
     """The path kernel the single-instance solver launches (the library's
     choice in launch_stream)."""
     if precision == 64 and features == 0 and row_major:
         return "fk_stream_f64_l1"
+    if precision == 32 and lds:
+        return "fk_stream_f32_lds<%d>" % features
     return "fk_stream_f%d<%d>" % (precision, features)
 
 
@@ -227,11 +229,15 @@ def _timed_solver(p, steps, warmup, **kw):
     u, se = s.get()
     s.close()
     # the library keeps the gather copy row-major while it fits 80 KiB
-    # (automatic layout): FP32 8 bytes per node, FP64 16
-    row_major = kw.get("gather_layout", "auto") == "nodes" or (
-        kw.get("gather_layout", "auto") == "auto" and p.nx * p.ny * (8 if p.precision == 32 else 16) <= 80 * 1024)
+    # (automatic layout): FP32 8 bytes per node, FP64 16; a single FP32
+    # instance without a reflecting edge whose row-major copy fits 156 KiB has
+    # it staged in LDS
+    layout = kw.get("gather_layout", "auto")
+    node_bytes = 8 if p.precision == 32 else 16
+    lds = p.precision == 32 and not p.reflect and layout != "cells" and p.nx * p.ny * 8 <= 156 * 1024
+    row_major = layout == "nodes" or (layout == "auto" and (p.nx * p.ny * node_bytes <= 80 * 1024 or lds))
     return dict(reports=reports + timed, timed=timed, wall=wall, kern_ms=kern_ms, launches=launches, u=u, se=se,
-                row_major=row_major)
+                row_major=row_major, lds=lds)
 
 
 def _features(p):
@@ -247,7 +253,7 @@ def _roofline(p, run, workload):
     fl = flops_per_step(p.precision, p.src_kind == "gaussian")
     achieved = fl * steps_total / launches / avg_kernel_s / 1e12
     peak = PEAK_TFLOPS[p.precision]
-    kernel = path_kernel_name(p.precision, _features(p), run["row_major"])
+    kernel = path_kernel_name(p.precision, _features(p), run["row_major"], run["lds"])
     return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
             "traffic": measured_traffic(kernel, workload), "kernel": kernel,
             "kernel_ms_avg": avg_kernel_s * 1e3, "flops_per_path_step": fl,

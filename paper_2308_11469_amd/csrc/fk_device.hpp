@@ -38,6 +38,9 @@ constexpr int kFeatAll = kFeatDisc | kFeatSource | kFeatGeneral | kFeatReflect;
 // Not a feature: a build of the plain kernel for instances whose gather copy
 // is row-major (held in the vector L1), with its own instruction order.
 constexpr int kRowMajor = 16;
+// Not a feature: FP32 kernels of one instance whose row-major copy is staged
+// in LDS (a 1024-thread block per CU shares it).
+constexpr int kLdsGrid = 32;
 
 enum : int32_t { BC_ZERO = 0, BC_PLANE_WAVE = 1, BC_BILINEAR = 2, BC_TABLE = 3, BC_PLANE_WAVE_ROBIN = 4 };
 enum : int32_t { HOLE_NONE = 0, HOLE_DISC = 1, HOLE_BOX = 2 };

@@ -38,8 +38,11 @@ namespace fkk {
 // shift alpha != k^2 or a damping, bit 3 a reflecting edge
 // l1_grid: every instance reads a row-major copy (picks the four-wave build
 // of the plain FP64 kernel)
+// lds_bytes > 0: one FP32 instance without a reflecting edge whose row-major
+// copy (lds_bytes) is staged in LDS by 1024-thread blocks (n_blocks / 4 of them)
 hipError_t launch_stream(int precision, int features, const fkd::Inst *d_insts, const fkd::EngineQueue *Q,
-                         unsigned long long *head, int n_blocks, hipStream_t s, bool l1_grid = false);
+                         unsigned long long *head, int n_blocks, hipStream_t s, bool l1_grid = false,
+                         size_t lds_bytes = 0);
 hipError_t launch_reset(const fkd::Inst *d_insts, const int32_t *which, int32_t n, const int32_t *n_dev,
                         unsigned long long *head, hipStream_t s);
 hipError_t launch_update(const fkd::Inst *d_insts, const int32_t *which, int32_t n_inst, const int32_t *n_dev,

@@ -19,6 +19,9 @@
 
 namespace fkd {
 
+// bytes in LDS (address space 3): reads through it are ds_read instructions
+typedef __attribute__((address_space(3))) const unsigned char lds_u8;
+
 // Per-precision constants of an instance, hoisted out of the stepping loop.
 // The normals' lookup tables per precision (FP64 only; they live in LDS).
 template <class R> struct TablesOf { using type = F64Tables; };
@@ -65,7 +68,8 @@ template <class R> struct Consts {
     // same order, so both layouts fill the registers identically.
     uint32_t sx, sy, second;
     __amdgpu_buffer_rsrc_t grid;   // buffer resource of the iterate grid
-    __device__ Consts(const Inst &D, const typename TablesOf<R>::type *T)
+    const lds_u8 *lgrid;           // the row-major FP32 copy staged in LDS (kLdsGrid kernels)
+    __device__ Consts(const Inst &D, const typename TablesOf<R>::type *T, const lds_u8 *L = nullptr)
         : x0((R)D.x0), y0((R)D.y0), idx((R)D.idx), idy((R)D.idy), sigma((R)D.sigma), k2((R)D.k2),
           ox((R)(-D.x0 * D.idx)), oy((R)(-D.y0 * D.idy)),
           cxf((R)D.cx), cyf((R)D.cy), r2f((R)D.r2), band((R)(1e-5 * (D.r + 1.0))),
@@ -76,7 +80,7 @@ template <class R> struct Consts {
           cells(D.cells), q(D.q), alpha((R)D.alpha), damp((R)D.damp),
           general(D.alpha != D.k2 || D.damp != 0.0),
           key0(D.key0), key1(D.key1),
-          tab(T)
+          tab(T), lgrid(L)
     {
         lx0l = (R)(D.x0 - (double)lx0);
         lx1l = (R)(D.x1 - (double)lx1);
@@ -321,6 +325,7 @@ __device__ __forceinline__ void lerp(const Cell<R> &c, R u00r, R u00i, R u10r, R
 }
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ u32x4 grid_load(const __amdgpu_buffer_rsrc_t &g, uint32_t off)
 {
@@ -348,13 +353,27 @@ template <> struct CellReads<double> {
 // scheduler puts between them was measured to cost extra requests (the line
 // is not yet allocated, or already evicted), so the reads of a cell are
 // fenced off from the scheduler.
+// With the row-major FP32 copy staged in LDS (kLdsGrid), the same two
+// pairs of corners come from LDS, in 8-byte reads (a row offset is only
+// 8-byte aligned).
+template <int F = 0>
 __device__ __forceinline__ void issue_reads(const Consts<float> &K, uint32_t off, CellReads<float> &r)
 {
-    __builtin_amdgcn_sched_barrier(0);
-    r.a = grid_load(K.grid, off);
-    r.b = grid_load(K.grid, off + K.second);
-    __builtin_amdgcn_sched_barrier(0);
+    if constexpr ((F & kLdsGrid) != 0) {
+        typedef __attribute__((address_space(3))) const u32x2 lds_u2;
+        const lds_u2 *a = (const lds_u2 *)(K.lgrid + off);
+        const lds_u2 *b = (const lds_u2 *)(K.lgrid + off + K.second);
+        const u32x2 a0 = a[0], a1 = a[1], b0 = b[0], b1 = b[1];
+        r.a = u32x4{a0.x, a0.y, a1.x, a1.y};
+        r.b = u32x4{b0.x, b0.y, b1.x, b1.y};
+    } else {
+        __builtin_amdgcn_sched_barrier(0);
+        r.a = grid_load(K.grid, off);
+        r.b = grid_load(K.grid, off + K.second);
+        __builtin_amdgcn_sched_barrier(0);
+    }
 }
+template <int F = 0>
 __device__ __forceinline__ void issue_reads(const Consts<double> &K, uint32_t off, CellReads<double> &r)
 {
     r.a0 = grid_load(K.grid, off);
@@ -431,7 +450,7 @@ __device__ __forceinline__ void local_time_term(const Inst &D, const Consts<R> &
 {
     CellReads<R> g;
     g.c = locate(K, fx, fy);
-    issue_reads(K, g.c.off, g);
+    issue_reads<F>(K, g.c.off, g);
     R vr, vi;
     value(g, vr, vi);
     double gr = -(double)(ik * vi), gi = (double)(ik * vr);
@@ -502,7 +521,7 @@ __device__ __forceinline__ void lt_eval(const Inst &D, const Consts<R> &K, LtQue
         const R fy = face == 2 ? K.ly0 : (face == 3 ? K.ly1 : c);
         CellReads<R> g;
         g.c = locate(K, fx, fy);
-        issue_reads(K, g.c.off, g);
+        issue_reads<F>(K, g.c.off, g);
         R vr, vi;
         value(g, vr, vi);
         double gr = -(double)(ik * vi), gi = (double)(ik * vr);
@@ -612,7 +631,7 @@ __device__ __forceinline__ bool advance(const Inst &D, const Consts<R> &K, PathS
         // orders: +1-3% over both reads after the normals, +1% over the
         // second pair of normals run under both reads or under the second.)
         g0.c = locate(K, P.x, P.y);
-        issue_reads(K, g0.c.off, g0);
+        issue_reads<F>(K, g0.c.off, g0);
         asm volatile("" : "+v"(ctr0));
     }
     // The round keys k + r (Weyl constants) are loop-invariant; hoisted, all
@@ -633,7 +652,7 @@ __device__ __forceinline__ bool advance(const Inst &D, const Consts<R> &K, PathS
         // compiler would move it there), and the second cell's reads follow
         asm volatile("" : : "v"(z1x), "v"(z1y));
         g1.c = locate(K, x1, y1);
-        issue_reads(K, g1.c.off, g1);
+        issue_reads<F>(K, g1.c.off, g1);
     }
     // a reflecting edge mirrors each step back into the rectangle
     const bool refl = (F & kFeatReflect) && K.reflect;
@@ -694,10 +713,10 @@ __device__ __forceinline__ bool advance(const Inst &D, const Consts<R> &K, PathS
     if constexpr (!early) {
         g0.c = locate(K, P.x, P.y);
         g1.c = locate(K, x1, y1);
-        issue_reads(K, g0.c.off, g0);
+        issue_reads<F>(K, g0.c.off, g0);
         uint32_t o1 = g1.c.off;
         if (!early && K.cells) after_reads(o1, g0);
-        issue_reads(K, o1, g1);
+        issue_reads<F>(K, o1, g1);
     }
     R v0r, v0i, v1r, v1i;
     value(g0, v0r, v0i);
@@ -849,10 +868,10 @@ __device__ __forceinline__ bool tail_pass(const Inst &D, const Consts<R> &K, Tai
         CellReads<R> g0, g1;
         g0.c = locate(K, px, py);
         g1.c = locate(K, x1, y1);
-        issue_reads(K, g0.c.off, g0);
+        issue_reads<F>(K, g0.c.off, g0);
         uint32_t o1 = g1.c.off;
         if (K.cells) after_reads(o1, g0);
-        issue_reads(K, o1, g1);
+        issue_reads<F>(K, o1, g1);
         R v0r, v0i, v1r, v1i;
         value(g0, v0r, v0i);
         value(g1, v1r, v1i);
@@ -978,10 +997,10 @@ __device__ __forceinline__ bool tail_pass_grouped(const Inst &D, const Consts<R>
         CellReads<R> g0, g1;
         g0.c = locate(K, px, py);
         g1.c = locate(K, x1, y1);
-        issue_reads(K, g0.c.off, g0);
+        issue_reads<F>(K, g0.c.off, g0);
         uint32_t o1 = g1.c.off;
         if (K.cells) after_reads(o1, g0);
-        issue_reads(K, o1, g1);
+        issue_reads<F>(K, o1, g1);
         R v0r, v0i, v1r, v1i;
         value(g0, v0r, v0i);
         value(g1, v1r, v1i);
@@ -1234,11 +1253,29 @@ __device__ __forceinline__ void stream_paths(const Inst *__restrict__ insts, con
 {
     __shared__ typename TablesOf<R>::type tables;
     setup_tables<R>(tables);
-    __shared__ unsigned long long lds_acc[4][2][12];   // two node accumulators per wave
+    // waves per block: 4, or 16 when the block shares the staged FP32 grid
+    constexpr bool kLds = (F & kLdsGrid) != 0;
+    constexpr int kWpb = kLds ? 16 : 4;
+    __shared__ unsigned long long lds_acc[kWpb][2][12];   // two node accumulators per wave
     // the queue of local-time moves of each wave (reflecting edge only)
     constexpr bool kLt = (F & kFeatReflect) != 0;
     using LtS = typename std::conditional<kLt, LtStore<R>, LtNone>::type;
-    __shared__ LtS lt_store[4];
+    __shared__ LtS lt_store[kWpb];
+    // the staged copy of the (only) instance's row-major FP32 iterate
+    const lds_u8 *lgrid = nullptr;
+    if constexpr (kLds) {
+        extern __shared__ u32x2 lds_grid_words[];
+        typedef __attribute__((address_space(3))) u32x2 lds_w;
+        lds_w *L = (lds_w *)lds_grid_words;
+        if (Q->n_seg > 0) {
+            const Inst &D0 = insts[Q->seg_inst[0]];
+            const int nn = D0.nx * D0.ny;
+            const u32x2 *src = (const u32x2 *)D0.gather;
+            for (int i = threadIdx.x; i < nn; i += blockDim.x) L[i] = src[i];
+        }
+        __syncthreads();
+        lgrid = (const lds_u8 *)L;
+    }
     LtQueue<R> ltq;
     if constexpr (kLt) ltq.s = (LtStore<R> *)&lt_store[threadIdx.x / kWave];
     ltq.count = 0;
@@ -1258,7 +1295,7 @@ __device__ __forceinline__ void stream_paths(const Inst *__restrict__ insts, con
         int32_t seg = find_segment(Q, nseg, g);
         const int32_t inst = Q->seg_inst[seg];
         const Inst &D = insts[inst];
-        const Consts<R> K(D, &tables);
+        const Consts<R> K(D, &tables, lgrid);
         const bool use_u = D.state->use_u != 0;
         Coef<R> cu;
         cu.re = use_u ? ((F & kFeatGeneral) ? K.alpha : K.k2) : (R)0;
@@ -1501,6 +1538,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FK_WAV
 fk_stream_f64(const Inst *__restrict__ insts, const EngineQueue *__restrict__ Q, unsigned long long *head)
 {
     stream_paths<double, F>(insts, Q, head);
+}
+
+// FP32 with the row-major copy of u_n staged in LDS: one 1024-thread block
+// per CU shares it (up to about 141 x 141 nodes), single-instance launches only
+template <int F>
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(FK_WAVES_F32)))
+fk_stream_f32_lds(const Inst *__restrict__ insts, const EngineQueue *__restrict__ Q, unsigned long long *head)
+{
+    stream_paths<float, F | kLdsGrid>(insts, Q, head);
 }
 
 // the plain FP64 kernel at four waves, for a row-major copy in the vector L1
@@ -1873,9 +1919,34 @@ static void launch_stream_f(int precision, dim3 grid, dim3 block, const Inst *d_
         hipLaunchKernelGGL(fk_stream_f64<F>, grid, block, 0, s, d_insts, Q, head);
 }
 
-hipError_t launch_stream(int precision, int features, const Inst *d_insts, const EngineQueue *Q,
-                         unsigned long long *head, int n_blocks, hipStream_t s, bool l1_grid)
+template <int F>
+static hipError_t launch_lds(const Inst *d_insts, const EngineQueue *Q, unsigned long long *head, int n_blocks,
+                             size_t lds_bytes, hipStream_t s)
 {
+    hipError_t e = hipFuncSetAttribute((const void *)fk_stream_f32_lds<F>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds_bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(fk_stream_f32_lds<F>, dim3(n_blocks), dim3(1024), lds_bytes, s, d_insts, Q, head);
+    return hipGetLastError();
+}
+
+hipError_t launch_stream(int precision, int features, const Inst *d_insts, const EngineQueue *Q,
+                         unsigned long long *head, int n_blocks, hipStream_t s, bool l1_grid, size_t lds_bytes)
+{
+    if (precision == 32 && lds_bytes > 0 && (features & kFeatReflect) == 0) {
+        // the same waves in 1024-thread blocks (four 256-thread blocks each)
+        const int nb = n_blocks / 4 > 0 ? n_blocks / 4 : 1;
+        switch (features & kFeatAll) {
+        case 0: return launch_lds<0>(d_insts, Q, head, nb, lds_bytes, s);
+        case 1: return launch_lds<1>(d_insts, Q, head, nb, lds_bytes, s);
+        case 2: return launch_lds<2>(d_insts, Q, head, nb, lds_bytes, s);
+        case 3: return launch_lds<3>(d_insts, Q, head, nb, lds_bytes, s);
+        case 4: return launch_lds<4>(d_insts, Q, head, nb, lds_bytes, s);
+        case 5: return launch_lds<5>(d_insts, Q, head, nb, lds_bytes, s);
+        case 6: return launch_lds<6>(d_insts, Q, head, nb, lds_bytes, s);
+        default: return launch_lds<7>(d_insts, Q, head, nb, lds_bytes, s);
+        }
+    }
     dim3 grid(n_blocks), block(256);
     if (precision == 64 && (features & kFeatAll) == 0 && l1_grid) {
         hipLaunchKernelGGL(fk_stream_f64_l1, grid, block, 0, s, d_insts, Q, head);

@@ -141,7 +141,7 @@ static void host_bc(const HostProblem &P, const fk_bc &B, double x, double y, do
 }
 
 fk_status setup_problem(const fk_domain *domain, const fk_source *f, const fk_bc *g_outer, const fk_bc *g_inner,
-                        const fk_params *params, HostProblem &P)
+                        const fk_params *params, HostProblem &P, bool single_instance)
 {
     if (!domain || !params) return fail(FK_EINVAL, "domain and params are required");
     P.dom = *domain;
@@ -286,9 +286,14 @@ fk_status setup_problem(const fk_domain *domain, const fk_source *f, const fk_bc
     // Above that nearly every read misses to L2, and the cell-major copy
     // halves the L2 requests per step.
     const size_t node_bytes = p.precision == 32 ? 8 : 16;
+    // a single FP32 instance whose row-major copy fits LDS reads it from
+    // there (no L2 requests for the gather at all)
+    const bool lds_fit = single_instance && p.precision == 32 && !reflecting &&
+                         P.n_nodes() * node_bytes <= kLdsGridBytes;
     if (p.gather_layout == FK_GATHER_CELLS) P.cells = 1;
     else if (p.gather_layout == FK_GATHER_NODES) P.cells = 0;
-    else P.cells = P.n_nodes() * node_bytes > kL1GatherBytes ? 1 : 0;
+    else P.cells = (P.n_nodes() * node_bytes > kL1GatherBytes && !lds_fit) ? 1 : 0;
+    P.lds_grid = (lds_fit && !P.cells) ? 1 : 0;
     if (P.cells && P.n_cells() * 4 * node_bytes >= ((size_t)1 << 31))
         return fail(FK_EINVAL, "grid too large for the cell-major copy (2 GiB); use FK_GATHER_NODES");
     const int64_t nint = (int64_t)P.interior.size();

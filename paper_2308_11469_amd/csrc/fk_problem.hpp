@@ -27,6 +27,10 @@ fk_status hip_fail(hipError_t e, const char *what);
 // 2.40e11 against 2.28e11 path-steps/s) and cell-major from 129x129 on
 // (257x257: 2.39e11 against 1.35e11).
 constexpr size_t kL1GatherBytes = 80 * 1024;
+// Largest FP32 row-major copy a single-instance launch stages in LDS (a
+// 1024-thread block per CU holds it beside 3 KiB of node accumulators within
+// the CU's 160 KiB): about 141 x 141 nodes.
+constexpr size_t kLdsGridBytes = 156 * 1024;
 
 struct HostProblem {
     fk_domain dom{};
@@ -42,6 +46,7 @@ struct HostProblem {
     int32_t items_per_node = 0;
     int64_t n_items = 0;
     int32_t cells = 0;                // the gather copy of u_n is cell-major
+    int32_t lds_grid = 0;             // single-instance FP32: the row-major copy is staged in LDS
     // optional parts of the stepping loop this instance needs (bit 0 a hole,
     // bit 1 a source term, bit 2 a shift alpha != k^2 or damping, bit 3 a
     // reflecting edge); the path kernel is compiled per set
@@ -65,8 +70,11 @@ struct HostProblem {
 };
 
 // Validates and prepares a problem.  Returns FK_OK or FK_EINVAL (message set).
+// single_instance: the problem runs alone in its launches (the solver), so an
+// FP32 iterate that fits LDS is staged there (row-major copy; the automatic
+// layout picks it), which a batched launch of mixed instances cannot do.
 fk_status setup_problem(const fk_domain *domain, const fk_source *f, const fk_bc *g_outer, const fk_bc *g_inner,
-                        const fk_params *params, HostProblem &out);
+                        const fk_params *params, HostProblem &out, bool single_instance = false);
 
 // Device bytes of one instance's buffers (grids, node list, slots, stats,
 // table, state), each part 256-byte aligned.

@@ -68,7 +68,7 @@ fk_status fk_helmholtz_arena_bytes(const fk_domain *domain, const fk_bc *g_outer
 {
     if (!bytes) return fail(FK_EINVAL, "bytes is NULL");
     HostProblem P;
-    fk_status st = setup_problem(domain, nullptr, g_outer, nullptr, params, P);
+    fk_status st = setup_problem(domain, nullptr, g_outer, nullptr, params, P, true);
     if (st != FK_OK) return st;
     *bytes = solver_bytes(P);
     return FK_OK;
@@ -82,7 +82,7 @@ fk_status fk_helmholtz_create(const fk_domain *domain, const fk_source *f, const
     *out = nullptr;
     fk_solver *s = new (std::nothrow) fk_solver();
     if (!s) return fail(FK_ENOMEM, "host allocation failed");
-    fk_status st = setup_problem(domain, f, g_outer, g_inner, params, s->P);
+    fk_status st = setup_problem(domain, f, g_outer, g_inner, params, s->P, true);
     if (st != FK_OK) {
         delete s;
         return st;
@@ -149,7 +149,7 @@ static fk_status run_one(fk_solver *s, fk_iter_report *rep)
     FK_HIP(fkk::launch_reset(s->d_inst, nullptr, 1, nullptr, s->d_head, s->stream));
     FK_HIP(hipEventRecord(s->ev0, s->stream));
     FK_HIP(fkk::launch_stream(prec, s->P.features(), s->d_inst, s->d_queue, s->d_head, s->n_blocks, s->stream,
-                              s->P.cells == 0));
+                              s->P.cells == 0, s->P.lds_grid ? s->P.n_nodes() * 8 : 0));
     FK_HIP(hipEventRecord(s->ev1, s->stream));
     FK_HIP(fkk::launch_update(s->d_inst, nullptr, 1, nullptr, (int32_t)s->P.interior.size(), s->stream));
     if (s->pdd_blocks > 0)

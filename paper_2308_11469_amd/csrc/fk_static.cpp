@@ -59,7 +59,7 @@ fk_status fk_helmholtz_step_static(const fk_domain *domain, const fk_source *f, 
     if (n < 0) return fail(FK_EINVAL, "n must be >= 0");
     if (n > 0 && !u_n) return fail(FK_EINVAL, "u_n is required for n > 0 (NULL means u_0 = 0)");
     HostProblem P;
-    fk_status st = setup_problem(domain, f, g_outer, g_inner, params, P);
+    fk_status st = setup_problem(domain, f, g_outer, g_inner, params, P, true);
     if (st != FK_OK) return st;
     // record | queue | head | instance buffers, as in a solver's arena
     const size_t need = align256(sizeof(fkd::Inst)) + align256(sizeof(fkd::EngineQueue)) + 256 + instance_bytes(P);
@@ -91,7 +91,8 @@ fk_status fk_helmholtz_step_static(const fk_domain *domain, const fk_source *f, 
     FK_HIP(hipMemcpyAsync(d_queue, &q, sizeof(q), hipMemcpyHostToDevice, s));
     FK_HIP(fkk::launch_reset(d_inst, nullptr, 1, nullptr, d_head, s));
     FK_HIP(fkk::launch_stream(P.par.precision, P.features(), d_inst, d_queue, d_head,
-                              path_kernel_blocks(P.par.waves_per_cu), s, P.cells == 0));
+                              path_kernel_blocks(P.par.waves_per_cu), s, P.cells == 0,
+                              P.lds_grid ? P.n_nodes() * 8 : 0));
     FK_HIP(fkk::launch_update(d_inst, nullptr, 1, nullptr, (int32_t)P.interior.size(), s));
     FK_HIP(fkk::launch_advance(d_inst, nullptr, 1, nullptr, s));
     const size_t nn = P.n_nodes();

@@ -57,6 +57,7 @@ def test_headline_kernel_names_follow_the_library_choice():
     assert bench.path_kernel_name(64, 0, True) == "fk_stream_f64_l1"
     assert bench.path_kernel_name(64, 2, False) == "fk_stream_f64<2>"
     assert bench.path_kernel_name(32, 0, True) == "fk_stream_f32<0>"
+    assert bench.path_kernel_name(32, 2, True, lds=True) == "fk_stream_f32_lds<2>"
     assert bench.flops_per_step(64, True) == 60.0
 
 

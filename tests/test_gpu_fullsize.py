@@ -267,15 +267,15 @@ def test_annulus_shape3_bench_configuration_fp64_and_fp32():
     g32, _ = s32.get()
     s.close()
     s32.close()
-    # Reflected paths here run 2000 steps on average (up to ~2e4): FP32
-    # rounding of the position flips the exit decision of a few paths per
-    # node near the hole, and a path that escapes in one precision and is
-    # absorbed in the other differs by O(0.1) in score.  So the bar is per
-    # node fraction: 99.9% within 0.1 SE, none beyond 0.5 SE, RMS 0.01 SE.
+    # Reflected paths here run 2000 steps on average (up to ~2e4).  The FP32
+    # position is compensated (its drift is set by the rounding of the step,
+    # not of the position), so exit decisions agree with FP64 as on short
+    # paths: every node within 0.1 SE (measured: max 0.03 SE; uncompensated,
+    # one node in 15370 was at 0.18 SE).
     r = np.abs(interior_values(p, g32) - interior_values(p, g)) / np.abs(interior_values(p, se))
     say("annulus3 FP32 vs FP64: max %.4f SE, rms %.4f SE, %d of %d nodes above 0.1 SE"
         % (r.max(), np.sqrt(np.mean(r ** 2)), int((r > 0.1).sum()), r.size))
-    assert (r > 0.1).mean() <= 1e-3 and r.max() <= 0.5 and np.sqrt(np.mean(r ** 2)) <= 0.01
+    assert r.max() <= 0.1
 
 
 def test_pdd_cavity65_bench_configuration():
@@ -300,3 +300,27 @@ def test_pdd_cavity65_bench_configuration():
     frame.ravel()[iface] = g.ravel()[iface]
     ref = pdd.fill_blocks(p, u1, frame, cuts, cuts)
     assert np.max(np.abs(g - ref)) <= 1e-11 * max(1.0, np.abs(ref).max())
+
+
+def test_source129_fp32_lds_staged_copy_bit_identical():
+    # the 129 x 129 FP32 iterate (133 KB) fits LDS: the single-instance
+    # launch stages its row-major copy there (automatic layout); the
+    # cell-major copy read through L2, and the batched engine (no staging),
+    # give the same iterate bit for bit
+    p = W.cavity_source(precision=32).replace(M=1024)
+    out = []
+    for layout in ("auto", "cells"):
+        s = fkh.Solver(p, gather_layout=layout)
+        s.iterate(2)
+        out.append(s.get())
+        s.close()
+    e = fkh.Engine(1, precision=32, max_grid_nodes=p.nx * p.ny + 1024, max_items=1 << 20, max_table=16,
+                   max_instance_nodes=p.nx * p.ny)
+    sl = e.add(p)
+    e.tick()
+    e.tick()
+    out.append(e.get(sl))
+    e.close()
+    say("source129 FP32: LDS-staged, cells, engine")
+    for u, se in out[1:]:
+        assert np.array_equal(u, out[0][0]) and np.array_equal(se, out[0][1])
