@@ -303,6 +303,7 @@ def fp32_same_config(steps=3):
     rf = _roofline(p, run, HEADLINE_WORKLOAD)
     return dict(value=total / run["wall"], unit="path-steps/s", ms_per_step=run["wall"] / steps * 1e3,
                 kernel=rf["kernel"], kernel_ms_avg=rf["kernel_ms_avg"], roofline_frac=rf["frac"],
+                path_steps_per_launch=rf["path_steps_per_launch"], flops_per_path_step=rf["flops_per_path_step"],
                 traffic=rf["traffic"], valu_issue=rf["valu_issue"])
 
 
@@ -326,6 +327,7 @@ def cavity65(k, steps=5, warmup=2):
         out["fp%d" % prec] = dict(
             value=total / run["wall"], unit="path-steps/s", ms_per_step=ms, kernel=rf["kernel"],
             kernel_ms_avg=rf["kernel_ms_avg"], roofline_frac=rf["frac"], traffic=rf["traffic"],
+            path_steps_per_launch=rf["path_steps_per_launch"],
             valu_issue=rf["valu_issue"], iterations_per_solve=settle,
             solves_per_s=(1e3 / (ms * settle)) if settle else None,
             rms_error_vs_exact=float(np.sqrt(np.mean(np.abs(run["u"].ravel()[ids] - ex.ravel()[ids]) ** 2))))
@@ -507,7 +509,8 @@ def annulus_shape3(steps=3):
         out["fp%d" % prec] = dict(value=total / run["wall"], unit="path-steps/s",
                                   ms_per_step=run["wall"] / steps * 1e3, kernel=rf["kernel"],
                                   kernel_ms_avg=rf["kernel_ms_avg"], path_steps_per_iteration=total / steps,
-                                  roofline_frac=rf["frac"], valu_issue=rf["valu_issue"])
+                                  path_steps_per_launch=rf["path_steps_per_launch"],
+                                  roofline_frac=rf["frac"], traffic=rf["traffic"], valu_issue=rf["valu_issue"])
     return out
 
 

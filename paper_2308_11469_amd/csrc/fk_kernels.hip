@@ -1142,28 +1142,36 @@ __device__ __forceinline__ unsigned long long contribution(int i, double2 sc, bo
     return (i & 1) ? lo : hi;
 }
 
-// A wave's two LDS node accumulators: the node it takes paths from now and
-// the one before, whose long paths may still be running.  A new node reuses
-// the older accumulator after moving its sums to the node's slot.
+// A wave's LDS node accumulators, a ring of kNodeAcc: the node it takes
+// paths from now and the ones before, whose long paths may still be
+// running.  A new node takes the oldest accumulator after moving its sums
+// to that node's slot (device-scope atomics, performed beyond the per-XCD
+// L2).  With two, about 0.5% of the paths on the 65 x 65 cavity outlived two
+// node changes and went to global memory one by one (half of the launch's
+// 84 MB of writes); four keep nearly all of them in LDS.
+constexpr int kNodeAcc = 4;
 struct NodeAcc {
-    unsigned long long *buf0, *buf1;
-    int32_t node0, node1;
-    int cur;                        // 0: node0 is the current node, 1: node1
+    // most recent first: b0 holds the current node n0's sums (12 each); a new
+    // node evicts (b3, n3) and takes b3 as its b0 (node -1: none)
+    unsigned long long *b0, *b1, *b2, *b3;
+    int32_t n0, n1, n2, n3;
 };
 
 // Scores the parked paths of the wave and adds them to their node sums:
 // exact 64-bit LDS atomics (no return) into the accumulator of the path's
-// node, or, for a path that outlived two node changes of its wave, straight
-// to the node's slot in global memory.
+// node, or, for a path that outlived four node changes of its wave,
+// straight to the node's slot in global memory.
 template <int F>
 __device__ __forceinline__ void deposit_parked(const Inst &D, Pending &Q, const NodeAcc &A)
 {
     if (Q.live) {
         const double2 sc = score<F>(D, Q);
         const bool ok = fabs(sc.x) < 0x1p21 && fabs(sc.y) < 0x1p21;
-        unsigned long long *dst = Q.node_idx == A.node0   ? A.buf0
-                                  : Q.node_idx == A.node1 ? A.buf1
-                                                          : (unsigned long long *)(D.slots + Q.node_idx);
+        unsigned long long *dst = Q.node_idx == A.n0   ? A.b0
+                                  : Q.node_idx == A.n1 ? A.b1
+                                  : Q.node_idx == A.n2 ? A.b2
+                                  : Q.node_idx == A.n3 ? A.b3
+                                                       : (unsigned long long *)(D.slots + Q.node_idx);
 #pragma unroll 1
         for (int i = 0; i < kSlotSums; ++i) {
             const unsigned long long v = contribution(i, sc, ok, Q.t, !Q.exited);
@@ -1256,7 +1264,7 @@ __device__ __forceinline__ void stream_paths(const Inst *__restrict__ insts, con
     // waves per block: 4, or 16 when the block shares the staged FP32 grid
     constexpr bool kLds = (F & kLdsGrid) != 0;
     constexpr int kWpb = kLds ? 16 : 4;
-    __shared__ unsigned long long lds_acc[kWpb][2][12];   // two node accumulators per wave
+    __shared__ unsigned long long lds_acc[kWpb][kNodeAcc * 12];   // node accumulators per wave
     // the queue of local-time moves of each wave (reflecting edge only)
     constexpr bool kLt = (F & kFeatReflect) != 0;
     using LtS = typename std::conditional<kLt, LtStore<R>, LtNone>::type;
@@ -1281,9 +1289,14 @@ __device__ __forceinline__ void stream_paths(const Inst *__restrict__ insts, con
     ltq.count = 0;
     ltq.own0 = ltq.own1 = 0ull;
     NodeAcc A;
-    A.buf0 = lds_acc[threadIdx.x / kWave][0];
-    A.buf1 = lds_acc[threadIdx.x / kWave][1];
-    if ((threadIdx.x & (kWave - 1)) < 24) A.buf0[threadIdx.x & (kWave - 1)] = 0ull;
+    {
+        unsigned long long *w = lds_acc[threadIdx.x / kWave];
+        A.b0 = w;
+        A.b1 = w + 12;
+        A.b2 = w + 24;
+        A.b3 = w + 36;
+        if ((threadIdx.x & (kWave - 1)) < kNodeAcc * 12) w[threadIdx.x & (kWave - 1)] = 0ull;
+    }
     __builtin_amdgcn_wave_barrier();
     const int32_t nseg = Q->n_seg;
     const int64_t total = nseg > 0 ? Q->seg_end[nseg - 1] : 0;
@@ -1306,8 +1319,7 @@ __device__ __forceinline__ void stream_paths(const Inst *__restrict__ insts, con
         // wave-uniform pool: path indices [pool_m, pool_end) of one node
         int64_t pool_m = 0, pool_end = 0;
         int32_t pool_node_idx = 0, pool_node = 0;
-        A.node0 = A.node1 = -1;
-        A.cur = 0;
+        A.n0 = A.n1 = A.n2 = A.n3 = -1;
         R pool_sx = (R)0, pool_sy = (R)0, pool_sxl = (R)0, pool_syl = (R)0;
         bool more = true;       // the queue may hold further items of this instance
         auto open_item = [&](int64_t gg) {
@@ -1325,15 +1337,18 @@ __device__ __forceinline__ void stream_paths(const Inst *__restrict__ insts, con
             pool_sy = (R)sy;
             pool_sxl = (R)(sx - (double)pool_sx);
             pool_syl = (R)(sy - (double)pool_sy);
-            // a new node takes the older accumulator (wave-uniform branch)
-            if (A.cur == 0 && pool_node_idx != A.node0) {
-                flush_acc(D, A.buf1, A.node1);
-                A.node1 = pool_node_idx;
-                A.cur = 1;
-            } else if (A.cur == 1 && pool_node_idx != A.node1) {
-                flush_acc(D, A.buf0, A.node0);
-                A.node0 = pool_node_idx;
-                A.cur = 0;
+            // a new node takes the oldest accumulator (wave-uniform branch)
+            if (pool_node_idx != A.n0) {
+                flush_acc(D, A.b3, A.n3);
+                unsigned long long *const b = A.b3;
+                A.b3 = A.b2;
+                A.n3 = A.n2;
+                A.b2 = A.b1;
+                A.n2 = A.n1;
+                A.b1 = A.b0;
+                A.n1 = A.n0;
+                A.b0 = b;
+                A.n0 = pool_node_idx;
             }
         };
         open_item(g);
@@ -1505,8 +1520,10 @@ __device__ __forceinline__ void stream_paths(const Inst *__restrict__ insts, con
             }
         }
         flush();
-        flush_acc(D, A.buf0, A.node0);
-        flush_acc(D, A.buf1, A.node1);
+        flush_acc(D, A.b0, A.n0);
+        flush_acc(D, A.b1, A.n1);
+        flush_acc(D, A.b2, A.n2);
+        flush_acc(D, A.b3, A.n3);
     }
 }
 

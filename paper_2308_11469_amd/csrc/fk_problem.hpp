@@ -28,9 +28,9 @@ fk_status hip_fail(hipError_t e, const char *what);
 // (257x257: 2.39e11 against 1.35e11).
 constexpr size_t kL1GatherBytes = 80 * 1024;
 // Largest FP32 row-major copy a single-instance launch stages in LDS (a
-// 1024-thread block per CU holds it beside 3 KiB of node accumulators within
-// the CU's 160 KiB): about 141 x 141 nodes.
-constexpr size_t kLdsGridBytes = 156 * 1024;
+// 1024-thread block per CU holds it beside the 16 waves' node accumulators,
+// 6 KiB, within the CU's 160 KiB): about 139 x 139 nodes.
+constexpr size_t kLdsGridBytes = 152 * 1024;
 
 struct HostProblem {
     fk_domain dom{};

@@ -96,10 +96,14 @@ def test_gather_layout_sizes_and_validation(lib):
     grow = 64 * 64 * 32 - 65 * 65 * 8
     assert abs((cells - nodes) - grow) <= 256
     assert size(p32, "auto")[1] == nodes            # 33.8 KB row-major copy fits L1
-    # a single FP32 instance up to 156 KiB of row-major copy is staged in LDS
-    # (the solver's automatic layout keeps it row-major); above, cell-major
-    mid = p32.replace(nx=129, ny=129)
-    assert size(mid, "auto")[1] == size(mid, "nodes")[1] != size(mid, "cells")[1]
+    # a single FP32 instance up to 152 KiB of row-major copy (139 x 139
+    # nodes) is staged in LDS (the solver's automatic layout keeps it
+    # row-major); above, cell-major
+    for n in (129, 139):
+        mid = p32.replace(nx=n, ny=n)
+        assert size(mid, "auto")[1] == size(mid, "nodes")[1] != size(mid, "cells")[1]
+    over = p32.replace(nx=140, ny=140)
+    assert size(over, "auto")[1] == size(over, "cells")[1] != size(over, "nodes")[1]
     big = p32.replace(nx=257, ny=257)
     assert size(big, "auto")[1] == size(big, "cells")[1] != size(big, "nodes")[1]
     p64 = W.cavity_65(precision=64)

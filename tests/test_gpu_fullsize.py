@@ -302,12 +302,16 @@ def test_pdd_cavity65_bench_configuration():
     assert np.max(np.abs(g - ref)) <= 1e-11 * max(1.0, np.abs(ref).max())
 
 
-def test_source129_fp32_lds_staged_copy_bit_identical():
-    # the 129 x 129 FP32 iterate (133 KB) fits LDS: the single-instance
-    # launch stages its row-major copy there (automatic layout); the
-    # cell-major copy read through L2, and the batched engine (no staging),
-    # give the same iterate bit for bit
+@pytest.mark.parametrize("n", [129, 139])
+def test_source_fp32_lds_staged_copy_bit_identical(n):
+    # the 129 x 129 FP32 iterate (133 KB) fits LDS, and so does the largest
+    # that is staged (139 x 139, 155 KB beside the node accumulators): the
+    # single-instance launch stages its row-major copy there (automatic
+    # layout); the cell-major copy read through L2, and the batched engine
+    # (no staging), give the same iterate bit for bit
     p = W.cavity_source(precision=32).replace(M=1024)
+    if n != p.nx:
+        p = p.replace(nx=n, ny=n)
     out = []
     for layout in ("auto", "cells"):
         s = fkh.Solver(p, gather_layout=layout)
@@ -321,6 +325,6 @@ def test_source129_fp32_lds_staged_copy_bit_identical():
     e.tick()
     out.append(e.get(sl))
     e.close()
-    say("source129 FP32: LDS-staged, cells, engine")
+    say("source", n, "FP32: LDS-staged, cells, engine")
     for u, se in out[1:]:
         assert np.array_equal(u, out[0][0]) and np.array_equal(se, out[0][1])
