@@ -50,7 +50,10 @@ FLOPS_GAUSSIAN_SOURCE = 10.0
 # counters (scaled by a plain copy of known size), valid only for the kernel
 # sources they were taken on
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fk_stream_traffic.json")
-KERNEL_SOURCES = ["fk_kernels.hip", "fk_device.hpp", "fk_internal.hpp"]
+# the path kernels and the host code that picks their launch (item size,
+# gather layout, LDS staging): counter figures hold for these sources only
+KERNEL_SOURCES = ["fk_kernels.hip", "fk_device.hpp", "fk_internal.hpp", "fk_problem.cpp", "fk_problem.hpp",
+                  "fk_solver.cpp"]
 
 HEADLINE_WORKLOAD = ("unit-square cavity 129x129, Gaussian source (1+0.5i) at (0.3,0.6) sigma=0.05, "
                      "plane wave theta=pi/6, k=3.5, M=16384, h=5e-5, single instance")
