@@ -114,7 +114,7 @@ def _issue(k):
 
 
 ONLY = ("headline", "fp32_same_config", "cavity65", "batch256_tick", "served_vs_plain", "serving",
-        "serving_sweep", "annulus", "pdd")
+        "serving_sweep", "annulus", "pdd", "tuned_tick")
 
 
 def parse(argv=None):
@@ -368,6 +368,53 @@ def batch256_tick():
                 roofline_frac=FLOPS_PER_STEP[32] * steps / (kern_ms / 1e3) / 1e12 / PEAK_TFLOPS[32])
 
 
+def tuned_tick(n_sub=16):
+    """Every 16th rectangle of the 256-rectangle workload in one FP32 engine:
+    one tick (after a warm-up tick) with the library's own launch choice and
+    one with the autotuner's per-instance item size and gather layout
+    (proxy of 256 paths, item sizes 128-1024, both layouts, each proxy winner
+    checked at the full M against the library's choice; cached per shape in
+    a temporary file).  Launch parameters never change results, which is
+    checked here too; the tuning time is reported beside."""
+    import tempfile
+
+    import numpy as np
+    import torch
+    from paper_2308_11469_amd import autotune, fkh
+    from paper_2308_11469_amd import workloads as W
+    probs = W.rect_batch(256)[::n_sub]
+    nodes = sum(p.nx * p.ny for p in probs)
+    _log("tuned_tick: tuning %d shapes" % len(probs))
+    with tempfile.TemporaryDirectory() as d:
+        tuner = autotune.Tuner(cache_path=os.path.join(d, "tune.json"), proxy_paths=256,
+                               ppi=(128, 256, 512, 1024), waves=(16,))
+        t0 = time.perf_counter()
+        cfgs = [tuner.instance_config(p) for p in probs]
+        tune_s = time.perf_counter() - t0
+    out = {"instances": len(probs), "tune_s": tune_s, "timed_runs": tuner.timed,
+           "tuned_configs": sum(1 for c in cfgs if c["paths_per_item"] != 0)}
+    us = {}
+    for mode in ("auto", "tuned"):
+        _log("tuned_tick: %s" % mode)
+        eng = fkh.Engine(len(probs), precision=32, max_grid_nodes=nodes + 4096, max_items=1 << 31,
+                         max_table=16, max_instance_nodes=max(p.nx * p.ny for p in probs))
+        slots = [eng.add(p, **(c if mode == "tuned" else {})) for p, c in zip(probs, cfgs)]
+        assert all(s is not None for s in slots)
+        eng.tick()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = eng.tick()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        us[mode] = [eng.get(s)[0] for s in slots]
+        eng.close()
+        steps = sum(r["path_steps"] for r in reps.values())
+        out[mode] = {"tick_s": wall, "path_steps": int(steps), "value": steps / wall, "unit": "path-steps/s"}
+    out["tuned_over_auto"] = out["tuned"]["value"] / out["auto"]["value"]
+    out["bit_identical"] = all(np.array_equal(a, b) for a, b in zip(us["auto"], us["tuned"]))
+    return out
+
+
 def served_vs_plain(n_sub=16, spacing=32):
     """Solves/s at the stopping rule (settled, max |du| < tol or max_iters) on
     every 16th instance of the 256-rectangle workload:
@@ -585,6 +632,7 @@ def main(argv=None):
         "serving": serving_window,
         "annulus": annulus_shape3,
         "pdd": lambda: pdd_cavity65(a.k),
+        "tuned_tick": tuned_tick,
     }
     if a.only == "serving_sweep":
         cap = serving_window()["solves_per_s"]
