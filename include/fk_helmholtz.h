@@ -200,6 +200,19 @@ typedef struct fk_solver fk_solver;
 fk_status fk_helmholtz_arena_bytes(const fk_domain *domain, const fk_bc *g_outer,
                                    const fk_params *params, size_t *bytes);
 
+/* The work items a solver launches for this problem (the persistent stream
+ * kernel's queue).  Every unknown node's M paths are split into
+ * *items_large items of *paths_large paths first (0 and 0 when the caller
+ * fixed paths_per_item, or when too few nodes would share them), then
+ * *items_small items of up to *paths_small paths; *n_items = unknown nodes x
+ * (*items_large + *items_small).  The queue hands out every large item before
+ * the first small one.  Host-only like fk_helmholtz_arena_bytes; g_outer may
+ * be NULL unless it is a TABLE; any output pointer may be NULL.  The split
+ * never changes results (node sums are exact integers). */
+fk_status fk_helmholtz_work_items(const fk_domain *domain, const fk_bc *g_outer, const fk_params *params,
+                                  int64_t *n_items, int32_t *paths_large, int32_t *items_large,
+                                  int32_t *paths_small, int32_t *items_small);
+
 /* Validates the problem, classifies the grid nodes (unknown: interior or on
  * a reflecting edge; absorbing edge; hole), uploads the boundary data and
  * sets u_0 = 0.  device_arena: device memory of at least
@@ -258,10 +271,13 @@ fk_status fk_helmholtz_set_iterate(fk_solver *s, const double *u_reim, int32_t n
  * device as its own Dirichlet problem of the same Poisson step,
  *   (Delta_h - (alpha - k^2)) u_{n+1} = f - (alpha + i p) u_n,
  * 5-point Laplacian, boundary values = the new interface values and g, by
- * fast diagonalisation (DST-I in x and y).  The iteration report's
- * statistics (max_du, sup, max_se, noise_ratio, path_steps) cover the
- * interface nodes.  Host arrays, copied.  FK_EINVAL: not a plain rectangle
- * with an absorbing edge, called after the first iteration or twice, no cut,
+ * fast diagonalisation (DST-I in x and y).  With a hole (disc or box), a
+ * block with a hole node in it or on its frame is not a rectangle's
+ * Dirichlet problem: its unknown nodes keep their own paths, like the
+ * interface.  The iteration report's statistics (max_du, sup, max_se,
+ * noise_ratio, path_steps) cover the nodes that run paths.  Host arrays,
+ * copied.  FK_EINVAL: a reflecting edge, called after the first iteration or
+ * twice, no cut,
  * cuts not strictly increasing within [1, nx-2] / [1, ny-2], or a block
  * wider than 64 nodes (a second call is rejected even when the cuts left no
  * block).  Allocates its device tables (freed at destroy).  FK_ENOMEM (the

@@ -15,7 +15,14 @@ interface values is needed.  The subdomains are the blocks of unknown nodes
 between consecutive lines (or the rectangle's edge); each solves
 (Delta_h - (alpha - k^2)) U_{n+1} = f - (alpha + i p) U_n with the same
 5-point operator as ``fd.py``, here by sparse LU of the block's own matrix.
-Plain rectangles with an absorbing edge only.
+
+With a hole (the scattering problem's disc, or a box) a block that has a
+hole node in it or on its frame holds part of the hole's boundary: it is
+not the rectangle's Dirichlet problem any more.  Reading taken for those
+blocks: their unknown nodes keep the Feynman-Kac estimator (they join the
+interface in the first stage), and only the blocks clear of the hole are
+solved in the second.  An absorbing edge only (a reflecting edge has no
+Dirichlet frame).
 """
 from __future__ import annotations
 
@@ -27,8 +34,8 @@ from . import fd, fkmc
 
 
 def check(p, cuts_x, cuts_y):
-    if p.domain_kind != "rect" or getattr(p, "reflect", False):
-        raise ValueError("PDD here needs a plain rectangle with an absorbing edge")
+    if getattr(p, "reflect", False):
+        raise ValueError("PDD here needs an absorbing edge")
     for cuts, n in ((cuts_x, p.nx), (cuts_y, p.ny)):
         c = list(cuts)
         if any(not (1 <= v <= n - 2) for v in c) or any(b <= a for a, b in zip(c, c[1:])):
@@ -46,8 +53,9 @@ def interface_ids(p, cuts_x, cuts_y) -> np.ndarray:
     return ids[on].astype(np.int32)
 
 
-def blocks(p, cuts_x, cuts_y):
-    """The subdomains as index ranges [i0, i1) x [j0, j1) of unknown nodes."""
+def all_blocks(p, cuts_x, cuts_y):
+    """Every block between consecutive cut lines (or the edge), as index
+    ranges [i0, i1) x [j0, j1)."""
     xs = [0] + list(cuts_x) + [p.nx - 1]
     ys = [0] + list(cuts_y) + [p.ny - 1]
     out = []
@@ -57,6 +65,33 @@ def blocks(p, cuts_x, cuts_y):
             if i1 > i0 and j1 > j0:
                 out.append((i0, i1, j0, j1))
     return out
+
+
+def clear_of_hole(p, block) -> bool:
+    """No node of the block or of its frame lies in the hole."""
+    i0, i1, j0, j1 = block
+    return not np.any(fkmc.node_classes(p)[j0 - 1:j1 + 1, i0 - 1:i1 + 1] == 2)
+
+
+def blocks(p, cuts_x, cuts_y):
+    """The subdomains solved by finite differences: the blocks clear of the
+    hole (every block on a plain rectangle)."""
+    return [b for b in all_blocks(p, cuts_x, cuts_y) if clear_of_hole(p, b)]
+
+
+def mc_ids(p, cuts_x, cuts_y) -> np.ndarray:
+    """The nodes of the Feynman-Kac stage: the interface, and the unknown
+    nodes of the blocks that touch the hole; grid order."""
+    ids = set(interface_ids(p, cuts_x, cuts_y).tolist())
+    cls = fkmc.node_classes(p)
+    for blk in all_blocks(p, cuts_x, cuts_y):
+        if not clear_of_hole(p, blk):
+            i0, i1, j0, j1 = blk
+            for j in range(j0, j1):
+                for i in range(i0, i1):
+                    if cls[j, i] == 0:
+                        ids.add(j * p.nx + i)
+    return np.array(sorted(ids), dtype=np.int32)
 
 
 def block_solve(p, u_prev, u_frame, block):
@@ -104,9 +139,10 @@ def fill_blocks(p, u_prev, u_frame, cuts_x, cuts_y):
 
 def pdd_step(p, u_prev, n, cuts_x, cuts_y, nthreads=0):
     """U_{n+1} by PDD from U_n (u_prev, full grid; None for U_0 = 0):
-    Feynman-Kac at the interface nodes (``fkmc.fk_nodes``), then the blocks.
-    Returns (new full grid, the interface estimates)."""
-    ids = interface_ids(p, cuts_x, cuts_y)
+    Feynman-Kac at the interface nodes and at the nodes of blocks touching a
+    hole (``fkmc.fk_nodes``), then the other blocks.  Returns (new full
+    grid, the Feynman-Kac estimates)."""
+    ids = mc_ids(p, cuts_x, cuts_y)
     est = fkmc.fk_nodes(p, u_prev, n, ids, nthreads)
     frame = fkmc.boundary_grid(p)
     frame.ravel()[ids] = est["mean"]

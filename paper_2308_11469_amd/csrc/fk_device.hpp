@@ -103,10 +103,12 @@ struct Inst {
     double alpha, damp, q;                           // shift, damping p, q = exp(-(alpha - k^2) h)
     int64_t M, jmax;
     uint32_t key0, key1;
-    int32_t crn, ppi;                                // ppi: paths per item
-    int32_t items_per_node, cells;                   // cells: the gather copy is cell-major
+    int32_t crn, ppi;                                // ppi: paths per small item
+    int32_t items_per_node, cells;                   // small items per node; cells: the gather copy is cell-major
     int32_t prec, pad1;                              // 32 or 64: the instance's stepping precision
-    int64_t n_items;
+    int64_t n_items;                                 // all items (large, then small)
+    int64_t n_items_a;                               // large items (items_a per node, first in the queue)
+    int32_t ppi_a, items_a;                          // paths per large item, large items per node
     const int32_t *nodes;                            // interior node ids
     double2 *u64;                                    // iterate, FP64 master
     void *gather;                                    // copy of u_n the paths read: FP32 row-major nodes

@@ -326,7 +326,8 @@ fk_status fk_engine_add(fk_engine *e, const fk_domain *domain, const fk_source *
     S.tasks.clear();
     const double a = S.P.dom.x1 - S.P.dom.x0, b = S.P.dom.y1 - S.P.dom.y0;
     // mean exit time of a rectangle ~ 0.0351 * 2 a^2 b^2 / (a^2 + b^2) (unit square: 0.0351)
-    S.est_cost = 0.0351 * 2.0 * a * a * b * b / (a * a + b * b) / S.P.par.h * (double)S.P.ppi;
+    S.est_cost = 0.0351 * 2.0 * a * a * b * b / (a * a + b * b) / S.P.par.h * (double)S.P.par.M /
+                 (double)(S.P.items_a + S.P.items_per_node);
     fkd::Inst D = make_inst(S.P, S.B);
     const hipStream_t s = e->cap_stream;
     st = upload_instance(S.P, S.B, s);

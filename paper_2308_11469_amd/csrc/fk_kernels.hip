@@ -1324,10 +1324,20 @@ __device__ __forceinline__ void stream_paths(const Inst *__restrict__ insts, con
         bool more = true;       // the queue may hold further items of this instance
         auto open_item = [&](int64_t gg) {
             const int64_t item = gg - (seg > 0 ? Q->seg_end[seg - 1] : 0);
-            pool_node_idx = (int32_t)(item / D.items_per_node);
-            const int64_t chunk = item % D.items_per_node;
-            pool_m = chunk * D.ppi;
-            pool_end = pool_m + D.ppi < D.M ? pool_m + D.ppi : D.M;
+            if (item < D.n_items_a) {
+                // a large item: paths [chunk ppi_a, (chunk + 1) ppi_a) of its node
+                pool_node_idx = (int32_t)(item / D.items_a);
+                const int64_t chunk = item % D.items_a;
+                pool_m = chunk * D.ppi_a;
+                pool_end = pool_m + D.ppi_a;
+            } else {
+                // a small item, after the node's large ones
+                const int64_t it = item - D.n_items_a;
+                pool_node_idx = (int32_t)(it / D.items_per_node);
+                const int64_t chunk = it % D.items_per_node;
+                pool_m = (int64_t)D.items_a * D.ppi_a + chunk * D.ppi;
+                pool_end = pool_m + D.ppi < D.M ? pool_m + D.ppi : D.M;
+            }
             pool_node = D.nodes[pool_node_idx];
             const int32_t gi = pool_node % D.nx, gj = pool_node / D.nx;
             // the start node, and in FP32 its rounding remainder (the

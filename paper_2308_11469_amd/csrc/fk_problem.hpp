@@ -42,9 +42,11 @@ struct HostProblem {
     std::vector<int32_t> interior;    // unknown node ids, longest expected paths first
     std::vector<double> grid0;        // initial grid (re, im): 0 interior, g elsewhere
     int64_t jmax = 0;
-    int32_t ppi = 0;                  // paths per work item
-    int32_t items_per_node = 0;
-    int64_t n_items = 0;
+    int32_t ppi = 0;                  // paths per (small) work item
+    int32_t items_per_node = 0;       // small items per node
+    int32_t ppi_a = 0;                // paths per large item (0: none)
+    int32_t items_a = 0;              // large items per node, ahead of the small ones
+    int64_t n_items = 0;              // all items: nodes x (items_a + items_per_node)
     int32_t cells = 0;                // the gather copy of u_n is cell-major
     int32_t lds_grid = 0;             // single-instance FP32: the row-major copy is staged in LDS
     // optional parts of the stepping loop this instance needs (bit 0 a hole,
@@ -124,11 +126,13 @@ struct PddPlan {
     };
     std::vector<Block> blocks;
     std::vector<double> tables;
-    std::vector<int32_t> iface;   // interface node ids, in the problem's work order
+    std::vector<int32_t> iface;   // the nodes that run paths: the interface and the unknown nodes of
+                                  // blocks touching the hole, in the problem's work order
     int32_t max_nodes = 0;        // largest block
 };
-// FK_EINVAL: not a plain rectangle with an absorbing edge, no cut, cuts not
-// strictly increasing within [1, n - 2], or a block wider than 64 nodes.
+// A block with a hole node in it or on its frame is not solved: its unknown
+// nodes run paths.  FK_EINVAL: a reflecting edge, no cut, cuts not strictly
+// increasing within [1, n - 2], or a block wider than 64 nodes.
 fk_status plan_pdd(const HostProblem &P, const int32_t *cuts_x, int32_t n_cuts_x, const int32_t *cuts_y,
                    int32_t n_cuts_y, PddPlan &out);
 // Makes the PDD node list the problem's work list.  With the automatic item

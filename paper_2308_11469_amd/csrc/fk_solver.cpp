@@ -74,6 +74,21 @@ fk_status fk_helmholtz_arena_bytes(const fk_domain *domain, const fk_bc *g_outer
     return FK_OK;
 }
 
+fk_status fk_helmholtz_work_items(const fk_domain *domain, const fk_bc *g_outer, const fk_params *params,
+                                  int64_t *n_items, int32_t *paths_large, int32_t *items_large,
+                                  int32_t *paths_small, int32_t *items_small)
+{
+    HostProblem P;
+    fk_status st = setup_problem(domain, nullptr, g_outer, nullptr, params, P, true);
+    if (st != FK_OK) return st;
+    if (n_items) *n_items = P.n_items;
+    if (paths_large) *paths_large = P.ppi_a;
+    if (items_large) *items_large = P.items_a;
+    if (paths_small) *paths_small = P.ppi;
+    if (items_small) *items_small = P.items_per_node;
+    return FK_OK;
+}
+
 fk_status fk_helmholtz_create(const fk_domain *domain, const fk_source *f, const fk_bc *g_outer,
                               const fk_bc *g_inner, const fk_params *params, void *device_arena,
                               size_t arena_bytes, void *hip_stream, fk_solver **out)

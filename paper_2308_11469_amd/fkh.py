@@ -79,7 +79,7 @@ class fk_engine_config(C.Structure):
 
 
 # every entry point of include/fk_helmholtz.h
-EXPORTS = ["fk_helmholtz_arena_bytes", "fk_helmholtz_create", "fk_helmholtz_iterate", "fk_helmholtz_solve",
+EXPORTS = ["fk_helmholtz_arena_bytes", "fk_helmholtz_work_items", "fk_helmholtz_create", "fk_helmholtz_iterate", "fk_helmholtz_solve",
            "fk_helmholtz_get", "fk_helmholtz_node_stats", "fk_helmholtz_set_iterate", "fk_helmholtz_set_pdd",
            "fk_helmholtz_cancel", "fk_engine_node_stats", "fk_engine_set_iterate", "fk_engine_set_pdd",
            "fk_helmholtz_timing", "fk_helmholtz_step_static",
@@ -107,6 +107,7 @@ def lib():
         P = C.POINTER
         sig = {
             "fk_helmholtz_arena_bytes": [P(fk_domain), P(fk_bc), P(fk_params), P(C.c_size_t)],
+            "fk_helmholtz_work_items": [P(fk_domain), P(fk_bc), P(fk_params), i64p, i32p, i32p, i32p, i32p],
             "fk_helmholtz_create": [P(fk_domain), P(fk_source), P(fk_bc), P(fk_bc), P(fk_params), vp, C.c_size_t,
                                     vp, P(vp)],
             "fk_helmholtz_iterate": [vp, C.c_int32, P(fk_iter_report)],
@@ -337,6 +338,18 @@ class Solver:
 
 
 STATIC_SCRATCH_BYTES = 16 * 1024 * 1024   # FK_STATIC_SCRATCH_BYTES
+
+
+def work_items(problem, paths_per_item=0, gather_layout="auto"):
+    """The work items of a solver launch (fk_helmholtz_work_items): large
+    items first, then small ones, per unknown node."""
+    m = Marshalled(problem, paths_per_item, gather_layout)
+    n = C.c_int64()
+    pl, il, ps, is_ = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+    _check(lib().fk_helmholtz_work_items(C.byref(m.domain), C.byref(m.outer), C.byref(m.params), C.byref(n),
+                                         C.byref(pl), C.byref(il), C.byref(ps), C.byref(is_)))
+    return dict(n_items=n.value, paths_large=pl.value, items_large=il.value, paths_small=ps.value,
+                items_small=is_.value)
 
 
 def step_static(problem, u_n, n, u_next, se=None, stream=None, paths_per_item=0, gather_layout="auto"):

@@ -81,6 +81,36 @@ def test_arena_size_grows_with_grid_and_paths(lib):
     assert a < b < c
 
 
+def test_work_items_guided_and_uniform(lib):
+    # automatic item size: large items (a whole number of small ones, at most
+    # three quarters of M) ahead of small ones, as long as 3 x 4096 large
+    # items result; a fixed item size is uniform; small problems stay uniform
+    def check(p, wi):
+        a, b = wi["items_large"] * wi["paths_large"], wi["paths_small"]
+        assert a <= 3 * p.M // 4 and (a == 0 or a % b == 0)
+        assert a + (wi["items_small"] - 1) * b < p.M <= a + wi["items_small"] * b
+    c3 = W.cavity_source(precision=64)
+    wi = fkh.work_items(c3)
+    assert (wi["paths_large"], wi["items_large"], wi["paths_small"], wi["items_small"]) == (12288, 1, 1024, 4)
+    assert wi["n_items"] == 127 * 127 * 5
+    check(c3, wi)
+    c2 = W.cavity_65(precision=64)
+    wi = fkh.work_items(c2)
+    assert (wi["paths_large"], wi["items_large"], wi["paths_small"], wi["items_small"]) == (768, 4, 256, 4)
+    check(c2, wi)
+    for p in (W.rect_batch(256)[:24] + [W.annulus_shape3(k=0.5, nx=101, ny=161, M=4096, h=1e-4, precision=32)]):
+        wi = fkh.work_items(p)
+        check(p, wi)
+        assert wi["items_large"] * (wi["n_items"] // (wi["items_large"] + wi["items_small"])) >= 3 * 4096 \
+            or wi["items_large"] == 0
+    # reflecting edge: uniform items
+    assert fkh.work_items(W.annulus_shape3(k=0.5, nx=101, ny=161, M=4096, h=1e-4, precision=32))["items_large"] == 0
+    wi = fkh.work_items(c3, paths_per_item=256)
+    assert (wi["paths_large"], wi["items_large"], wi["paths_small"], wi["items_small"]) == (0, 0, 256, 64)
+    wi = fkh.work_items(W.cavity_small())
+    assert wi["items_large"] == 0 and wi["n_items"] == 49 * wi["items_small"]
+
+
 def test_gather_layout_sizes_and_validation(lib):
     # FP32: cell-major copy is 32 B per cell instead of 8 B per node; FP64:
     # 64 B per cell, or no copy at all (row-major paths read the FP64 master)

@@ -206,6 +206,27 @@ def test_paths_per_item_does_not_change_results(precision):
         assert np.array_equal(g, runs[0][0]) and np.array_equal(se, runs[0][1]) and np.array_equal(sj, runs[0][2])
 
 
+@pytest.mark.parametrize("precision", [64, 32])
+def test_guided_items_bit_identical_to_uniform(precision):
+    # the automatic split gives every node one large item of 768 paths, then
+    # one of 256 (large items first in the queue); a fixed item size gives
+    # uniform items of 256: same iterates, errors and exit-step sums
+    p = W.cavity_source(precision=precision).replace(M=1024)
+    wi = fkh.work_items(p)
+    assert (wi["paths_large"], wi["items_large"], wi["paths_small"], wi["items_small"]) == (768, 1, 256, 1)
+    runs = []
+    for ppi in (0, 256):
+        s = fkh.Solver(p, paths_per_item=ppi)
+        s.iterate(2)
+        g, se = s.get()
+        sj, _ = s.node_stats()
+        runs.append((g, se, sj))
+        s.close()
+    say("guided vs uniform items", precision, wi)
+    assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
+    assert np.array_equal(runs[0][2], runs[1][2])
+
+
 # ------------------------------------------------------------ FP32 path
 
 @pytest.mark.parametrize("precision", [32, 64])

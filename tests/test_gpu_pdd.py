@@ -32,8 +32,12 @@ def _cases():
     # degenerate cuts: at 1 and n - 2 (nothing outside them), adjacent lines
     # 7 and 8 (no block between), one-node-wide blocks (the DST of size 1)
     degenerate = (W.cavity_small().replace(nx=23, ny=17, M=96, seed=13), [1, 7, 8, 19, 21], [2, 8, 15])
+    # the scattering problem's disc across the four middle blocks: their
+    # nodes run paths like the interface, the other twelve blocks are solved
+    disc = (W.scatter_problem(k=2.0, theta=0.7, N=41, M=96, seed=3, precision=64, h=2e-3, table_len=2048),
+            [10, 20, 30], [10, 20, 30])
     return {"plain_33": plain, "source_general_aniso": general, "wide_blocks_65": wide,
-            "degenerate_cuts": degenerate}
+            "degenerate_cuts": degenerate, "disc_hole_41": disc}
 
 
 def frame_of(p, g, ids):
@@ -48,7 +52,7 @@ def test_pdd_interfaces_and_blocks_match_oracle(name):
     say("pdd", name)
     s = fkh.Solver(p)
     s.set_pdd(cx, cy)
-    ids = pdd.interface_ids(p, cx, cy)
+    ids = pdd.mc_ids(p, cx, cy)
     u = None
     for it in range(3):
         s.iterate(1)
@@ -88,7 +92,7 @@ def test_pdd_fp32_blocks_from_own_interfaces():
     cuts = [32, 64, 96]
     s = fkh.Solver(p)
     s.set_pdd(cuts, cuts)
-    ids = pdd.interface_ids(p, cuts, cuts)
+    ids = pdd.mc_ids(p, cuts, cuts)
     s.iterate(1)
     u1 = s.get()[0]
     s.iterate(1)
@@ -112,7 +116,7 @@ def test_pdd_iteration_settles_on_the_plane_wave():
     s.close()
     ex = W.exact_solution(p)
     ids = fkmc.interior_ids(p)
-    iface = pdd.interface_ids(p, cuts, cuts)
+    iface = pdd.mc_ids(p, cuts, cuts)
     err = np.abs(g.ravel()[ids] - ex.ravel()[ids])
     err_if = np.abs(g.ravel()[iface] - ex.ravel()[iface])
     max_se = np.abs(se.ravel()[iface]).max()
@@ -125,13 +129,14 @@ def test_pdd_iteration_settles_on_the_plane_wave():
     assert err.max() <= err_if.max() + 1e-3
 
 
-@pytest.mark.parametrize("bad", ["after_iterate", "twice", "twice_no_blocks", "disc", "too_wide", "no_cut",
+@pytest.mark.parametrize("bad", ["after_iterate", "twice", "twice_no_blocks", "reflecting", "too_wide", "no_cut",
                                  "unsorted"])
 def test_pdd_argument_checks(bad):
     p = W.cavity_small().replace(nx=33, ny=33, M=64)
     cx, cy = [16], [16]
-    if bad == "disc":
-        p = W.scatter_problem(k=2.0, theta=0.0, N=33, M=64, seed=1, precision=64, table_len=256)
+    if bad == "reflecting":
+        p = W.annulus_shape3(k=0.5, nx=21, ny=33, M=64, h=1e-3, precision=64)
+        cx, cy = [10], [16]
     if bad == "too_wide":
         p = W.cavity_65().replace(nx=129, ny=129, M=64)
         cx, cy = [100], [64]
@@ -227,7 +232,7 @@ def test_engine_pdd_matches_oracle():
     e = _pdd_engine(64)
     sl = e.add(p)
     assert e.set_pdd(sl, cx, cy)
-    ids = pdd.interface_ids(p, cx, cy)
+    ids = pdd.mc_ids(p, cx, cy)
     u = None
     for it in range(2):
         e.tick()

@@ -42,6 +42,51 @@ def test_blocks_from_exact_interfaces_reproduce_global_fd_step(case):
     assert np.max(np.abs(bad - exact)) > 1e-3
 
 
+def _disc_case():
+    # the scattering problem (sound-soft disc r = 0.25 in [-1, 1]^2, exact
+    # series data) on 41 x 41: the cut lines 10, 20, 30 put the disc across
+    # the four middle blocks
+    p = W.scatter_problem(k=2.0, theta=0.7, N=41, M=64, seed=3, precision=64, h=2e-3, table_len=2048)
+    return p, [10, 20, 30], [10, 20, 30]
+
+
+def test_blocks_with_a_hole_reproduce_global_fd_step():
+    # blocks touching the disc are not Dirichlet rectangles: their nodes take
+    # exact values like the interface, the other blocks are solved and the
+    # global FD step comes back
+    p, cx, cy = _disc_case()
+    cls = fkmc.node_classes(p)
+    u_prev = smooth_field(p)
+    u_prev[cls != 0] = fkmc.boundary_grid(p)[cls != 0]
+    exact = fd.neumann(p, 1, u0=u_prev)[0]
+    ids = pdd.mc_ids(p, cx, cy)
+    assert len(pdd.blocks(p, cx, cy)) == 12 and len(pdd.all_blocks(p, cx, cy)) == 16
+    frame = fkmc.boundary_grid(p)
+    frame.ravel()[ids] = exact.ravel()[ids]
+    got = pdd.fill_blocks(p, u_prev, frame, cx, cy)
+    assert np.max(np.abs(got - exact)) < 1e-11 * max(1.0, np.abs(exact).max())
+    # a wrong value at a node of a block touching the disc stays there (no
+    # block is solved from it); one on an interface line moves its blocks
+    frame2 = frame.copy()
+    inner = [i for i in ids if 10 < i % p.nx < 20 and 10 < i // p.nx < 20]
+    frame2.ravel()[inner[0]] += 1.0
+    bad = pdd.fill_blocks(p, u_prev, frame2, cx, cy)
+    assert np.count_nonzero(np.abs(bad - exact) > 1e-9) == 1
+
+
+def test_interfaces_and_blocks_partition_the_unknowns_with_a_hole():
+    p, cx, cy = _disc_case()
+    seen = np.zeros(p.nx * p.ny, int)
+    seen[pdd.mc_ids(p, cx, cy)] += 1
+    for i0, i1, j0, j1 in pdd.blocks(p, cx, cy):
+        for j in range(j0, j1):
+            seen[j * p.nx + i0: j * p.nx + i1] += 1
+    unknown = fkmc.node_classes(p).ravel() == 0
+    assert np.all(seen[unknown] == 1) and np.all(seen[~unknown] == 0)
+    # the Monte Carlo stage is the interface plus the middle blocks' nodes
+    assert len(pdd.mc_ids(p, cx, cy)) > len(pdd.interface_ids(p, cx, cy))
+
+
 def test_interfaces_and_blocks_partition_the_unknowns():
     p = W.cavity_small().replace(nx=23, ny=17)
     cuts_x, cuts_y = [1, 7, 20], [8]
