@@ -113,8 +113,8 @@ def _issue(k):
             "instructions_per_path_step": k["valu_instructions_per_path_step"]}
 
 
-ONLY = ("headline", "fp32_same_config", "cavity65", "batch256_tick", "served_vs_plain", "serving",
-        "serving_sweep", "annulus", "pdd", "tuned_tick")
+ONLY = ("headline", "fp32_same_config", "cavity65", "batch256_tick", "served_vs_plain", "scatter_served_vs_plain",
+        "serving", "serving_pdd", "serving_sweep", "annulus", "pdd", "tuned_tick")
 
 
 def parse(argv=None):
@@ -415,9 +415,9 @@ def tuned_tick(n_sub=16):
     return out
 
 
-def served_vs_plain(n_sub=16, spacing=32):
-    """Solves/s at the stopping rule (settled, max |du| < tol or max_iters) on
-    every 16th instance of the 256-rectangle workload:
+def _served_comparison(probs, spacing, unknown_mask, max_table, tag):
+    """Solves/s at the stopping rule (settled, max |du| < tol or max_iters)
+    of the given requests:
 
     - plain: the FP64 single-instance solver with paths from every unknown
       node, the instances one after another;
@@ -428,19 +428,19 @@ def served_vs_plain(n_sub=16, spacing=32):
       them solved on the device in the same tick; Sec. 3's two-stage
       procedure).
 
-    RMS error of each result against the exact plane wave (mean over the
-    instances) beside each rate."""
+    RMS error of each result against the exact solution over the unknown
+    nodes (mean over the instances) beside each rate."""
     import numpy as np
     import torch
     from paper_2308_11469_amd import fkh, serving
     from paper_2308_11469_amd import workloads as W
-    probs = W.rect_batch(256)[::256 // n_sub]
     nodes = sum(p.nx * p.ny for p in probs)
 
     def rms(p, u):
-        return float(np.sqrt(np.mean(np.abs(u - W.exact_solution(p))[1:-1, 1:-1] ** 2)))
+        m = unknown_mask(p)
+        return float(np.sqrt(np.mean(np.abs(u - W.exact_solution(p))[m] ** 2)))
 
-    _log("served_vs_plain: plain FP64")
+    _log("%s: plain FP64" % tag)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     err_p, its_p = [], []
@@ -460,11 +460,13 @@ def served_vs_plain(n_sub=16, spacing=32):
            "plain_fp64": dict(wall_s=t_plain, solves_per_s=len(probs) / t_plain,
                               rms_error=float(np.mean(err_p)), iterations_mean=float(np.mean(its_p)))}
     for name, pdd in (("served_fp32", False), ("served_fp32_pdd", True)):
-        _log("served_vs_plain: %s" % name)
+        _log("%s: %s" % (tag, name))
         eng = fkh.Engine(len(probs), precision=32, max_grid_nodes=nodes + 4096, max_items=1 << 28,
-                         max_table=16, max_instance_nodes=max(p.nx * p.ny for p in probs))
-        reqs = [serving.Request(i, 0.0, p, pdd=(serving.grid_cuts(p.nx, spacing), serving.grid_cuts(p.ny, spacing))
-                                if pdd else None) for i, p in enumerate(probs)]
+                         max_table=max_table, max_instance_nodes=max(p.nx * p.ny for p in probs))
+        reqs = []
+        for i, p in enumerate(probs):
+            cx, cy = serving.grid_cuts(p.nx, spacing), serving.grid_cuts(p.ny, spacing)
+            reqs.append(serving.Request(i, 0.0, p, pdd=(cx, cy) if pdd and (cx or cy) else None))
         srv = serving.Server(eng, keep_results=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -483,28 +485,75 @@ def served_vs_plain(n_sub=16, spacing=32):
     return out
 
 
-def _scatter_requests(n, rate, seed=5):
+def served_vs_plain(n_sub=16, spacing=32):
+    """The served-vs-plain comparison (see _served_comparison) on every 16th
+    instance of the 256-rectangle workload, errors against the exact plane
+    wave."""
+    from paper_2308_11469_amd import workloads as W
+    probs = W.rect_batch(256)[::256 // n_sub]
+
+    def interior(p):
+        import numpy as np
+        m = np.zeros((p.ny, p.nx), bool)
+        m[1:-1, 1:-1] = True
+        return m
+    return _served_comparison(probs, spacing, interior, 16, "served_vs_plain")
+
+
+def scatter_served_vs_plain(n_sub=16, spacing=32):
+    """The same comparison on the scattering stream's requests: the first 16
+    of every 12th of the 400 arrivals that the server's predicted-contraction
+    rule admits,
+    grids 33..257 on [-1, 1]^2 around the sound-soft disc, errors against the
+    exact disc series.  With the decomposition, the blocks touching the disc
+    keep their own paths and the others are solved."""
+    import numpy as np
+    from paper_2308_11469_amd import serving
+    from paper_2308_11469_amd import workloads as W
+    _, params = W.scatter_stream(400, 200.0, 5)
+    probs = []
+    for q in params[::12]:
+        p = W.scatter_problem(q["k"], q["theta"], q["N"], q["M"], q["seed"], precision=32)
+        if serving.predicted_rho(p) < 0.98:
+            probs.append(p)
+    probs = probs[:n_sub]
+
+    def unknown(p):
+        xs = p.x0 + np.arange(p.nx) * ((p.x1 - p.x0) / (p.nx - 1))
+        ys = p.y0 + np.arange(p.ny) * ((p.y1 - p.y0) / (p.ny - 1))
+        X, Y = np.meshgrid(xs, ys)
+        m = (X - p.cx) ** 2 + (Y - p.cy) ** 2 > p.r ** 2
+        m[0, :] = m[-1, :] = m[:, 0] = m[:, -1] = False
+        return m
+    return _served_comparison(probs, spacing, unknown, len(probs) * 4 * 8192, "scatter_served_vs_plain")
+
+
+def _scatter_requests(n, rate, seed=5, pdd_spacing=None):
     """The scattering stream's requests; each problem (with its boundary
     table from the disc series) is built when the server first looks at the
-    request, so requests turned away at a full queue cost nothing."""
+    request, so requests turned away at a full queue cost nothing.  With
+    pdd_spacing, requests carry decomposition lines every pdd_spacing nodes
+    (grids too small for a line run without)."""
     from paper_2308_11469_amd import serving
     from paper_2308_11469_amd import workloads as W
     arrivals, params = W.scatter_stream(n, rate, seed)
     reqs = []
     for r, (t, q) in enumerate(zip(arrivals, params)):
         make = (lambda q=q: W.scatter_problem(q["k"], q["theta"], q["N"], q["M"], q["seed"], precision=32))
-        reqs.append(serving.Request(r, float(t), None, make=make))
+        cuts = serving.grid_cuts(q["N"], pdd_spacing) if pdd_spacing else []
+        reqs.append(serving.Request(r, float(t), None, make=make, pdd=(cuts, cuts) if cuts else None))
     return reqs
 
 
-def serving_window(n_requests=400, rate=200.0, max_queue=32, slots=8):
+def serving_window(n_requests=400, rate=200.0, max_queue=32, slots=8, pdd_spacing=None):
     """The scattering request stream (Poisson arrivals, k ~ U[1, 4], grids
     33..257, M 1024..8192, h = 1e-4, FP32) through the continuous-batching
     loop with a bounded waiting queue: completed solves/s, p50 / p99 latency
-    of the completed requests, turned-away requests by reason, queue growth."""
+    of the completed requests, turned-away requests by reason, queue growth.
+    With pdd_spacing, every request carries decomposition lines."""
     import numpy as np
     from paper_2308_11469_amd import fkh, serving
-    reqs = _scatter_requests(n_requests, rate)
+    reqs = _scatter_requests(n_requests, rate, pdd_spacing=pdd_spacing)
     eng = fkh.Engine(slots, precision=32, max_grid_nodes=slots * 257 * 257, max_items=1 << 26,
                      max_table=slots * 4 * 8192, max_instance_nodes=257 * 257)
     last = [time.perf_counter()]
@@ -524,6 +573,7 @@ def serving_window(n_requests=400, rate=200.0, max_queue=32, slots=8):
     out = serving.latency_summary(res, wall, srv.tick_log)
     its = [r.iterations for r in res.values() if r.outcome in ("converged", "max_iters")]
     out.update(requests=n_requests, offered_rate_per_s=rate, max_queue=max_queue, slots=slots, wall_s=wall,
+               pdd_spacing=pdd_spacing,
                ticks=srv.ticks, max_resident=max((t["resident"] for t in srv.tick_log), default=0),
                iterations_per_solve_median=float(np.median(its)) if its else None)
     return out
@@ -629,7 +679,9 @@ def main(argv=None):
         "cavity65": lambda: cavity65(a.k),
         "batch256_tick": batch256_tick,
         "served_vs_plain": served_vs_plain,
+        "scatter_served_vs_plain": scatter_served_vs_plain,
         "serving": serving_window,
+        "serving_pdd": lambda: serving_window(pdd_spacing=32),
         "annulus": annulus_shape3,
         "pdd": lambda: pdd_cavity65(a.k),
         "tuned_tick": tuned_tick,
@@ -662,8 +714,8 @@ def main(argv=None):
         "extra": h["extra"],
     }
     if not a.no_extras and a.only is None:
-        for name in ("fp32_same_config", "cavity65", "served_vs_plain", "annulus", "pdd", "batch256_tick",
-                     "serving"):
+        for name in ("fp32_same_config", "cavity65", "served_vs_plain", "scatter_served_vs_plain", "annulus", "pdd",
+                     "batch256_tick", "serving", "serving_pdd"):
             out["extra"][name] = parts[name]()
     if not a.no_cpu and a.only is None:
         _log("cpu_baseline")
