@@ -83,8 +83,25 @@ typedef enum {
  * REFLECTING, d_n u - i k u = g_outer on the edge (Robin, Sec. 2.3): the
  * edge nodes are unknowns, the paths are reflected there and only the hole
  * absorbs them, so a reflecting edge needs a hole, an explicit step cap
- * (fk_params.max_steps) and sides longer than 6 sqrt(2 h). */
-typedef enum { FK_DOMAIN_RECT = 0, FK_DOMAIN_RECT_MINUS_DISC = 1, FK_DOMAIN_RECT_MINUS_BOX = 2 } fk_domain_kind;
+ * (fk_params.max_steps) and sides longer than 6 sqrt(2 h).
+ *
+ * DISC_MINUS_RHOMBUS / DISC_MINUS_DISC (the annular domains of Sec. 2.5 with
+ * a disc as the outer boundary): Omega is the open disc inscribed in the
+ * square [x0, x1] x [y0, y1] (x1 - x0 = y1 - y0) minus the closed rhombus
+ * |x - cx| / r + |y - cy| / ry <= 1 (a node within 1e-9 of its edge counts
+ * as in it) or minus the closed disc of radius r at (cx, cy), strictly
+ * inside.  The disc's edge reflects (edge = REFLECTING, with the Robin
+ * datum g_outer): a path past the circle is mirrored radially, the local
+ * time grows by twice the overshoot, the datum is taken at the move's foot
+ * on the circle (outward normal radial).  Grid nodes outside the closed disc
+ * are exterior: no unknowns.  These domains serve the exit-time and
+ * local-time solves (k = 0, alpha = 0, no damping: the iterate never enters
+ * a path) in FP64 stepping, in the single-instance solver (fk_engine_add
+ * rejects them). */
+typedef enum {
+    FK_DOMAIN_RECT = 0, FK_DOMAIN_RECT_MINUS_DISC = 1, FK_DOMAIN_RECT_MINUS_BOX = 2,
+    FK_DOMAIN_DISC_MINUS_RHOMBUS = 3, FK_DOMAIN_DISC_MINUS_DISC = 4
+} fk_domain_kind;
 typedef enum { FK_EDGE_ABSORBING = 0, FK_EDGE_REFLECTING = 1 } fk_edge_kind;
 typedef struct {
     int32_t kind;

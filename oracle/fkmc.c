@@ -66,6 +66,16 @@
  *     face) and discounted to the end of the step.  Then the step is
  *     absorbed when the point lies in the closed hole.  Every edge node of
  *     the grid is an unknown.
+ *   - Curved reflecting edge (the annular domains of Sec. 2.5 with a disc as
+ *     the outer boundary; a reading, as above): the disc is the one inscribed
+ *     in the square [x0, x1] x [y0, y1]; a point that left it is mirrored
+ *     radially, X' = c + (R - o) (X - c) / |X - c| with the overshoot
+ *     o = |X - c| - R, the local time grows by 2 o and the integrand is taken
+ *     at the foot c + R (X - c) / |X - c| (outward normal (X - c) / |X - c|).
+ *     The hole is a disc or a rhombus |x - cx| / r + |y - cy| / ry <= 1.
+ *     Grid nodes outside the closed disc are exterior: no unknowns; the
+ *     bilinear interpolant reads each of them as its nearest unknown node
+ *     (the remap table, built by the caller).
  */
 #include <math.h>
 #include <stdint.h>
@@ -77,7 +87,8 @@
 
 /* ---------------------------------------------------------------- types -- */
 
-enum { ORC_RECT = 0, ORC_RECT_MINUS_DISC = 1, ORC_RECT_MINUS_BOX = 2 };
+enum { ORC_RECT = 0, ORC_RECT_MINUS_DISC = 1, ORC_RECT_MINUS_BOX = 2, ORC_DISC_MINUS_RHOMBUS = 3,
+       ORC_DISC_MINUS_DISC = 4 };
 enum { ORC_SRC_ZERO = 0, ORC_SRC_CONST = 1, ORC_SRC_GAUSSIAN = 2 };
 enum { ORC_BC_ZERO = 0, ORC_BC_PLANE_WAVE = 1, ORC_BC_BILINEAR = 2, ORC_BC_TABLE = 3,
        ORC_BC_PLANE_WAVE_ROBIN = 4 };
@@ -116,8 +127,11 @@ typedef struct {
     double alpha;          /* shift, >= k^2 */
     double p;              /* damping */
     double ry;             /* RECT_MINUS_BOX: the hole is [cx-r, cx+r] x [cy-ry, cy+ry] */
-    int32_t reflect;       /* 1: the rectangle's edge reflects (Robin datum outer) */
+    int32_t reflect;       /* 1: the outer edge reflects (Robin datum outer) */
     int32_t pad2;
+    const int32_t *remap;  /* disc domains: node id -> node read by the interpolant
+                              (an exterior node's nearest unknown node; itself
+                              otherwise); NULL: identity */
 } orc_problem;
 
 /* --------------------------------------------------------------- Philox -- */
@@ -176,16 +190,32 @@ void orc_node_xy(const orc_problem *P, int32_t node_id, double xy[2])
     xy[1] = P->y0 + (double)j * grid_dy(P);
 }
 
-/* The closed hole: the disc of radius r at (cx, cy), or the box
- * [cx - r, cx + r] x [cy - ry, cy + ry]. */
+static int disc_domain(const orc_problem *P)
+{
+    return P->domain_kind == ORC_DISC_MINUS_RHOMBUS || P->domain_kind == ORC_DISC_MINUS_DISC;
+}
+
+/* The outer disc of a disc domain: inscribed in the (square) grid box. */
+static void outer_disc(const orc_problem *P, double *ox, double *oy, double *R)
+{
+    *ox = 0.5 * (P->x0 + P->x1);
+    *oy = 0.5 * (P->y0 + P->y1);
+    *R = 0.5 * (P->x1 - P->x0);
+}
+
+/* The closed hole: the disc of radius r at (cx, cy), the box
+ * [cx - r, cx + r] x [cy - ry, cy + ry], or the rhombus
+ * |x - cx| / r + |y - cy| / ry <= 1. */
 static int in_hole(const orc_problem *P, double x, double y)
 {
-    if (P->domain_kind == ORC_RECT_MINUS_DISC) {
+    if (P->domain_kind == ORC_RECT_MINUS_DISC || P->domain_kind == ORC_DISC_MINUS_DISC) {
         double ex = x - P->cx, ey = y - P->cy;
         return ex * ex + ey * ey <= P->r * P->r;
     }
     if (P->domain_kind == ORC_RECT_MINUS_BOX)
         return x >= P->cx - P->r && x <= P->cx + P->r && y >= P->cy - P->ry && y <= P->cy + P->ry;
+    if (P->domain_kind == ORC_DISC_MINUS_RHOMBUS)
+        return fabs(x - P->cx) / P->r + fabs(y - P->cy) / P->ry <= 1.0;
     return 0;
 }
 
@@ -204,6 +234,8 @@ int orc_outside(const orc_problem *P, double x, double y)
  * x0 + i dx. */
 static int node_in_hole(const orc_problem *P, double x, double y)
 {
+    if (P->domain_kind == ORC_DISC_MINUS_RHOMBUS)
+        return fabs(x - P->cx) / P->r + fabs(y - P->cy) / P->ry <= 1.0 + 1e-9;
     if (P->domain_kind != ORC_RECT_MINUS_BOX) return in_hole(P, x, y);
     const double ex = 1e-9 * grid_dx(P), ey = 1e-9 * grid_dy(P);
     return x >= P->cx - P->r - ex && x <= P->cx + P->r + ex && y >= P->cy - P->ry - ey
@@ -211,21 +243,54 @@ static int node_in_hole(const orc_problem *P, double x, double y)
 }
 
 /* 0 unknown (interior, or on a reflecting edge), 1 on an absorbing edge,
- * 2 in the closed hole. */
+ * 2 in the closed hole, 3 outside the closed disc of a disc domain. */
 int orc_node_class(const orc_problem *P, int32_t node_id)
 {
     int32_t i = node_id % P->nx, j = node_id / P->nx;
     double xy[2];
     orc_node_xy(P, node_id, xy);
     if (node_in_hole(P, xy[0], xy[1])) return 2;
+    if (disc_domain(P)) {
+        double ox, oy, R;
+        outer_disc(P, &ox, &oy, &R);
+        const double ex = xy[0] - ox, ey = xy[1] - oy;
+        return ex * ex + ey * ey > R * R * (1.0 + 1e-12) ? 3 : 0;
+    }
     if (!P->reflect && (i == 0 || j == 0 || i == P->nx - 1 || j == P->ny - 1)) return 1;
     return 0;
+}
+
+/* Nearest point of the segment a-b to (x, y), and its squared distance. */
+static double segment_project(double ax, double ay, double bx, double by, double x, double y, double p[2])
+{
+    const double vx = bx - ax, vy = by - ay;
+    double t = ((x - ax) * vx + (y - ay) * vy) / (vx * vx + vy * vy);
+    t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+    p[0] = ax + t * vx;
+    p[1] = ay + t * vy;
+    return (x - p[0]) * (x - p[0]) + (y - p[1]) * (y - p[1]);
 }
 
 /* Nearest point of the hole's boundary to (x, y), and its distance. */
 static double hole_project(const orc_problem *P, double x, double y, double p[2])
 {
-    if (P->domain_kind == ORC_RECT_MINUS_DISC) {
+    if (P->domain_kind == ORC_DISC_MINUS_RHOMBUS) {
+        /* the four sides between the vertices (cx + r, cy), (cx, cy + ry),
+           (cx - r, cy), (cx, cy - ry); the first nearest wins */
+        const double vx[5] = {P->cx + P->r, P->cx, P->cx - P->r, P->cx, P->cx + P->r};
+        const double vy[5] = {P->cy, P->cy + P->ry, P->cy, P->cy - P->ry, P->cy};
+        double best = -1.0, q[2];
+        for (int e = 0; e < 4; ++e) {
+            const double d2 = segment_project(vx[e], vy[e], vx[e + 1], vy[e + 1], x, y, q);
+            if (best < 0.0 || d2 < best) {
+                best = d2;
+                p[0] = q[0];
+                p[1] = q[1];
+            }
+        }
+        return sqrt(best);
+    }
+    if (P->domain_kind == ORC_RECT_MINUS_DISC || P->domain_kind == ORC_DISC_MINUS_DISC) {
         double ex = x - P->cx, ey = y - P->cy;
         double d = sqrt(ex * ex + ey * ey);
         if (d > 0.0) {
@@ -367,9 +432,17 @@ void orc_robin(const orc_problem *P, int face, double x, double y, double g[2])
         bc_eval(P, &P->outer, x, y, g);
         return;
     }
-    const double dn = face == 0 ? -cos(P->outer.c[2])
-                    : face == 1 ? cos(P->outer.c[2])
-                    : face == 2 ? -sin(P->outer.c[2]) : sin(P->outer.c[2]);
+    double dn;
+    if (face == 4) {
+        /* the disc's edge: outward normal (x - c) / R at the foot */
+        double ox, oy, R;
+        outer_disc(P, &ox, &oy, &R);
+        dn = ((x - ox) * cos(P->outer.c[2]) + (y - oy) * sin(P->outer.c[2])) / R;
+    } else {
+        dn = face == 0 ? -cos(P->outer.c[2])
+           : face == 1 ? cos(P->outer.c[2])
+           : face == 2 ? -sin(P->outer.c[2]) : sin(P->outer.c[2]);
+    }
     double kr, ki, w[2];
     kappa_of(P, &kr, &ki);
     plane_wave_eval(P, &P->outer, x, y, w);
@@ -387,7 +460,7 @@ void orc_fill_boundary(const orc_problem *P, double *u)
     int64_t nn = (int64_t)P->nx * P->ny;
     for (int64_t id = 0; id < nn; ++id) {
         int cls = orc_node_class(P, (int32_t)id);
-        if (cls == 0) continue;
+        if (cls == 0 || cls == 3) continue;   /* exterior nodes are read through the remap */
         double xy[2], g[2];
         orc_node_xy(P, (int32_t)id, xy);
         orc_g(P, cls, xy[0], xy[1], g);
@@ -409,6 +482,12 @@ void orc_interp(const orc_problem *P, const double *u, double x, double y, doubl
     if (q > P->ny - 2) q = P->ny - 2;
     double a = fx - (double)p, b = fy - (double)q;
     int64_t i00 = p + (int64_t)P->nx * q, i10 = i00 + 1, i01 = i00 + P->nx, i11 = i01 + 1;
+    if (P->remap) {
+        i00 = P->remap[i00];
+        i10 = P->remap[i10];
+        i01 = P->remap[i01];
+        i11 = P->remap[i11];
+    }
     for (int c = 0; c < 2; ++c)
         out[c] = (1.0 - a) * (1.0 - b) * u[2 * i00 + c] + a * (1.0 - b) * u[2 * i10 + c]
                + (1.0 - a) * b * u[2 * i01 + c] + a * b * u[2 * i11 + c];
@@ -453,8 +532,32 @@ static void local_time_integrand(const orc_problem *P, const double *u, int face
  * dxi = 2 x overshoot times the discounted integrand at the foot of the
  * move to lt.  One mirror per coordinate suffices: the rectangle is wider
  * than any single step (checked at set-up). */
+static void reflect_disc(const orc_problem *P, const double *u, int64_t t, double X[2], double lt[2])
+{
+    double ox, oy, R;
+    outer_disc(P, &ox, &oy, &R);
+    const double ex = X[0] - ox, ey = X[1] - oy;
+    const double d2 = ex * ex + ey * ey;
+    if (d2 <= R * R) return;
+    const double d = sqrt(d2);
+    const double o = d - R;                   /* overshoot */
+    const double s = (R - o) / d, f = R / d;
+    const double footx = ox + f * ex, footy = oy + f * ey;
+    X[0] = ox + s * ex;
+    X[1] = oy + s * ey;
+    const double w = exp(-(P->alpha - P->k * P->k) * (double)t * P->h);
+    double v[2];
+    local_time_integrand(P, u, 4, footx, footy, v);
+    lt[0] += w * (2.0 * o) * v[0];
+    lt[1] += w * (2.0 * o) * v[1];
+}
+
 static void reflect_step(const orc_problem *P, const double *u, int64_t t, double X[2], double lt[2])
 {
+    if (disc_domain(P)) {
+        reflect_disc(P, u, t, X, lt);
+        return;
+    }
     double dxi_x = 0.0, dxi_y = 0.0;
     int fx = -1, fy = -1;
     if (X[0] < P->x0) {

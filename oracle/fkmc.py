@@ -16,7 +16,7 @@ import numpy as np
 
 from . import build as _build
 
-_KIND_DOMAIN = {"rect": 0, "rect_minus_disc": 1, "rect_minus_box": 2}
+_KIND_DOMAIN = {"rect": 0, "rect_minus_disc": 1, "rect_minus_box": 2, "disc_minus_rhombus": 3, "disc_minus_disc": 4}
 _KIND_SRC = {"zero": 0, "const": 1, "gaussian": 2}
 _KIND_BC = {"zero": 0, "plane_wave": 1, "bilinear": 2, "table": 3, "plane_wave_robin": 4}
 
@@ -37,7 +37,8 @@ class _Problem(C.Structure):
                 ("k", C.c_double), ("h", C.c_double), ("M", C.c_int64), ("seed", C.c_uint64),
                 ("jmax", C.c_int64), ("crn", C.c_int32), ("g_unprojected", C.c_int32),
                 ("alpha", C.c_double), ("p", C.c_double),
-                ("ry", C.c_double), ("reflect", C.c_int32), ("pad2", C.c_int32)]
+                ("ry", C.c_double), ("reflect", C.c_int32), ("pad2", C.c_int32),
+                ("remap", C.POINTER(C.c_int32))]
 
 
 _lib = None
@@ -131,6 +132,20 @@ class Handle:
         s.reflect = 1 if getattr(p, "reflect", False) else 0
         self.s = s
         self.ref = C.byref(s)
+        if p.domain_kind in ("disc_minus_rhombus", "disc_minus_disc"):
+            # exterior nodes are read as their nearest unknown node (ties: the
+            # lowest id)
+            n = p.nx * p.ny
+            cls = np.array([lib().orc_node_class(self.ref, i) for i in range(n)], dtype=np.int32)
+            xs = p.x0 + (np.arange(n) % p.nx) * ((p.x1 - p.x0) / (p.nx - 1))
+            ys = p.y0 + (np.arange(n) // p.nx) * ((p.y1 - p.y0) / (p.ny - 1))
+            unk = np.nonzero(cls == 0)[0]
+            remap = np.arange(n, dtype=np.int32)
+            for e in np.nonzero(cls == 3)[0]:
+                d2 = (xs[unk] - xs[e]) ** 2 + (ys[unk] - ys[e]) ** 2
+                remap[e] = unk[int(np.argmin(d2))]
+            self._remap = remap
+            s.remap = remap.ctypes.data_as(C.POINTER(C.c_int32))
 
 
 # ----------------------------------------------------------- RNG pieces

@@ -41,9 +41,13 @@ constexpr int kRowMajor = 16;
 // Not a feature: FP32 kernels of one instance whose row-major copy is staged
 // in LDS (a 1024-thread block per CU shares it).
 constexpr int kLdsGrid = 32;
+// The outer edge is the disc inscribed in the grid's square, reflecting
+// (always with kFeatReflect and a hole); FP64 kernels only, the local-time
+// terms evaluated at once (a move has a foot with two coordinates).
+constexpr int kFeatCurved = 64;
 
 enum : int32_t { BC_ZERO = 0, BC_PLANE_WAVE = 1, BC_BILINEAR = 2, BC_TABLE = 3, BC_PLANE_WAVE_ROBIN = 4 };
-enum : int32_t { HOLE_NONE = 0, HOLE_DISC = 1, HOLE_BOX = 2 };
+enum : int32_t { HOLE_NONE = 0, HOLE_DISC = 1, HOLE_BOX = 2, HOLE_RHOMBUS = 3 };
 enum : int32_t { SRC_ZERO = 0, SRC_CONST = 1, SRC_GAUSSIAN = 2 };
 
 struct BCDev {
@@ -91,11 +95,13 @@ struct Inst {
     double x0, x1, y0, y1, dx, dy, idx, idy;
     double cx, cy, r, r2;
     double bx0, bx1, by0, by1;                       // box hole
+    double ry;                                       // rhombus hole: |x - cx| / r + |y - cy| / ry <= 1
+    double ocx, ocy, orad, orad2;                    // disc domains: the outer disc (centre, R, R^2)
     float x0_rd, x1_ru, y0_rd, y1_ru;                // edges rounded outward to binary32
     float bx0_ru, bx1_rd, by0_ru, by1_rd;            // box edges rounded inward to binary32
     float x0_ri, x1_ri, y0_ri, y1_ri;                // edges rounded inward (reflection tests)
     int32_t nx, ny, hole, n_interior;                // hole: HOLE_NONE / _DISC / _BOX
-    int32_t reflect, pad0;                           // 1: the rectangle's edge reflects
+    int32_t reflect, curved;                         // 1: the outer edge reflects; 1: it is the disc
     int32_t src_kind, g_unproj;
     double src_re, src_im, src_cx, src_cy, src_c;   // src_c = 1 / (2 sigma^2)
     BCDev outer, inner;
@@ -299,7 +305,9 @@ __device__ __forceinline__ void normals(uint32_t ra, uint32_t rb, const NoTables
 
 // ------------------------------------------------------------- geometry
 
-// The closed hole (FP64, the problem's own comparisons).
+// The closed hole (FP64, the problem's own comparisons).  The rhombus only
+// occurs in disc domains (kernels with kFeatCurved).
+template <int F>
 __device__ __forceinline__ bool in_hole(const Inst &D, double x, double y)
 {
     if (D.hole == HOLE_DISC) {
@@ -307,13 +315,44 @@ __device__ __forceinline__ bool in_hole(const Inst &D, double x, double y)
         return ex * ex + ey * ey <= D.r2;
     }
     if (D.hole == HOLE_BOX) return x >= D.bx0 && x <= D.bx1 && y >= D.by0 && y <= D.by1;
+    if ((F & kFeatCurved) && D.hole == HOLE_RHOMBUS) return fabs(x - D.cx) / D.r + fabs(y - D.cy) / D.ry <= 1.0;
     return false;
+}
+
+// Nearest point of the segment a-b to (x, y); returns the squared distance.
+__device__ __forceinline__ double segment_project(double ax, double ay, double bx, double by, double x, double y,
+                                                  double &px, double &py)
+{
+    const double vx = bx - ax, vy = by - ay;
+    double t = ((x - ax) * vx + (y - ay) * vy) / (vx * vx + vy * vy);
+    t = fmin(fmax(t, 0.0), 1.0);
+    px = ax + t * vx;
+    py = ay + t * vy;
+    return (x - px) * (x - px) + (y - py) * (y - py);
 }
 
 // Nearest point of the hole's boundary and its distance.  Disc: radial
 // projection.  Box: from inside, the nearest face; from outside, the clamp.
+// Rhombus: the nearest of its four sides (the first one on a tie).
+template <int F>
 __device__ __forceinline__ double hole_project(const Inst &D, double x, double y, double &px, double &py)
 {
+    if ((F & kFeatCurved) && D.hole == HOLE_RHOMBUS) {
+        const double vx[5] = {D.cx + D.r, D.cx, D.cx - D.r, D.cx, D.cx + D.r};
+        const double vy[5] = {D.cy, D.cy + D.ry, D.cy, D.cy - D.ry, D.cy};
+        double best = -1.0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            double qx, qy;
+            const double d2 = segment_project(vx[e], vy[e], vx[e + 1], vy[e + 1], x, y, qx, qy);
+            if (best < 0.0 || d2 < best) {
+                best = d2;
+                px = qx;
+                py = qy;
+            }
+        }
+        return sqrt(best);
+    }
     if (D.hole == HOLE_DISC) {
         const double ex = x - D.cx, ey = y - D.cy;
         const double d = sqrt(ex * ex + ey * ey);
@@ -326,7 +365,7 @@ __device__ __forceinline__ double hole_project(const Inst &D, double x, double y
         }
         return fabs(d - D.r);
     }
-    if (in_hole(D, x, y)) {
+    if (in_hole<F>(D, x, y)) {
         double dd[4] = {x - D.bx0, D.bx1 - x, y - D.by0, D.by1 - y};
         int e = 0;
         for (int c = 1; c < 4; ++c)
@@ -345,10 +384,11 @@ __device__ __forceinline__ double hole_project(const Inst &D, double x, double y
 // the clamp (outer part); in the closed hole, its projection; inside the
 // domain (a path stopped by the cap), the nearest of the four edges and the
 // hole.  Returns 1 for the outer boundary, 2 for the hole.
+template <int F>
 __device__ __forceinline__ int project(const Inst &D, double x, double y, double &px, double &py)
 {
     if (D.reflect) {
-        hole_project(D, x, y, px, py);
+        hole_project<F>(D, x, y, px, py);
         return 2;
     }
     if (x <= D.x0 || x >= D.x1 || y <= D.y0 || y >= D.y1) {
@@ -356,19 +396,19 @@ __device__ __forceinline__ int project(const Inst &D, double x, double y, double
         py = fmin(fmax(y, D.y0), D.y1);
         return 1;
     }
-    if (!(D.hole && in_hole(D, x, y))) {
+    if (!(D.hole && in_hole<F>(D, x, y))) {
         double dd[4] = {x - D.x0, D.x1 - x, y - D.y0, D.y1 - y};
         int e = 0;
         for (int c = 1; c < 4; ++c)
             if (dd[c] < dd[e]) e = c;
         double hx, hy;
-        if (!D.hole || dd[e] <= hole_project(D, x, y, hx, hy)) {
+        if (!D.hole || dd[e] <= hole_project<F>(D, x, y, hx, hy)) {
             px = e == 0 ? D.x0 : (e == 1 ? D.x1 : x);
             py = e == 2 ? D.y0 : (e == 3 ? D.y1 : y);
             return 1;
         }
     }
-    hole_project(D, x, y, px, py);
+    hole_project<F>(D, x, y, px, py);
     return 2;
 }
 
@@ -430,7 +470,10 @@ __device__ __forceinline__ double2 robin_datum(const Inst &D, int face, double x
 {
     const BCDev &B = D.outer;
     if (B.kind != BC_PLANE_WAVE_ROBIN) return bc_eval<F>(D, B, x, y);
-    const double dn = face == 0 ? -B.c[2] : (face == 1 ? B.c[2] : (face == 2 ? -B.c[3] : B.c[3]));
+    // face 4 (kernels with kFeatCurved): the disc's edge, outward normal
+    // (x - c) / R at the foot
+    const double dn = ((F & kFeatCurved) && face == 4) ? ((x - D.ocx) * B.c[2] + (y - D.ocy) * B.c[3]) / D.orad
+                    : (face == 0 ? -B.c[2] : (face == 1 ? B.c[2] : (face == 2 ? -B.c[3] : B.c[3])));
     const double2 w = plane_wave<F>(B, x, y);
     // i (kappa dn - k) = -ki dn + i (kr dn - k)
     const double ar = -B.c[5] * dn, ai = B.c[4] * dn - D.k;
@@ -446,7 +489,7 @@ __device__ __forceinline__ double2 exit_datum(const Inst &D, double x, double y,
         return bc_eval<F>(D, (outer || !exited) ? D.outer : D.inner, x, y);
     }
     double px, py;
-    const int which = project(D, x, y, px, py);
+    const int which = project<F>(D, x, y, px, py);
     const BCDev *B = which == 2 ? &D.inner : &D.outer;
     return bc_eval<F>(D, *B, px, py);
 }

@@ -145,7 +145,7 @@ __device__ __forceinline__ float exp_src(float a, const NoTables &)
 // box's edges likewise rounded inward); the disc test runs in FP32 and falls
 // back to FP64 only within a thin band around the circle.
 template <int F>
-__device__ __forceinline__ bool is_out(const Inst &, const Consts<double> &K, double x, double y)
+__device__ __forceinline__ bool is_out(const Inst &D, const Consts<double> &K, double x, double y)
 {
     if (!((F & kFeatReflect) && K.reflect) && (x <= K.ex0 || x >= K.ex1 || y <= K.ey0 || y >= K.ey1))
         return true;
@@ -154,6 +154,7 @@ __device__ __forceinline__ bool is_out(const Inst &, const Consts<double> &K, do
         return ex * ex + ey * ey <= K.r2f;
     }
     if ((F & kFeatDisc) && K.hole == HOLE_BOX) return x >= K.hx0 && x <= K.hx1 && y >= K.hy0 && y <= K.hy1;
+    if ((F & kFeatCurved) && K.hole == HOLE_RHOMBUS) return fabs(x - D.cx) / D.r + fabs(y - D.cy) / D.ry <= 1.0;
     return false;
 }
 template <int F>
@@ -273,6 +274,29 @@ __device__ __forceinline__ Mirror<float> reflect_c(const Consts<float> &K, float
 __device__ __forceinline__ Mirror<double> reflect_c(const Consts<double> &K, double &x, double &y, double &, double &)
 {
     return reflect(K, x, y);
+}
+
+// Reflection at the disc's edge (disc domains, FP64): a point past the
+// circle is mirrored radially, X' = c + (R - o) (X - c) / |X - c| with the
+// overshoot o = |X - c| - R; the local time grows by 2 o, and the move's foot
+// c + R (X - c) / |X - c| is returned in (fx, fy).  face 4, or -1 for none.
+__device__ __forceinline__ Mirror<double> reflect_disc(const Inst &D, double &x, double &y, double &fx, double &fy)
+{
+    Mirror<double> m{0.0, 0.0, -1, -1};
+    const double ex = x - D.ocx, ey = y - D.ocy;
+    const double d2 = ex * ex + ey * ey;
+    if (d2 > D.orad2) {
+        const double d = sqrt(d2);
+        const double o = d - D.orad;
+        const double s = (D.orad - o) / d, f = D.orad / d;
+        fx = D.ocx + f * ex;
+        fy = D.ocy + f * ey;
+        x = D.ocx + s * ex;
+        y = D.ocy + s * ey;
+        m.lx = 2.0 * o;
+        m.fx = 4;
+    }
+    return m;
 }
 
 // Bilinear interpolation of u_n at (x, y): cell p = floor((x - x0)/dx)
@@ -657,11 +681,18 @@ __device__ __forceinline__ bool advance(const Inst &D, const Consts<R> &K, PathS
     // a reflecting edge mirrors each step back into the rectangle
     const bool refl = (F & kFeatReflect) && K.reflect;
     Mirror<R> m1{(R)0, (R)0, -1, -1}, m2{(R)0, (R)0, -1, -1};
-    if (refl) m1 = reflect_c(K, x1, y1, x1l, y1l);
+    R f1x = (R)0, f1y = (R)0, f2x = (R)0, f2y = (R)0;   // feet of the disc's mirror moves
+    if (refl) {
+        if constexpr ((F & kFeatCurved) != 0) m1 = reflect_disc(D, x1, y1, f1x, f1y);   // single instance
+        else m1 = reflect_c(K, x1, y1, x1l, y1l);
+    }
     R x2, y2, x2l, y2l;
     move(K, x1, x1l, z1x, x2, x2l);
     move(K, y1, y1l, z1y, y2, y2l);
-    if (refl) m2 = reflect_c(K, x2, y2, x2l, y2l);
+    if (refl) {
+        if constexpr ((F & kFeatCurved) != 0) m2 = reflect_disc(D, x2, y2, f2x, f2y);
+        else m2 = reflect_c(K, x2, y2, x2l, y2l);
+    }
     const bool general = (F & kFeatGeneral) && K.general;
     bool out1, out2, second;
     if constexpr ((F & kFeatReflect) != 0) {
@@ -701,12 +732,18 @@ __device__ __forceinline__ bool advance(const Inst &D, const Consts<R> &K, PathS
                 const int c = __builtin_ctz(todo);
                 todo &= todo - 1u;
                 const bool s2 = c >= 2, ym = (c & 1) != 0;
-                const int face = ym ? (s2 ? m2.fy : m1.fy) : (s2 ? m2.fx : m1.fx);
-                const R px = s2 ? x2 : x1, py = s2 ? y2 : y1;
-                const R fx = face == 0 ? K.lx0 : (face == 1 ? K.lx1 : px);
-                const R fy = face == 2 ? K.ly0 : (face == 3 ? K.ly1 : py);
-                const R dxi = ym ? (s2 ? m2.ly : m1.ly) : (s2 ? m2.lx : m1.lx);
-                local_time_term<R, F>(D, K, face, fx, fy, dxi, s2 ? w2 : w1, cu.ik, P);
+                if constexpr ((F & kFeatCurved) != 0) {
+                    // the disc's edge: one radial move per step, at its foot
+                    local_time_term<R, F>(D, K, 4, s2 ? f2x : f1x, s2 ? f2y : f1y, s2 ? m2.lx : m1.lx,
+                                          s2 ? w2 : w1, cu.ik, P);
+                } else {
+                    const int face = ym ? (s2 ? m2.fy : m1.fy) : (s2 ? m2.fx : m1.fx);
+                    const R px = s2 ? x2 : x1, py = s2 ? y2 : y1;
+                    const R fx = face == 0 ? K.lx0 : (face == 1 ? K.lx1 : px);
+                    const R fy = face == 2 ? K.ly0 : (face == 3 ? K.ly1 : py);
+                    const R dxi = ym ? (s2 ? m2.ly : m1.ly) : (s2 ? m2.lx : m1.lx);
+                    local_time_term<R, F>(D, K, face, fx, fy, dxi, s2 ? w2 : w1, cu.ik, P);
+                }
             } while (todo);
         }
     }
@@ -1265,8 +1302,9 @@ __device__ __forceinline__ void stream_paths(const Inst *__restrict__ insts, con
     constexpr bool kLds = (F & kLdsGrid) != 0;
     constexpr int kWpb = kLds ? 16 : 4;
     __shared__ unsigned long long lds_acc[kWpb][kNodeAcc * 12];   // node accumulators per wave
-    // the queue of local-time moves of each wave (reflecting edge only)
-    constexpr bool kLt = (F & kFeatReflect) != 0;
+    // the queue of local-time moves of each wave (reflecting rectangle edge;
+    // the disc's moves are evaluated at once)
+    constexpr bool kLt = (F & kFeatReflect) != 0 && (F & kFeatCurved) == 0;
     using LtS = typename std::conditional<kLt, LtStore<R>, LtNone>::type;
     __shared__ LtS lt_store[kWpb];
     // the staged copy of the (only) instance's row-major FP32 iterate
@@ -1915,7 +1953,17 @@ __global__ void fk_debug_paths_kernel(const Inst *__restrict__ inst, const int32
     const double sx = D.x0 + (double)gi * D.dx, sy = D.y0 + (double)gj * D.dy;
     start(P, (R)sx, (R)sy, (R)(sx - (double)(R)sx), (R)(sy - (double)(R)sy));
     bool exited = false;
-    while (!advance<R, kFeatAll>(D, K, P, (uint32_t)ms[i], (uint32_t)node, ctr3, cu, exited)) {
+    if constexpr (sizeof(R) == 8) {
+        if (D.curved) {
+            while (!advance<R, kFeatAll | kFeatCurved>(D, K, P, (uint32_t)ms[i], (uint32_t)node, ctr3, cu, exited)) {
+            }
+        } else {
+            while (!advance<R, kFeatAll>(D, K, P, (uint32_t)ms[i], (uint32_t)node, ctr3, cu, exited)) {
+            }
+        }
+    } else {
+        while (!advance<R, kFeatAll>(D, K, P, (uint32_t)ms[i], (uint32_t)node, ctr3, cu, exited)) {
+        }
     }
     J[i] = P.t;
     Pending Q;
@@ -1975,6 +2023,17 @@ hipError_t launch_stream(int precision, int features, const Inst *d_insts, const
         }
     }
     dim3 grid(n_blocks), block(256);
+    if (features & kFeatCurved) {
+        // disc domains: FP64 only (checked at set-up); a hole and the
+        // reflecting edge always
+        switch (features & kFeatAll) {
+        case 9: hipLaunchKernelGGL(fk_stream_f64<9 | kFeatCurved>, grid, block, 0, s, d_insts, Q, head); break;
+        case 11: hipLaunchKernelGGL(fk_stream_f64<11 | kFeatCurved>, grid, block, 0, s, d_insts, Q, head); break;
+        case 13: hipLaunchKernelGGL(fk_stream_f64<13 | kFeatCurved>, grid, block, 0, s, d_insts, Q, head); break;
+        default: hipLaunchKernelGGL(fk_stream_f64<15 | kFeatCurved>, grid, block, 0, s, d_insts, Q, head); break;
+        }
+        return hipGetLastError();
+    }
     if (precision == 64 && (features & kFeatAll) == 0 && l1_grid) {
         hipLaunchKernelGGL(fk_stream_f64_l1, grid, block, 0, s, d_insts, Q, head);
         return hipGetLastError();

@@ -183,8 +183,8 @@ fk_status setup_problem(const fk_domain *domain, const fk_source *f, const fk_bc
     if (g_inner) P.inner = *g_inner;
     else std::memset(&P.inner, 0, sizeof(P.inner));
     const fk_domain &d = P.dom;
-    if (d.kind != FK_DOMAIN_RECT && d.kind != FK_DOMAIN_RECT_MINUS_DISC && d.kind != FK_DOMAIN_RECT_MINUS_BOX)
-        return fail(FK_EINVAL, "unknown domain kind");
+    if (d.kind < FK_DOMAIN_RECT || d.kind > FK_DOMAIN_DISC_MINUS_DISC) return fail(FK_EINVAL, "unknown domain kind");
+    const bool disc_dom = P.disc_domain();
     if (d.edge != FK_EDGE_ABSORBING && d.edge != FK_EDGE_REFLECTING)
         return fail(FK_EINVAL, "edge must be FK_EDGE_ABSORBING or FK_EDGE_REFLECTING");
     if (!finite_all({d.x0, d.x1, d.y0, d.y1}) || !(d.x1 > d.x0) || !(d.y1 > d.y0))
@@ -204,6 +204,28 @@ fk_status setup_problem(const fk_domain *domain, const fk_source *f, const fk_bc
             return fail(FK_EINVAL, "box hole needs a finite centre and half-sides r, ry > 0");
         if (!(d.cx - d.r > d.x0 && d.cx + d.r < d.x1 && d.cy - d.ry > d.y0 && d.cy + d.ry < d.y1))
             return fail(FK_EINVAL, "box must lie strictly inside the rectangle");
+    }
+    if (disc_dom) {
+        const double side = d.x1 - d.x0;
+        if (!(std::fabs(side - (d.y1 - d.y0)) <= 1e-12 * side))
+            return fail(FK_EINVAL, "a disc domain needs a square box (the disc is inscribed in it)");
+        if (d.edge != FK_EDGE_REFLECTING) return fail(FK_EINVAL, "a disc domain's edge must reflect");
+        const double ocx = 0.5 * (d.x0 + d.x1), ocy = 0.5 * (d.y0 + d.y1), R = 0.5 * side;
+        const bool rh = d.kind == FK_DOMAIN_DISC_MINUS_RHOMBUS;
+        if (!finite_all({d.cx, d.cy, d.r}) || !(d.r > 0.0) || (rh && !(d.ry > 0.0 && std::isfinite(d.ry))))
+            return fail(FK_EINVAL, "the hole needs a finite centre and r > 0 (and ry > 0 for the rhombus)");
+        // the hole strictly inside the disc: its farthest point nearer than R
+        const double far = rh ? std::fmax(std::hypot(std::fabs(d.cx - ocx) + d.r, d.cy - ocy),
+                                          std::hypot(d.cx - ocx, std::fabs(d.cy - ocy) + d.ry))
+                              : std::hypot(d.cx - ocx, d.cy - ocy) + d.r;
+        if (!(far < R)) return fail(FK_EINVAL, "the hole must lie strictly inside the disc");
+        // a step is shorter than 8.2 sqrt(2 h): one radial mirror lands inside
+        if (!(side > 12.0 * std::sqrt(2.0 * params->h)))
+            return fail(FK_EINVAL, "a disc domain needs a diameter longer than 12 sqrt(2 h)");
+        if (params->precision != 64) return fail(FK_EINVAL, "a disc domain needs FP64 stepping");
+        if (params->k != 0.0 || params->alpha != 0.0 || params->damping != 0.0)
+            return fail(FK_EINVAL, "a disc domain serves the exit-time and local-time solves: k = 0, "
+                                   "alpha = 0, no damping");
     }
     const bool reflecting = d.edge == FK_EDGE_REFLECTING;
     if (reflecting) {
@@ -261,17 +283,25 @@ fk_status setup_problem(const fk_domain *domain, const fk_source *f, const fk_bc
             const size_t id = (size_t)i + (size_t)d.nx * j;
             const double x = d.x0 + (double)i * dx, y = d.y0 + (double)j * dy;
             uint8_t c = 0;
-            if (d.kind == FK_DOMAIN_RECT_MINUS_DISC) {
+            if (d.kind == FK_DOMAIN_RECT_MINUS_DISC || d.kind == FK_DOMAIN_DISC_MINUS_DISC) {
                 const double ex = x - d.cx, ey = y - d.cy;
                 if (ex * ex + ey * ey <= d.r * d.r) c = 2;
+            } else if (d.kind == FK_DOMAIN_DISC_MINUS_RHOMBUS) {
+                if (std::fabs(x - d.cx) / d.r + std::fabs(y - d.cy) / d.ry <= 1.0 + 1e-9) c = 2;
             } else if (d.kind == FK_DOMAIN_RECT_MINUS_BOX) {
                 if (x >= d.cx - d.r - tx && x <= d.cx + d.r + tx && y >= d.cy - d.ry - ty && y <= d.cy + d.ry + ty)
                     c = 2;
             }
             if (c == 0 && !reflecting && (i == 0 || j == 0 || i == d.nx - 1 || j == d.ny - 1)) c = 1;
+            if (c == 0 && disc_dom) {
+                // outside the closed disc: exterior, no unknown, value 0
+                const double R = 0.5 * (d.x1 - d.x0);
+                const double ex = x - 0.5 * (d.x0 + d.x1), ey = y - 0.5 * (d.y0 + d.y1);
+                if (ex * ex + ey * ey > R * R * (1.0 + 1e-12)) c = 3;
+            }
             P.cls[id] = c;
             if (c == 0) P.interior.push_back((int32_t)id);
-            else host_bc(P, c == 2 ? P.inner : P.outer, x, y, P.grid0[2 * id], P.grid0[2 * id + 1]);
+            else if (c != 3) host_bc(P, c == 2 ? P.inner : P.outer, x, y, P.grid0[2 * id], P.grid0[2 * id + 1]);
         }
     }
     // Work order: nodes with the longest expected paths first, so that the
@@ -288,7 +318,9 @@ fk_status setup_problem(const fk_domain *domain, const fk_source *f, const fk_bc
         for (int32_t id : P.interior) {
             const double x = d.x0 + (double)(id % d.nx) * dx, y = d.y0 + (double)(id / d.nx) * dy;
             double dc = 0.0;
-            if (d.kind == FK_DOMAIN_RECT_MINUS_DISC) {
+            if (d.kind == FK_DOMAIN_DISC_MINUS_RHOMBUS) {
+                dc = std::fmax(std::fabs(x - d.cx) / d.r + std::fabs(y - d.cy) / d.ry - 1.0, 0.0) * std::fmin(d.r, d.ry);
+            } else if (d.kind == FK_DOMAIN_RECT_MINUS_DISC || d.kind == FK_DOMAIN_DISC_MINUS_DISC) {
                 dc = std::sqrt((x - d.cx) * (x - d.cx) + (y - d.cy) * (y - d.cy)) - d.r;
             } else if (d.kind == FK_DOMAIN_RECT_MINUS_BOX) {
                 const double ox = std::fmax(std::fabs(x - d.cx) - d.r, 0.0);
@@ -430,9 +462,16 @@ fkd::Inst make_inst(const HostProblem &P, const InstanceBuffers &B)
     // reflection: x < x0 exactly iff x < RU(x0), x > x1 iff x > RD(x1)
     D.x0_ri = ru(d.x0); D.x1_ri = rd(d.x1); D.y0_ri = ru(d.y0); D.y1_ri = rd(d.y1);
     D.nx = d.nx; D.ny = d.ny;
-    D.hole = d.kind == FK_DOMAIN_RECT_MINUS_DISC ? fkd::HOLE_DISC
-           : (d.kind == FK_DOMAIN_RECT_MINUS_BOX ? fkd::HOLE_BOX : fkd::HOLE_NONE);
+    D.hole = (d.kind == FK_DOMAIN_RECT_MINUS_DISC || d.kind == FK_DOMAIN_DISC_MINUS_DISC) ? fkd::HOLE_DISC
+           : d.kind == FK_DOMAIN_RECT_MINUS_BOX ? fkd::HOLE_BOX
+           : d.kind == FK_DOMAIN_DISC_MINUS_RHOMBUS ? fkd::HOLE_RHOMBUS : fkd::HOLE_NONE;
     D.reflect = P.reflect() ? 1 : 0;
+    D.curved = P.disc_domain() ? 1 : 0;
+    D.ry = d.ry;
+    D.ocx = 0.5 * (d.x0 + d.x1);
+    D.ocy = 0.5 * (d.y0 + d.y1);
+    D.orad = 0.5 * (d.x1 - d.x0);
+    D.orad2 = D.orad * D.orad;
     D.n_interior = (int32_t)P.interior.size();
     D.src_kind = P.src.kind;
     D.g_unproj = P.par.g_unprojected ? 1 : 0;

@@ -55,9 +55,14 @@ struct HostProblem {
     int features() const
     {
         return (dom.kind != FK_DOMAIN_RECT ? 1 : 0) | (src.kind != FK_SRC_ZERO ? 2 : 0) |
-               (alpha() != par.k * par.k || par.damping != 0.0 ? 4 : 0) | (reflect() ? 8 : 0);
+               (alpha() != par.k * par.k || par.damping != 0.0 ? 4 : 0) | (reflect() ? 8 : 0) |
+               (disc_domain() ? fkd::kFeatCurved : 0);
     }
     bool reflect() const { return dom.edge == FK_EDGE_REFLECTING; }
+    bool disc_domain() const
+    {
+        return dom.kind == FK_DOMAIN_DISC_MINUS_RHOMBUS || dom.kind == FK_DOMAIN_DISC_MINUS_DISC;
+    }
     double alpha() const { return par.alpha == 0.0 ? par.k * par.k : par.alpha; }
     size_t n_nodes() const { return (size_t)dom.nx * (size_t)dom.ny; }
     size_t n_cells() const { return (size_t)(dom.nx - 1) * (size_t)(dom.ny - 1); }

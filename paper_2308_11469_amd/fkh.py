@@ -22,7 +22,7 @@ FK_OK, FK_EINVAL, FK_ENOMEM, FK_EDEVICE, FK_EDIVERGED, FK_ENOTCONVERGED, FK_EBUS
 STATUS_NAMES = {0: "FK_OK", 1: "FK_EINVAL", 2: "FK_ENOMEM", 3: "FK_EDEVICE", 4: "FK_EDIVERGED",
                 5: "FK_ENOTCONVERGED", 6: "FK_EBUSY", 7: "FK_ECANCELLED"}
 
-_DOMAIN = {"rect": 0, "rect_minus_disc": 1, "rect_minus_box": 2}
+_DOMAIN = {"rect": 0, "rect_minus_disc": 1, "rect_minus_box": 2, "disc_minus_rhombus": 3, "disc_minus_disc": 4}
 _SRC = {"zero": 0, "const": 1, "gaussian": 2}
 _BC = {"zero": 0, "plane_wave": 1, "bilinear": 2, "table": 3, "plane_wave_robin": 4}
 GATHER = {"auto": 0, "nodes": 1, "cells": 2}   # layout of the gathered copy of u_n (fk_gather_layout)

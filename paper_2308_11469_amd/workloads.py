@@ -38,6 +38,11 @@ import numpy as np
 RECT = "rect"
 RECT_MINUS_DISC = "rect_minus_disc"
 RECT_MINUS_BOX = "rect_minus_box"
+# the disc inscribed in the square [x0, x1] x [y0, y1], with a reflecting
+# edge, minus a closed rhombus |x - cx| / r + |y - cy| / ry <= 1 or a closed
+# disc of radius r at (cx, cy)
+DISC_MINUS_RHOMBUS = "disc_minus_rhombus"
+DISC_MINUS_DISC = "disc_minus_disc"
 
 
 @dataclass
@@ -290,6 +295,17 @@ def annulus_shape3(k: float = 0.5, nx: int = 41, ny: int = 65, M: int = 4096, h:
     return _annulus("annulus_shape3_k%g_%dx%d" % (k, nx, ny), -0.5, 0.5, -0.8, 0.8,
                     (RECT_MINUS_BOX, 0.0, 0.0, 0.05, 0.4), nx, ny, k, h, M, int(math.ceil(64.0 / h)),
                     precision, seed)
+
+
+def annulus_shape2(k: float = 0.0, n: int = 41, M: int = 4096, h: float = 1e-4, precision: int = 64,
+                   seed: int = 12) -> Problem:
+    """The paper's shape 2 as read here: the disc of radius 0.45 at
+    (0.8, 0.5) with a reflecting edge, minus the rhombus of diagonals 0.15
+    (half-diagonals 0.075 along x and y) at the disc's centre (the printed
+    hole centre (0, 0) lies outside the disc); n x n grid on the disc's
+    bounding square.  Step cap 60 / h."""
+    return _annulus("annulus_shape2", 0.35, 1.25, 0.05, 0.95, (DISC_MINUS_RHOMBUS, 0.8, 0.5, 0.075, 0.075),
+                    n, n, k, h, M, int(math.ceil(60.0 / h)), precision, seed)
 
 
 def annulus_fig2(k: float = 0.8, n: int = 21, M: int = 4096, h: float = 1e-4, precision: int = 64,

@@ -216,3 +216,32 @@ def test_annulus_workloads_accepted(lib):
                                          inner=W.BC("plane_wave", 1.0, 0.4), alpha=3.0, damping=0.5)):
         st, nbytes = arena_status(p)
         assert st == fkh.FK_OK, (p.name, fkh.lib().fk_helmholtz_last_error())
+
+
+@pytest.mark.parametrize("bad", ["not_square", "absorbing", "fp32", "k_positive", "alpha", "damping",
+                                 "hole_outside", "rhombus_flat", "small_disc"])
+def test_disc_domain_validation(lib, bad):
+    # the disc inscribed in a square box, reflecting, FP64, exit-time and
+    # local-time solves (k = 0, alpha = 0, no damping) only
+    p = W.annulus_shape2(n=21)
+    assert arena_status(p)[0] == fkh.FK_OK
+    assert arena_status(p.replace(domain_kind=W.DISC_MINUS_DISC, r=0.1))[0] == fkh.FK_OK
+    if bad == "not_square":
+        p = p.replace(y1=p.y1 + 0.1)
+    elif bad == "absorbing":
+        p = p.replace(reflect=False)
+    elif bad == "fp32":
+        p = p.replace(precision=32)
+    elif bad == "k_positive":
+        p = p.replace(k=0.5)
+    elif bad == "alpha":
+        p = p.replace(alpha=1.0)
+    elif bad == "damping":
+        p = p.replace(damping=0.5)
+    elif bad == "hole_outside":
+        p = p.replace(cx=0.0, cy=0.0)      # the printed centre of Table 1's shape 2
+    elif bad == "rhombus_flat":
+        p = p.replace(ry=0.0)
+    elif bad == "small_disc":
+        p = p.replace(h=0.01)
+    assert arena_status(p)[0] == fkh.FK_EINVAL

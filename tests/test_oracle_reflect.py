@@ -234,3 +234,92 @@ def test_mc_reflected_paths_stay_in_rectangle_and_end_in_hole():
 def test_reflecting_problem_needs_explicit_step_cap():
     with pytest.raises(ValueError):
         fkmc.jmax_auto(W.annulus_shape1().replace(jmax=0))
+
+
+# ------------------------------------------------ the disc's curved edge
+
+def concentric(h, M, n=21, a=0.15):
+    """The unit disc of radius 0.5 at (0.5, 0.5) with a reflecting edge,
+    minus the closed disc of radius a at its centre."""
+    return W.Problem(name="concentric", domain_kind=W.DISC_MINUS_DISC, x0=0.0, x1=1.0, y0=0.0, y1=1.0,
+                     cx=0.5, cy=0.5, r=a, reflect=True, nx=n, ny=n, k=0.0, h=h, M=M, seed=31,
+                     jmax=int(math.ceil(60.0 / h)), outer=W.BC("zero"), inner=W.BC("zero"))
+
+
+def concentric_exact(which, rho, R=0.5, a=0.15):
+    # Delta w = -1, w(a) = 0, w'(R) = 0:  w = R^2/2 ln(rho/a) - (rho^2 - a^2)/4
+    # Delta L = 0,  L(a) = 0, L'(R) = 1:  L = R ln(rho/a)
+    if which == "exit_time":
+        return R * R / 2.0 * np.log(rho / a) - (rho ** 2 - a * a) / 4.0
+    return R * np.log(rho / a)
+
+
+@pytest.mark.parametrize("which", ["exit_time", "local_time"])
+def test_mc_curved_edge_matches_concentric_closed_forms(which):
+    # the radial mirror and its local time 2 x overshoot against the closed
+    # forms of the concentric annulus; the hole's radius is shrunk by the
+    # continuity correction of the once-per-step exit test (O(sqrt h) bias)
+    h = 2e-5
+    p = concentric(h, M=4000)
+    if which == "exit_time":
+        p = p.replace(src_kind="const", src_amp=-1.0 + 0j)
+    else:
+        p = p.replace(outer=W.BC("bilinear", coeffs=(1.0 + 0j, 0j, 0j, 0j)))
+    cls = fkmc.node_classes(p).ravel()
+    # nodes at several radii, the edge's own nodes (on the circle) included
+    ids = np.array([10 + 21 * 10 + d for d in (4, 6, 8, 10)] + [10 + 21 * 0, 0 + 21 * 10], dtype=np.int32)
+    assert np.all(cls[ids] == 0)
+    xs = p.x0 + (ids % p.nx) * 0.05
+    ys = p.y0 + (ids // p.nx) * 0.05
+    rho = np.hypot(xs - 0.5, ys - 0.5)
+    est = fkmc.fk_nodes(p, None, 0, ids)
+    a_eff = 0.15 - CF.bgk_beta() * math.sqrt(2.0 * h)
+    ref = concentric_exact(which, rho, a=a_eff)
+    err = np.abs(est["mean"].real - ref)
+    assert np.all(err < 4.0 * est["se"].real + 0.015 * ref), (err, est["se"].real, ref)
+    assert est["capped"].sum() == 0
+
+
+def test_mc_curved_edge_local_time_uses_twice_the_overshoot():
+    # power of the pin above: half the local-time increment (a plausible slip)
+    # misses the closed form by far more than its tolerance
+    p = concentric(2e-5, M=2000).replace(outer=W.BC("bilinear", coeffs=(0.5 + 0j, 0j, 0j, 0j)))
+    ids = np.array([10 + 21 * 10 + 8], dtype=np.int32)
+    est = fkmc.fk_nodes(p, None, 0, ids)
+    full = concentric_exact("local_time", np.array([0.4]), a=0.15 - CF.bgk_beta() * math.sqrt(4e-5))[0]
+    assert abs(est["mean"].real[0] - full) > 0.3 * full
+
+
+def test_disc_domain_node_classes_and_paths_stay_in_the_disc():
+    p = W.annulus_shape2(n=41, h=1e-4, k=0.5)
+    cls = fkmc.node_classes(p)
+    X, Y = np.meshgrid(np.linspace(p.x0, p.x1, p.nx), np.linspace(p.y0, p.y1, p.ny))
+    outside = (X - 0.8) ** 2 + (Y - 0.5) ** 2 > 0.45 ** 2 * (1 + 1e-12)
+    rhombus = np.abs(X - 0.8) / 0.075 + np.abs(Y - 0.5) / 0.075 <= 1 + 1e-9
+    assert np.array_equal(cls == 2, rhombus) and np.array_equal(cls == 3, outside & ~rhombus)
+    assert np.array_equal(cls == 0, ~outside & ~rhombus)
+    ids = np.nonzero(cls.ravel() == 0)[0]
+    for nid in (int(ids[0]), int(ids[len(ids) // 2]), int(ids[-1])):
+        for m in range(4):
+            s, J, cap, (x, y) = fkmc.path(p, None, 0, nid, m)
+            assert not cap
+            # ends in the closed rhombus, within one step of its edge
+            assert abs(x - 0.8) / 0.075 + abs(y - 0.5) / 0.075 <= 1.0
+            assert (x - 0.8) ** 2 + (y - 0.5) ** 2 <= 0.45 ** 2
+
+
+def test_rhombus_projection_is_the_nearest_boundary_point():
+    p = W.annulus_shape2(n=21)
+    rng = np.random.default_rng(2)
+    t = np.linspace(0.0, 1.0, 20001)
+    vx = np.array([0.875, 0.8, 0.725, 0.8, 0.875])
+    vy = np.array([0.5, 0.575, 0.5, 0.425, 0.5])
+    pts = np.concatenate([np.stack([vx[e] + t * (vx[e + 1] - vx[e]), vy[e] + t * (vy[e + 1] - vy[e])], 1)
+                          for e in range(4)])
+    for _ in range(200):
+        x, y = 0.8 + rng.uniform(-0.2, 0.2), 0.5 + rng.uniform(-0.2, 0.2)
+        which, (px, py) = fkmc.project(p, x, y)
+        assert which == 2
+        brute = np.min(np.hypot(pts[:, 0] - x, pts[:, 1] - y))
+        assert abs(math.hypot(px - x, py - y) - brute) < 1e-5
+        assert abs(abs(px - 0.8) / 0.075 + abs(py - 0.5) / 0.075 - 1.0) < 1e-12
