@@ -114,7 +114,7 @@ def _issue(k):
 
 
 ONLY = ("headline", "fp32_same_config", "cavity65", "batch256_tick", "served_vs_plain", "scatter_served_vs_plain",
-        "serving", "serving_pdd", "serving_sweep", "annulus", "pdd", "tuned_tick")
+        "serving", "serving_pdd", "serving_sweep", "annulus", "disc_annulus", "pdd", "tuned_tick")
 
 
 def parse(argv=None):
@@ -246,7 +246,7 @@ def _timed_solver(p, steps, warmup, **kw):
 def _features(p):
     return ((1 if p.domain_kind != "rect" else 0) | (2 if p.src_kind != "zero" else 0)
             | (4 if (p.alpha is not None and p.alpha != p.k * p.k) or p.damping != 0.0 else 0)
-            | (8 if p.reflect else 0))
+            | (8 if p.reflect else 0) | (64 if p.domain_kind in ("disc_minus_rhombus", "disc_minus_disc") else 0))
 
 
 def _roofline(p, run, workload):
@@ -614,6 +614,27 @@ def annulus_shape3(steps=3):
     return out
 
 
+def disc_annulus_shape2(steps=3):
+    """The annular problem of Sec. 2.3 on the paper's shape 2 as read here
+    (the disc of radius 0.45 minus the centred rhombus of diagonals 0.15,
+    reflecting curved edge) at the grid step 0.01 of its FE mesh (91 x 91
+    nodes on the disc's square), k = 0.5, M = 4096, h = 1e-4: path-steps/s of
+    the FP64 disc kernel, one iteration per step after two warm-up
+    iterations."""
+    from paper_2308_11469_amd import workloads as W
+    out = {"workload": "annulus shape 2, 91x91, k=0.5, M=4096, h=1e-4, reflecting disc edge"}
+    _log("disc annulus FP64")
+    p = W.annulus_shape2(k=0.5, n=91, M=4096, h=1e-4)
+    run = _timed_solver(p, steps, 2)
+    total = sum(r["path_steps"] for r in run["timed"])
+    rf = _roofline(p, run, out["workload"])
+    out["fp64"] = dict(value=total / run["wall"], unit="path-steps/s", ms_per_step=run["wall"] / steps * 1e3,
+                       kernel=rf["kernel"], kernel_ms_avg=rf["kernel_ms_avg"],
+                       path_steps_per_iteration=total / steps, path_steps_per_launch=rf["path_steps_per_launch"],
+                       roofline_frac=rf["frac"], traffic=rf["traffic"], valu_issue=rf["valu_issue"])
+    return out
+
+
 def pdd_cavity65(k, n_iters=12):
     """The 65x65 cavity (FP64, M = 4096, h = 1e-4) by probabilistic domain
     decomposition: paths from the nodes on the grid lines 16, 32, 48 in x
@@ -683,6 +704,7 @@ def main(argv=None):
         "serving": serving_window,
         "serving_pdd": lambda: serving_window(pdd_spacing=32),
         "annulus": annulus_shape3,
+        "disc_annulus": disc_annulus_shape2,
         "pdd": lambda: pdd_cavity65(a.k),
         "tuned_tick": tuned_tick,
     }
@@ -714,8 +736,8 @@ def main(argv=None):
         "extra": h["extra"],
     }
     if not a.no_extras and a.only is None:
-        for name in ("fp32_same_config", "cavity65", "served_vs_plain", "scatter_served_vs_plain", "annulus", "pdd",
-                     "batch256_tick", "serving", "serving_pdd"):
+        for name in ("fp32_same_config", "cavity65", "served_vs_plain", "scatter_served_vs_plain", "annulus",
+                     "disc_annulus", "pdd", "batch256_tick", "serving", "serving_pdd"):
             out["extra"][name] = parts[name]()
     if not a.no_cpu and a.only is None:
         _log("cpu_baseline")

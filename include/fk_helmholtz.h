@@ -94,10 +94,11 @@ typedef enum {
  * datum g_outer): a path past the circle is mirrored radially, the local
  * time grows by twice the overshoot, the datum is taken at the move's foot
  * on the circle (outward normal radial).  Grid nodes outside the closed disc
- * are exterior: no unknowns.  These domains serve the exit-time and
- * local-time solves (k = 0, alpha = 0, no damping: the iterate never enters
- * a path) in FP64 stepping, in the single-instance solver (fk_engine_add
- * rejects them). */
+ * are exterior: no unknowns; each carries the value of its nearest unknown
+ * node (fk_helmholtz_exterior_nodes), so that the bilinear interpolant of
+ * the iterate in the cells the circle cuts reads the iterate extended beyond
+ * the circle.  Any k, alpha and damping; FP64 stepping; the single-instance
+ * solver and fk_helmholtz_step_static (fk_engine_add rejects them). */
 typedef enum {
     FK_DOMAIN_RECT = 0, FK_DOMAIN_RECT_MINUS_DISC = 1, FK_DOMAIN_RECT_MINUS_BOX = 2,
     FK_DOMAIN_DISC_MINUS_RHOMBUS = 3, FK_DOMAIN_DISC_MINUS_DISC = 4
@@ -230,6 +231,19 @@ fk_status fk_helmholtz_work_items(const fk_domain *domain, const fk_bc *g_outer,
                                   int64_t *n_items, int32_t *paths_large, int32_t *items_large,
                                   int32_t *paths_small, int32_t *items_small);
 
+/* Disc domains (Sec. 2.5's annular problems with a disc as the outer
+ * boundary): the grid nodes outside the disc and, for each, the unknown node
+ * whose value it carries in the iterate (its nearest unknown node; ties: the
+ * lowest node id), so that the bilinear interpolant reads the iterate
+ * extended beyond the circle in the cells the circle cuts.  *n_pairs
+ * receives their count; pairs (host, may be NULL) receives 2 *n_pairs ints
+ * (exterior node id, unknown node id) when cap >= *n_pairs.  Other domains:
+ * *n_pairs = 0.  Host-only like fk_helmholtz_arena_bytes; g_outer may be
+ * NULL unless it is a TABLE.  FK_EINVAL: an invalid problem, n_pairs NULL,
+ * or pairs given with cap < *n_pairs (*n_pairs is still set). */
+fk_status fk_helmholtz_exterior_nodes(const fk_domain *domain, const fk_bc *g_outer, const fk_params *params,
+                                      int32_t *pairs, int64_t cap, int64_t *n_pairs);
+
 /* Validates the problem, classifies the grid nodes (unknown: interior or on
  * a reflecting edge; absorbing edge; hole), uploads the boundary data and
  * sets u_0 = 0.  device_arena: device memory of at least
@@ -265,7 +279,8 @@ fk_status fk_helmholtz_solve(fk_solver *s, fk_iter_report *final_report);
  * handle (not with or after fk_helmholtz_destroy). */
 fk_status fk_helmholtz_cancel(fk_solver *s);
 
-/* Copies the current iterate u_n (nx*ny complex) and, if se_reim is not NULL,
+/* Copies the current iterate u_n (nx*ny complex; a disc domain's exterior
+ * nodes hold their nearest unknown node's value) and, if se_reim is not NULL,
  * the per-node standard errors (SE_re, SE_im; 0 on nodes that are not
  * unknowns) of the last iteration.  on_device != 0: the pointers are device pointers. */
 fk_status fk_helmholtz_get(fk_solver *s, double *u_reim, double *se_reim, int32_t on_device);
@@ -276,7 +291,8 @@ fk_status fk_helmholtz_node_stats(fk_solver *s, int64_t *sum_j, int64_t *capped)
 
 /* Replaces the iterate by u_reim (nx*ny complex, host or device) on unknown
  * nodes and sets the iteration index to n (the next iteration uses counter
- * word n).  Absorbing-edge and hole nodes keep their data.  Used to resume from a
+ * word n).  Absorbing-edge and hole nodes keep their data; a disc domain's
+ * exterior nodes take their nearest unknown node's value.  Used to resume from a
  * checkpoint and to feed the same u_n to another implementation. */
 fk_status fk_helmholtz_set_iterate(fk_solver *s, const double *u_reim, int32_t n, int32_t on_device);
 
@@ -312,7 +328,9 @@ fk_status fk_helmholtz_set_pdd(fk_solver *s, const int32_t *cuts_x, int32_t n_cu
  * FK_STATIC_SCRATCH_BYTES per GPU (held until the process ends): no device
  * allocation, no pinned host memory, no events.
  *   u_n     device, nx*ny complex (unknown nodes read; edge and hole nodes
- *           take the problem's data), or NULL for u_0 = 0 (then n must be 0)
+ *           take the problem's data, a disc domain's exterior nodes their
+ *           nearest unknown node's value), or NULL for u_0 = 0 (then n must
+ *           be 0)
  *   n       index of u_n (the Philox counter word of the iteration)
  *   u_next  device, nx*ny complex: receives u_{n+1}; se: device or NULL,
  *           nx*ny complex standard errors; report (host, may be NULL):

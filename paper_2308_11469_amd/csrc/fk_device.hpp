@@ -111,7 +111,7 @@ struct Inst {
     uint32_t key0, key1;
     int32_t crn, ppi;                                // ppi: paths per small item
     int32_t items_per_node, cells;                   // small items per node; cells: the gather copy is cell-major
-    int32_t prec, pad1;                              // 32 or 64: the instance's stepping precision
+    int32_t prec, n_ext;                             // 32 or 64: the instance's stepping precision; ext pairs
     int64_t n_items;                                 // all items (large, then small)
     int64_t n_items_a;                               // large items (items_a per node, first in the queue)
     int32_t ppi_a, items_a;                          // paths per large item, large items per node
@@ -124,6 +124,8 @@ struct Inst {
     double2 *se;                                     // per grid node
     int64_t *node_sum_j, *node_capped;               // per grid node
     DevState *state;
+    const int32_t *ext;                              // disc domains: n_ext pairs (exterior node, the unknown
+                                                     // node whose value it carries)
 };
 
 // ------------------------------------------------------------ Philox4x32-10

@@ -49,6 +49,9 @@ hipError_t launch_update(const fkd::Inst *d_insts, const int32_t *which, int32_t
                          int32_t max_interior, hipStream_t s);
 hipError_t launch_advance(const fkd::Inst *d_insts, const int32_t *which, int32_t n, const int32_t *n_dev,
                           hipStream_t s);
+// Disc domains: the exterior nodes of one instance take the values of their
+// nearest unknown nodes (after launch_update, on the same stream).
+hipError_t launch_extend(const fkd::Inst *d_inst, int32_t n_ext, hipStream_t s);
 // The blocks of one PDD step: right-hand sides into each task's rhs buffer,
 // then the fast-diagonalisation solve of every block and component, written
 // into the iterate and its gather copy.  The task count is *n_dev when given

@@ -1653,6 +1653,31 @@ __device__ __forceinline__ unsigned long long bits_of(double v)
 // mean and unbiased variance, the new iterate (FP64 master and FP32 copy),
 // and the instance status by atomics that do not depend on order (max of
 // non-negative doubles via their bit patterns, integer sums).
+// Writes the value of a grid node into the FP64 master and the gather copy.
+// In the cell-major copy a node is corner dp + 2 dq of cell (gi - dp, gj - dq)
+// for each of the (up to four) cells around it that exist (corner index
+// 0..3 = (p,q), (p+1,q), (p,q+1), (p+1,q+1)); a node on the rectangle's edge
+// has two, a corner one.
+__device__ __forceinline__ void store_node(const Inst &D, int32_t node, double mr, double mi)
+{
+    D.u64[node] = make_double2(mr, mi);
+    const int gi = node % D.nx, gj = node / D.nx, cw = D.nx - 1;
+    if (D.prec == 32 && !D.cells) {
+        ((float2 *)D.gather)[node] = make_float2((float)mr, (float)mi);
+    } else if (D.cells) {
+#pragma unroll
+        for (int cq = 1; cq >= 0; --cq)
+#pragma unroll
+            for (int cp = 1; cp >= 0; --cp) {
+                const int p = gi - cp, q = gj - cq;
+                if (p < 0 || p > D.nx - 2 || q < 0 || q > D.ny - 2) continue;
+                const int at = 4 * (p + cw * q) + cp + 2 * cq;
+                if (D.prec == 32) ((float2 *)D.gather)[at] = make_float2((float)mr, (float)mi);
+                else ((double2 *)D.gather)[at] = make_double2(mr, mi);
+            }
+    }
+}
+
 __global__ void __launch_bounds__(256) fk_update_kernel(const Inst *__restrict__ insts,
                                                         const int32_t *__restrict__ which,
                                                         const int32_t *__restrict__ n_dev)
@@ -1682,26 +1707,7 @@ __global__ void __launch_bounds__(256) fk_update_kernel(const Inst *__restrict__
         const double vi = fmax((q_im - s_im * mi) / (Mf - 1.0), 0.0);
         const double ser = sqrt(vr / Mf), sei = sqrt(vi / Mf);
         const double2 old = use_u ? D.u64[node] : make_double2(0.0, 0.0);
-        D.u64[node] = make_double2(mr, mi);
-        // the gather copy: a node is corner dp + 2 dq of cell (gi - dp, gj - dq)
-        // for each of the (up to four) cells around it that exist (corner
-        // index 0..3 = (p,q), (p+1,q), (p,q+1), (p+1,q+1)); an unknown node on
-        // a reflecting edge has two, a corner one
-        const int gi = node % D.nx, gj = node / D.nx, cw = D.nx - 1;
-        if (D.prec == 32 && !D.cells) {
-            ((float2 *)D.gather)[node] = make_float2((float)mr, (float)mi);
-        } else if (D.cells) {
-#pragma unroll
-            for (int cq = 1; cq >= 0; --cq)
-#pragma unroll
-                for (int cp = 1; cp >= 0; --cp) {
-                    const int p = gi - cp, q = gj - cq;
-                    if (p < 0 || p > D.nx - 2 || q < 0 || q > D.ny - 2) continue;
-                    const int at = 4 * (p + cw * q) + cp + 2 * cq;
-                    if (D.prec == 32) ((float2 *)D.gather)[at] = make_float2((float)mr, (float)mi);
-                    else ((double2 *)D.gather)[at] = make_double2(mr, mi);
-                }
-        }
+        store_node(D, node, mr, mi);
         D.se[node] = make_double2(ser, sei);
         D.node_sum_j[node] = sj;
         D.node_capped[node] = nc;
@@ -1756,6 +1762,20 @@ __global__ void __launch_bounds__(256) fk_update_kernel(const Inst *__restrict__
         atomicAdd(&st->nonfinite, (unsigned long long)nf);
         atomicAdd(&st->ratio_fx, (unsigned long long)rq);
         atomicAdd(&st->ratio_n, (unsigned long long)rn);
+    }
+}
+
+// Disc domains: after the update, each grid node outside the disc takes the
+// new value of its nearest unknown node (the pairs of D.ext), so that the
+// bilinear interpolant of the next iteration reads the iterate extended
+// beyond the circle in the cells the circle cuts.  Runs after the update
+// kernel has finished (a launch of its own on the same stream).
+__global__ void __launch_bounds__(256) fk_extend_kernel(const Inst *__restrict__ inst)
+{
+    const Inst &D = *inst;
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < D.n_ext; i += gridDim.x * blockDim.x) {
+        const double2 v = D.u64[D.ext[2 * i + 1]];
+        store_node(D, D.ext[2 * i], v.x, v.y);
     }
 }
 
@@ -1968,7 +1988,8 @@ __global__ void fk_debug_paths_kernel(const Inst *__restrict__ inst, const int32
     J[i] = P.t;
     Pending Q;
     park<R>(Q, P, exited, 0);
-    score_out[i] = score<kFeatAll>(D, Q);
+    // the rhombus hole's projection is compiled only with the curved edge
+    score_out[i] = D.curved ? score<kFeatAll | kFeatCurved>(D, Q) : score<kFeatAll>(D, Q);
     if constexpr (sizeof(R) == 4)
         xj[i] = make_double2((double)P.x + (double)P.xl, (double)P.y + (double)P.yl);
     else
@@ -2070,6 +2091,14 @@ hipError_t launch_update(const Inst *d_insts, const int32_t *which, int32_t n_in
     if (n_inst <= 0 || max_interior <= 0) return hipSuccess;
     hipLaunchKernelGGL(fk_update_kernel, dim3(blocks_for(max_interior, 256), n_inst), dim3(256), 0, s, d_insts,
                        which, n_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_extend(const Inst *d_inst, int32_t n_ext, hipStream_t s)
+{
+    if (n_ext <= 0) return hipSuccess;
+    const int nb = blocks_for(n_ext, 256) < 1024 ? blocks_for(n_ext, 256) : 1024;
+    hipLaunchKernelGGL(fk_extend_kernel, dim3(nb), dim3(256), 0, s, d_inst);
     return hipGetLastError();
 }
 

@@ -170,6 +170,56 @@ static void host_bc(const HostProblem &P, const fk_bc &B, double x, double y, do
     }
 }
 
+// Disc domains: each grid node outside the disc (class 3) is paired with its
+// nearest unknown node (ties: the lowest node id), whose value it carries in
+// the iterate.  The search visits square rings of growing index radius
+// around the node and stops once the ring's nearest possible node is
+// farther than the best found (with a relative margin of 1e-9, so that
+// every node at a rounding-level tie is compared).  Distances are formed in
+// separate statements, so no step is fused into a multiply-add.
+static void exterior_pairs(HostProblem &P)
+{
+    const fk_domain &d = P.dom;
+    const double sx = (d.x1 - d.x0) / (double)(d.nx - 1), sy = (d.y1 - d.y0) / (double)(d.ny - 1);
+    auto coord = [](double o, double st, int32_t i) {
+        const double t = (double)i * st;
+        return o + t;
+    };
+    const double hmin = std::fmin(sx, sy);
+    P.ext.clear();
+    for (int32_t je = 0; je < d.ny; ++je)
+        for (int32_t ie = 0; ie < d.nx; ++ie) {
+            const int32_t e = ie + d.nx * je;
+            if (P.cls[(size_t)e] != 3) continue;
+            const double xe = coord(d.x0, sx, ie), ye = coord(d.y0, sy, je);
+            double best = INFINITY;
+            int32_t arg = -1;
+            const int32_t rmax = std::max(d.nx, d.ny);
+            for (int32_t r = 1; r <= rmax; ++r) {
+                for (int32_t j = std::max(je - r, 0); j <= std::min(je + r, d.ny - 1); ++j)
+                    for (int32_t i = std::max(ie - r, 0); i <= std::min(ie + r, d.nx - 1); ++i) {
+                        if (std::max(std::abs(i - ie), std::abs(j - je)) != r) continue;
+                        const int32_t u = i + d.nx * j;
+                        if (P.cls[(size_t)u] != 0) continue;
+                        const double ex = coord(d.x0, sx, i) - xe;
+                        const double ey = coord(d.y0, sy, j) - ye;
+                        const double ex2 = ex * ex;
+                        const double ey2 = ey * ey;
+                        const double d2 = ex2 + ey2;
+                        if (d2 < best || (d2 == best && u < arg)) {
+                            best = d2;
+                            arg = u;
+                        }
+                    }
+                // every node of the rings further out is at least (r + 1) hmin away
+                const double reach = (double)(r + 1) * hmin;
+                if (arg >= 0 && reach * reach > best * (1.0 + 1e-9)) break;
+            }
+            P.ext.push_back(e);
+            P.ext.push_back(arg);
+        }
+}
+
 fk_status setup_problem(const fk_domain *domain, const fk_source *f, const fk_bc *g_outer, const fk_bc *g_inner,
                         const fk_params *params, HostProblem &P, bool single_instance)
 {
@@ -223,9 +273,6 @@ fk_status setup_problem(const fk_domain *domain, const fk_source *f, const fk_bc
         if (!(side > 12.0 * std::sqrt(2.0 * params->h)))
             return fail(FK_EINVAL, "a disc domain needs a diameter longer than 12 sqrt(2 h)");
         if (params->precision != 64) return fail(FK_EINVAL, "a disc domain needs FP64 stepping");
-        if (params->k != 0.0 || params->alpha != 0.0 || params->damping != 0.0)
-            return fail(FK_EINVAL, "a disc domain serves the exit-time and local-time solves: k = 0, "
-                                   "alpha = 0, no damping");
     }
     const bool reflecting = d.edge == FK_EDGE_REFLECTING;
     if (reflecting) {
@@ -303,6 +350,10 @@ fk_status setup_problem(const fk_domain *domain, const fk_source *f, const fk_bc
             if (c == 0) P.interior.push_back((int32_t)id);
             else if (c != 3) host_bc(P, c == 2 ? P.inner : P.outer, x, y, P.grid0[2 * id], P.grid0[2 * id + 1]);
         }
+    }
+    if (disc_dom) {
+        if (P.interior.empty()) return fail(FK_EINVAL, "the disc domain has no unknown grid node");
+        exterior_pairs(P);
     }
     // Work order: nodes with the longest expected paths first, so that the
     // last items of a launch have short paths and the lanes drain quickly at
@@ -394,6 +445,7 @@ size_t instance_bytes(const HostProblem &P)
     b += 2 * align256(nn * sizeof(int64_t));             // sum_j, capped
     b += align256(P.table.size() * sizeof(double));      // table
     b += align256(sizeof(fkd::DevState));
+    b += align256(P.ext.size() * sizeof(int32_t));       // exterior pairs
     return b;
 }
 
@@ -416,6 +468,7 @@ InstanceBuffers carve(const HostProblem &P, char *base)
     B.capped = (int64_t *)take(nn * sizeof(int64_t));
     B.table = (double2 *)take(P.table.size() * sizeof(double));
     B.state = (fkd::DevState *)take(sizeof(fkd::DevState));
+    B.ext = (int32_t *)take(P.ext.size() * sizeof(int32_t));
     return B;
 }
 
@@ -509,6 +562,8 @@ fkd::Inst make_inst(const HostProblem &P, const InstanceBuffers &B)
     D.node_sum_j = B.sum_j;
     D.node_capped = B.capped;
     D.state = B.state;
+    D.ext = B.ext;
+    D.n_ext = (int32_t)(P.ext.size() / 2);
     return D;
 }
 
@@ -554,6 +609,8 @@ fk_status upload_instance(const HostProblem &P, const InstanceBuffers &B, hipStr
     FK_HIP(hipMemcpyAsync(B.nodes, P.interior.data(), P.interior.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     if (!P.table.empty())
         FK_HIP(hipMemcpyAsync(B.table, P.table.data(), P.table.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    if (!P.ext.empty())
+        FK_HIP(hipMemcpyAsync(B.ext, P.ext.data(), P.ext.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     std::vector<double> zeros(2 * nn, 0.0);
     std::vector<int64_t> zi(nn, 0);
     std::vector<fkd::Slot> zs(P.interior.size());
@@ -673,12 +730,17 @@ fk_status load_iterate(const HostProblem &P, const InstanceBuffers &B, const dou
     } else {
         std::memcpy(full.data(), u_reim, nn * sizeof(double2));
     }
-    // boundary and hole nodes keep their data
+    // boundary and hole nodes keep their data; exterior nodes carry their
+    // nearest unknown node's value
     for (size_t i = 0; i < nn; ++i)
         if (P.cls[i] != 0) {
             full[2 * i] = P.grid0[2 * i];
             full[2 * i + 1] = P.grid0[2 * i + 1];
         }
+    for (size_t e = 0; e < P.ext.size(); e += 2) {
+        full[2 * (size_t)P.ext[e]] = full[2 * (size_t)P.ext[e + 1]];
+        full[2 * (size_t)P.ext[e] + 1] = full[2 * (size_t)P.ext[e + 1] + 1];
+    }
     std::vector<uint8_t> gc;
     gather_copy(P, full.data(), gc);
     fkd::DevState st;

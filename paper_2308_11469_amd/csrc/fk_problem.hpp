@@ -38,9 +38,11 @@ struct HostProblem {
     fk_bc outer{}, inner{};
     fk_params par{};
     std::vector<double> table;        // outer TABLE samples (re, im), copied
-    std::vector<uint8_t> cls;         // 0 unknown (interior or reflecting edge), 1 absorbing edge, 2 hole
+    std::vector<uint8_t> cls;         // 0 unknown (interior or reflecting edge), 1 absorbing edge, 2 hole,
+                                      // 3 outside a disc domain's disc
     std::vector<int32_t> interior;    // unknown node ids, longest expected paths first
     std::vector<double> grid0;        // initial grid (re, im): 0 interior, g elsewhere
+    std::vector<int32_t> ext;         // disc domains: pairs (exterior node, its nearest unknown node)
     int64_t jmax = 0;
     int32_t ppi = 0;                  // paths per (small) work item
     int32_t items_per_node = 0;       // small items per node
@@ -98,6 +100,7 @@ struct InstanceBuffers {
     int64_t *sum_j, *capped;
     double2 *table;
     fkd::DevState *state;
+    int32_t *ext;
 };
 InstanceBuffers carve(const HostProblem &P, char *base);
 fkd::Inst make_inst(const HostProblem &P, const InstanceBuffers &B);
@@ -113,7 +116,8 @@ void gather_copy(const HostProblem &P, const double *grid, std::vector<uint8_t> 
 
 // Replaces the iterate on the unknown nodes by u_reim (nx*ny complex, host, or
 // device when on_device) and sets the iteration index to n (use_u = 1):
-// absorbing-edge and hole nodes keep the problem's data, the gather copy is
+// absorbing-edge and hole nodes keep the problem's data, a disc domain's
+// exterior nodes take their nearest unknown node's value, the gather copy is
 // rebuilt from the FP64 values, the status record is cleared.  Synchronises s.
 fk_status load_iterate(const HostProblem &P, const InstanceBuffers &B, const double *u_reim, int32_t n,
                        bool on_device, hipStream_t s);

@@ -89,6 +89,22 @@ fk_status fk_helmholtz_work_items(const fk_domain *domain, const fk_bc *g_outer,
     return FK_OK;
 }
 
+fk_status fk_helmholtz_exterior_nodes(const fk_domain *domain, const fk_bc *g_outer, const fk_params *params,
+                                      int32_t *pairs, int64_t cap, int64_t *n_pairs)
+{
+    if (!n_pairs) return fail(FK_EINVAL, "n_pairs is NULL");
+    HostProblem P;
+    fk_status st = setup_problem(domain, nullptr, g_outer, nullptr, params, P, true);
+    if (st != FK_OK) return st;
+    const int64_t n = (int64_t)(P.ext.size() / 2);
+    *n_pairs = n;
+    if (pairs) {
+        if (cap < n) return fail(FK_EINVAL, "pairs holds fewer than n_pairs entries");
+        std::memcpy(pairs, P.ext.data(), P.ext.size() * sizeof(int32_t));
+    }
+    return FK_OK;
+}
+
 fk_status fk_helmholtz_create(const fk_domain *domain, const fk_source *f, const fk_bc *g_outer,
                               const fk_bc *g_inner, const fk_params *params, void *device_arena,
                               size_t arena_bytes, void *hip_stream, fk_solver **out)
@@ -167,6 +183,7 @@ static fk_status run_one(fk_solver *s, fk_iter_report *rep)
                               s->P.cells == 0, s->P.lds_grid ? s->P.n_nodes() * 8 : 0));
     FK_HIP(hipEventRecord(s->ev1, s->stream));
     FK_HIP(fkk::launch_update(s->d_inst, nullptr, 1, nullptr, (int32_t)s->P.interior.size(), s->stream));
+    FK_HIP(fkk::launch_extend(s->d_inst, (int32_t)(s->P.ext.size() / 2), s->stream));
     if (s->pdd_blocks > 0)
         FK_HIP(fkk::launch_pdd(s->d_inst, s->d_pdd_tasks, s->pdd_blocks, nullptr, s->pdd_blocks, s->pdd_max_nodes,
                                s->stream));

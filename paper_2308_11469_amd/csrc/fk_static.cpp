@@ -94,6 +94,7 @@ fk_status fk_helmholtz_step_static(const fk_domain *domain, const fk_source *f, 
                               path_kernel_blocks(P.par.waves_per_cu), s, P.cells == 0,
                               P.lds_grid ? P.n_nodes() * 8 : 0));
     FK_HIP(fkk::launch_update(d_inst, nullptr, 1, nullptr, (int32_t)P.interior.size(), s));
+    FK_HIP(fkk::launch_extend(d_inst, (int32_t)(P.ext.size() / 2), s));
     FK_HIP(fkk::launch_advance(d_inst, nullptr, 1, nullptr, s));
     const size_t nn = P.n_nodes();
     FK_HIP(hipMemcpyAsync(u_next, B.u64, nn * sizeof(double2), hipMemcpyDeviceToDevice, s));

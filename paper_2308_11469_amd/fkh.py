@@ -79,7 +79,8 @@ class fk_engine_config(C.Structure):
 
 
 # every entry point of include/fk_helmholtz.h
-EXPORTS = ["fk_helmholtz_arena_bytes", "fk_helmholtz_work_items", "fk_helmholtz_create", "fk_helmholtz_iterate", "fk_helmholtz_solve",
+EXPORTS = ["fk_helmholtz_arena_bytes", "fk_helmholtz_work_items", "fk_helmholtz_exterior_nodes",
+           "fk_helmholtz_create", "fk_helmholtz_iterate", "fk_helmholtz_solve",
            "fk_helmholtz_get", "fk_helmholtz_node_stats", "fk_helmholtz_set_iterate", "fk_helmholtz_set_pdd",
            "fk_helmholtz_cancel", "fk_engine_node_stats", "fk_engine_set_iterate", "fk_engine_set_pdd",
            "fk_helmholtz_timing", "fk_helmholtz_step_static",
@@ -108,6 +109,7 @@ def lib():
         sig = {
             "fk_helmholtz_arena_bytes": [P(fk_domain), P(fk_bc), P(fk_params), P(C.c_size_t)],
             "fk_helmholtz_work_items": [P(fk_domain), P(fk_bc), P(fk_params), i64p, i32p, i32p, i32p, i32p],
+            "fk_helmholtz_exterior_nodes": [P(fk_domain), P(fk_bc), P(fk_params), i32p, C.c_int64, i64p],
             "fk_helmholtz_create": [P(fk_domain), P(fk_source), P(fk_bc), P(fk_bc), P(fk_params), vp, C.c_size_t,
                                     vp, P(vp)],
             "fk_helmholtz_iterate": [vp, C.c_int32, P(fk_iter_report)],
@@ -350,6 +352,19 @@ def work_items(problem, paths_per_item=0, gather_layout="auto"):
                                          C.byref(pl), C.byref(il), C.byref(ps), C.byref(is_)))
     return dict(n_items=n.value, paths_large=pl.value, items_large=il.value, paths_small=ps.value,
                 items_small=is_.value)
+
+
+def exterior_nodes(problem):
+    """Disc domains (fk_helmholtz_exterior_nodes): an (n, 2) int32 array of
+    (exterior node, the unknown node whose value it carries)."""
+    m = Marshalled(problem)
+    n = C.c_int64()
+    _check(lib().fk_helmholtz_exterior_nodes(C.byref(m.domain), C.byref(m.outer), C.byref(m.params), None, 0,
+                                             C.byref(n)))
+    out = np.zeros((max(n.value, 1), 2), dtype=np.int32)
+    _check(lib().fk_helmholtz_exterior_nodes(C.byref(m.domain), C.byref(m.outer), C.byref(m.params),
+                                             out.ctypes.data_as(C.POINTER(C.c_int32)), n.value, C.byref(n)))
+    return out[:n.value]
 
 
 def step_static(problem, u_n, n, u_next, se=None, stream=None, paths_per_item=0, gather_layout="auto"):

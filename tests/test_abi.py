@@ -6,6 +6,7 @@ import math
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_2308_11469_amd import build, fkh
@@ -218,26 +219,21 @@ def test_annulus_workloads_accepted(lib):
         assert st == fkh.FK_OK, (p.name, fkh.lib().fk_helmholtz_last_error())
 
 
-@pytest.mark.parametrize("bad", ["not_square", "absorbing", "fp32", "k_positive", "alpha", "damping",
-                                 "hole_outside", "rhombus_flat", "small_disc"])
+@pytest.mark.parametrize("bad", ["not_square", "absorbing", "fp32", "hole_outside", "rhombus_flat", "small_disc"])
 def test_disc_domain_validation(lib, bad):
-    # the disc inscribed in a square box, reflecting, FP64, exit-time and
-    # local-time solves (k = 0, alpha = 0, no damping) only
+    # the disc inscribed in a square box, reflecting, FP64; any k, shift and
+    # damping
     p = W.annulus_shape2(n=21)
     assert arena_status(p)[0] == fkh.FK_OK
     assert arena_status(p.replace(domain_kind=W.DISC_MINUS_DISC, r=0.1))[0] == fkh.FK_OK
+    assert arena_status(p.replace(k=1.12, alpha=2.0, damping=0.5,
+                                  outer=W.BC("plane_wave_robin", 1.0, 0.4)))[0] == fkh.FK_OK
     if bad == "not_square":
         p = p.replace(y1=p.y1 + 0.1)
     elif bad == "absorbing":
         p = p.replace(reflect=False)
     elif bad == "fp32":
         p = p.replace(precision=32)
-    elif bad == "k_positive":
-        p = p.replace(k=0.5)
-    elif bad == "alpha":
-        p = p.replace(alpha=1.0)
-    elif bad == "damping":
-        p = p.replace(damping=0.5)
     elif bad == "hole_outside":
         p = p.replace(cx=0.0, cy=0.0)      # the printed centre of Table 1's shape 2
     elif bad == "rhombus_flat":
@@ -245,3 +241,32 @@ def test_disc_domain_validation(lib, bad):
     elif bad == "small_disc":
         p = p.replace(h=0.01)
     assert arena_status(p)[0] == fkh.FK_EINVAL
+
+
+@pytest.mark.parametrize("case", ["shape2_21", "shape2_46", "shape2_33x41", "disc_hole_40", "rectangle"])
+def test_exterior_nodes_are_the_oracles_nearest_unknown_nodes(lib, case):
+    # the library's pairs (exterior node, the unknown node it reads) against
+    # the oracle's own remap table, built by brute force over every unknown
+    # node: bit-identical, ties included (the square grid of a disc centred in
+    # its box has many equidistant candidates)
+    from oracle import fkmc
+    if case == "shape2_21":
+        p = W.annulus_shape2(n=21)
+    elif case == "shape2_46":
+        p = W.annulus_shape2(n=46)
+    elif case == "shape2_33x41":
+        p = W.annulus_shape2(n=33).replace(ny=41)
+    elif case == "disc_hole_40":
+        p = W.annulus_shape2(n=40).replace(domain_kind=W.DISC_MINUS_DISC, r=0.1)
+    else:
+        p = W.annulus_shape1(n=13)
+    pairs = fkh.exterior_nodes(p)
+    cls = fkmc.node_classes(p).ravel()
+    ext = np.nonzero(cls == 3)[0]
+    if case == "rectangle":
+        assert len(pairs) == 0 and len(ext) == 0
+        return
+    assert np.array_equal(pairs[:, 0], ext)
+    remap = fkmc.Handle(p)._remap
+    assert np.array_equal(pairs[:, 1], remap[ext])
+    assert np.all(cls[pairs[:, 1]] == 0)

@@ -3,9 +3,10 @@ boundary is a disc; Table 1's shape 2 as read here: the disc of radius 0.45
 at (0.8, 0.5) minus the rhombus of diagonals 0.15 at its centre).  The
 radially mirrored paths, their local time and the datum at the move's foot
 against the oracle (exit steps bit for bit, scores and node estimates to
-1e-12 in FP64), for the exit-time and local-time solves (k = 0) these
-domains serve; and Table 1's row for shape 2 (sup E[tau], sup E[xi],
-k_*^A) from the GPU, extrapolated in sqrt(h)."""
+1e-12 in FP64): the exit-time and local-time solves (k = 0) and the
+annular iteration at k > 0, whose iterate is read beyond the circle through
+each exterior node's nearest unknown node; Table 1's row for shape 2
+(sup E[tau], sup E[xi], k_*^A) from the GPU, extrapolated in sqrt(h)."""
 import math
 
 import numpy as np
@@ -36,15 +37,39 @@ def _cases():
     s2 = W.annulus_shape2(n=21, M=64, h=1e-4)
     exit2 = serving.exit_time_problem(s2, M=64)
     local2 = serving.local_time_problem(s2, M=64)
-    # a Robin datum that varies along the circle, a plane wave on the rhombus
-    # and a Gaussian source: the foot's coordinates, the rhombus projection
-    # and the source kernel (feature bits 0, 1, 3 and the curved edge)
+    # a Robin datum that varies along the circle, a bilinear datum on the
+    # rhombus and a Gaussian source: the foot's coordinates, the rhombus
+    # projection and the source kernel (feature bits 0, 1, 3 and the curved
+    # edge)
     mixed = s2.replace(outer=W.BC("bilinear", coeffs=(0.5 + 0.2j, 1.0 - 0.5j, -0.7 + 0.1j, 0.3 + 0.3j)),
-                       inner=W.BC("plane_wave", 0.8 - 0.3j, 0.4), src_kind="gaussian", src_amp=0.3 + 0.2j,
+                       inner=W.BC("bilinear", coeffs=(0.3 + 0.1j, 1.0 - 0.5j, 0.4j, -0.2 + 0j)),
+                       src_kind="gaussian", src_amp=0.3 + 0.2j,
                        src_cx=0.7, src_cy=0.6, src_sigma=0.1, seed=43)
     conc = serving.exit_time_problem(concentric(), M=64)
+    # the annular iteration at k > 0: the plane wave's own data, and a
+    # shifted, damped iteration with a source on the disc hole
+    wave = s2.replace(k=1.0, outer=W.BC("plane_wave_robin", 1.0, 0.4), inner=W.BC("plane_wave", 1.0, 0.4),
+                      seed=44)
+    general = concentric(M=64).replace(k=0.9, alpha=2.0, damping=0.5, src_kind="gaussian",
+                                       src_amp=0.3 - 0.2j, src_cx=0.3, src_cy=0.6, src_sigma=0.1,
+                                       outer=W.BC("bilinear", coeffs=(0.2j, 0.5, -0.3 + 0.1j, 0.1)),
+                                       inner=W.BC("plane_wave", 1.0 - 0.5j, 1.1), seed=45)
     return {"shape2_exit_time": exit2, "shape2_local_time": local2, "shape2_mixed_data": mixed,
-            "concentric_exit_time": conc}
+            "concentric_exit_time": conc, "shape2_k1_plane_wave": wave, "concentric_general_k09": general}
+
+
+def plane_wave_iterate(p, theta=0.4):
+    """A k > 0 iterate for the paths to read: the plane wave at the unknown
+    nodes, the inner datum on the hole's nodes (as the iteration carries it
+    from n = 1 on; the oracle's own fill), 1e3 at the exterior ones (which
+    the library replaces by their nearest unknown node's value, and which
+    the oracle reads through its remap)."""
+    X, Y = np.meshgrid(np.linspace(p.x0, p.x1, p.nx), np.linspace(p.y0, p.y1, p.ny))
+    u = np.exp(1j * p.k * (X * math.cos(theta) + Y * math.sin(theta)))
+    cls = fkmc.node_classes(p).ravel()
+    u.ravel()[cls == 2] = fkmc.boundary_grid(p).ravel()[cls == 2]
+    u.ravel()[cls == 3] = 1e3
+    return u
 
 
 @pytest.mark.parametrize("name", list(_cases().keys()))
@@ -60,9 +85,14 @@ def test_disc_paths_bit_exact_exit_steps(name):
     rad = np.hypot(X - 0.5 * (p.x0 + p.x1), Y - 0.5 * (p.y0 + p.y1))
     nodes = list(ids[np.argsort(-rad)[:8]]) + list(rng.choice(ids, size=16, replace=False))
     pairs = [(int(n), int(m)) for n in nodes for m in rng.integers(0, p.M, 6)]
+    u, it = None, 0
+    if p.k > 0:
+        # the paths of iteration 2 read a given iterate
+        u, it = plane_wave_iterate(p), 2
+        s.set_iterate(u, it)
     J, sc, xj = s.debug_paths([a for a, _ in pairs], [b for _, b in pairs])
     for c, (n, m) in enumerate(pairs):
-        so, Jo, capo, xo = fkmc.path(p, None, 0, n, m)
+        so, Jo, capo, xo = fkmc.path(p, u, it, n, m)
         assert J[c] == Jo, (name, n, m, J[c], Jo)
         assert abs(sc[c] - so) <= 1e-12 * max(1.0, abs(so)), (name, n, m, sc[c], so)
         assert abs(xj[c][0] - xo[0]) < 1e-12 and abs(xj[c][1] - xo[1]) < 1e-12
@@ -83,9 +113,13 @@ def test_disc_node_estimates_fp64(name):
         orc = fkmc.fk_nodes(p, u, it)
         assert_fp64_node_parity(interior_values(p, g), sj[ids], orc, p.M, label="%s it %d" % (name, it))
         assert cp.sum() == 0
-        # exterior nodes carry nothing
+        # exterior nodes carry their nearest unknown node's new value (the
+        # oracle's own remap table), and no standard error
         cls = fkmc.node_classes(p).ravel()
-        assert np.all(g.ravel()[cls == 3] == 0) and np.all(se.ravel()[cls == 3] == 0)
+        ext = np.nonzero(cls == 3)[0]
+        remap = fkmc.Handle(p)._remap
+        assert len(ext) > 0 and np.array_equal(g.ravel()[ext], g.ravel()[remap[ext]])
+        assert np.all(se.ravel()[ext] == 0)
         u = g
     s.close()
 
@@ -140,3 +174,33 @@ def test_table1_shape2_suprema_and_kstar_from_gpu():
     assert abs(est["local_time"] - R * math.log(R / a)) <= 0.01 * est["local_time"]
     assert abs(est["local_time"] - t["sup_xi"]) <= 0.03 * t["sup_xi"]
     assert abs(ks - t["kstar_A"]) <= 0.03 * t["kstar_A"]
+
+
+def test_table1_shape2_convergence_outcomes():
+    # Table 1's column for shape 2: the annular iteration (30 iterates of
+    # fresh paths, the paper's inner datum -exp(-i k x) and g2 = 0) converges
+    # at k = 0.70, 0.95, 0.96 and diverges at 1.12.  With common random
+    # numbers the iteration is one fixed linear map, and the change shrinks
+    # or grows by its spectral radius per iterate: below one at 0.96, above
+    # at 1.12.
+    t = PV.table1()[2]
+    for k, converges in t["tested"]:
+        p = W.annulus_shape2(k=k, n=46, M=4096, h=1e-4, seed=57)
+        s = fkh.Solver(p)
+        rows = [s.iterate(1) for _ in range(30)]
+        s.close()
+        du = [r["max_du"] for r in rows]
+        sup = [r["sup"] for r in rows]
+        say("shape2 k=%.2f sup at 10/20/30 %.3f %.3f %.3f, max change %.3g %.3g %.3g"
+            % (k, sup[9], sup[19], sup[29], du[9], du[19], du[29]))
+        if converges:
+            assert sup[29] < 1.2 and du[29] < du[9]
+        else:
+            assert du[29] > du[19] > du[9] and sup[29] > 2.0 * sup[9]
+    for k, above in ((0.96, False), (1.12, True)):
+        s = fkh.Solver(W.annulus_shape2(k=k, n=46, M=4096, h=1e-4, seed=57).replace(crn=True))
+        du = [s.iterate(1)["max_du"] for _ in range(30)]
+        s.close()
+        rate = (du[29] / du[19]) ** 0.1
+        say("shape2 k=%.2f CRN change ratio per iterate %.4f" % (k, rate))
+        assert (rate > 1.0) == above

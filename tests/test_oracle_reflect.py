@@ -323,3 +323,69 @@ def test_rhombus_projection_is_the_nearest_boundary_point():
         brute = np.min(np.hypot(pts[:, 0] - x, pts[:, 1] - y))
         assert abs(math.hypot(px - x, py - y) - brute) < 1e-5
         assert abs(abs(px - 0.8) / 0.075 + abs(py - 0.5) / 0.075 - 1.0) < 1e-12
+
+
+def disc_plane_wave(theta=0.4, **kw):
+    """Shape 2 (reading: the centred rhombus) with the plane wave's own data:
+    its Robin datum on the circle, the wave itself on the rhombus."""
+    return W.annulus_shape2(n=41, k=1.0, h=5e-5, M=8000, seed=23).replace(
+        outer=W.BC("plane_wave_robin", 1.0, theta), inner=W.BC("plane_wave", 1.0, theta), **kw)
+
+
+def disc_sample(p):
+    """The five unknown nodes nearest the circle (their paths mirror at once
+    and their cells are cut by it) and three inside."""
+    X, Y = np.meshgrid(np.linspace(p.x0, p.x1, p.nx), np.linspace(p.y0, p.y1, p.ny))
+    ids0 = np.nonzero(fkmc.node_classes(p).ravel() == 0)[0]
+    rad = np.hypot(X.ravel()[ids0] - 0.8, Y.ravel()[ids0] - 0.5)
+    return X, Y, np.concatenate([ids0[np.argsort(-rad)[:5]], ids0[np.argsort(rad)[[40, 200, 600]]]]).astype(np.int32)
+
+
+@pytest.mark.parametrize("case", ["plain", "shifted_damped"])
+def test_mc_curved_edge_plane_wave_is_fixed_point(case):
+    # one step of the annular iteration at k > 0 from the exact solution
+    # returns it on the disc domain: the Robin coupling i k I_h[u_n] + g2 at
+    # the foot with the outward radial normal, the rhombus datum, and the
+    # iterate read in the cells the circle cuts through the exterior nodes'
+    # nearest unknown nodes.  The exterior entries of u_n hold 1e3: they are
+    # never read themselves.
+    kw = {} if case == "plain" else dict(alpha=2.0, damping=0.5)
+    p = disc_plane_wave(**kw)
+    X, Y, ids = disc_sample(p)
+    exact = CF.plane_wave(p.k, 0.4, X, Y, damping=p.damping)
+    u = exact.copy()
+    u.ravel()[fkmc.node_classes(p).ravel() == 3] = 1e3
+    est = fkmc.fk_nodes(p, u, 1, ids)
+    err = np.abs(est["mean"] - exact.ravel()[ids])
+    se = np.abs(est["se"])
+    kappa = abs(np.sqrt(complex(p.k ** 2, p.damping)))
+    bias = CF.bgk_beta() * math.sqrt(2.0 * p.h) * kappa
+    # reading a neighbour's value instead of the extension moves I_h[u_n] on
+    # the circle by at most |grad w| sqrt(2) dx; the local time (mean < 0.95)
+    # multiplies it by k
+    remap = p.k * kappa * math.sqrt(2.0) * ((p.x1 - p.x0) / (p.nx - 1)) * 0.95
+    assert np.all(err < 5.0 * se + 2.0 * bias + remap), (err, se, bias, remap)
+    assert est["capped"].sum() == 0
+
+
+def test_mc_curved_edge_fixed_point_check_rejects_a_wrong_field():
+    # power of the check above: the opposite plane wave solves the equation,
+    # not the Robin condition with this g2 on the circle
+    p = disc_plane_wave().replace(M=2000)
+    X, Y, ids = disc_sample(p)
+    other = CF.plane_wave(p.k, 0.4 + math.pi, X, Y)
+    est = fkmc.fk_nodes(p, other, 1, ids)
+    assert np.min(np.abs(est["mean"] - other.ravel()[ids])) > 0.5
+
+
+def test_mc_curved_edge_never_reads_exterior_entries():
+    p = disc_plane_wave().replace(M=600)
+    X, Y, ids = disc_sample(p)
+    u = CF.plane_wave(p.k, 0.4, X, Y)
+    ext = fkmc.node_classes(p).ravel() == 3
+    a, b = u.copy(), u.copy()
+    a.ravel()[ext] = 0.0
+    b.ravel()[ext] = -7.0 + 3.0j
+    ea = fkmc.fk_nodes(p, a, 1, ids[:5])
+    eb = fkmc.fk_nodes(p, b, 1, ids[:5])
+    assert np.array_equal(ea["mean"], eb["mean"])

@@ -77,6 +77,23 @@ def test_static_step_matches_allocating_path_on_two_calls(precision):
     assert q3["n"] == 4
 
 
+def test_static_step_on_a_disc_domain():
+    # a disc domain at k > 0: the exterior nodes take their nearest unknown
+    # node's value after the update in both paths, so that the second call's
+    # paths read the same extended iterate
+    p = W.annulus_shape2(n=21, k=1.0, M=128).replace(outer=W.BC("plane_wave_robin", 1.0, 0.4),
+                                                     inner=W.BC("plane_wave", 1.0, 0.4))
+    u1, se1, r1 = allocating(p, None, 0)
+    v1, sv1, q1 = static(p, None, 0)
+    say("static step disc", r1["path_steps"])
+    assert np.array_equal(u1, v1) and np.array_equal(se1, sv1)
+    same_report(r1, q1)
+    u2, se2, r2 = allocating(p, u1, 1)
+    v2, sv2, q2 = static(p, v1, 1)
+    assert np.array_equal(u2, v2) and np.array_equal(se2, sv2)
+    same_report(r2, q2)
+
+
 def test_static_step_rejects_a_problem_beyond_the_array():
     p = W.cavity_65().replace(nx=513, ny=513, M=64)
     out = torch.zeros((p.ny, p.nx), dtype=torch.complex128, device="cuda")
