@@ -305,9 +305,9 @@ fk_status fk_engine_add(fk_engine *e, const fk_domain *domain, const fk_source *
     fk_status st = setup_problem(domain, f, g_outer, g_inner, params, P);
     if (st != FK_OK) return st;
     if (P.par.precision != e->cfg.precision) return fail(FK_EINVAL, "instance precision differs from the engine's");
-    // the disc's moves are evaluated at once, the rectangle's through the
-    // wave's queue: in one launch their sums would not be added in the same
-    // order as alone, so disc domains stay in the single-instance solver
+    // the disc kernels mirror every path radially (they serve disc domains
+    // alone) and an engine launch mixes instances, so disc domains stay in
+    // the single-instance solver
     if (P.disc_domain()) return fail(FK_EINVAL, "disc domains run in the single-instance solver, not the engine");
     if ((int64_t)P.interior.size() > e->max_interior_cap) return fail(FK_ENOMEM, "instance grid exceeds the engine");
     if (free_slot < 0) return fail(FK_EBUSY, "no free engine slot");

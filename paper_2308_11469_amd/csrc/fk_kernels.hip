@@ -494,7 +494,8 @@ __device__ __forceinline__ void local_time_term(const Inst &D, const Consts<R> &
 // instead of being evaluated at once (reflecting edge, path kernels): up to
 // four per lane (bits of todo: step 1 x face, step 1 y face, step 2 x face,
 // step 2 y face, the chronological order), each with w dxi, the foot's
-// coordinate along its face and the face.
+// coordinate along its face and the face.  The disc's edge has at most one
+// move per step (bits 0 and 2), its foot's x and y in coord[kk], coord[kk+1].
 template <class R> struct LtEvents {
     uint32_t bits;     // todo (bits 0-3) | the four faces (2 bits each, from bit 4)
     R dxi[4];          // increments of the local time
@@ -516,9 +517,13 @@ constexpr int kLtCap = 2 * kWave;   // queued moves per wave
 
 template <class R> struct LtStore {
     double cw[kLtCap];      // w dxi
-    R coord[kLtCap];        // the foot's coordinate along its face
+    R coord[kLtCap];        // the foot's coordinate along its face (the disc: its x)
     int32_t fo[kLtCap];     // face | owner lane << 2
     double res_r[kWave], res_i[kWave];
+};
+// The disc's edge: a foot has two coordinates (face 4 throughout).
+template <class R> struct LtStoreC : LtStore<R> {
+    R coord2[kLtCap];       // the foot's y
 };
 struct LtNone {};
 
@@ -534,15 +539,22 @@ template <class R> struct LtQueue {
 template <class R, int F>
 __device__ __forceinline__ void lt_eval(const Inst &D, const Consts<R> &K, LtQueue<R> &Q, R ik, PathState<R> &P)
 {
+    constexpr bool kC = (F & kFeatCurved) != 0;
     const int lane = threadIdx.x & (kWave - 1);
     const int n = Q.count < kWave ? Q.count : kWave;
     LtStore<R> &S = *Q.s;
     if (lane < n) {
         const int fo = S.fo[lane];
-        const int face = fo & 3;
+        const int face = kC ? 4 : fo & 3;
         const R c = S.coord[lane];
-        const R fx = face == 0 ? K.lx0 : (face == 1 ? K.lx1 : c);
-        const R fy = face == 2 ? K.ly0 : (face == 3 ? K.ly1 : c);
+        R fx, fy;
+        if constexpr (kC) {
+            fx = c;
+            fy = static_cast<LtStoreC<R> &>(S).coord2[lane];
+        } else {
+            fx = face == 0 ? K.lx0 : (face == 1 ? K.lx1 : c);
+            fy = face == 2 ? K.ly0 : (face == 3 ? K.ly1 : c);
+        }
         CellReads<R> g;
         g.c = locate(K, fx, fy);
         issue_reads<F>(K, g.c.off, g);
@@ -574,12 +586,13 @@ __device__ __forceinline__ void lt_eval(const Inst &D, const Consts<R> &K, LtQue
     if (rest > 0) {
         // positions 64.. move down to 0..
         double cw = 0.0;
-        R co = (R)0;
+        R co = (R)0, co2 = (R)0;
         int32_t fo = 0;
         if (lane < rest) {
             cw = S.cw[kWave + lane];
             co = S.coord[kWave + lane];
             fo = S.fo[kWave + lane];
+            if constexpr (kC) co2 = static_cast<LtStoreC<R> &>(S).coord2[kWave + lane];
         }
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -588,6 +601,7 @@ __device__ __forceinline__ void lt_eval(const Inst &D, const Consts<R> &K, LtQue
             S.cw[lane] = cw;
             S.coord[lane] = co;
             S.fo[lane] = fo;
+            if constexpr (kC) static_cast<LtStoreC<R> &>(S).coord2[lane] = co2;
         }
     }
     Q.own0 = rest > 0 ? Q.own1 : 0ull;
@@ -603,7 +617,7 @@ __device__ __forceinline__ void lt_eval(const Inst &D, const Consts<R> &K, LtQue
 // 64 more).  Every lane of the wave calls it.
 template <class R, int F>
 __device__ __forceinline__ void lt_push(const Inst &D, const Consts<R> &K, LtQueue<R> &Q, R ik, PathState<R> &P,
-                                        bool has, double cw, R coord, int face)
+                                        bool has, double cw, R coord, R coord2, int face)
 {
     const unsigned long long b = __ballot(has);
     if (b == 0ull) return;
@@ -615,6 +629,7 @@ __device__ __forceinline__ void lt_push(const Inst &D, const Consts<R> &K, LtQue
         Q.s->cw[q] = cw;
         Q.s->coord[q] = coord;
         Q.s->fo[q] = face | (lane << 2);
+        if constexpr ((F & kFeatCurved) != 0) static_cast<LtStoreC<R> *>(Q.s)->coord2[q] = coord2;
         if (q < kWave) Q.own0 |= 1ull << q;
         else Q.own1 |= 1ull << (q - kWave);
     }
@@ -627,10 +642,20 @@ template <class R, int F>
 __device__ __forceinline__ void lt_trip(const Inst &D, const Consts<R> &K, LtQueue<R> &Q, R ik, PathState<R> &P,
                                         const LtEvents<R> &ev, bool fin)
 {
+    if constexpr ((F & kFeatCurved) != 0) {
+        // the disc: at most one move per step (bits 0 and 2), its foot in
+        // coord[kk], coord[kk + 1]
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk)
-        lt_push<R, F>(D, K, Q, ik, P, ((ev.bits >> kk) & 1u) != 0u, (kk < 2 ? ev.w1 : ev.w2) * (double)ev.dxi[kk],
-                      ev.coord[kk], (int)((ev.bits >> (4 + 2 * kk)) & 3u));
+        for (int kk = 0; kk < 4; kk += 2)
+            lt_push<R, F>(D, K, Q, ik, P, ((ev.bits >> kk) & 1u) != 0u,
+                          (kk < 2 ? ev.w1 : ev.w2) * (double)ev.dxi[kk], ev.coord[kk], ev.coord[kk + 1], 4);
+    } else {
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+            lt_push<R, F>(D, K, Q, ik, P, ((ev.bits >> kk) & 1u) != 0u,
+                          (kk < 2 ? ev.w1 : ev.w2) * (double)ev.dxi[kk], ev.coord[kk], (R)0,
+                          (int)((ev.bits >> (4 + 2 * kk)) & 3u));
+    }
     if (__ballot(fin && (Q.own0 | Q.own1) != 0ull))
         while (Q.count > 0) lt_eval<R, F>(D, K, Q, ik, P);
 }
@@ -710,7 +735,19 @@ __device__ __forceinline__ bool advance(const Inst &D, const Consts<R> &K, PathS
         // own moves.
         uint32_t todo = (uint32_t)(m1.fx >= 0) | ((uint32_t)(m1.fy >= 0) << 1);
         if (second) todo |= ((uint32_t)(m2.fx >= 0) << 2) | ((uint32_t)(m2.fy >= 0) << 3);
-        if constexpr (kDefer) {
+        if constexpr (kDefer && (F & kFeatCurved) != 0) {
+            // the disc: one radial move per step (bits 0 and 2), with its
+            // foot's two coordinates
+            ev->w1 = general ? P.w * K.q : 1.0;
+            ev->w2 = general ? ev->w1 * K.q : 1.0;
+            ev->bits = todo;
+            ev->dxi[0] = m1.lx;
+            ev->coord[0] = f1x;
+            ev->coord[1] = f1y;
+            ev->dxi[2] = m2.lx;
+            ev->coord[2] = f2x;
+            ev->coord[3] = f2y;
+        } else if constexpr (kDefer) {
             // the moves in chronological order; the foot of an x-face move is
             // (face, y of the mirrored point), of a y-face move (x, face)
             ev->w1 = general ? P.w * K.q : 1.0;
@@ -1302,10 +1339,11 @@ __device__ __forceinline__ void stream_paths(const Inst *__restrict__ insts, con
     constexpr bool kLds = (F & kLdsGrid) != 0;
     constexpr int kWpb = kLds ? 16 : 4;
     __shared__ unsigned long long lds_acc[kWpb][kNodeAcc * 12];   // node accumulators per wave
-    // the queue of local-time moves of each wave (reflecting rectangle edge;
-    // the disc's moves are evaluated at once)
-    constexpr bool kLt = (F & kFeatReflect) != 0 && (F & kFeatCurved) == 0;
-    using LtS = typename std::conditional<kLt, LtStore<R>, LtNone>::type;
+    // the queue of local-time moves of each wave (reflecting edge; the
+    // disc's moves carry both coordinates of their foot)
+    constexpr bool kLt = (F & kFeatReflect) != 0;
+    using LtQ = typename std::conditional<(F & kFeatCurved) != 0, LtStoreC<R>, LtStore<R>>::type;
+    using LtS = typename std::conditional<kLt, LtQ, LtNone>::type;
     __shared__ LtS lt_store[kWpb];
     // the staged copy of the (only) instance's row-major FP32 iterate
     const lds_u8 *lgrid = nullptr;

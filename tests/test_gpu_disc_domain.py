@@ -125,9 +125,9 @@ def test_disc_node_estimates_fp64(name):
 
 
 def test_disc_domain_rejected_by_the_engine():
-    # the disc's local-time moves are evaluated at once, a rectangle's
-    # through the wave's queue: in one launch the sums would not be added as
-    # alone, so the engine takes no disc domain
+    # the disc kernels mirror every path radially (they serve disc domains
+    # alone) and an engine launch mixes instances, so the engine takes no
+    # disc domain
     e = fkh.Engine(4, precision=64, max_grid_nodes=1 << 14, max_items=1 << 16, max_table=16,
                    max_instance_nodes=1024)
     with pytest.raises(ValueError):
