@@ -278,6 +278,31 @@ def test_annulus_shape3_bench_configuration_fp64_and_fp32():
     assert r.max() <= 0.1
 
 
+def test_disc_annulus_shape2_bench_configuration():
+    # the disc-edge bench line: shape 2 at 91 x 91, k = 0.5, M = 4096,
+    # h = 1e-4; sampled nodes on the circle (their paths mirror at once, their
+    # cells reach the exterior nodes), next to the rhombus and between; the
+    # second iteration reads the first one's extension beyond the circle
+    p = W.annulus_shape2(k=0.5, n=91, M=4096, h=1e-4)
+    s = fkh.Solver(p)
+    s.iterate(1)
+    u1, _ = s.get()
+    s.iterate(1)
+    g, _ = s.get()
+    sj, _ = s.node_stats()
+    s.close()
+    cls = fkmc.node_classes(p).ravel()
+    ids0 = np.nonzero(cls == 0)[0]
+    X = p.x0 + (ids0 % p.nx) * ((p.x1 - p.x0) / (p.nx - 1))
+    Y = p.y0 + (ids0 // p.nx) * ((p.y1 - p.y0) / (p.ny - 1))
+    rad = np.hypot(X - 0.8, Y - 0.5)
+    order = np.argsort(-rad)
+    ids = np.concatenate([ids0[order[:4]], ids0[order[[300, 1500, 3000]]], ids0[order[-2:]]]).astype(np.int32)
+    orc = fkmc.fk_nodes(p, u1, 1, ids)
+    say("disc annulus shape 2 91x91: oracle nodes", len(ids))
+    assert_fp64_node_parity(g.ravel()[ids], sj[ids], orc, p.M, label="disc shape 2 full size")
+
+
 def test_pdd_cavity65_bench_configuration():
     # the PDD bench line: interfaces on the lines 16, 32, 48; sampled
     # interface nodes against the oracle, every block against its LU
