@@ -253,7 +253,9 @@ fk_status fk_helmholtz_exterior_nodes(const fk_domain *domain, const fk_bc *g_ou
  * 32/64, hole not strictly inside, TABLE or PLANE_WAVE_ROBIN as inner datum,
  * PLANE_WAVE_ROBIN on an absorbing edge, table_len < 2, a reflecting edge
  * without a hole, without max_steps, with g_unprojected or with a side not
- * longer than 6 sqrt(2 h).  FK_ENOMEM: arena too small. */
+ * longer than 6 sqrt(2 h); a disc domain in a box that is not square, with
+ * an absorbing edge, in FP32, with a diameter not longer than 12 sqrt(2 h)
+ * or with no unknown node.  FK_ENOMEM: arena too small. */
 fk_status fk_helmholtz_create(const fk_domain *domain, const fk_source *f, const fk_bc *g_outer,
                               const fk_bc *g_inner, const fk_params *params, void *device_arena,
                               size_t arena_bytes, void *hip_stream, fk_solver **out);

@@ -270,3 +270,16 @@ def test_exterior_nodes_are_the_oracles_nearest_unknown_nodes(lib, case):
     remap = fkmc.Handle(p)._remap
     assert np.array_equal(pairs[:, 1], remap[ext])
     assert np.all(cls[pairs[:, 1]] == 0)
+
+
+def test_exterior_nodes_buffer_too_small(lib):
+    p = W.annulus_shape2(n=21)
+    m = fkh.Marshalled(p)
+    n = C.c_int64()
+    assert lib.fk_helmholtz_exterior_nodes(C.byref(m.domain), C.byref(m.outer), C.byref(m.params), None, 0,
+                                           C.byref(n)) == fkh.FK_OK and n.value > 0
+    buf = (C.c_int32 * (2 * n.value))()
+    assert lib.fk_helmholtz_exterior_nodes(C.byref(m.domain), C.byref(m.outer), C.byref(m.params), buf,
+                                           n.value - 1, C.byref(n)) == fkh.FK_EINVAL
+    assert lib.fk_helmholtz_exterior_nodes(C.byref(m.domain), C.byref(m.outer), C.byref(m.params), buf,
+                                           n.value, None) == fkh.FK_EINVAL
