@@ -204,3 +204,23 @@ def test_table1_shape2_convergence_outcomes():
         rate = (du[29] / du[19]) ** 0.1
         say("shape2 k=%.2f CRN change ratio per iterate %.4f" % (k, rate))
         assert (rate > 1.0) == above
+
+
+def test_disc_checkpoint_resume_bit_identity():
+    # resuming from a saved iterate (the host extends it to the exterior
+    # nodes) continues exactly as the uninterrupted run (where the device
+    # extends it after each update)
+    p = _cases()["shape2_k1_plane_wave"].replace(M=128)
+    s = fkh.Solver(p)
+    s.iterate(2)
+    saved, _ = s.get()
+    s.iterate(2)
+    ref, ref_se = s.get()
+    s.close()
+    r = fkh.Solver(p)
+    r.set_iterate(saved, 2)
+    r.iterate(2)
+    got, got_se = r.get()
+    r.close()
+    say("disc checkpoint/resume")
+    assert np.array_equal(got, ref) and np.array_equal(got_se, ref_se)
