@@ -619,19 +619,21 @@ def disc_annulus_shape2(steps=3):
     (the disc of radius 0.45 minus the centred rhombus of diagonals 0.15,
     reflecting curved edge) at the grid step 0.01 of its FE mesh (91 x 91
     nodes on the disc's square), k = 0.5, M = 4096, h = 1e-4: path-steps/s of
-    the FP64 disc kernel, one iteration per step after two warm-up
-    iterations."""
+    the disc kernels in both precisions, one iteration per step after two
+    warm-up iterations."""
     from paper_2308_11469_amd import workloads as W
     out = {"workload": "annulus shape 2, 91x91, k=0.5, M=4096, h=1e-4, reflecting disc edge"}
-    _log("disc annulus FP64")
-    p = W.annulus_shape2(k=0.5, n=91, M=4096, h=1e-4)
-    run = _timed_solver(p, steps, 2)
-    total = sum(r["path_steps"] for r in run["timed"])
-    rf = _roofline(p, run, out["workload"])
-    out["fp64"] = dict(value=total / run["wall"], unit="path-steps/s", ms_per_step=run["wall"] / steps * 1e3,
-                       kernel=rf["kernel"], kernel_ms_avg=rf["kernel_ms_avg"],
-                       path_steps_per_iteration=total / steps, path_steps_per_launch=rf["path_steps_per_launch"],
-                       roofline_frac=rf["frac"], traffic=rf["traffic"], valu_issue=rf["valu_issue"])
+    for prec in (64, 32):
+        _log("disc annulus FP%d" % prec)
+        p = W.annulus_shape2(k=0.5, n=91, M=4096, h=1e-4, precision=prec)
+        run = _timed_solver(p, steps, 2)
+        total = sum(r["path_steps"] for r in run["timed"])
+        rf = _roofline(p, run, out["workload"])
+        out["fp%d" % prec] = dict(value=total / run["wall"], unit="path-steps/s",
+                                  ms_per_step=run["wall"] / steps * 1e3, kernel=rf["kernel"],
+                                  kernel_ms_avg=rf["kernel_ms_avg"], path_steps_per_iteration=total / steps,
+                                  path_steps_per_launch=rf["path_steps_per_launch"], roofline_frac=rf["frac"],
+                                  traffic=rf["traffic"], valu_issue=rf["valu_issue"])
     return out
 
 

@@ -97,8 +97,10 @@ typedef enum {
  * are exterior: no unknowns; each carries the value of its nearest unknown
  * node (fk_helmholtz_exterior_nodes), so that the bilinear interpolant of
  * the iterate in the cells the circle cuts reads the iterate extended beyond
- * the circle.  Any k, alpha and damping; FP64 stepping; the single-instance
- * solver and fk_helmholtz_step_static (fk_engine_add rejects them). */
+ * the circle.  Any k, alpha and damping; FP64 or FP32 stepping (FP32: the
+ * compensated position is tested and mirrored at the circle in FP64); the
+ * single-instance solver and fk_helmholtz_step_static (fk_engine_add rejects
+ * them). */
 typedef enum {
     FK_DOMAIN_RECT = 0, FK_DOMAIN_RECT_MINUS_DISC = 1, FK_DOMAIN_RECT_MINUS_BOX = 2,
     FK_DOMAIN_DISC_MINUS_RHOMBUS = 3, FK_DOMAIN_DISC_MINUS_DISC = 4
@@ -254,8 +256,8 @@ fk_status fk_helmholtz_exterior_nodes(const fk_domain *domain, const fk_bc *g_ou
  * PLANE_WAVE_ROBIN on an absorbing edge, table_len < 2, a reflecting edge
  * without a hole, without max_steps, with g_unprojected or with a side not
  * longer than 6 sqrt(2 h); a disc domain in a box that is not square, with
- * an absorbing edge, in FP32, with a diameter not longer than 12 sqrt(2 h)
- * or with no unknown node.  FK_ENOMEM: arena too small. */
+ * an absorbing edge, with a diameter not longer than 12 sqrt(2 h) or with no
+ * unknown node.  FK_ENOMEM: arena too small. */
 fk_status fk_helmholtz_create(const fk_domain *domain, const fk_source *f, const fk_bc *g_outer,
                               const fk_bc *g_inner, const fk_params *params, void *device_arena,
                               size_t arena_bytes, void *hip_stream, fk_solver **out);

@@ -42,9 +42,9 @@ constexpr int kRowMajor = 16;
 // in LDS (a 1024-thread block per CU shares it).
 constexpr int kLdsGrid = 32;
 // The outer edge is the disc inscribed in the grid's square, reflecting
-// (always with kFeatReflect and a hole); FP64 kernels of disc domains only
-// (every path is mirrored radially), whose queued local-time moves carry
-// both coordinates of their foot.
+// (always with kFeatReflect and a hole); kernels of disc domains only (every
+// path is mirrored radially), whose queued local-time moves carry both
+// coordinates of their foot.
 constexpr int kFeatCurved = 64;
 
 enum : int32_t { BC_ZERO = 0, BC_PLANE_WAVE = 1, BC_BILINEAR = 2, BC_TABLE = 3, BC_PLANE_WAVE_ROBIN = 4 };

@@ -171,6 +171,9 @@ __device__ __forceinline__ bool is_out(const Inst &D, const Consts<float> &K, fl
         return exd * exd + eyd * eyd <= D.r2;
     }
     if ((F & kFeatDisc) && K.hole == HOLE_BOX) return x >= K.hx0 && x <= K.hx1 && y >= K.hy0 && y <= K.hy1;
+    // the rhombus (disc domains) in FP64, as the FP64 kernels test it
+    if ((F & kFeatCurved) && K.hole == HOLE_RHOMBUS)
+        return fabs((double)x - D.cx) / D.r + fabs((double)y - D.cy) / D.ry <= 1.0;
     return false;
 }
 
@@ -297,6 +300,34 @@ __device__ __forceinline__ Mirror<double> reflect_disc(const Inst &D, double &x,
         m.fx = 4;
     }
     return m;
+}
+// With the compensated FP32 position: the point x + xl is tested and
+// mirrored in FP64 (the same arithmetic as above), and the mirrored point is
+// split back into its binary32 value and the rest.  Every lane forms the
+// test: with one lane in ten mirroring per trip, a wave almost never skips
+// the mirror branch, so a binary32 pre-test would save nothing.
+__device__ __forceinline__ Mirror<float> reflect_disc_c(const Inst &D, float &x, float &y, float &xl, float &yl,
+                                                        float &fx, float &fy)
+{
+    Mirror<float> m{0.0f, 0.0f, -1, -1};
+    double X = (double)x + (double)xl, Y = (double)y + (double)yl, FX = 0.0, FY = 0.0;
+    const Mirror<double> md = reflect_disc(D, X, Y, FX, FY);
+    if (md.fx >= 0) {
+        x = (float)X;
+        xl = (float)(X - (double)x);
+        y = (float)Y;
+        yl = (float)(Y - (double)y);
+        fx = (float)FX;
+        fy = (float)FY;
+        m.lx = (float)md.lx;
+        m.fx = 4;
+    }
+    return m;
+}
+__device__ __forceinline__ Mirror<double> reflect_disc_c(const Inst &D, double &x, double &y, double &, double &,
+                                                         double &fx, double &fy)
+{
+    return reflect_disc(D, x, y, fx, fy);
 }
 
 // Bilinear interpolation of u_n at (x, y): cell p = floor((x - x0)/dx)
@@ -708,14 +739,14 @@ __device__ __forceinline__ bool advance(const Inst &D, const Consts<R> &K, PathS
     Mirror<R> m1{(R)0, (R)0, -1, -1}, m2{(R)0, (R)0, -1, -1};
     R f1x = (R)0, f1y = (R)0, f2x = (R)0, f2y = (R)0;   // feet of the disc's mirror moves
     if (refl) {
-        if constexpr ((F & kFeatCurved) != 0) m1 = reflect_disc(D, x1, y1, f1x, f1y);   // single instance
+        if constexpr ((F & kFeatCurved) != 0) m1 = reflect_disc_c(D, x1, y1, x1l, y1l, f1x, f1y);
         else m1 = reflect_c(K, x1, y1, x1l, y1l);
     }
     R x2, y2, x2l, y2l;
     move(K, x1, x1l, z1x, x2, x2l);
     move(K, y1, y1l, z1y, y2, y2l);
     if (refl) {
-        if constexpr ((F & kFeatCurved) != 0) m2 = reflect_disc(D, x2, y2, f2x, f2y);
+        if constexpr ((F & kFeatCurved) != 0) m2 = reflect_disc_c(D, x2, y2, x2l, y2l, f2x, f2y);
         else m2 = reflect_c(K, x2, y2, x2l, y2l);
     }
     const bool general = (F & kFeatGeneral) && K.general;
@@ -1614,7 +1645,9 @@ __device__ __forceinline__ void stream_paths(const Inst *__restrict__ insts, con
 }
 
 // Occupancy targets (waves per SIMD) of the path kernels; they bound the
-// registers the compiler may use.  FP64 runs three waves.  A second build of
+// registers the compiler may use.  FP32 runs four waves, also where that
+// spills (the reflecting kernels): at three the FP32 disc kernel spilled
+// nothing but ran 4% slower, the rectangle's 10%.  FP64 runs three waves.  A second build of
 // the plain FP64 kernel runs four (128 VGPRs, a small spill): 2% faster on
 // the 65 x 65 cavity, whose row-major copy sits in the vector L1, but 37%
 // slower on 257 x 257 with the cell-major copy, where the loop is bound by
@@ -2011,13 +2044,8 @@ __global__ void fk_debug_paths_kernel(const Inst *__restrict__ inst, const int32
     const double sx = D.x0 + (double)gi * D.dx, sy = D.y0 + (double)gj * D.dy;
     start(P, (R)sx, (R)sy, (R)(sx - (double)(R)sx), (R)(sy - (double)(R)sy));
     bool exited = false;
-    if constexpr (sizeof(R) == 8) {
-        if (D.curved) {
-            while (!advance<R, kFeatAll | kFeatCurved>(D, K, P, (uint32_t)ms[i], (uint32_t)node, ctr3, cu, exited)) {
-            }
-        } else {
-            while (!advance<R, kFeatAll>(D, K, P, (uint32_t)ms[i], (uint32_t)node, ctr3, cu, exited)) {
-            }
+    if (D.curved) {
+        while (!advance<R, kFeatAll | kFeatCurved>(D, K, P, (uint32_t)ms[i], (uint32_t)node, ctr3, cu, exited)) {
         }
     } else {
         while (!advance<R, kFeatAll>(D, K, P, (uint32_t)ms[i], (uint32_t)node, ctr3, cu, exited)) {
@@ -2083,13 +2111,12 @@ hipError_t launch_stream(int precision, int features, const Inst *d_insts, const
     }
     dim3 grid(n_blocks), block(256);
     if (features & kFeatCurved) {
-        // disc domains: FP64 only (checked at set-up); a hole and the
-        // reflecting edge always
+        // disc domains: a hole and the reflecting edge always
         switch (features & kFeatAll) {
-        case 9: hipLaunchKernelGGL(fk_stream_f64<9 | kFeatCurved>, grid, block, 0, s, d_insts, Q, head); break;
-        case 11: hipLaunchKernelGGL(fk_stream_f64<11 | kFeatCurved>, grid, block, 0, s, d_insts, Q, head); break;
-        case 13: hipLaunchKernelGGL(fk_stream_f64<13 | kFeatCurved>, grid, block, 0, s, d_insts, Q, head); break;
-        default: hipLaunchKernelGGL(fk_stream_f64<15 | kFeatCurved>, grid, block, 0, s, d_insts, Q, head); break;
+        case 9: launch_stream_f<9 | kFeatCurved>(precision, grid, block, d_insts, Q, head, s); break;
+        case 11: launch_stream_f<11 | kFeatCurved>(precision, grid, block, d_insts, Q, head, s); break;
+        case 13: launch_stream_f<13 | kFeatCurved>(precision, grid, block, d_insts, Q, head, s); break;
+        default: launch_stream_f<15 | kFeatCurved>(precision, grid, block, d_insts, Q, head, s); break;
         }
         return hipGetLastError();
     }

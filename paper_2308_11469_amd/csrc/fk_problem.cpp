@@ -272,7 +272,6 @@ fk_status setup_problem(const fk_domain *domain, const fk_source *f, const fk_bc
         // a step is shorter than 8.2 sqrt(2 h): one radial mirror lands inside
         if (!(side > 12.0 * std::sqrt(2.0 * params->h)))
             return fail(FK_EINVAL, "a disc domain needs a diameter longer than 12 sqrt(2 h)");
-        if (params->precision != 64) return fail(FK_EINVAL, "a disc domain needs FP64 stepping");
     }
     const bool reflecting = d.edge == FK_EDGE_REFLECTING;
     if (reflecting) {

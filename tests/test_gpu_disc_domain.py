@@ -224,3 +224,53 @@ def test_disc_checkpoint_resume_bit_identity():
     r.close()
     say("disc checkpoint/resume")
     assert np.array_equal(got, ref) and np.array_equal(got_se, ref_se)
+
+
+@pytest.mark.parametrize("name", ["shape2_k1_plane_wave", "concentric_general_k09", "shape2_mixed_data"])
+def test_disc_fp32_within_tenth_se_of_fp64(name):
+    # FP32 stepping on the disc domain (compensated position, the test and
+    # the radial mirror at the circle formed in FP64) against FP64 on the
+    # same streams and the same u_n: every unknown node within 0.1 SE
+    p = _cases()[name].replace(M=1024)
+    s64 = fkh.Solver(p)
+    s32 = fkh.Solver(p.replace(precision=32))
+    s64.iterate(1)
+    s32.iterate(1)
+    g64, _ = s64.get()
+    s64.iterate(1)
+    s32.set_iterate(g64, 1)
+    s32.iterate(1)
+    g64b, se64b = s64.get()
+    g32b, _ = s32.get()
+    s64.close()
+    s32.close()
+    d = np.abs(interior_values(p, g32b) - interior_values(p, g64b))
+    se = np.abs(interior_values(p, se64b))
+    say("disc fp32", name, "max %.4f SE" % (d / se).max())
+    assert np.all(d <= 0.1 * se)
+    # the exterior nodes carry their pairs' FP32-path values as well
+    cls = fkmc.node_classes(p).ravel()
+    ext = np.nonzero(cls == 3)[0]
+    remap = fkmc.Handle(p)._remap
+    assert np.array_equal(g32b.ravel()[ext], g32b.ravel()[remap[ext]])
+
+
+def test_disc_fp32_bench_configuration_within_tenth_se():
+    # the disc bench line's configuration (shape 2, 91 x 91, k = 0.5,
+    # M = 4096, h = 1e-4): FP32 against FP64 from the same u_1
+    p = W.annulus_shape2(k=0.5, n=91, M=4096, h=1e-4)
+    s64 = fkh.Solver(p)
+    s64.iterate(1)
+    u1, _ = s64.get()
+    s64.iterate(1)
+    g64, se64 = s64.get()
+    s64.close()
+    s32 = fkh.Solver(p.replace(precision=32))
+    s32.set_iterate(u1, 1)
+    s32.iterate(1)
+    g32, _ = s32.get()
+    s32.close()
+    r = np.abs(interior_values(p, g32) - interior_values(p, g64)) / np.abs(interior_values(p, se64))
+    say("disc shape 2 91x91 FP32 vs FP64: max %.4f SE, rms %.4f SE over %d nodes"
+        % (r.max(), np.sqrt(np.mean(r ** 2)), r.size))
+    assert r.max() <= 0.1
