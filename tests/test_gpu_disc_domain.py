@@ -5,8 +5,9 @@ radially mirrored paths, their local time and the datum at the move's foot
 against the oracle (exit steps bit for bit, scores and node estimates to
 1e-12 in FP64): the exit-time and local-time solves (k = 0) and the
 annular iteration at k > 0, whose iterate is read beyond the circle through
-each exterior node's nearest unknown node; Table 1's row for shape 2
-(sup E[tau], sup E[xi], k_*^A) from the GPU, extrapolated in sqrt(h)."""
+each exterior node's nearest unknown node; FP32 stepping within 0.1 SE of
+FP64; Table 1's row for shape 2 (sup E[tau], sup E[xi], k_*^A, the
+converging and diverging k) from the GPU."""
 import math
 
 import numpy as np
