@@ -172,11 +172,12 @@ static void host_bc(const HostProblem &P, const fk_bc &B, double x, double y, do
 
 // Disc domains: each grid node outside the disc (class 3) is paired with its
 // nearest unknown node (ties: the lowest node id), whose value it carries in
-// the iterate.  The search visits square rings of growing index radius
-// around the node and stops once the ring's nearest possible node is
-// farther than the best found (with a relative margin of 1e-9, so that
-// every node at a rounding-level tie is compared).  Distances are formed in
-// separate statements, so no step is fused into a multiply-add.
+// the iterate.  Only unknown nodes with a 4-neighbour that is not unknown can
+// be nearest: from any other unknown node u, the neighbour one grid step
+// towards the exterior node is unknown and strictly nearer.  So each
+// exterior node is compared with that frontier (a few times the grid's side
+// in size), in increasing node order.  Distances are formed in separate
+// statements, so no step is fused into a multiply-add.
 static void exterior_pairs(HostProblem &P)
 {
     const fk_domain &d = P.dom;
@@ -185,7 +186,20 @@ static void exterior_pairs(HostProblem &P)
         const double t = (double)i * st;
         return o + t;
     };
-    const double hmin = std::fmin(sx, sy);
+    auto unknown = [&](int32_t i, int32_t j) { return P.cls[(size_t)i + (size_t)d.nx * j] == 0; };
+    std::vector<int32_t> front;
+    for (int32_t j = 0; j < d.ny; ++j)
+        for (int32_t i = 0; i < d.nx; ++i) {
+            if (!unknown(i, j)) continue;
+            if ((i > 0 && !unknown(i - 1, j)) || (i + 1 < d.nx && !unknown(i + 1, j)) ||
+                (j > 0 && !unknown(i, j - 1)) || (j + 1 < d.ny && !unknown(i, j + 1)))
+                front.push_back(i + d.nx * j);
+        }
+    std::vector<double> fx(front.size()), fy(front.size());
+    for (size_t k = 0; k < front.size(); ++k) {
+        fx[k] = coord(d.x0, sx, front[k] % d.nx);
+        fy[k] = coord(d.y0, sy, front[k] / d.nx);
+    }
     P.ext.clear();
     for (int32_t je = 0; je < d.ny; ++je)
         for (int32_t ie = 0; ie < d.nx; ++ie) {
@@ -194,26 +208,16 @@ static void exterior_pairs(HostProblem &P)
             const double xe = coord(d.x0, sx, ie), ye = coord(d.y0, sy, je);
             double best = INFINITY;
             int32_t arg = -1;
-            const int32_t rmax = std::max(d.nx, d.ny);
-            for (int32_t r = 1; r <= rmax; ++r) {
-                for (int32_t j = std::max(je - r, 0); j <= std::min(je + r, d.ny - 1); ++j)
-                    for (int32_t i = std::max(ie - r, 0); i <= std::min(ie + r, d.nx - 1); ++i) {
-                        if (std::max(std::abs(i - ie), std::abs(j - je)) != r) continue;
-                        const int32_t u = i + d.nx * j;
-                        if (P.cls[(size_t)u] != 0) continue;
-                        const double ex = coord(d.x0, sx, i) - xe;
-                        const double ey = coord(d.y0, sy, j) - ye;
-                        const double ex2 = ex * ex;
-                        const double ey2 = ey * ey;
-                        const double d2 = ex2 + ey2;
-                        if (d2 < best || (d2 == best && u < arg)) {
-                            best = d2;
-                            arg = u;
-                        }
-                    }
-                // every node of the rings further out is at least (r + 1) hmin away
-                const double reach = (double)(r + 1) * hmin;
-                if (arg >= 0 && reach * reach > best * (1.0 + 1e-9)) break;
+            for (size_t k = 0; k < front.size(); ++k) {
+                const double ex = fx[k] - xe;
+                const double ey = fy[k] - ye;
+                const double ex2 = ex * ex;
+                const double ey2 = ey * ey;
+                const double d2 = ex2 + ey2;
+                if (d2 < best) {   // the frontier is in increasing id order: ties keep the lowest
+                    best = d2;
+                    arg = front[k];
+                }
             }
             P.ext.push_back(e);
             P.ext.push_back(arg);

@@ -242,7 +242,8 @@ def test_disc_domain_validation(lib, bad):
     assert arena_status(p)[0] == fkh.FK_EINVAL
 
 
-@pytest.mark.parametrize("case", ["shape2_21", "shape2_46", "shape2_33x41", "disc_hole_40", "rectangle"])
+@pytest.mark.parametrize("case", ["shape2_21", "shape2_46", "shape2_129", "shape2_33x41", "disc_hole_40",
+                                  "thin_annulus_65", "rectangle"])
 def test_exterior_nodes_are_the_oracles_nearest_unknown_nodes(lib, case):
     # the library's pairs (exterior node, the unknown node it reads) against
     # the oracle's own remap table, built by brute force over every unknown
@@ -255,8 +256,13 @@ def test_exterior_nodes_are_the_oracles_nearest_unknown_nodes(lib, case):
         p = W.annulus_shape2(n=46)
     elif case == "shape2_33x41":
         p = W.annulus_shape2(n=33).replace(ny=41)
+    elif case == "shape2_129":
+        p = W.annulus_shape2(n=129)
     elif case == "disc_hole_40":
         p = W.annulus_shape2(n=40).replace(domain_kind=W.DISC_MINUS_DISC, r=0.1)
+    elif case == "thin_annulus_65":
+        # the hole's rim a cell or two from the circle: both rims are frontier
+        p = W.annulus_shape2(n=65).replace(domain_kind=W.DISC_MINUS_DISC, r=0.42)
     else:
         p = W.annulus_shape1(n=13)
     pairs = fkh.exterior_nodes(p)
