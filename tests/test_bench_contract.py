@@ -59,6 +59,14 @@ def test_headline_kernel_names_follow_the_library_choice():
     assert bench.path_kernel_name(32, 0, True) == "fk_stream_f32<0>"
     assert bench.path_kernel_name(32, 2, True, lds=True) == "fk_stream_f32_lds<2>"
     assert bench.flops_per_step(64, True) == 60.0
+    # disc domains run the curved-edge builds (feature bit 6 with a hole and
+    # the reflecting edge)
+    from paper_2308_11469_amd import workloads as W
+    p = W.annulus_shape2(k=0.5, n=91)
+    assert bench._features(p) == 73
+    assert bench.path_kernel_name(64, bench._features(p), False) == "fk_stream_f64<73>"
+    assert bench.path_kernel_name(32, bench._features(p), True) == "fk_stream_f32<73>"
+    assert bench._features(W.annulus_shape3(nx=21, ny=33)) == 9
 
 
 def test_only_parts_parse():
