@@ -214,8 +214,11 @@ static int in_hole(const orc_problem *P, double x, double y)
     }
     if (P->domain_kind == ORC_RECT_MINUS_BOX)
         return x >= P->cx - P->r && x <= P->cx + P->r && y >= P->cy - P->ry && y <= P->cy + P->ry;
-    if (P->domain_kind == ORC_DISC_MINUS_RHOMBUS)
-        return fabs(x - P->cx) / P->r + fabs(y - P->cy) / P->ry <= 1.0;
+    if (P->domain_kind == ORC_DISC_MINUS_RHOMBUS) {
+        /* |x - cx| / r + |y - cy| / ry <= 1, multiplied through by r ry > 0 */
+        const double a = fabs(x - P->cx) * P->ry, b = fabs(y - P->cy) * P->r;
+        return a + b <= P->r * P->ry;
+    }
     return 0;
 }
 

@@ -308,6 +308,17 @@ __device__ __forceinline__ void normals(uint32_t ra, uint32_t rb, const NoTables
 
 // ------------------------------------------------------------- geometry
 
+// The closed rhombus |x - cx| / r + |y - cy| / ry <= 1, multiplied through
+// by r ry > 0 (no division).  Separate statements: no product is fused into
+// the sum, so every build rounds it the same way.
+__device__ __forceinline__ bool in_rhombus(const Inst &D, double x, double y)
+{
+    const double a = fabs(x - D.cx) * D.ry;
+    const double b = fabs(y - D.cy) * D.r;
+    const double lim = D.r * D.ry;
+    return a + b <= lim;
+}
+
 // The closed hole (FP64, the problem's own comparisons).  The rhombus only
 // occurs in disc domains (kernels with kFeatCurved).
 template <int F>
@@ -318,7 +329,7 @@ __device__ __forceinline__ bool in_hole(const Inst &D, double x, double y)
         return ex * ex + ey * ey <= D.r2;
     }
     if (D.hole == HOLE_BOX) return x >= D.bx0 && x <= D.bx1 && y >= D.by0 && y <= D.by1;
-    if ((F & kFeatCurved) && D.hole == HOLE_RHOMBUS) return fabs(x - D.cx) / D.r + fabs(y - D.cy) / D.ry <= 1.0;
+    if ((F & kFeatCurved) && D.hole == HOLE_RHOMBUS) return in_rhombus(D, x, y);
     return false;
 }
 

@@ -154,7 +154,7 @@ __device__ __forceinline__ bool is_out(const Inst &D, const Consts<double> &K, d
         return ex * ex + ey * ey <= K.r2f;
     }
     if ((F & kFeatDisc) && K.hole == HOLE_BOX) return x >= K.hx0 && x <= K.hx1 && y >= K.hy0 && y <= K.hy1;
-    if ((F & kFeatCurved) && K.hole == HOLE_RHOMBUS) return fabs(x - D.cx) / D.r + fabs(y - D.cy) / D.ry <= 1.0;
+    if ((F & kFeatCurved) && K.hole == HOLE_RHOMBUS) return in_rhombus(D, x, y);
     return false;
 }
 template <int F>
@@ -172,8 +172,7 @@ __device__ __forceinline__ bool is_out(const Inst &D, const Consts<float> &K, fl
     }
     if ((F & kFeatDisc) && K.hole == HOLE_BOX) return x >= K.hx0 && x <= K.hx1 && y >= K.hy0 && y <= K.hy1;
     // the rhombus (disc domains) in FP64, as the FP64 kernels test it
-    if ((F & kFeatCurved) && K.hole == HOLE_RHOMBUS)
-        return fabs((double)x - D.cx) / D.r + fabs((double)y - D.cy) / D.ry <= 1.0;
+    if ((F & kFeatCurved) && K.hole == HOLE_RHOMBUS) return in_rhombus(D, (double)x, (double)y);
     return false;
 }
 
