@@ -544,7 +544,8 @@ static void reflect_disc(const orc_problem *P, const double *u, int64_t t, doubl
     if (d2 <= R * R) return;
     const double d = sqrt(d2);
     const double o = d - R;                   /* overshoot */
-    const double s = (R - o) / d, f = R / d;
+    const double inv = 1.0 / d;               /* one reciprocal for both scale factors */
+    const double s = (R - o) * inv, f = R * inv;
     const double footx = ox + f * ex, footy = oy + f * ey;
     X[0] = ox + s * ex;
     X[1] = oy + s * ey;

@@ -290,7 +290,8 @@ __device__ __forceinline__ Mirror<double> reflect_disc(const Inst &D, double &x,
     if (d2 > D.orad2) {
         const double d = sqrt(d2);
         const double o = d - D.orad;
-        const double s = (D.orad - o) / d, f = D.orad / d;
+        const double inv = 1.0 / d;
+        const double s = (D.orad - o) * inv, f = D.orad * inv;
         fx = D.ocx + f * ex;
         fy = D.ocy + f * ey;
         x = D.ocx + s * ex;
