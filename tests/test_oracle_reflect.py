@@ -303,8 +303,9 @@ def test_disc_domain_node_classes_and_paths_stay_in_the_disc():
         for m in range(4):
             s, J, cap, (x, y) = fkmc.path(p, None, 0, nid, m)
             assert not cap
-            # ends in the closed rhombus, within one step of its edge
-            assert abs(x - 0.8) / 0.075 + abs(y - 0.5) / 0.075 <= 1.0
+            # ends in the closed rhombus (the oracle's test: |x - cx| ry +
+            # |y - cy| r <= r ry)
+            assert abs(x - 0.8) * 0.075 + abs(y - 0.5) * 0.075 <= 0.075 * 0.075
             assert (x - 0.8) ** 2 + (y - 0.5) ** 2 <= 0.45 ** 2
 
 
