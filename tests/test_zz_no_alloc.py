@@ -77,12 +77,13 @@ def test_static_step_matches_allocating_path_on_two_calls(precision):
     assert q3["n"] == 4
 
 
-def test_static_step_on_a_disc_domain():
+@pytest.mark.parametrize("precision", [64, 32])
+def test_static_step_on_a_disc_domain(precision):
     # a disc domain at k > 0: the exterior nodes take their nearest unknown
     # node's value after the update in both paths, so that the second call's
     # paths read the same extended iterate
-    p = W.annulus_shape2(n=21, k=1.0, M=128).replace(outer=W.BC("plane_wave_robin", 1.0, 0.4),
-                                                     inner=W.BC("plane_wave", 1.0, 0.4))
+    p = W.annulus_shape2(n=21, k=1.0, M=128, precision=precision).replace(
+        outer=W.BC("plane_wave_robin", 1.0, 0.4), inner=W.BC("plane_wave", 1.0, 0.4))
     u1, se1, r1 = allocating(p, None, 0)
     v1, sv1, q1 = static(p, None, 0)
     say("static step disc", r1["path_steps"])
